@@ -1,0 +1,512 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these retypes the oracle's formulas: they check closed forms
+(polynomial reproduction, barrier function), theorems (M-matrix, regular
+splitting, structure of N-hat), brute force (dense LU), textbook properties
+(GMRES minimal residual, finite termination, adjoint identities) and the
+paper's printed numbers (Tables 6 and 7, the 5 corner cycles).
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import oracle as O
+from paper_2108_13468_amd import inputs
+from tests.mms import exponential_mms
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def problem(inst):
+    return O.Problem(inst.N, inst.eps, c1=inst.c1_at, c2=inst.c2_at,
+                     r=(inst.r_const if inst.r_const is not None else None),
+                     sigma=inst.sigma, clow_x=inst.clow[0], clow_y=inst.clow[1])
+
+
+def plain(N, eps, r=1.0):
+    inst = inputs.plain(N, eps)
+    return O.Problem(N, eps, c1=inst.c1_at, c2=inst.c2_at, r=r)
+
+
+def dense(p):
+    return p.csr().toarray()
+
+
+def read_golden(name):
+    rows = []
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([float(t) for t in line.split()])
+    return rows
+
+
+# ---------------------------------------------------------------- mesh ----
+
+def test_mesh_small_case_transition():
+    # tau = min(1/2, 2 eps ln N) with eps = 1e-2, N = 64 -> 0.0832
+    tau, x, h = O.mesh_axis(64, 1e-2, 2.0, 1.0)
+    assert tau == pytest.approx(2 * 1e-2 * np.log(64), rel=1e-15)
+    assert x[0] == 0.0 and x[-1] == pytest.approx(1.0, abs=1e-15)
+    assert x[32] == pytest.approx(tau, rel=1e-15)
+    assert np.all(np.diff(x) > 0)
+    np.testing.assert_allclose(h[1:33], 2 * tau / 64, rtol=1e-14)
+    np.testing.assert_allclose(h[33:], 2 * (1 - tau) / 64, rtol=1e-14)
+    np.testing.assert_allclose(np.diff(x), h[1:], rtol=1e-12)
+
+
+def test_mesh_uniform_when_eps_large():
+    tau, x, h = O.mesh_axis(32, 1.0, 2.0, 1.0)
+    assert tau == 0.5
+    np.testing.assert_allclose(x, np.linspace(0, 1, 33), atol=1e-15)
+
+
+# ------------------------------------------------------------ operator ----
+
+@pytest.mark.parametrize("N,eps", [(8, 1e-2), (16, 1e-4), (64, 1e-2), (32, 1e-8)])
+def test_m_matrix_sign_pattern(N, eps):
+    """Upwind stencil: positive diagonal, non-positive off-diagonals, weak
+    row diagonal dominance (row sums >= r >= 0): an M-matrix (Sec. 3)."""
+    p = plain(N, eps)
+    A = dense(p)
+    d = np.diag(A)
+    off = A - np.diag(d)
+    assert np.all(d > 0)
+    assert np.all(off <= 0)
+    assert np.all(A.sum(axis=1) >= p.r - 1e-9 * d)
+
+
+@pytest.mark.parametrize("N,eps", [(16, 1e-2), (32, 1e-5), (64, 1e-2)])
+def test_polynomial_reproduction(N, eps):
+    """Rows away from the boundary: A 1 = r, A x = -c1 + r x,
+    A x^2 = -2 eps - c1 (2 x_i + h_{i+1}) + r x_i^2, and the same in y
+    (the upwind difference quotients are exact for these polynomials)."""
+    p = plain(N, eps)
+    n1 = N - 1
+    X, Y = np.meshgrid(p.x[1:N], p.y[1:N])
+    c1 = p.c1x[1:N][None, :]
+    c2 = p.c2y[1:N][:, None]
+    hx1 = p.hx[2:N + 1][None, :]
+    ky1 = p.hy[2:N + 1][:, None]
+    r = p.r.reshape(n1, n1)
+    inner = np.zeros((n1, n1), bool)
+    inner[1:-1, 1:-1] = True
+    cases = [
+        (np.ones_like(X), r),
+        (X, -c1 + r * X),
+        (X ** 2, -2 * eps - c1 * (2 * X + hx1) + r * X ** 2),
+        (Y, -c2 + r * Y),
+        (Y ** 2, -2 * eps - c2 * (2 * Y + ky1) + r * Y ** 2),
+    ]
+    for u, expect in cases:
+        got = p.A(u.ravel()).reshape(n1, n1)
+        scale = np.abs(dense(p)).sum(axis=1).reshape(n1, n1) * np.abs(u).max()
+        err = np.abs(got - expect)[inner] / scale[inner]
+        assert err.max() < 1e-13
+
+
+@pytest.mark.parametrize("N,eps", [(16, 1e-3), (64, 1e-2), (128, 1e-6)])
+def test_barrier_function(N, eps):
+    """A W >= min c1 for W = 2 - x_i on every row (barrier function behind
+    ||A^{-1}||_inf <= 2 / Clow, Sec. 3.1)."""
+    p = plain(N, eps)
+    X, _ = np.meshgrid(p.x[1:N], p.y[1:N])
+    AW = p.A((2 - X).ravel())
+    assert AW.min() >= p.c1x.min() * (1 - 1e-12)
+
+
+def test_transpose_and_csr_consistency():
+    p = plain(16, 1e-3)
+    A = dense(p)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(p.n)
+    np.testing.assert_allclose(p.A(x), A @ x, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+    np.testing.assert_allclose(p.AT(x), A.T @ x, rtol=1e-13, atol=1e-13 * np.abs(A).max())
+
+
+# ----------------------------------------------------- discretisation ----
+
+@pytest.mark.parametrize("N", [128, 256])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_table6_mms_errors(N, eps):
+    """Exponential MMS max error vs Table 6 (solved exactly here by SuperLU;
+    the paper's errors carry its loose FGMRES tolerance): within 1%."""
+    ref = {(e, int(n)): v for e, n, v in read_golden("table6_exponential_mms_errors.txt")}
+    p = problem(inputs.mms_exponential(N, eps))
+    u, f = exponential_mms(eps, p.x, p.y)
+    U = spla.spsolve(p.csr().tocsc(), f)
+    err = np.abs(U - u).max()
+    assert err == pytest.approx(ref[(eps, N)], rel=0.01)
+
+
+def test_mms_almost_first_order_rate():
+    """Errors decay like N^-1 ln N: rate log2(E_N/E_2N) matches the paper's
+    Table 6 ratios (0.72 for 128 -> 256)."""
+    ref = {(e, int(n)): v for e, n, v in read_golden("table6_exponential_mms_errors.txt")}
+    errs = {}
+    for N in (64, 128, 256):
+        p = problem(inputs.mms_exponential(N, 1e-5))
+        u, f = exponential_mms(1e-5, p.x, p.y)
+        errs[N] = np.abs(spla.spsolve(p.csr().tocsc(), f) - u).max()
+    rate = np.log2(errs[128] / errs[256])
+    assert rate == pytest.approx(np.log2(ref[(1e-5, 128)] / ref[(1e-5, 256)]), abs=0.01)
+    assert 0.6 < np.log2(errs[64] / errs[128]) < 0.8
+
+
+# --------------------------------------------------------- solver: LU ----
+
+@pytest.mark.parametrize("N,eps,tol", [(8, 1e-2, 1e-12), (16, 1e-4, 1e-12), (16, 1e-8, 1e-8)])
+def test_fgmres_matches_dense_lu(N, eps, tol):
+    p = plain(N, eps)
+    rng = np.random.default_rng(N)
+    F = rng.standard_normal(p.n)
+    ue = np.linalg.solve(dense(p), F)
+    u, st, info, hist = p.fgmres(F, tol=tol)
+    assert st == 0 and info.converged
+    # ||A^{-1}||_inf <= 2 / Clow bounds the error by the residual
+    assert np.abs(u - ue).max() <= 2 * np.abs(F - p.A(u)).max() + 1e-14 * np.abs(ue).max()
+    assert np.abs(u - ue).max() <= 1e3 * tol * np.abs(ue).max()
+
+
+def test_small_case_against_dense_lu():
+    """N = 64, eps = 1e-2, 63^2 unknowns, preconditioned FGMRES(50) to 1e-10."""
+    inst = inputs.small_case()
+    p = problem(inst)
+    F = O.sine_series(inst.N, p.x, p.y, inst.a)
+    ue = np.linalg.solve(dense(p), F)
+    u, st, info, hist = p.fgmres(F, tol=1e-10, restart=50)
+    assert st == 0
+    assert np.linalg.norm(F - p.A(u)) <= 1e-10 * np.linalg.norm(F)
+    assert np.abs(u - ue).max() <= 1e-8 * np.abs(ue).max()
+
+
+# ------------------------------------------------- preconditioner: M-hat ----
+
+def extract(op, n):
+    return np.column_stack([op(e) for e in np.eye(n)])
+
+
+@pytest.mark.parametrize("N,eps", [(8, 1e-2), (12, 1e-3), (16, 1e-5)])
+def test_mhat_structure(N, eps):
+    """M-hat (exact corner) = A with the West entries dropped on rows with
+    i > N/2 and the South entries dropped on rows with j > N/2: N-hat = M-hat - A
+    is non-negative with at most two entries per row, each the negative of a
+    diffusion coupling of A (Sec. 3.1)."""
+    p = plain(N, eps)
+    A = dense(p)
+    Minv = extract(lambda b: p.M_inv(b, corner="exact"), p.n)
+    M = np.linalg.inv(Minv)
+    Nh = M - A
+    scale = np.abs(A).max()
+    Nh[np.abs(Nh) < 1e-9 * scale] = 0.0
+    n1, h = N - 1, N // 2
+    expect = np.zeros_like(A)
+    for j in range(1, N):
+        for i in range(1, N):
+            pr = (j - 1) * n1 + (i - 1)
+            if i > h and i > 1:
+                expect[pr, pr - 1] = -A[pr, pr - 1]
+            if j > h and j > 1:
+                expect[pr, pr - n1] = -A[pr, pr - n1]
+    np.testing.assert_allclose(Nh, expect, rtol=1e-7, atol=1e-9 * scale)
+    assert np.all(Nh >= 0)
+    assert (np.count_nonzero(Nh, axis=1) <= 2).all()
+
+
+@pytest.mark.parametrize("N,eps", [(8, 1e-2), (16, 1e-3), (16, 1e-6)])
+def test_regular_splitting_contraction(N, eps):
+    """rho(I - M-hat^{-1} A) < 1 (regular splitting of an M-matrix)."""
+    p = plain(N, eps)
+    A = dense(p)
+    Minv = extract(lambda b: p.M_inv(b, corner="exact"), p.n)
+    rho = np.abs(np.linalg.eigvals(np.eye(p.n) - Minv @ A)).max()
+    assert rho < 1.0
+
+
+def test_practical_M_tends_to_mhat():
+    """With many corner V-cycles, M^{-1} b -> M-hat^{-1} b."""
+    p = plain(32, 1e-4)
+    b = np.random.default_rng(1).standard_normal(p.n)
+    z_hat = p.M_inv(b, corner="exact")
+    z = p.M_inv(b, mg_fixed=60)
+    assert np.abs(z - z_hat).max() <= 1e-11 * np.abs(z_hat).max()
+
+
+def test_region_solves_are_exact():
+    """Each region solve inverts its block exactly: apply the block's own
+    rows of A (with the dropped couplings excluded) to the result."""
+    N, eps = 16, 1e-3
+    p = plain(N, eps)
+    A = dense(p)
+    n1, h = N - 1, N // 2
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(p.n)
+    z = np.zeros(p.n)
+    z = p.solve_region("I", b, z)
+    idx = lambda i, j: (j - 1) * n1 + (i - 1)
+    for j in range(h + 1, N):
+        for i in range(h + 1, N):
+            pr = idx(i, j)
+            s = A[pr, pr] * z[pr]
+            if i < n1:
+                s += A[pr, idx(i + 1, j)] * z[idx(i + 1, j)]
+            if j < n1:
+                s += A[pr, idx(i, j + 1)] * z[idx(i, j + 1)]
+            assert s == pytest.approx(b[pr], rel=1e-12, abs=1e-12 * abs(A[pr, pr] * z[pr]))
+    z = p.solve_region("Y", b, z)
+    for i in range(h + 1, N):
+        for j in range(1, h + 1):
+            pr = idx(i, j)
+            s = A[pr, pr] * z[pr]
+            if i < n1:
+                s += A[pr, idx(i + 1, j)] * z[idx(i + 1, j)]
+            if j > 1:
+                s += A[pr, idx(i, j - 1)] * z[idx(i, j - 1)]
+            s += A[pr, idx(i, j + 1)] * z[idx(i, j + 1)]
+            assert s == pytest.approx(b[pr], rel=1e-10, abs=1e-10 * abs(A[pr, pr] * z[pr]))
+
+
+# ---------------------------------------------------------- multigrid ----
+
+def test_restriction_is_full_weighting_on_uniform_part():
+    """S_c^{-1} P^T S_f equals 1/16 [1 2 1; 2 4 2; 1 2 1] at interior coarse
+    nodes of a uniform level (Sec. 3.2 remark on full weighting)."""
+    p = plain(64, 1e-4)
+    n0, n1c = p.levels[0], p.levels[1]
+    rf = np.zeros(n0 * n0)
+    ic, jc = 5, 7  # coarse node, fine node (10, 14)
+    W = np.outer([1, 2, 1], [1, 2, 1]) / 16.0
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            rf[:] = 0.0
+            fi, fj = 2 * ic + di, 2 * jc + dj
+            rf[(fj - 1) * n0 + (fi - 1)] = 1.0
+            bc = p.level_op("restrict", 0, rf)
+            assert bc[(jc - 1) * n1c + (ic - 1)] == pytest.approx(W[dj + 1, di + 1], rel=1e-12)
+
+
+def test_interpolation_reproduces_bilinear():
+    """P is bilinear: coarse samples of x*y interpolate to fine samples of
+    x*y exactly (x*y vanishes on the Dirichlet sides x=0 and y=0)."""
+    p = plain(64, 1e-4)
+    n0, n1c = p.levels[0], p.levels[1]
+    xf, yf = p.x[1:n0 + 1], p.y[1:n0 + 1]
+    xc, yc = xf[1::2], yf[1::2]
+    zc = np.outer(yc, xc).ravel()
+    zf = p.level_op("interp", 0, zc)
+    np.testing.assert_allclose(zf, np.outer(yf, xf).ravel(), rtol=1e-12, atol=1e-18)
+
+
+def test_gauss_seidel_is_triangular_solve():
+    """One downstream GS sweep = (D + U)^{-1} (b - L z) with U the East and
+    North couplings."""
+    p = plain(16, 1e-4)
+    n0 = p.levels[0]
+    A0 = extract(lambda v: p.level_op("apply", 0, v), n0 * n0)
+    D = np.diag(np.diag(A0))
+    Up = np.triu(A0, 1)
+    Lo = np.tril(A0, -1)
+    rng = np.random.default_rng(4)
+    b, z = rng.standard_normal(n0 * n0), rng.standard_normal(n0 * n0)
+    got = p.level_gs(0, b, z)
+    np.testing.assert_allclose(got, np.linalg.solve(D + Up, b - Lo @ z), rtol=1e-12, atol=1e-14)
+
+
+def test_corner_mg_converges_to_exact():
+    p = plain(64, 1e-5)
+    b = np.random.default_rng(5).standard_normal(p.h ** 2)
+    z, _ = p.corner_mg(b, fixed=40)
+    ze = p.corner_exact(b)
+    assert np.abs(z - ze).max() <= 1e-11 * np.abs(ze).max()
+
+
+@pytest.mark.parametrize("N", [128, 256, 512])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_corner_cycles_and_table7_iterations(N, eps):
+    """Paper-comparable mode (sigma = 5/2, ||R||_2 <= 10 ln N / N): every
+    corner solve takes 5 V-cycles for the 1e3 reduction (Sec. 3.2), and the
+    FGMRES iteration counts are those of Table 7."""
+    ref = {(e, int(n)): int(v) for e, n, v in read_golden("table7_exponential_iterations.txt")}
+    p = problem(inputs.mms_exponential(N, eps))
+    _, f = exponential_mms(eps, p.x, p.y)
+    u, st, info, hist = p.fgmres(f, tol=10 * np.log(N) / N, absolute=True)
+    assert st == 0
+    assert info.mg_cycles_min == 5 and info.mg_cycles_max == 5
+    assert info.iterations == ref[(eps, N)]
+
+
+def test_table7_eps_small_rows_within_two():
+    ref = {(e, int(n)): int(v) for e, n, v in read_golden("table7_exponential_iterations.txt")}
+    for eps in (1e-5, 1e-7):
+        for N in (128, 256, 512):
+            p = problem(inputs.mms_exponential(N, eps))
+            _, f = exponential_mms(eps, p.x, p.y)
+            u, st, info, _ = p.fgmres(f, tol=10 * np.log(N) / N, absolute=True)
+            assert abs(info.iterations - ref[(eps, N)]) <= 2
+
+
+# -------------------------------------------------------------- FGMRES ----
+
+def test_gmres_minimal_residual_property():
+    """Unpreconditioned: the k-th residual estimate equals min over the
+    Krylov space K_k(A, F) of ||F - A y|| (computed by least squares)."""
+    p = plain(8, 1e-2)
+    A = dense(p)
+    F = np.random.default_rng(6).standard_normal(p.n)
+    u, st, info, hist = p.fgmres(F, tol=1e-14, precond=False, restart=60, maxit=60)
+    K = [F / np.linalg.norm(F)]
+    for k in range(1, 12):
+        basis = np.column_stack(K)
+        AK = A @ basis
+        y, *_ = np.linalg.lstsq(AK, F, rcond=None)
+        assert hist[k] == pytest.approx(np.linalg.norm(F - AK @ y), rel=1e-6)
+        w = A @ K[-1]
+        for q in K:
+            w -= (w @ q) * q
+        K.append(w / np.linalg.norm(w))
+
+
+def test_gmres_finite_termination_and_monotone():
+    p = plain(8, 1e-2)
+    F = np.random.default_rng(7).standard_normal(p.n)
+    u, st, info, hist = p.fgmres(F, tol=1e-12, precond=False, restart=p.n, maxit=p.n)
+    assert st == 0 and info.iterations <= p.n
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+
+
+def test_fgmres_restart_and_true_residual():
+    inst = inputs.small_case()
+    p = problem(inst)
+    F = O.sine_series(inst.N, p.x, p.y, inst.a)
+    u, st, info, hist = p.fgmres(F, tol=1e-10, restart=3)
+    assert st == 0 and info.restarts >= 2
+    assert np.linalg.norm(F - p.A(u)) <= 1e-10 * np.linalg.norm(F)
+    assert info.true_res == pytest.approx(np.linalg.norm(F - p.A(u)), rel=1e-6)
+
+
+def test_fgmres_maxit_reports_no_convergence():
+    p = plain(32, 1e-2)
+    F = np.random.default_rng(8).standard_normal(p.n)
+    u, st, info, hist = p.fgmres(F, tol=1e-14, maxit=1)
+    assert st == 1 and not info.converged and info.iterations == 1
+
+
+# ------------------------------------------------------------- adjoint ----
+
+@pytest.mark.parametrize("N,eps", [(16, 1e-3), (64, 1e-6)])
+def test_transpose_identities(N, eps):
+    p = plain(N, eps)
+    rng = np.random.default_rng(9)
+    x, y = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    assert p.A(x) @ y == pytest.approx(x @ p.AT(y), rel=1e-13)
+    for kw in (dict(corner="exact"), dict(mg_fixed=2)):
+        lhs = p.M_inv(x, **kw) @ y
+        rhs = x @ p.M_inv(y, transpose=True, **kw)
+        assert lhs == pytest.approx(rhs, rel=1e-11)
+
+
+def test_adjoint_solve_matches_dense():
+    p = plain(16, 1e-4)
+    g = np.random.default_rng(10).standard_normal(p.n)
+    lam, st, info, _ = p.fgmres(g, tol=1e-12, transpose=True)
+    ref = np.linalg.solve(dense(p).T, g)
+    assert st == 0
+    assert np.abs(lam - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_projection_adjoints_and_partition_of_unity():
+    p = plain(32, 1e-3)
+    rng = np.random.default_rng(11)
+    a = rng.standard_normal((4, 5))
+    lam = rng.standard_normal(p.n)
+    F = O.sine_series(32, p.x, p.y, a)
+    g = O.sine_project(32, p.x, p.y, lam, 5, 4)
+    assert F @ lam == pytest.approx((g * a).sum(), rel=1e-12)
+    R = rng.standard_normal((4, 4))
+    r = O.bilinear(32, p.x, p.y, R)
+    G = O.bilinear_project(32, p.x, p.y, lam, 4)
+    assert r @ lam == pytest.approx((G * R).sum(), rel=1e-12)
+    np.testing.assert_allclose(O.bilinear(32, p.x, p.y, np.ones((4, 4))), 1.0, rtol=1e-14)
+    # a bilinear function of (x, y) is reproduced exactly
+    t = np.linspace(0, 1, 4)
+    Rb = (1 + 2 * t[None, :]) * (3 - t[:, None])  # [q, p] = f(x_p, y_q)
+    X, Y = np.meshgrid(p.x[1:32], p.y[1:32])
+    np.testing.assert_allclose(O.bilinear(32, p.x, p.y, Rb), ((1 + 2 * X) * (3 - Y)).ravel(), rtol=1e-13)
+
+
+def _dense_misfit(N, eps, a, R, uobs):
+    x = O.mesh_axis(N, eps)[1]
+    r = O.bilinear(N, x, x, R)
+    inst = inputs.plain(N, eps)
+    p = O.Problem(N, eps, c1=inst.c1_at, c2=inst.c2_at, r=r)
+    F = O.sine_series(N, p.x, p.y, a)
+    A = dense(p)
+    u = np.linalg.solve(A, F)
+    return 0.5 * np.sum((u - uobs) ** 2), u, A, p
+
+
+def test_adjoint_gradient_vs_dense_and_fd():
+    """Gradient of J = 0.5 ||u - u_obs||^2 w.r.t. the sine coefficients and
+    the bilinear r controls at N = 32: oracle adjoint (FGMRES on A^T with M^T)
+    vs a dense adjoint (LU of A^T) and vs central differences (h = 1e-6)."""
+    N, eps = 32, 1e-4
+    case = inputs.adjoint_case(N=N, eps=eps, K=4, m=4)
+    _, uref, _, _ = _dense_misfit(N, eps, case.a_ref, case.R_ref, 0.0)
+    uobs = uref + case.noise
+    a, R = case.inst.a, case.inst.r_ctrl
+    J, u, A, p = _dense_misfit(N, eps, a, R, uobs)
+    lam, st, _, _ = p.fgmres(u - uobs, tol=1e-12, transpose=True)
+    ga = O.sine_project(N, p.x, p.y, lam, 4, 4)
+    gR = -O.bilinear_project(N, p.x, p.y, lam * u, 4)
+    lam_d = np.linalg.solve(A.T, u - uobs)
+    np.testing.assert_allclose(ga, O.sine_project(N, p.x, p.y, lam_d, 4, 4), rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gR, -O.bilinear_project(N, p.x, p.y, lam_d * u, 4), rtol=1e-9, atol=1e-12)
+    hstep = 1e-6
+    for (l, k) in [(0, 0), (2, 1), (3, 3)]:
+        ap, am = a.copy(), a.copy()
+        ap[l, k] += hstep
+        am[l, k] -= hstep
+        fd = (_dense_misfit(N, eps, ap, R, uobs)[0] - _dense_misfit(N, eps, am, R, uobs)[0]) / (2 * hstep)
+        assert ga[l, k] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+    for (q, pp) in [(0, 1), (2, 2)]:
+        Rp, Rm = R.copy(), R.copy()
+        Rp[q, pp] += hstep
+        Rm[q, pp] -= hstep
+        fd = (_dense_misfit(N, eps, a, Rp, uobs)[0] - _dense_misfit(N, eps, a, Rm, uobs)[0]) / (2 * hstep)
+        assert gR[q, pp] == pytest.approx(fd, rel=1e-4, abs=1e-9)
+
+
+# ------------------------------------------------------------ scaled mode ----
+
+@pytest.mark.parametrize("N,eps", [(16, 1e-6), (64, 1e-2)])
+def test_scaled_mode_solves_same_system(N, eps):
+    """FGMRES on D^{-1/2} A D^{-1/2} returns the solution of A u = F."""
+    p = plain(N, eps)
+    F = np.random.default_rng(12).standard_normal(p.n)
+    ue = np.linalg.solve(dense(p), F)
+    u, st, info, hist = p.fgmres(F, tol=1e-11, scaled=True)
+    assert st == 0
+    assert np.abs(u - ue).max() <= 1e-8 * np.abs(ue).max()
+    d = np.sqrt(np.diag(dense(p)))
+    rs = (F - p.A(u)) / d
+    assert np.linalg.norm(rs) <= 1.01e-11 * np.linalg.norm(F / d)
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+
+
+def test_unscaled_residual_floor_is_above_target_at_small_eps():
+    """Why the scaled system is used for relative-residual targets: even the
+    exact solution rounded to FP64 has an unscaled relative residual far above
+    1e-8 when eps is small (the floor is ~ unit roundoff * || |A| |u| || / ||F||),
+    while the scaled residual of the same vector is below it."""
+    import scipy.sparse.linalg as spla
+    inst = inputs.plain(256, 1e-8)
+    p = problem(inst)
+    F = O.sine_series(256, p.x, p.y, inst.a)
+    A = p.csr()
+    U = spla.spsolve(A.tocsc(), F)
+    r = F - p.A(U)
+    assert np.linalg.norm(r) / np.linalg.norm(F) > 1e-7
+    d = np.sqrt(A.diagonal())
+    assert np.linalg.norm(r / d) / np.linalg.norm(F / d) < 1e-8
