@@ -1,0 +1,203 @@
+/*
+ * blp.h -- C ABI of the MI355X boundary-layer-preconditioned FGMRES solver.
+ *
+ * Method: MacLachlan, Madden & Nhan, "A Boundary-Layer Preconditioner for
+ * Singularly Perturbed Convection Diffusion" (arXiv 2108.13468).
+ *
+ * Problem (Sec. 1, eq. 2D):  -eps Lap u - c . grad u + r u = f  on (0,1)^2,
+ * u = 0 on the boundary, eps in (0,1], c1 > 0, c2 >= 0, r >= 0 (Sec. 3).
+ * Discretisation: upwind 5-point stencil (Sec. 3, 2D stencil) on the tensor
+ * Shishkin mesh with N cells per axis, transition
+ * tau = min(1/2, sigma eps ln(N) / clow) and N/2 uniform cells on each side
+ * (Sec. 2.2 eq. tau 1D, Sec. 3 eq. tau exponential).
+ *
+ * Unknowns: the (N-1)^2 interior nodes (i, j), 1 <= i, j <= N-1, stored
+ * x-fastest: index (j-1)(N-1) + (i-1).  Several right-hand sides are stacked
+ * contiguously (stride (N-1)^2).
+ *
+ * Pointers: arguments documented "host" are read on the calling thread and
+ * not kept; arguments documented "device" are device pointers (for example
+ * torch.Tensor.data_ptr() of a CUDA/HIP tensor) read or written on the
+ * stream given to blp_assemble.  The library copies every coefficient at
+ * assemble time and keeps no caller pointer after a call returns.  All
+ * device memory the library allocates belongs to the problem handle and is
+ * freed by blp_destroy.
+ *
+ * Errors: every int-returning call returns BLP_OK (0), BLP_W_NOCONV (+1, a
+ * solve stopped at its iteration cap; outputs hold the last iterate) or a
+ * negative BLP_E_* code.  blp_strerror() names a code.  Calls on one handle
+ * must not overlap in time (one host thread at a time per handle).
+ */
+#ifndef BLP_H
+#define BLP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLP_OK 0
+#define BLP_W_NOCONV 1
+#define BLP_E_INVAL (-1)   /* argument outside the method's assumptions     */
+#define BLP_E_NOMEM (-2)   /* device or host allocation failed              */
+#define BLP_E_HIP (-3)     /* a HIP runtime call or kernel launch failed    */
+#define BLP_E_STATE (-4)   /* call out of order (e.g. solve before setup)   */
+#define BLP_E_NUMERIC (-5) /* NaN or Inf met in a residual norm             */
+
+typedef struct blp_problem blp_problem;
+
+/* Coefficient fields.  kind:
+ *   BLP_CONST     v[0]
+ *   BLP_AXIS      N+1 nodal values along the field's own axis (c1 along x,
+ *                 c2 along y); the paper's workloads have c1 = c1(x),
+ *                 c2 = c2(y)
+ *   BLP_NODAL     (N-1)^2 interior values, x-fastest (r only)
+ *   BLP_BILINEAR  m x m controls on a uniform grid of [0,1]^2, x-fastest
+ *                 (v[q*m + p] at (p/(m-1), q/(m-1))), hat-function
+ *                 interpolation (r only)
+ * All v are host pointers. */
+#define BLP_CONST 0
+#define BLP_AXIS 1
+#define BLP_NODAL 2
+#define BLP_BILINEAR 3
+typedef struct {
+  int kind;
+  int m;
+  const double *v;
+} blp_field;
+
+/* Shishkin mesh parameters (eq. tau exponential): sigma and the lower bounds
+ * clow_x <= c1, clow_y <= c2.  The workloads use sigma = 2, clow = 1; the
+ * paper's Sec. 3.3 tests use sigma = 5/2. */
+typedef struct {
+  double sigma;
+  double clow_x, clow_y;
+} blp_mesh_opts;
+
+/* One mesh axis: nodes[0..N] (host, N+1 doubles).  Returns tau through
+ * *tau (may be NULL).  Pure host computation in FP64.  Errors: BLP_E_INVAL
+ * for odd N, N < 4, eps outside (0,1] or non-positive sigma/clow. */
+int blp_mesh(int N, double eps, double sigma, double clow, double *nodes,
+             double *tau);
+
+/* Build the discrete operator on the device (Sec. 3, 2D stencil) and the
+ * per-axis stencil tables; uploads r (BLP_BILINEAR controls are expanded to
+ * nodal values by a kernel).  stream: a hipStream_t (NULL = default stream)
+ * that every later call on this handle uses.  Errors: BLP_E_INVAL (odd N,
+ * N < 4 or N > 2048, eps outside (0,1], c1 <= 0, c2 < 0, r < 0, NaN, bad field kind),
+ * BLP_E_NOMEM, BLP_E_HIP. */
+int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2,
+                 const blp_field *r, const blp_mesh_opts *mesh, void *stream,
+                 blp_problem **out);
+
+/* Mesh nodes of an assembled problem (host arrays of N+1 doubles each). */
+int blp_nodes(const blp_problem *p, double *x, double *y);
+
+/* Preconditioner setup (Sec. 3.1 and 3.2; setup phase described in
+ * Sec. 3.3): Thomas factorisations of the X and Y edge-layer lines (no
+ * pivoting, Lemma diag_dom), the corner multigrid hierarchy (full
+ * coarsening, rediscretised levels, FE rescaling) and the FP32 copies used
+ * by the mixed-precision mode.
+ *   mg_fixed  > 0: every corner solve runs exactly this many V(1,1) cycles
+ *             (makes M a fixed linear operator; needed for M^T identities)
+ *             = 0: stationary iteration until the corner residual of the
+ *             rescaled system has dropped by mg_rtol (paper: 1e-3), at most
+ *             mg_maxcyc cycles.
+ * Errors: BLP_E_INVAL, BLP_E_NOMEM, BLP_E_HIP. */
+typedef struct {
+  int mg_fixed;
+  double mg_rtol;
+  int mg_maxcyc;
+} blp_prec_opts;
+int blp_precondition(blp_problem *p, const blp_prec_opts *opts);
+
+/* Solver options.
+ *   tol, absolute   stop when ||r|| <= tol (absolute) or <= tol ||F||
+ *   scaled          1: the residual is that of the symmetrically Jacobi-
+ *                   scaled system D^{-1/2} A D^{-1/2} (D = diag A), i.e.
+ *                   ||D^{-1/2}(F - A u)||; 0: the plain residual ||F - A u||
+ *   restart, maxit  FGMRES(restart), cap on total inner iterations
+ *   precision       BLP_FP64, or BLP_MIXED: FP32 preconditioner, FP32
+ *                   Krylov vectors and FP32-stored SpMV operands inside an
+ *                   FP64 restarted outer loop (FP64 true residuals,
+ *                   Hessenberg/Givens and solution)
+ *   precond         1: boundary-layer preconditioner M; 0: none */
+#define BLP_FP64 0
+#define BLP_MIXED 1
+typedef struct {
+  double tol;
+  int absolute;
+  int scaled;
+  int restart;
+  int maxit;
+  int precision;
+  int precond;
+} blp_solve_opts;
+
+typedef struct {
+  int iterations;       /* inner iterations (preconditioner applies) */
+  int restarts;         /* completed restart (outer) cycles */
+  int converged;
+  double res;           /* final true residual norm (per opts.scaled) */
+  double norm_F;        /* norm of the right-hand side (per opts.scaled) */
+  long mg_cycles_total; /* corner V-cycles over all applies */
+  int mg_cycles_min, mg_cycles_max;
+  double solve_ms;      /* wall time of the call */
+} blp_solve_info;
+
+/* Solve A U = F (Sec. 3.3: FGMRES, right preconditioned with M) from U = 0,
+ * for nrhs right-hand sides sharing the operator.  F, U: device, nrhs
+ * stacked vectors of (N-1)^2 doubles.  info: host, nrhs entries (may be
+ * NULL).  hist: host, (maxit+1) doubles per right-hand side or NULL;
+ * hist[0] = initial residual norm, hist[k] = residual estimate after inner
+ * iteration k (FP64 mode; in mixed mode the outer true residuals are
+ * recorded at restart boundaries).  Errors: BLP_E_STATE before
+ * blp_precondition, BLP_E_INVAL, BLP_E_NUMERIC, BLP_E_HIP; BLP_W_NOCONV if
+ * any right-hand side hit maxit. */
+int blp_solve(blp_problem *p, int nrhs, const double *F, double *U,
+              const blp_solve_opts *opts, blp_solve_info *info, double *hist);
+
+/* Adjoint solve A^T Lambda = G with the transposed preconditioner M^T
+ * (block lower triangular: corner cycle for A_CC^T, X lines bottom to top,
+ * Y lines left to right, interior sweep from the bottom-left).  Same
+ * arguments and errors as blp_solve. */
+int blp_solve_adjoint(blp_problem *p, int nrhs, const double *G, double *Lambda,
+                      const blp_solve_opts *opts, blp_solve_info *info,
+                      double *hist);
+
+/* Single operator applications on one vector (device in/out, (N-1)^2
+ * doubles), for tests: BLP_OP_A (y = A x), BLP_OP_AT (y = A^T x),
+ * BLP_OP_MINV (y = M^{-1} x), BLP_OP_MINVT (y = M^{-T} x), and the FP32
+ * preconditioner in FP64 arguments: BLP_OP_MINV32.  cycles (host, may be
+ * NULL) receives the corner V-cycles used.  Errors: BLP_E_STATE,
+ * BLP_E_INVAL, BLP_E_HIP. */
+#define BLP_OP_A 0
+#define BLP_OP_AT 1
+#define BLP_OP_MINV 2
+#define BLP_OP_MINVT 3
+#define BLP_OP_MINV32 4
+int blp_apply(blp_problem *p, int op, const double *x, double *y, int *cycles);
+
+/* Right-hand side and gradient helpers for the sine-series forcing and the
+ * bilinear reaction field (problem data of the workloads).
+ * blp_sine_rhs:     F_ij = sum_{k<=K,l<=L} a[(l-1)K+(k-1)] sin(k pi x_i) sin(l pi y_j)
+ *                   a: host K*L doubles; F: device (N-1)^2 doubles.
+ * blp_sine_project: g_kl = sum_ij w_ij sin(k pi x_i) sin(l pi y_j)
+ *                   (adjoint of blp_sine_rhs); w: device, g: host K*L.
+ * blp_bilinear_project: G[q*m+p] = sum_ij w_ij phi_p(x_i) phi_q(y_j)
+ *                   w: device (N-1)^2, G: host m*m.
+ * blp_mul: out_ij = a_ij * b_ij (device vectors), used for dJ/dr = -lambda u. */
+int blp_sine_rhs(blp_problem *p, int K, int L, const double *a, double *F);
+int blp_sine_project(blp_problem *p, int K, int L, const double *w, double *g);
+int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G);
+int blp_mul(blp_problem *p, const double *a, const double *b, double *out);
+
+/* Device bytes held by the handle. */
+long long blp_footprint(const blp_problem *p);
+
+void blp_destroy(blp_problem *p);
+const char *blp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

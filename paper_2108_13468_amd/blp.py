@@ -1,0 +1,256 @@
+"""Python binding of the HIP library libblp.so (C ABI in include/blp.h).
+
+Argument marshalling only: device buffers are torch tensors on the HIP
+device (their data_ptr() is passed), host arrays are numpy arrays, and the
+problem's stream is torch's current stream at assemble time.  Every step of
+the solver runs in the library's kernels.  There is no fallback: if the
+library is not built, loading raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libblp.so")
+
+BLP_OK, BLP_W_NOCONV = 0, 1
+BLP_CONST, BLP_AXIS, BLP_NODAL, BLP_BILINEAR = 0, 1, 2, 3
+BLP_FP64, BLP_MIXED = 0, 1
+OPS = {"A": 0, "AT": 1, "MINV": 2, "MINVT": 3, "MINV32": 4}
+
+# Symbols declared in include/blp.h (checked by the CPU tests).
+EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_solve",
+           "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
+           "blp_bilinear_project", "blp_mul", "blp_footprint", "blp_destroy", "blp_strerror")
+
+_dp = C.POINTER(C.c_double)
+
+
+class Field(C.Structure):
+    _fields_ = [("kind", C.c_int), ("m", C.c_int), ("v", _dp)]
+
+
+class MeshOpts(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("clow_x", C.c_double), ("clow_y", C.c_double)]
+
+
+class PrecOpts(C.Structure):
+    _fields_ = [("mg_fixed", C.c_int), ("mg_rtol", C.c_double), ("mg_maxcyc", C.c_int)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("absolute", C.c_int), ("scaled", C.c_int),
+                ("restart", C.c_int), ("maxit", C.c_int), ("precision", C.c_int),
+                ("precond", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("res", C.c_double), ("norm_F", C.c_double), ("mg_cycles_total", C.c_long),
+                ("mg_cycles_min", C.c_int), ("mg_cycles_max", C.c_int),
+                ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BlpError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libblp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch first: its HIP runtime and the one libblp.so links against share
+        # the soname libamdhip64.so.7, so loading torch first makes the dynamic
+        # loader bind libblp.so to the same runtime instance (one device context
+        # per process instead of two).
+        import torch  # noqa: F401
+        if not os.path.exists(LIBPATH):
+            raise BlpError("libblp.so not built: run __graft_entry__.build() "
+                           "(or python paper_2108_13468_amd/build.py)")
+        L = C.CDLL(LIBPATH)
+        vp = C.c_void_p
+        L.blp_mesh.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.blp_assemble.argtypes = [C.c_int, C.c_double, C.POINTER(Field), C.POINTER(Field),
+                                   C.POINTER(Field), C.POINTER(MeshOpts), vp, C.POINTER(vp)]
+        L.blp_nodes.argtypes = [vp, _dp, _dp]
+        L.blp_precondition.argtypes = [vp, C.POINTER(PrecOpts)]
+        for f in ("blp_solve", "blp_solve_adjoint"):
+            getattr(L, f).argtypes = [vp, C.c_int, vp, vp, C.POINTER(SolveOpts),
+                                      C.POINTER(SolveInfo), _dp]
+        L.blp_apply.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
+        L.blp_sine_rhs.argtypes = [vp, C.c_int, C.c_int, _dp, vp]
+        L.blp_sine_project.argtypes = [vp, C.c_int, C.c_int, vp, _dp]
+        L.blp_bilinear_project.argtypes = [vp, C.c_int, vp, _dp]
+        L.blp_mul.argtypes = [vp, vp, vp, vp]
+        L.blp_footprint.restype = C.c_longlong
+        L.blp_footprint.argtypes = [vp]
+        L.blp_destroy.argtypes = [vp]
+        L.blp_strerror.restype = C.c_char_p
+        L.blp_strerror.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise BlpError("%s failed: %s (%d)" % (what, lib().blp_strerror(rc).decode(), rc))
+    return rc
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mesh(N, eps, sigma=2.0, clow=1.0):
+    nodes = np.zeros(N + 1)
+    tau = C.c_double()
+    _check(lib().blp_mesh(N, eps, sigma, clow, nodes.ctypes.data_as(_dp), C.byref(tau)), "blp_mesh")
+    return tau.value, nodes
+
+
+def _field(spec, N, keep):
+    """spec: float (constant), ('axis', values[N+1]), ('nodal', values[(N-1)^2]),
+    ('bilinear', controls[m, m] indexed [q, p])."""
+    if np.isscalar(spec):
+        arr, kind, m = _f64([spec]), BLP_CONST, 0
+    else:
+        tag, vals = spec
+        arr = _f64(vals).ravel()
+        kind = {"axis": BLP_AXIS, "nodal": BLP_NODAL, "bilinear": BLP_BILINEAR}[tag]
+        m = int(np.asarray(vals).shape[0]) if tag == "bilinear" else 0
+    keep.append(arr)
+    return Field(kind, m, arr.ctypes.data_as(_dp))
+
+
+class Problem:
+    """An assembled operator on the device (one handle of the C library)."""
+
+    def __init__(self, N, eps, c1, c2, r, sigma=2.0, clow=(1.0, 1.0), stream=None):
+        import torch
+        self.torch = torch
+        self.N, self.eps, self.n = N, eps, (N - 1) ** 2
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        keep = []
+        f1, f2, fr = _field(c1, N, keep), _field(c2, N, keep), _field(r, N, keep)
+        mo = MeshOpts(sigma, clow[0], clow[1])
+        h = C.c_void_p()
+        _check(lib().blp_assemble(N, eps, C.byref(f1), C.byref(f2), C.byref(fr), C.byref(mo),
+                                  C.c_void_p(stream.cuda_stream), C.byref(h)), "blp_assemble")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().blp_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def nodes(self):
+        x, y = np.zeros(self.N + 1), np.zeros(self.N + 1)
+        _check(lib().blp_nodes(self._h, x.ctypes.data_as(_dp), y.ctypes.data_as(_dp)), "blp_nodes")
+        return x, y
+
+    def precondition(self, mg_fixed=0, mg_rtol=1e-3, mg_maxcyc=20):
+        o = PrecOpts(mg_fixed, mg_rtol, mg_maxcyc)
+        _check(lib().blp_precondition(self._h, C.byref(o)), "blp_precondition")
+        return self
+
+    def _vec(self, x, nrhs=None):
+        t = self.torch
+        if not (isinstance(x, t.Tensor) and x.is_cuda and x.dtype == t.float64 and x.is_contiguous()):
+            raise TypeError("expected a contiguous float64 tensor on the HIP device")
+        if x.numel() % self.n:
+            raise ValueError("vector length must be a multiple of (N-1)^2")
+        return x
+
+    def _solve(self, fn, F, tol, scaled, restart, maxit, precision, precond, absolute, hist):
+        t = self.torch
+        F = self._vec(F)
+        nrhs = F.numel() // self.n
+        U = t.empty_like(F)
+        o = SolveOpts(tol, int(absolute), int(scaled), restart, maxit,
+                      BLP_MIXED if precision == "mixed" else BLP_FP64, int(precond))
+        infos = (SolveInfo * nrhs)()
+        h = np.zeros(nrhs * (maxit + 1)) if hist else None
+        rc = _check(fn(self._h, nrhs, C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
+                       C.byref(o), infos, h.ctypes.data_as(_dp) if hist else None), "solve")
+        out = [i.as_dict() for i in infos]
+        for d in out:
+            d["status"] = rc
+        if hist:
+            return U, out, h.reshape(nrhs, maxit + 1)
+        return U, out
+
+    def solve(self, F, tol=1e-8, scaled=True, restart=50, maxit=1000, precision="fp64",
+              precond=True, absolute=False, hist=False):
+        return self._solve(lib().blp_solve, F, tol, scaled, restart, maxit, precision, precond,
+                           absolute, hist)
+
+    def solve_adjoint(self, G, tol=1e-8, scaled=True, restart=50, maxit=1000, precision="fp64",
+                      precond=True, absolute=False, hist=False):
+        return self._solve(lib().blp_solve_adjoint, G, tol, scaled, restart, maxit, precision,
+                           precond, absolute, hist)
+
+    def apply(self, op, x):
+        x = self._vec(x)
+        y = self.torch.empty_like(x)
+        cyc = C.c_int(0)
+        _check(lib().blp_apply(self._h, OPS[op], C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                               C.byref(cyc)), "blp_apply")
+        self.last_cycles = cyc.value
+        return y
+
+    def sine_rhs(self, a):
+        a = _f64(a)
+        L, K = a.shape
+        F = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
+        _check(lib().blp_sine_rhs(self._h, K, L, a.ctypes.data_as(_dp), C.c_void_p(F.data_ptr())),
+               "blp_sine_rhs")
+        return F
+
+    def sine_project(self, w, K, L):
+        g = np.zeros(K * L)
+        _check(lib().blp_sine_project(self._h, K, L, C.c_void_p(self._vec(w).data_ptr()),
+                                      g.ctypes.data_as(_dp)), "blp_sine_project")
+        return g.reshape(L, K)
+
+    def bilinear_project(self, w, m):
+        G = np.zeros(m * m)
+        _check(lib().blp_bilinear_project(self._h, m, C.c_void_p(self._vec(w).data_ptr()),
+                                          G.ctypes.data_as(_dp)), "blp_bilinear_project")
+        return G.reshape(m, m)
+
+    def mul(self, a, b):
+        out = self.torch.empty_like(a)
+        _check(lib().blp_mul(self._h, C.c_void_p(self._vec(a).data_ptr()),
+                             C.c_void_p(self._vec(b).data_ptr()), C.c_void_p(out.data_ptr())),
+               "blp_mul")
+        return out
+
+    def footprint(self):
+        return int(lib().blp_footprint(self._h))
+
+
+def from_instance(inst, nodal_r=None):
+    """Assemble a problem from an inputs.Instance (coefficients sampled at the
+    mesh nodes, which blp_mesh returns)."""
+    _, x = mesh(inst.N, inst.eps, inst.sigma, inst.clow[0])
+    _, y = mesh(inst.N, inst.eps, inst.sigma, inst.clow[1])
+    if inst.r_ctrl is not None:
+        r = ("bilinear", inst.r_ctrl)
+    elif nodal_r is not None:
+        r = ("nodal", nodal_r)
+    else:
+        r = float(inst.r_const)
+    return Problem(inst.N, inst.eps, ("axis", inst.c1_at(x)), ("axis", inst.c2_at(y)), r,
+                   sigma=inst.sigma, clow=inst.clow)

@@ -1,0 +1,87 @@
+// Device-side building blocks shared by the solver kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BLP_DEV __device__ __forceinline__
+
+// A tensor grid with nx x ny unknowns (nodes 1..nx, 1..ny) and the per-axis
+// tables of the upwind 5-point stencil (Sec. 3, 2D stencil):
+//   W_i  = -eps/(hbar_i h_i)                 (coupling to i-1)
+//   E_i  = -eps/(hbar_i h_{i+1}) - c1_i/h_{i+1}  (coupling to i+1)
+//   Dx_i = -(W_i + E_i)                      (x part of the diagonal)
+// and likewise S_j, N_j, Dy_j along y; the diagonal is C_ij = Dx_i + Dy_j + r_ij.
+// Tables hold n+2 entries with zeros at index 0 and n+1, so a coupling to a
+// node outside the grid reads as zero.  This separable form holds because
+// c1 depends on x alone and c2 on y alone.
+template <typename T>
+struct Grid {
+  int nx, ny;
+  const T *W, *E, *Dx;  // x tables
+  const T *S, *N, *Dy;  // y tables
+  const T *r;           // nodal r, r[(j-1)*rld + (i-1)], or nullptr
+  int rld;
+  T rc;                 // constant r when r == nullptr
+  BLP_DEV T C(int i, int j) const {
+    return Dx[i] + Dy[j] + (r ? r[(size_t)(j - 1) * rld + (i - 1)] : rc);
+  }
+};
+
+BLP_DEV size_t vidx(int i, int j, int ld) { return (size_t)(j - 1) * ld + (i - 1); }
+
+// Control block of one corner solve (device memory).
+struct MgCtrl {
+  int gate;          // 1 once the corner iteration has stopped
+  int cycles;        // V-cycles performed in the current corner solve
+  double bnorm2;     // ||S b||^2 (forward) or ||b||^2 (transposed)
+  double res2;       // last corner residual norm^2
+  double rtol2;      // (relative tolerance)^2
+  int maxcyc;
+  unsigned int counter;  // arrival counter of the reduction kernels
+};
+
+// Status block of the Krylov iteration (device memory, copied to the host).
+struct KrylovStatus {
+  double est;        // |g_{j+1}|, residual estimate after the last step
+  double hn;         // h_{j+1,j}
+  double wn0;        // ||w|| before orthogonalisation
+  double beta;       // norm from the last residual / norm kernel
+  int happy;         // breakdown flag of the last step
+  int mg_cycles;     // corner cycles of the last preconditioner apply
+  unsigned int counter;
+  int pad;
+};
+
+// Wave-level sum of a double (wave64).
+BLP_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Block sum (blockDim.x multiple of 64, at most 1024); result valid in all
+// threads.  sh must hold 16 doubles.
+BLP_DEV double block_sum(double v, double *sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < nw; ++k) s += sh[k];
+  return s;
+}
+
+// "Last block" pattern: every block publishes its partial, then the last
+// block to arrive sees all partials.  Returns true in the whole last block.
+BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int prev = atomicAdd(counter, 1u);
+    *sh_flag = (prev == gridDim.x * gridDim.y - 1);
+  }
+  __syncthreads();
+  if (*sh_flag) __threadfence();
+  return *sh_flag;
+}

@@ -1,0 +1,170 @@
+// Operator kernels: the upwind 5-point stencil applied on the fly from the
+// per-axis tables (no stored matrix), residuals and norms, problem-data
+// helpers (sine-series forcing, bilinear reaction field) and conversions.
+#pragma once
+#include "common.h"
+
+// Stencil application on the fine grid, one thread per column and a strip of
+// `rows` rows per block (the x_{j-1}, x_j, x_{j+1} values roll in registers;
+// x_{i+-1} come from neighbouring threads of the same coalesced row loads).
+//   y = A x            (TR = false)   or   y = A^T x   (TR = true)
+//   RESID: y = F - (A x)
+//   SCALE: y *= 1/sqrt(C_ij)        (symmetric Jacobi scaling of the output)
+// Arithmetic in FP64 whatever the storage types.  With RESID the kernel also
+// reduces ||y||^2 (last block writes st->beta = ||y||).
+template <typename TX, typename TO, bool TR, bool SCALE, bool RESID>
+__global__ __launch_bounds__(256) void k_stencil(Grid<double> g, const TX *__restrict__ x,
+                                                 TO *__restrict__ y,
+                                                 const double *__restrict__ F, int rows,
+                                                 double *partials, KrylovStatus *st) {
+  __shared__ double sh[16];
+  __shared__ bool last;
+  const int n = g.nx;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const int j0 = blockIdx.y * rows + 1;
+  const int j1 = min(j0 + rows - 1, g.ny);
+  double acc = 0.0;
+  if (i <= n) {
+    const double cw = TR ? g.E[i - 1] : g.W[i];
+    const double ce = TR ? g.W[i + 1] : g.E[i];
+    const double dx = g.Dx[i];
+    double xs = j0 > 1 ? (double)x[vidx(i, j0 - 1, n)] : 0.0;
+    double xc = (double)x[vidx(i, j0, n)];
+    for (int j = j0; j <= j1; ++j) {
+      const double xn = j < g.ny ? (double)x[vidx(i, j + 1, n)] : 0.0;
+      const double xw = i > 1 ? (double)x[vidx(i - 1, j, n)] : 0.0;
+      const double xe = i < n ? (double)x[vidx(i + 1, j, n)] : 0.0;
+      const double cs = TR ? g.N[j - 1] : g.S[j];
+      const double cn = TR ? g.S[j + 1] : g.N[j];
+      const size_t q = vidx(i, j, n);
+      const double C = dx + g.Dy[j] + (g.r ? g.r[q] : g.rc);
+      double v = C * xc + cw * xw + ce * xe + cs * xs + cn * xn;
+      if (RESID) v = F[q] - v;
+      if (SCALE) v /= sqrt(C);
+      y[q] = (TO)v;
+      if (RESID) acc += v * v;
+      xs = xc;
+      xc = xn;
+    }
+  }
+  if (!RESID) return;
+  acc = block_sum(acc, sh);
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) partials[bid] = acc;
+  if (!arrive_last(&st->counter, &last)) return;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < (int)(gridDim.x * gridDim.y); ++b) s += partials[b];
+    st->beta = sqrt(s);
+    st->counter = 0;
+    __threadfence();
+  }
+}
+
+// ||F|| (or ||F / sqrt(C)|| when SCALE) into st->beta.
+template <bool SCALE>
+__global__ __launch_bounds__(256) void k_norm(Grid<double> g, const double *F, double *partials,
+                                              KrylovStatus *st) {
+  __shared__ double sh[16];
+  __shared__ bool last;
+  const int n = g.nx;
+  const size_t tot = (size_t)n * g.ny;
+  double acc = 0.0;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
+       q += (size_t)gridDim.x * blockDim.x) {
+    double v = F[q];
+    if (SCALE) {
+      const int i = (int)(q % n) + 1, j = (int)(q / n) + 1;
+      v /= sqrt(g.C(i, j));
+    }
+    acc += v * v;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+  if (!arrive_last(&st->counter, &last)) return;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < (int)gridDim.x; ++b) s += partials[b];
+    st->beta = sqrt(s);
+    st->counter = 0;
+    __threadfence();
+  }
+}
+
+template <typename TA, typename TB>
+__global__ void k_convert(const TA *a, TB *b, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) b[q] = (TB)a[q];
+}
+
+template <typename T>
+__global__ void k_div(const T *a, const T *d, T *out, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = a[q] / d[q];
+}
+
+__global__ void k_mul(const double *a, const double *b, double *out, size_t n) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = a[q] * b[q];
+}
+
+// Per-axis function tables: tab[k*(N+1) + i] = sin((k+1) pi x_i) (kind 0) or
+// the hat function phi_k(x_i) on m uniform nodes of [0,1] (kind 1).
+__global__ void k_axis_table(const double *x, int N, int K, int kind, double *tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (i > N) return;
+  double v;
+  if (kind == 0) {
+    v = sin((k + 1) * M_PI * x[i]);
+  } else {
+    const double t = fabs(x[i] * (K - 1) - k);
+    v = t < 1.0 ? 1.0 - t : 0.0;
+  }
+  tab[(size_t)k * (N + 1) + i] = v;
+}
+
+// F_ij = sum_{l,k} a[l*K + k] tx[k][i] ty[l][j]  (separable synthesis).
+__global__ void k_synth(int N, int K, int L, const double *a, const double *tx,
+                        const double *ty, double *F) {
+  const int n1 = N - 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  const int j = blockIdx.y + 1;
+  if (i > n1) return;
+  double s = 0.0;
+  for (int l = 0; l < L; ++l) {
+    double sx = 0.0;
+    for (int k = 0; k < K; ++k) sx += a[l * K + k] * tx[(size_t)k * (N + 1) + i];
+    s += sx * ty[(size_t)l * (N + 1) + j];
+  }
+  F[vidx(i, j, n1)] = s;
+}
+
+// Projection onto separable functions, stage 1: per row j and function k,
+// t[k][j] = sum_i w_ij tx[k][i].  One block per row.
+__global__ __launch_bounds__(256) void k_project_rows(int N, int K, const double *w,
+                                                      const double *tx, double *t) {
+  __shared__ double sh[16];
+  const int n1 = N - 1;
+  const int j = blockIdx.x + 1;
+  for (int k = 0; k < K; ++k) {
+    double acc = 0.0;
+    for (int i = threadIdx.x + 1; i <= n1; i += blockDim.x)
+      acc += w[vidx(i, j, n1)] * tx[(size_t)k * (N + 1) + i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) t[(size_t)k * n1 + (j - 1)] = acc;
+  }
+}
+
+// Stage 2: g[l*K + k] = sum_j t[k][j] ty[l][j].  One block per (k, l).
+__global__ __launch_bounds__(256) void k_project_cols(int N, int K, const double *t,
+                                                      const double *ty, double *g) {
+  __shared__ double sh[16];
+  const int n1 = N - 1;
+  const int k = blockIdx.x, l = blockIdx.y;
+  double acc = 0.0;
+  for (int j = threadIdx.x + 1; j <= n1; j += blockDim.x)
+    acc += t[(size_t)k * n1 + (j - 1)] * ty[(size_t)l * (N + 1) + j];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) g[l * K + k] = acc;
+}

@@ -1,0 +1,71 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/blp.h declares, and its host-only entry points (mesh, argument
+validation) behave as documented.  No compute call reaches the GPU here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_13468_amd import blp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "blp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(blp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert declared_symbols() == sorted(blp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = blp.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+
+
+@pytest.mark.parametrize("N,eps,sigma,clow", [(64, 1e-2, 2.0, 1.0), (1024, 1e-6, 2.0, 1.0),
+                                              (256, 1e-4, 2.5, 3.0), (8, 1.0, 2.0, 1.0)])
+def test_mesh_matches_oracle(N, eps, sigma, clow):
+    tau, x = blp.mesh(N, eps, sigma, clow)
+    tau_o, x_o, _ = O.mesh_axis(N, eps, sigma, clow)
+    assert tau == tau_o
+    np.testing.assert_array_equal(x, x_o)
+
+
+@pytest.mark.parametrize("N,eps", [(63, 1e-2), (2, 1e-2), (64, 0.0), (64, 1.5), (64, float("nan"))])
+def test_mesh_rejects_bad_arguments(N, eps):
+    with pytest.raises(blp.BlpError):
+        blp.mesh(N, eps)
+
+
+def _assemble_rc(N, eps, c1, c2, r):
+    keep = []
+    f1, f2, fr = blp._field(c1, N, keep), blp._field(c2, N, keep), blp._field(r, N, keep)
+    h = C.c_void_p()
+    return blp.lib().blp_assemble(N, eps, C.byref(f1), C.byref(f2), C.byref(fr), None, None,
+                                  C.byref(h))
+
+
+@pytest.mark.parametrize("args", [
+    (63, 1e-2, 1.0, 1.0, 1.0),                      # odd N
+    (64, 2.0, 1.0, 1.0, 1.0),                       # eps > 1
+    (64, 1e-2, 0.0, 1.0, 1.0),                      # c1 <= 0
+    (64, 1e-2, 1.0, -1.0, 1.0),                     # c2 < 0
+    (64, 1e-2, 1.0, 1.0, -0.5),                     # r < 0
+    (64, 1e-2, float("nan"), 1.0, 1.0),             # NaN
+    (64, 1e-2, ("axis", np.r_[np.ones(64), 0.0]), 1.0, 1.0),  # c1 = 0 at a node
+])
+def test_assemble_validation(args):
+    assert _assemble_rc(*args) == -1
+
+
+def test_strerror_names_codes():
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert blp.lib().blp_strerror(code)

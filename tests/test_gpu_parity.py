@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.
+
+Tolerances (derived in the design doc):
+  * operator applies: ||y_gpu - y_orc||_inf <= 1e-14 || |A| |x| ||_inf
+    (different but equivalent association of the FP64 stencil sums);
+  * preconditioner applies with a fixed cycle count (a fixed linear map):
+    <= 1e-11 relative (rounding propagated through the sweeps and cycles);
+  * FP64 solves: equal iteration counts, residual histories within 1e-6
+    relative, and max-norm error against the oracle's tight solution
+    <= 1e-8 relative (the FP64 target);
+  * mixed solves: max-norm error <= 1e-6 relative (the mixed target).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_13468_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(inst, r_nodal=None, prec=True, mg_fixed=0):
+    """(GPU problem, oracle problem) for an inputs.Instance."""
+    from paper_2108_13468_amd import blp
+    gp = blp.from_instance(inst, nodal_r=r_nodal)
+    if prec:
+        gp.precondition(mg_fixed=mg_fixed)
+    _, x = O.mesh_axis(inst.N, inst.eps, inst.sigma, inst.clow[0])[:2]
+    _, y = O.mesh_axis(inst.N, inst.eps, inst.sigma, inst.clow[1])[:2]
+    if inst.r_ctrl is not None:
+        r = O.bilinear(inst.N, x, y, inst.r_ctrl)
+    elif r_nodal is not None:
+        r = r_nodal
+    else:
+        r = inst.r_const
+    op = O.Problem(inst.N, inst.eps, c1=inst.c1_at, c2=inst.c2_at, r=r, sigma=inst.sigma,
+                   clow_x=inst.clow[0], clow_y=inst.clow[1])
+    return gp, op
+
+
+def dev(v):
+    t = _torch()
+    return t.as_tensor(np.ascontiguousarray(v, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+CASES = [(64, 1e-2), (96, 1e-4), (130, 1e-6), (256, 1e-8)]
+
+
+@pytest.mark.parametrize("N,eps", CASES)
+def test_operator_parity(N, eps):
+    say("operator parity N=%d eps=%g" % (N, eps))
+    inst = inputs.plain(N, eps, seed=N)
+    gp, op = pair(inst, prec=False)
+    rng = np.random.default_rng(N)
+    x = rng.standard_normal(op.n)
+    absAx = np.abs(op.csr()) @ np.abs(x)
+    for name, ref in (("A", op.A(x)), ("AT", op.AT(x))):
+        y = host(gp.apply(name, dev(x)))
+        err = np.abs(y - ref).max() / absAx.max()
+        assert err <= 1e-14, (name, err)
+
+
+@pytest.mark.parametrize("N,eps", CASES)
+def test_preconditioner_parity_fixed_cycles(N, eps):
+    say("preconditioner parity N=%d eps=%g" % (N, eps))
+    inst = inputs.plain(N, eps, seed=N + 1)
+    gp, op = pair(inst, mg_fixed=2)
+    rng = np.random.default_rng(N + 1)
+    b = rng.standard_normal(op.n)
+    for name, tr in (("MINV", False), ("MINVT", True)):
+        ref = op.M_inv(b, transpose=tr, mg_fixed=2)
+        z = host(gp.apply(name, dev(b)))
+        err = np.abs(z - ref).max() / np.abs(ref).max()
+        assert err <= 1e-11, (name, err)
+
+
+@pytest.mark.parametrize("N,eps", [(64, 1e-2), (130, 1e-4), (256, 1e-6)])
+def test_preconditioner_adaptive_cycles_match(N, eps):
+    say("adaptive corner cycles N=%d eps=%g" % (N, eps))
+    inst = inputs.plain(N, eps, seed=N + 2)
+    gp, op = pair(inst, mg_fixed=0)
+    b = np.random.default_rng(N + 2).standard_normal(op.n)
+    for name, tr in (("MINV", False), ("MINVT", True)):
+        ref = op.M_inv(b, transpose=tr)
+        z = host(gp.apply(name, dev(b)))
+        assert gp.last_cycles == op.last_prec_stats.mg_cycles_max
+        assert np.abs(z - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_region_pieces_via_fixed_many_cycles():
+    """With many cycles the GPU M^{-1} approaches the idealised M-hat^{-1}
+    (exact corner solve in the oracle)."""
+    say("M-hat limit")
+    inst = inputs.plain(64, 1e-4, seed=5)
+    gp, op = pair(inst, mg_fixed=40)
+    b = np.random.default_rng(5).standard_normal(op.n)
+    z = host(gp.apply("MINV", dev(b)))
+    ref = op.M_inv(b, corner="exact")
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_small_case_solve_parity():
+    """N = 64, eps = 1e-2, preconditioned GMRES(50) to relative residual 1e-10
+    on the plain system: same iterations and history as the oracle."""
+    say("small case solve")
+    inst = inputs.small_case()
+    gp, op = pair(inst)
+    F = O.sine_series(inst.N, op.x, op.y, inst.a)
+    Fg = gp.sine_rhs(inst.a)
+    assert np.abs(host(Fg) - F).max() <= 1e-14 * np.abs(F).max()
+    u_o, st, info_o, hist_o = op.fgmres(F, tol=1e-10, restart=50)
+    U, info, hist = gp.solve(Fg, tol=1e-10, scaled=False, restart=50, hist=True)
+    info = info[0]
+    assert info["converged"] and info_o.converged
+    assert info["iterations"] == info_o.iterations
+    k = info["iterations"]
+    np.testing.assert_allclose(hist[0, :k + 1], hist_o[:k + 1], rtol=1e-6)
+    ue = np.linalg.solve(op.csr().toarray(), F)
+    assert np.abs(host(U) - ue).max() <= 1e-8 * np.abs(ue).max()
+
+
+@pytest.mark.parametrize("N,eps", [(130, 1e-4), (256, 1e-6), (256, 1e-8)])
+def test_scaled_solve_parity(N, eps):
+    say("scaled solve N=%d eps=%g" % (N, eps))
+    inst = inputs.plain(N, eps, seed=N + 3)
+    gp, op = pair(inst)
+    F = O.sine_series(N, op.x, op.y, inst.a)
+    u_o, st, info_o, hist_o = op.fgmres(F, tol=1e-8, scaled=True)
+    U, info, hist = gp.solve(dev(F), tol=1e-8, scaled=True, hist=True)
+    info = info[0]
+    assert info["converged"]
+    assert info["iterations"] == info_o.iterations
+    assert info["mg_cycles_max"] == info_o.mg_cycles_max
+    k = info["iterations"]
+    np.testing.assert_allclose(hist[0, :k + 1], hist_o[:k + 1], rtol=1e-6)
+    # error against a tight oracle solve
+    u_t, _, _, _ = op.fgmres(F, tol=1e-11 if eps > 1e-8 else 1e-9, scaled=True)
+    err = np.abs(host(U) - u_t).max() / np.abs(u_t).max()
+    assert err <= 1e-8 * (10 if eps <= 1e-8 else 1)
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_mixed_solve_error(eps):
+    say("mixed solve N=256 eps=%g" % eps)
+    inst = inputs.plain(256, eps, seed=7)
+    gp, op = pair(inst)
+    F = O.sine_series(256, op.x, op.y, inst.a)
+    U, info = gp.solve(dev(F), tol=1e-8, scaled=True, precision="mixed")
+    info = info[0]
+    assert info["converged"], info
+    u_t, _, _, _ = op.fgmres(F, tol=1e-11, scaled=True)
+    err = np.abs(host(U) - u_t).max() / np.abs(u_t).max()
+    assert err <= 1e-6, err
+
+
+def test_adjoint_identities_and_solve():
+    say("adjoint identities")
+    inst = inputs.plain(96, 1e-5, seed=8)
+    gp, op = pair(inst, mg_fixed=3)
+    rng = np.random.default_rng(8)
+    x, y = rng.standard_normal(op.n), rng.standard_normal(op.n)
+    xd, yd = dev(x), dev(y)
+    Ax, ATy = host(gp.apply("A", xd)), host(gp.apply("AT", yd))
+    assert Ax @ y == pytest.approx(x @ ATy, rel=1e-13)
+    Mx, MTy = host(gp.apply("MINV", xd)), host(gp.apply("MINVT", yd))
+    assert Mx @ y == pytest.approx(x @ MTy, rel=1e-11)
+    gp.precondition(mg_fixed=0)
+    lam, info = gp.solve_adjoint(yd, tol=1e-10, scaled=True)
+    ref = np.linalg.solve(op.csr().toarray().T, y)
+    assert info[0]["converged"]
+    assert np.abs(host(lam) - ref).max() <= 1e-8 * np.abs(ref).max()
