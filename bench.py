@@ -1,0 +1,160 @@
+"""Benchmark: time to a relative residual of 1e-8 on the 1024 x 1024 Shishkin
+mesh at eps = 1e-6, FP64 and mixed precision, on one MI355X.
+
+A step is one FP64 solve followed by one mixed-precision solve of the same
+problem (boundary-layer-preconditioned FGMRES(50), zero initial guess, inputs
+resident on the device).  Setup (preconditioner construction) is timed once,
+apart.  The JSON line carries the per-kernel roofline of the dominant kernel
+(HIP events recorded by the library on its stream over the timed steps) and
+the CPU oracle timed on this host.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve time to rel-res 1e-8, 1024^2 eps=1e-6 (FP64 vs mixed) + HBM GB/s %peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the solver's multi-GPU path is not part of this "
+              "build (instances and right-hand sides shard without communication); run with "
+              "--gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2108_13468_amd import blp, inputs
+
+    torch.cuda.set_device(0)
+    inst = inputs.plain(args.N, args.eps, seed=1)
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    gp = blp.from_instance(inst)
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    gp.precondition()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    setup_ms = e0.elapsed_time(e1)
+    F = gp.sine_rhs(inst.a)
+    opts = dict(tol=1e-8, scaled=True, restart=50, maxit=2000)
+
+    def step():
+        U64, i64 = gp.solve(F, precision="fp64", **opts)
+        U32, i32 = gp.solve(F, precision="mixed", **opts)
+        return U64, i64[0], U32, i32[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    gp.timing(True)
+    t_fp64, t_mixed = [], []
+    ts, te = ev(), ev()
+    ts.record(stream)
+    for _ in range(args.steps):
+        a, b, c = ev(), ev(), ev()
+        a.record(stream)
+        U64, i64 = gp.solve(F, precision="fp64", **opts)
+        b.record(stream)
+        U32, i32 = gp.solve(F, precision="mixed", **opts)
+        c.record(stream)
+        torch.cuda.synchronize()
+        t_fp64.append(a.elapsed_time(b))
+        t_mixed.append(b.elapsed_time(c))
+        i64, i32 = i64[0], i32[0]
+    te.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ts.elapsed_time(te)
+    kt = gp.timing(False)
+
+    fp64_ms = float(np.median(t_fp64))
+    mixed_ms = float(np.median(t_mixed))
+    # dominant kernel class over the timed region
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms, nl, by = kt[dom]
+    avg_us = 1e3 * ms / max(nl, 1)
+    achieved = (by / max(nl, 1)) / (avg_us * 1e-6) / 1e9 if nl else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": dom, "avg_launch_us": round(avg_us, 2), "launches": nl,
+                "bytes_per_launch": by / max(nl, 1)}
+    kernels = {k: {"ms": round(v[0], 3), "launches": v[1],
+                   "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 2) if v[0] > 0 else 0.0}
+               for k, v in kt.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": round(mixed_ms, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_ms / args.steps, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "N=%d per side (%d unknowns), eps=%g, c=(1+x^2, 1+y), r=1, "
+                               "seeded 3x3 sine-series f, FGMRES(50) to relative residual 1e-8 "
+                               "of the Jacobi-scaled system" % (args.N, (args.N - 1) ** 2, args.eps),
+                   "N": args.N, "eps": args.eps},
+        "fp64_ms": round(fp64_ms, 3),
+        "mixed_ms": round(mixed_ms, 3),
+        "setup_ms": round(setup_ms, 3),
+        "iterations": {"fp64": i64["iterations"], "mixed": i32["iterations"],
+                       "mixed_restarts": i32["restarts"],
+                       "corner_cycles": [i64["mg_cycles_min"], i64["mg_cycles_max"]]},
+        "rel_res": {"fp64": i64["res"] / i64["norm_F"], "mixed": i32["res"] / i32["norm_F"]},
+        "footprint_bytes": gp.footprint(),
+        "roofline": roofline,
+        "kernels": kernels,
+        "paper_context": {"seconds": 0.921, "iterations": 5,
+                          "hardware": "one core of a 2.4 GHz Xeon, serial C",
+                          "stopping": "||R||_2 <= 10 ln(N)/N (absolute), sigma = 5/2, "
+                                      "manufactured solution (Table 7)"},
+    }
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        op = O.Problem(inst.N, inst.eps, c1=inst.c1_at, c2=inst.c2_at, r=inst.r_const)
+        Fo = O.sine_series(inst.N, op.x, op.y, inst.a)
+        t0 = time.perf_counter()
+        uo, st, info_o, _ = op.fgmres(Fo, tol=1e-8, scaled=True, maxit=2000)
+        cpu_ms = 1e3 * (time.perf_counter() - t0)
+        ut, _, _, _ = op.fgmres(Fo, tol=1e-10, scaled=True, maxit=2000)
+        scale = np.abs(ut).max()
+        out["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "one FP64 solve of the same problem to the same "
+                                         "tolerance (plain C oracle, single thread, %d "
+                                         "iterations)" % info_o.iterations}
+        out["err_vs_oracle"] = {
+            "fp64": float(np.abs(U64.cpu().numpy() - ut).max() / scale),
+            "mixed": float(np.abs(U32.cpu().numpy() - ut).max() / scale),
+            "reference": "oracle FGMRES to scaled relative residual 1e-10, max-norm relative"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

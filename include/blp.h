@@ -191,6 +191,24 @@ int blp_sine_project(blp_problem *p, int K, int L, const double *w, double *g);
 int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G);
 int blp_mul(blp_problem *p, const double *a, const double *b, double *out);
 
+/* Per-kernel-class timing with HIP events on the handle's stream.
+ * enable = 1: discard earlier records and start recording an event pair
+ * around every launch of the classes below; enable = 0: synchronise, stop
+ * recording and write, per class, the summed kernel time in ms (ms[k]), the
+ * number of launches (launches[k]) and the algorithmic bytes those launches
+ * move (bytes[k]: words read and written that the algorithm needs, at the
+ * precision of the launch).  Arrays have BLP_NCLASS entries; any may be NULL.
+ * Classes: 0 Gauss-Seidel smoothing sweep (corner levels; b, z old, z new
+ * per node), 1 triangular sweep from zero (interior region and first
+ * pre-smoothing; b, z per node), 2 edge-layer line solves (b, z and two
+ * factor words per node), 3 other multigrid kernels (residual, transfers,
+ * norms), 4 stencil SpMV / residual (x in, y out), 5 Arnoldi and solution
+ * update, 6 layout gathers/scatters and corner set-up.
+ * Errors: BLP_E_INVAL, BLP_E_HIP. */
+#define BLP_NCLASS 7
+int blp_timing(blp_problem *p, int enable, double *ms, long long *launches,
+               double *bytes);
+
 /* Device bytes held by the handle. */
 long long blp_footprint(const blp_problem *p);
 

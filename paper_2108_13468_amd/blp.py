@@ -22,7 +22,10 @@ OPS = {"A": 0, "AT": 1, "MINV": 2, "MINVT": 3, "MINV32": 4}
 # Symbols declared in include/blp.h (checked by the CPU tests).
 EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_solve",
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
-           "blp_bilinear_project", "blp_mul", "blp_footprint", "blp_destroy", "blp_strerror")
+           "blp_bilinear_project", "blp_mul", "blp_timing", "blp_footprint", "blp_destroy",
+           "blp_strerror")
+NCLASS = 7
+CLASSES = ("gs_sweep", "sweep", "lines", "mg_other", "spmv", "krylov", "layout")
 
 _dp = C.POINTER(C.c_double)
 
@@ -89,6 +92,7 @@ def lib():
         L.blp_sine_project.argtypes = [vp, C.c_int, C.c_int, vp, _dp]
         L.blp_bilinear_project.argtypes = [vp, C.c_int, vp, _dp]
         L.blp_mul.argtypes = [vp, vp, vp, vp]
+        L.blp_timing.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_longlong), _dp]
         L.blp_footprint.restype = C.c_longlong
         L.blp_footprint.argtypes = [vp]
         L.blp_destroy.argtypes = [vp]
@@ -236,6 +240,18 @@ class Problem:
                              C.c_void_p(self._vec(b).data_ptr()), C.c_void_p(out.data_ptr())),
                "blp_mul")
         return out
+
+    def timing(self, enable):
+        """enable=True starts per-kernel-class event timing; enable=False stops
+        it and returns {class: (ms, launches, algorithmic bytes)}."""
+        ms = np.zeros(NCLASS)
+        nl = (C.c_longlong * NCLASS)()
+        by = np.zeros(NCLASS)
+        _check(lib().blp_timing(self._h, int(bool(enable)), ms.ctypes.data_as(_dp), nl,
+                                by.ctypes.data_as(_dp)), "blp_timing")
+        if enable:
+            return None
+        return {c: (float(ms[k]), int(nl[k]), float(by[k])) for k, c in enumerate(CLASSES)}
 
     def footprint(self):
         return int(lib().blp_footprint(self._h))

@@ -120,6 +120,20 @@ struct blp_problem {
   long long bytes = 0;
   std::vector<void *> ws_allocs;
   long long ws_bytes = 0;
+  // kernel timing (blp_timing): event pairs per class, resolved on demand
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec { int cls; hipEvent_t a, b; double bytes; };
+  std::vector<Rec> recs;
+  hipEvent_t ev_next() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
 
   template <typename T>
   int alloc(T **p, size_t count, bool ws = false) {
@@ -147,6 +161,29 @@ struct blp_problem {
 };
 
 namespace {
+
+// Records an event pair around the launches issued during its lifetime when
+// timing is enabled.
+struct KScope {
+  blp_problem *p;
+  int cls;
+  double bytes;
+  hipEvent_t a = nullptr;
+  KScope(blp_problem *p_, int c, double b) : p(p_), cls(c), bytes(b) {
+    if (p->timing && (a = p->ev_next())) (void)hipEventRecord(a, p->stream);
+  }
+  void end() {
+    if (!a) return;
+    hipEvent_t b = p->ev_next();
+    if (b) {
+      (void)hipEventRecord(b, p->stream);
+      p->recs.push_back({cls, a, b, bytes});
+    }
+    a = nullptr;
+  }
+  ~KScope() { end(); }
+};
+enum { KC_GS = 0, KC_SWEEP, KC_LINES, KC_MG, KC_SPMV, KC_KRYLOV, KC_LAYOUT };
 
 template <typename T>
 FineDev<T> &fine(blp_problem *p);
@@ -194,19 +231,20 @@ void axis_mesh(int N, double tau, std::vector<double> &nodes, std::vector<double
 // Preconditioner apply                                                      //
 // ------------------------------------------------------------------------ //
 
-template <typename T, bool TR, bool GS>
+template <typename T, bool TR>
 void launch_sweep(blp_problem *p, const Grid<T> &g, int i0, int i1, int j0, int j1, const T *b,
-                  const T *ic, T *z, const T *zb, const int *gate) {
+                  const T *ic, T *z, const T *zb, const int *gate, int cls) {
   const int nb = (i1 - i0 + 1 + 63) / 64;
   SweepArgs<T> a{g, i0, i1, j0, j1, b, ic, z, zb, gate};
-  // Prefetch depth K: memory operations per step are 3 (b, 1/C, store), +2
-  // for Gauss-Seidel; K keeps K * ops below 63.  With more than 8 waves the
-  // register file allows K = 8 only.
-  constexpr int KD = GS ? 8 : 16;
+  const double pts = (double)(i1 - i0 + 1) * (j1 - j0 + 1);
+  KScope ks(p, cls, pts * (cls == KC_GS ? 3 : 2) * sizeof(T));
+  // superstep length K: two operand buffers and the results of a superstep
+  // stay in registers (5K values per lane); with more than 8 waves the
+  // register file allows K = 8.
   if (nb <= 8)
-    k_sweep<T, TR, GS, KD><<<1, 64 * nb, 0, p->stream>>>(a);
+    k_sweep<T, TR, 16><<<1, 64 * nb, 0, p->stream>>>(a);
   else
-    k_sweep<T, TR, GS, 8><<<1, 64 * nb, 0, p->stream>>>(a);
+    k_sweep<T, TR, 8><<<1, 64 * nb, 0, p->stream>>>(a);
 }
 
 template <typename T, bool TR>
@@ -237,7 +275,11 @@ void launch_lines(blp_problem *p, const T *v, const T *dh, T *z) {
   }
   a.gate = nullptr;
   const dim3 gl((h + 255) / 256, n1 - h);
-  k_gather_lines<T, TR><<<gl, 256, 0, p->stream>>>(v, dh, h, n1, f.bY);
+  {
+    KScope ks(p, KC_LAYOUT, 0.0);
+    k_gather_lines<T, TR><<<gl, 256, 0, p->stream>>>(v, dh, h, n1, f.bY);
+  }
+  KScope ks(p, KC_LINES, 2.0 * (n1 - h) * h * 4 * sizeof(T));
   if (h <= 64)
     k_lines<T, TR, 1><<<2, 64, 0, p->stream>>>(a);
   else if (h <= 128)
@@ -248,6 +290,8 @@ void launch_lines(blp_problem *p, const T *v, const T *dh, T *z) {
     k_lines<T, TR, 8><<<2, 64, 0, p->stream>>>(a);
   else
     k_lines<T, TR, 16><<<2, 64, 0, p->stream>>>(a);
+  ks.end();
+  KScope ks2(p, KC_LAYOUT, 0.0);
   k_scatter_lines<T, TR><<<gl, 256, 0, p->stream>>>(f.zY, h, n1, z);
 }
 
@@ -258,10 +302,22 @@ void interior_solve(blp_problem *p, const T *v, const T *dh, T *z) {
   const int h = p->h, n1 = p->n1;
   const Skew<TR> sk{h + 1, n1, h + 1, n1};
   const unsigned nb = blocks1d(f.nslotI);
-  k_gather_skew<T, TR><<<nb, 256, 0, p->stream>>>(sk, v, dh, n1, f.bI, f.nslotI);
-  launch_sweep<T, TR, false>(p, fine_grid<T>(p), h + 1, n1, h + 1, n1, f.bI, f.icI[TR ? 1 : 0],
-                             f.zI, z, nullptr);
+  {
+    KScope ks(p, KC_LAYOUT, 0.0);
+    k_gather_skew<T, TR><<<nb, 256, 0, p->stream>>>(sk, v, dh, n1, f.bI, f.nslotI);
+  }
+  launch_sweep<T, TR>(p, fine_grid<T>(p), h + 1, n1, h + 1, n1, f.bI, f.icI[TR ? 1 : 0], f.zI, z,
+                      nullptr, KC_SWEEP);
+  KScope ks(p, KC_LAYOUT, 0.0);
   k_scatter_skew<T, TR><<<nb, 256, 0, p->stream>>>(sk, f.zI, z, n1, f.nslotI);
+}
+
+// Gauss-Seidel rhs of a level into its t vector (t is free at that point).
+template <typename T, bool TR>
+void gs_rhs(blp_problem *p, const LevelDev<T> &lv, const int *gate) {
+  KScope ks(p, KC_MG, (double)lv.n * lv.n * 3 * sizeof(T));
+  k_gs_rhs<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.grid(), lv.b, lv.z, lv.t, lv.nslot,
+                                                             gate);
 }
 
 // One V(1,1) cycle on level l (Sec. 3.2).  zero_init: the level iterate is
@@ -272,20 +328,33 @@ void vcycle(blp_problem *p, int l, bool zero_init, const int *gate) {
   const LevelDev<T> &lv = L[l];
   const int n = lv.n;
   if (l == (int)L.size() - 1) {
+    KScope ks(p, KC_MG, (double)n * n * 2 * sizeof(T));
     k_mg_coarsest<T, TR><<<1, 64, 0, p->stream>>>(lv.view(TR), zero_init ? 1 : 0, gate);
     return;
   }
   const LevelDev<T> &cv = L[l + 1];
   const T *ic = lv.ic[TR ? 1 : 0];
-  if (zero_init)
-    launch_sweep<T, TR, false>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, nullptr, gate);
-  else
-    launch_sweep<T, TR, true>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, nullptr, gate);
-  k_mg_resid<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), gate);
-  k_mg_restrict<T, TR><<<blocks1d(cv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
+  if (zero_init) {
+    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, nullptr, gate, KC_SWEEP);
+  } else {
+    gs_rhs<T, TR>(p, lv, gate);
+    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, nullptr, gate, KC_GS);
+  }
+  {
+    KScope ks(p, KC_MG, (double)n * n * 3 * sizeof(T));
+    k_mg_resid<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), gate);
+  }
+  {
+    KScope ks(p, KC_MG, ((double)n * n + (double)cv.n * cv.n) * sizeof(T));
+    k_mg_restrict<T, TR><<<blocks1d(cv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
+  }
   vcycle<T, TR>(p, l + 1, true, gate);
-  k_mg_prolong<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
-  launch_sweep<T, TR, true>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, nullptr, gate);
+  {
+    KScope ks(p, KC_MG, ((double)n * n * 2 + (double)cv.n * cv.n) * sizeof(T));
+    k_mg_prolong<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
+  }
+  gs_rhs<T, TR>(p, lv, gate);
+  launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, nullptr, gate, KC_GS);
 }
 
 // Corner solve M_CC^{-1} b_0 (level 0 b and z).  Cycles are counted in ctrl.
@@ -554,6 +623,7 @@ constexpr int kRows = 16;  // rows per block of the stencil kernels
 
 template <bool TR, bool SCALE>
 void launch_residual(blp_problem *p, const double *F, const double *u, double *r) {
+  KScope ks(p, KC_SPMV, (double)p->n * 3 * sizeof(double));
   dim3 gr((p->n1 + 255) / 256, (p->n1 + kRows - 1) / kRows);
   k_stencil<double, double, TR, SCALE, true><<<gr, 256, 0, p->stream>>>(p->grid64(), u, r, F, kRows,
                                                                          p->partials, p->st);
@@ -561,6 +631,7 @@ void launch_residual(blp_problem *p, const double *F, const double *u, double *r
 
 template <typename TX, bool TR, bool SCALE>
 void launch_spmv(blp_problem *p, const TX *x, double *y) {
+  KScope ks(p, KC_SPMV, (double)p->n * (sizeof(TX) + sizeof(double)));
   dim3 gr((p->n1 + 255) / 256, (p->n1 + kRows - 1) / kRows);
   k_stencil<TX, double, TR, SCALE, false><<<gr, 256, 0, p->stream>>>(p->grid64(), x, y, nullptr,
                                                                       kRows, nullptr, nullptr);
@@ -635,11 +706,14 @@ int fgmres(blp_problem *p, const double *F, double *u, const blp_solve_opts *o,
       }
       launch_spmv<TV, TR, SCALE>(p, zj, p->w);
       const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
+      // CGS2: four passes over the j+1 basis vectors plus w traffic
+      KScope ks(p, KC_KRYLOV, (double)n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
       k_arnoldi_dot<TV><<<nb, 256, 0, p->stream>>>(V, n, j, p->w, n, p->partials, p->ks, ko, p->st);
       k_arnoldi_update<TV, false><<<nb, 256, 0, p->stream>>>(V, n, j, p->w, n, p->partials, p->ks, ko,
                                                               p->st);
       k_arnoldi_update<TV, true><<<nb, 256, 0, p->stream>>>(V, n, j, p->w, n, p->partials, p->ks, ko,
                                                              p->st);
+      ks.end();
       BLP_TRY(read_status(p));
       ++it;
       ncol = j + 1;
@@ -967,6 +1041,36 @@ int blp_mul(blp_problem *p, const double *a, const double *b, double *out) {
   return BLP_OK;
 }
 
+int blp_timing(blp_problem *p, int enable, double *ms, long long *launches, double *bytes) {
+  if (!p) return BLP_E_INVAL;
+  if (enable) {
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->recs.clear();
+    p->ev_used = 0;
+    p->timing = true;
+    return BLP_OK;
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  p->timing = false;
+  double sm[BLP_NCLASS] = {0}, sb[BLP_NCLASS] = {0};
+  long long sl[BLP_NCLASS] = {0};
+  for (const auto &r : p->recs) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    sm[r.cls] += t;
+    sb[r.cls] += r.bytes;
+    sl[r.cls] += 1;
+  }
+  for (int k = 0; k < BLP_NCLASS; ++k) {
+    if (ms) ms[k] = sm[k];
+    if (launches) launches[k] = sl[k];
+    if (bytes) bytes[k] = sb[k];
+  }
+  p->recs.clear();
+  p->ev_used = 0;
+  return BLP_OK;
+}
+
 long long blp_footprint(const blp_problem *p) { return p ? p->bytes + p->ws_bytes : 0; }
 
 void blp_destroy(blp_problem *p) {
@@ -974,6 +1078,7 @@ void blp_destroy(blp_problem *p) {
   (void)hipStreamSynchronize(p->stream);
   for (void *q : p->allocs) (void)hipFree(q);
   for (void *q : p->ws_allocs) (void)hipFree(q);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->st_h) (void)hipHostFree(p->st_h);
   if (p->ctrl_h) (void)hipHostFree(p->ctrl_h);
   delete p;

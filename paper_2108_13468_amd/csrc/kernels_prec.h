@@ -127,32 +127,36 @@ inline size_t skew_size(int mc, int mr) { return (size_t)((mc + 63) / 64) * (mr 
 // Forward (TR = false) solves, from the top-right corner to the bottom-left,
 //   C_ij z_ij + E_i z_{i+1,j} + N_j z_{i,j+1} = rhs_ij
 // (the upper-triangular part of the block: M_II of Sec. 3.1, and the
-// downstream pointwise Gauss-Seidel of Sec. 3.2).  Transposed (TR = true)
-// solves the transpose from the bottom-left corner:
+// downstream pointwise Gauss-Seidel of Sec. 3.2, whose not-yet-updated
+// neighbour terms k_gs_rhs folds into rhs beforehand).  Transposed
+// (TR = true) solves the transpose from the bottom-left corner:
 //   C_ij z_ij + E_{i-1} z_{i-1,j} + N_{j-1} z_{i,j-1} = rhs_ij.
 // Values just outside the rectangle on its upstream sides come from zb (a
 // grid vector in natural layout, e.g. already-solved neighbouring regions)
-// when they lie inside the grid, else are zero.  GS: the rhs also subtracts
-// the downstream neighbours' current (not yet updated) values -- one
-// Gauss-Seidel sweep in place.
+// when they lie inside the grid, else are zero.
 //
-// b, 1/C and z are in the skewed layout of the rectangle.  One workgroup;
+// rhs, 1/C and z are in the skewed layout of the rectangle.  One workgroup;
 // wave w owns band w, lane l one column.  The upstream-column value comes
 // from lane l-1 by a DPP shift, the upstream-row value is the lane's own
 // previous result.  Band w runs LAG = 64 + K steps behind band w-1 and takes
 // the band-boundary column from an LDS ring; an LDS-only barrier every K
-// steps orders the ring traffic.  Global operands of step s+K are loaded at
-// step s and used K steps later; every step issues the same memory
-// operations in every lane (idle steps use the sink row), so K is chosen to
-// keep K * (operations per step) below the 63 the vmcnt counter tracks.
+// steps (a superstep) orders the ring traffic.
+//
+// Memory pipelining: a wave that both loads and stores can only wait for all
+// of its outstanding memory operations at once, so work is organised by
+// supersteps with two register buffers: at the start of superstep m the wave
+// stores the results of superstep m-1 and issues the loads of superstep m+1,
+// then computes superstep m from registers.  Every operation outstanding at
+// the next wait was issued a whole superstep earlier.  Step offsets are
+// wave-uniform (scalar arithmetic); lanes add a constant lane offset.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SweepArgs {
   Grid<T> g;
   int i0, i1, j0, j1;
-  const T *b;     // skewed
+  const T *b;     // skewed rhs
   const T *ic;    // skewed 1/C
-  T *z;           // skewed
+  T *z;           // skewed solution
   const T *zb;    // natural-layout source of upstream boundary values, or null
   const int *gate;
 };
@@ -167,14 +171,13 @@ BLP_DEV void lds_barrier() {
   __builtin_amdgcn_s_barrier();
 }
 
-template <typename T, bool TR, bool GS, int K>
+template <typename T, bool TR, int K>
 __global__ __launch_bounds__(K > 8 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
   if (a.gate && *a.gate) return;
   constexpr int LAG = 64 + K, RING = 64;
   __shared__ T ring[16][RING];
   __shared__ T bnd[kSweepMaxRows];  // upstream boundary column, by row t
   __shared__ T ycu[kSweepMaxRows];  // upstream y coupling, by row t
-  __shared__ T ycd[kSweepMaxRows];  // downstream y coupling (GS), 0 off-grid
   const Grid<T> &g = a.g;
   const Skew<TR> sk{a.i0, a.i1, a.j0, a.j1};
   const int mc = sk.mc(), mr = sk.mr();
@@ -183,76 +186,112 @@ __global__ __launch_bounds__(K > 8 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
   for (int t = threadIdx.x; t < mr; t += blockDim.x) {
     const int j = sk.jrow(t);
     ycu[t] = TR ? g.N[j - 1] : g.N[j];
-    if (GS) {
-      const int jd = TR ? j + 1 : j - 1;
-      ycd[t] = (jd >= 1 && jd <= g.ny) ? (TR ? g.S[j + 1] : g.S[j]) : T(0);
-    }
     bnd[t] = ib_in ? a.zb[vidx(ib, j, g.nx)] : T(0);
   }
   __syncthreads();
 
-  const int lane = threadIdx.x & 63, band = threadIdx.x >> 6, nb = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int band = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int nb = blockDim.x >> 6;
   const int c = band * 64 + lane;
   const bool colok = c < mc;
   const int i = sk.icol(colok ? c : mc - 1);
   const T cu = colok ? (TR ? g.E[i - 1] : g.E[i]) : T(0);  // upstream x coupling
-  const int id = TR ? i + 1 : i - 1;                       // downstream x neighbour
-  const bool id_in = colok && id >= 1 && id <= g.nx;
-  const T cd = id_in ? (TR ? g.W[i + 1] : g.W[i]) : T(0);  // downstream x coupling
-  const int cx = (id_in && c + 1 < mc) ? c + 1 : c;        // column holding that neighbour
   const int jb = TR ? a.j0 - 1 : a.j1 + 1;
   T zrow = (colok && a.zb && jb >= 1 && jb <= g.ny) ? a.zb[vidx(i, jb, g.nx)] : T(0);
   T zlast = T(0);
   const int total = (nb - 1) * LAG + mr + 63;
-  const int smax = mr + 63;  // sink step of the band
-  const size_t base = sk.slot(band, 0, lane);
+  const int smax = mr + 63;  // steps 0..smax-1 are the band's work, smax its sink row
+  // this band's storage; step s of lane l is element (s * 64 + l)
+  const T *__restrict__ bb = a.b + sk.slot(band, 0, 0);
+  const T *__restrict__ ib_ = a.ic + sk.slot(band, 0, 0);
+  T *__restrict__ zz = a.z + sk.slot(band, 0, 0);
+  auto clampstep = [&](int s) { return (s >= 0 && s < smax) ? s : smax; };
 
-  T pb[K], pic[K], px[K], py[K];
-  auto load = [&](int s, int k) {
-    const int sc = (s >= 0 && s < smax) ? s : smax;
-    const size_t q = base + (size_t)sc * 64;
-    pb[k] = a.b[q];
-    pic[k] = a.ic[q];
-    if (GS) {
-      // (c+1, t) and (c, t+1), t = s - lane, with t clamped into the rectangle
-      // (a clamped operand only meets a zero coefficient or an idle step)
-      const int t = sc - lane;
-      const int tl = t < 0 ? 0 : (t >= mr ? mr - 1 : t);
-      px[k] = a.z[sk.at_ct(cx, tl)];
-      py[k] = a.z[sk.at_ct(c, tl + 1 < mr ? tl + 1 : tl)];
-    }
-  };
+  T Ab[K], Ai[K], Bb[K], Bi[K], res[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) load(k - band * LAG, k);
+  for (int k = 0; k < K; ++k) {
+    const int s = clampstep(k - band * LAG);
+    Ab[k] = bb[s * 64 + lane];
+    Ai[k] = ib_[s * 64 + lane];
+    res[k] = T(0);
+  }
+  int s_prev = -(1 << 20);  // first local step of the results held in res
 
-  for (int s0 = 0; s0 < total; s0 += K) {
+  // one superstep: store previous results, prefetch the next superstep into
+  // (Nb, Ni), compute from (Cb, Ci) into res
+  auto superstep = [&](int s0, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
+    const int sl = s0 - band * LAG;  // local step of k = 0
+#pragma unroll
+    for (int k = 0; k < K; ++k) zz[clampstep(s_prev + k) * 64 + lane] = res[k];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int s = s0 + k - band * LAG;
-      const int t = s - lane;
-      const bool act = colok && t >= 0 && t < mr;
-      const int tc = t < 0 ? 0 : (t >= mr ? mr - 1 : t);
-      // compute this step from slot k ...
-      T rhs = pb[k];
-      if (GS) rhs -= cd * px[k] + ycd[tc] * py[k];
-      T zin = wave_shr1(zlast);
-      const T zl0 = band == 0 ? bnd[tc] : ring[band - 1][tc & (RING - 1)];
-      zin = lane == 0 ? zl0 : zin;
-      const T t1 = rhs - ycu[tc] * zrow;
-      T zv = (t1 - cu * zin) * pic[k];
-      zv = act ? zv : T(0);
-      zrow = act ? zv : zrow;
-      const int ss = (s >= 0 && s < smax) ? s : smax;
-      a.z[base + (size_t)ss * 64] = zv;
-      if (lane == 63 && act) ring[band][tc & (RING - 1)] = zv;
-      zlast = zv;
-      // ... then refill slot k with the operands of step s + K (the slot's
-      // old values are dead here, so the loads reuse its registers in place)
-      __builtin_amdgcn_sched_barrier(0);
-      load(s + K, k);
+      const int s = clampstep(sl + K + k);
+      Nb[k] = bb[s * 64 + lane];
+      Ni[k] = ib_[s * 64 + lane];
     }
+    // LDS operands of the superstep, read up front so that no LDS latency
+    // sits on the step-to-step dependency chain (the ring rows read here were
+    // written at least one superstep earlier)
+    T yc[K], zb0[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int s = sl + k;
+      const int t = s - lane;
+      yc[k] = ycu[t < 0 ? 0 : (t >= mr ? mr - 1 : t)];
+      const int su = s < 0 ? 0 : (s >= mr ? mr - 1 : s);  // lane 0's row
+      zb0[k] = band == 0 ? bnd[su] : ring[band - 1][su & (RING - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int t = sl + k - lane;
+      // Values computed on idle steps only feed idle steps of the next lane,
+      // and land in padding slots; only the row carry needs masking.
+      T zin = wave_shr1(zlast);
+      zin = lane == 0 ? zb0[k] : zin;
+      const T t1 = Cb[k] - yc[k] * zrow;
+      const T zv = (t1 - cu * zin) * Ci[k];
+      zrow = (t >= 0) ? zv : zrow;
+      res[k] = zv;
+      // ring slot t mod 64: a slot is rewritten 64 rows later, i.e. 63 - K
+      // steps after its reader (band + 1) has read it
+      if (lane == 63) ring[band][t & (RING - 1)] = zv;
+      zlast = zv;
+    }
+    s_prev = sl;
     lds_barrier();
+  };
+  for (int s0 = 0; s0 < total; s0 += 2 * K) {
+    superstep(s0, Ab, Ai, Bb, Bi);
+    if (s0 + K >= total) break;
+    superstep(s0 + K, Bb, Bi, Ab, Ai);
   }
+#pragma unroll
+  for (int k = 0; k < K; ++k) zz[clampstep(s_prev + k) * 64 + lane] = res[k];
+}
+
+// Gauss-Seidel right-hand side, folded before a smoothing sweep: with the
+// current iterate z (skewed), rhs = b - (downstream couplings) * z, i.e.
+// forward b - W_i z_{i-1,j} - S_j z_{i,j-1}, transposed
+// b - W_{i+1} z_{i+1,j} - S_{j+1} z_{i,j+1}; the sweep then solves the
+// triangular system with this rhs, which is one Gauss-Seidel sweep.
+template <typename T, bool TR>
+__global__ void k_gs_rhs(Grid<T> g, const T *b, const T *z, T *out, size_t nslot, const int *gate) {
+  if (gate && *gate) return;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nslot) return;
+  const int n = g.nx;
+  const Skew<TR> sk{1, n, 1, n};
+  int i, j;
+  if (!sk.decode(q, i, j)) {
+    out[q] = T(0);
+    return;
+  }
+  const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
+  T v = b[q];
+  if (id >= 1 && id <= n) v -= (TR ? g.W[i + 1] : g.W[i]) * z[sk.at(id, j)];
+  if (jd >= 1 && jd <= g.ny) v -= (TR ? g.S[j + 1] : g.S[j]) * z[sk.at(i, jd)];
+  out[q] = v;
 }
 
 // Natural <-> skewed copies of a rectangle of the fine grid; the gather can
@@ -398,18 +437,28 @@ BLP_DEV void line_solve(const LineArgs<T> &a, int r, int q, int lane,
   }
   scan_affine_down(A, M, lane);
   T zn = dpp_mov<0x130>(T(0), A);  // value just after this lane's chunk
-  const long long lb = a.off[r] + (long long)q * a.sq[r];
 #pragma unroll
   for (int e = EP - 1; e >= 0; --e) {
     zn = y[e] + wv[e] * zn;
     zprev[e] = zn;
+  }
+}
+
+template <typename T, int EP>
+BLP_DEV void line_store(const LineArgs<T> &a, int r, int q, int lane, const T (&zl)[EP]) {
+  const long long lb = a.off[r] + (long long)q * a.sq[r];
+#pragma unroll
+  for (int e = 0; e < EP; ++e) {
     const int p = lane * EP + e;
-    if (p < h) a.z[r][lb + p] = zn;
+    if (p < a.h) a.z[r][lb + p] = zl[e];
   }
 }
 
 // One wave per region (block 0: Y, block 1: X).  The operands of line q+1
-// are loaded while line q is solved (two register buffers, alternating).
+// are loaded while line q is solved (two register buffers, alternating), and
+// line q's results are stored when line q+1 starts: the wave both loads and
+// stores, so it can only wait for all of its outstanding memory operations at
+// once, and this order makes them all a full line old at every wait.
 template <typename T, bool TR, int EP>
 __global__ __launch_bounds__(64) void k_lines(LineArgs<T> a) {
   if (a.gate && *a.gate) return;
@@ -427,11 +476,17 @@ __global__ __launch_bounds__(64) void k_lines(LineArgs<T> a) {
   LineBuf<T, EP> A_, B_;
   line_load<T, TR, EP>(a, r, 0, lane, A_);
   for (int q = 0; q < L; q += 2) {
+    if (q > 0) line_store<T, EP>(a, r, q - 1, lane, zprev);
     if (q + 1 < L) line_load<T, TR, EP>(a, r, q + 1, lane, B_);
     line_solve<T, TR, EP>(a, r, q, lane, A_, zprev);
-    if (q + 1 >= L) break;
+    if (q + 1 >= L) {
+      line_store<T, EP>(a, r, q, lane, zprev);
+      break;
+    }
+    line_store<T, EP>(a, r, q, lane, zprev);
     if (q + 2 < L) line_load<T, TR, EP>(a, r, q + 2, lane, A_);
     line_solve<T, TR, EP>(a, r, q + 1, lane, B_, zprev);
+    if (q + 2 >= L) line_store<T, EP>(a, r, q + 1, lane, zprev);
   }
 }
 
