@@ -198,12 +198,14 @@ int blp_mul(blp_problem *p, const double *a, const double *b, double *out);
  * number of launches (launches[k]) and the algorithmic bytes those launches
  * move (bytes[k]: words read and written that the algorithm needs, at the
  * precision of the launch).  Arrays have BLP_NCLASS entries; any may be NULL.
- * Classes: 0 Gauss-Seidel smoothing sweep (corner levels; b, z old, z new
- * per node), 1 triangular sweep from zero (interior region and first
- * pre-smoothing; b, z per node), 2 edge-layer line solves (b, z and two
- * factor words per node), 3 other multigrid kernels (residual, transfers,
- * norms), 4 stencil SpMV / residual (x in, y out), 5 Arnoldi and solution
- * update, 6 layout gathers/scatters and corner set-up.
+ * Classes (each the launches of one kernel family): 0 triangular sweeps
+ * (interior region and every multigrid smoothing sweep; right-hand side in,
+ * z out per node), 1 Gauss-Seidel right-hand-side pre-pass of the smoothing
+ * sweeps (b and z in, folded right-hand side out), 2 edge-layer line solves
+ * (b, z and two factor words per node), 3 other multigrid kernels (residual,
+ * transfers, coarsest level, norms), 4 stencil SpMV / residual (x in, y
+ * out), 5 Arnoldi and solution update, 6 layout gathers/scatters and corner
+ * set-up.
  * Errors: BLP_E_INVAL, BLP_E_HIP. */
 #define BLP_NCLASS 7
 int blp_timing(blp_problem *p, int enable, double *ms, long long *launches,

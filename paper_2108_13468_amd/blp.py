@@ -25,7 +25,7 @@ EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_sol
            "blp_bilinear_project", "blp_mul", "blp_timing", "blp_footprint", "blp_destroy",
            "blp_strerror")
 NCLASS = 7
-CLASSES = ("gs_sweep", "sweep", "lines", "mg_other", "spmv", "krylov", "layout")
+CLASSES = ("sweep", "gs_rhs", "lines", "mg_other", "spmv", "krylov", "layout")
 
 _dp = C.POINTER(C.c_double)
 

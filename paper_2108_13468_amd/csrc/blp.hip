@@ -82,7 +82,7 @@ struct FineDev {
   T *fac[4][3];   // line factors [Y fwd, X fwd, Y tr, X tr] x [d, m, w]
   T *icI[2];      // skewed 1/C of the interior region, per direction
   T *bI, *zI;     // skewed work vectors of the interior region
-  T *bY, *zY;     // line-major work vectors of the Y region
+  T *bL[2], *zL[2];  // line-major work vectors of the edge regions [Y, X], stride hp
   size_t nslotI;
 };
 
@@ -129,7 +129,9 @@ struct blp_problem {
   hipEvent_t ev_next() {
     if (ev_used == ev_pool.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      // timestamps only: no system-scope fence (the stream is synchronised
+      // before the times are read), so recording does not flush caches
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       ev_pool.push_back(e);
     }
     return ev_pool[ev_used++];
@@ -183,7 +185,9 @@ struct KScope {
   }
   ~KScope() { end(); }
 };
-enum { KC_GS = 0, KC_SWEEP, KC_LINES, KC_MG, KC_SPMV, KC_KRYLOV, KC_LAYOUT };
+// Timing classes: one kernel (template) each where it matters for roofline
+// accounting, so that a class average is a kernel average.
+enum { KC_SWEEP = 0, KC_GSRHS, KC_LINES, KC_MG, KC_SPMV, KC_KRYLOV, KC_LAYOUT };
 
 template <typename T>
 FineDev<T> &fine(blp_problem *p);
@@ -233,66 +237,71 @@ void axis_mesh(int N, double tau, std::vector<double> &nodes, std::vector<double
 
 template <typename T, bool TR>
 void launch_sweep(blp_problem *p, const Grid<T> &g, int i0, int i1, int j0, int j1, const T *b,
-                  const T *ic, T *z, const T *zb, const int *gate, int cls) {
+                  const T *ic, T *z, const int *gate) {
   const int nb = (i1 - i0 + 1 + 63) / 64;
-  SweepArgs<T> a{g, i0, i1, j0, j1, b, ic, z, zb, gate};
+  SweepArgs<T> a{g, i0, i1, j0, j1, b, ic, z, gate};
   const double pts = (double)(i1 - i0 + 1) * (j1 - j0 + 1);
-  KScope ks(p, cls, pts * (cls == KC_GS ? 3 : 2) * sizeof(T));
-  // superstep length K: two operand buffers and the results of a superstep
-  // stay in registers (5K values per lane); with more than 8 waves the
-  // register file allows K = 8.
+  KScope ks(p, KC_SWEEP, pts * 2 * sizeof(T));
+  // superstep of K steps = 4 chunks of 16 bytes per lane; D supersteps of
+  // loads in flight (D + 1 register buffers of 2K words); more than 8 waves
+  // leave registers for D = 1 only
+  constexpr int K = 4 * kChunk<T>;
   if (nb <= 8)
-    k_sweep<T, TR, 16><<<1, 64 * nb, 0, p->stream>>>(a);
+    k_sweep<T, TR, K, 4><<<1, 64 * nb, 0, p->stream>>>(a);
   else
-    k_sweep<T, TR, 8><<<1, 64 * nb, 0, p->stream>>>(a);
+    k_sweep<T, TR, K, 1><<<1, 64 * nb, 0, p->stream>>>(a);
+}
+
+// Row stride of the line-major edge-region buffers: h rounded up to a
+// multiple of 4, so that every thread's nodes are 16-byte aligned.
+inline int line_stride(int h) { return (h + 3) / 4 * 4; }
+
+template <typename T, bool TR, int EP, int W>
+void launch_lines_k(blp_problem *p, const LineArgs<T> &a) {
+  // D lines of operands in flight: 4 EP words per line and wave, within the
+  // 63 outstanding memory operations a wave can track and its registers
+  constexpr int D = EP >= 4 ? 4 : 6;
+  k_lines<T, TR, EP, W, D><<<2, 64 * W, 0, p->stream>>>(a);
 }
 
 template <typename T, bool TR>
 void launch_lines(blp_problem *p, const T *v, const T *dh, T *z) {
   FineDev<T> &f = fine<T>(p);
-  const int h = p->h, n1 = p->n1;
+  const int h = p->h, n1 = p->n1, hp = line_stride(h);
   LineArgs<T> a;
   a.g = fine_grid<T>(p);
   a.h = h;
   a.n1 = n1;
-  // region 0 (Y): gathered line-major buffer; region 1 (X): rows of v / z
-  a.b[0] = f.bY;
-  a.dh[0] = nullptr;
-  a.z[0] = f.zY;
-  a.off[0] = 0;
-  a.sq[0] = h;
-  a.b[1] = v;
-  a.dh[1] = dh;
-  a.z[1] = z;
-  a.off[1] = TR ? (long long)h * n1 : (long long)(n1 - 1) * n1;
-  a.sq[1] = TR ? n1 : -(long long)n1;
-  a.znat = z;
+  a.hp = hp;
   const int base = TR ? 2 : 0;
   for (int r = 0; r < 2; ++r) {
+    a.b[r] = f.bL[r];
+    a.z[r] = f.zL[r];
     a.fd[r] = f.fac[base + r][0];
     a.fm[r] = f.fac[base + r][1];
     a.fw[r] = f.fac[base + r][2];
   }
   a.gate = nullptr;
-  const dim3 gl((h + 255) / 256, n1 - h);
+  const dim3 gl((hp + 255) / 256, n1 - h, 2);
   {
     KScope ks(p, KC_LAYOUT, 0.0);
-    k_gather_lines<T, TR><<<gl, 256, 0, p->stream>>>(v, dh, h, n1, f.bY);
+    k_gather_lines<T, TR><<<gl, 256, 0, p->stream>>>(a.g, v, dh, z, h, n1, hp, f.bL[0], f.bL[1]);
   }
   KScope ks(p, KC_LINES, 2.0 * (n1 - h) * h * 4 * sizeof(T));
-  if (h <= 64)
-    k_lines<T, TR, 1><<<2, 64, 0, p->stream>>>(a);
-  else if (h <= 128)
-    k_lines<T, TR, 2><<<2, 64, 0, p->stream>>>(a);
-  else if (h <= 256)
-    k_lines<T, TR, 4><<<2, 64, 0, p->stream>>>(a);
-  else if (h <= 512)
-    k_lines<T, TR, 8><<<2, 64, 0, p->stream>>>(a);
+  // threads hold EP contiguous nodes; up to 4 waves per region
+  if (hp <= 64)
+    launch_lines_k<T, TR, 1, 1>(p, a);
+  else if (hp <= 128)
+    launch_lines_k<T, TR, 1, 2>(p, a);
+  else if (hp <= 256)
+    launch_lines_k<T, TR, 1, 4>(p, a);
+  else if (hp <= 512)
+    launch_lines_k<T, TR, 2, 4>(p, a);
   else
-    k_lines<T, TR, 16><<<2, 64, 0, p->stream>>>(a);
+    launch_lines_k<T, TR, 4, 4>(p, a);
   ks.end();
   KScope ks2(p, KC_LAYOUT, 0.0);
-  k_scatter_lines<T, TR><<<gl, 256, 0, p->stream>>>(f.zY, h, n1, z);
+  k_scatter_lines<T, TR><<<gl, 256, 0, p->stream>>>(f.zL[0], f.zL[1], h, n1, hp, z);
 }
 
 // Interior region: gather into the skewed layout, sweep, scatter back.
@@ -300,14 +309,14 @@ template <typename T, bool TR>
 void interior_solve(blp_problem *p, const T *v, const T *dh, T *z) {
   FineDev<T> &f = fine<T>(p);
   const int h = p->h, n1 = p->n1;
-  const Skew<TR> sk{h + 1, n1, h + 1, n1};
+  const SkewT<T, TR> sk{h + 1, n1, h + 1, n1};
   const unsigned nb = blocks1d(f.nslotI);
   {
     KScope ks(p, KC_LAYOUT, 0.0);
-    k_gather_skew<T, TR><<<nb, 256, 0, p->stream>>>(sk, v, dh, n1, f.bI, f.nslotI);
+    k_gather_skew<T, TR><<<nb, 256, 0, p->stream>>>(fine_grid<T>(p), sk, v, dh, z, f.bI, f.nslotI);
   }
-  launch_sweep<T, TR>(p, fine_grid<T>(p), h + 1, n1, h + 1, n1, f.bI, f.icI[TR ? 1 : 0], f.zI, z,
-                      nullptr, KC_SWEEP);
+  launch_sweep<T, TR>(p, fine_grid<T>(p), h + 1, n1, h + 1, n1, f.bI, f.icI[TR ? 1 : 0], f.zI,
+                      nullptr);
   KScope ks(p, KC_LAYOUT, 0.0);
   k_scatter_skew<T, TR><<<nb, 256, 0, p->stream>>>(sk, f.zI, z, n1, f.nslotI);
 }
@@ -315,7 +324,7 @@ void interior_solve(blp_problem *p, const T *v, const T *dh, T *z) {
 // Gauss-Seidel rhs of a level into its t vector (t is free at that point).
 template <typename T, bool TR>
 void gs_rhs(blp_problem *p, const LevelDev<T> &lv, const int *gate) {
-  KScope ks(p, KC_MG, (double)lv.n * lv.n * 3 * sizeof(T));
+  KScope ks(p, KC_GSRHS, (double)lv.n * lv.n * 3 * sizeof(T));
   k_gs_rhs<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.grid(), lv.b, lv.z, lv.t, lv.nslot,
                                                              gate);
 }
@@ -335,10 +344,10 @@ void vcycle(blp_problem *p, int l, bool zero_init, const int *gate) {
   const LevelDev<T> &cv = L[l + 1];
   const T *ic = lv.ic[TR ? 1 : 0];
   if (zero_init) {
-    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, nullptr, gate, KC_SWEEP);
+    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, gate);
   } else {
     gs_rhs<T, TR>(p, lv, gate);
-    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, nullptr, gate, KC_GS);
+    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, gate);
   }
   {
     KScope ks(p, KC_MG, (double)n * n * 3 * sizeof(T));
@@ -354,8 +363,11 @@ void vcycle(blp_problem *p, int l, bool zero_init, const int *gate) {
     k_mg_prolong<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
   }
   gs_rhs<T, TR>(p, lv, gate);
-  launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, nullptr, gate, KC_GS);
+  launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, gate);
 }
+
+// blocks of the corner residual-norm reduction (one partial each)
+constexpr int kMgNormBlocks = 256;
 
 // Corner solve M_CC^{-1} b_0 (level 0 b and z).  Cycles are counted in ctrl.
 template <typename T, bool TR>
@@ -363,7 +375,7 @@ int corner_solve(blp_problem *p) {
   std::vector<LevelDev<T>> &L = levels<T>(p);
   const LevelDev<T> &l0 = L[0];
   const blp_prec_opts &o = p->popts;
-  const int nblk = std::min(256, (int)blocks1d(l0.nslot));
+  const int nblk = std::min(kMgNormBlocks, (int)blocks1d(l0.nslot));
   if (o.mg_fixed > 0) {
     for (int c = 0; c < o.mg_fixed; ++c) {
       vcycle<T, TR>(p, 0, c == 0, nullptr);
@@ -438,7 +450,7 @@ int upload_level(blp_problem *p, const LevelHost &lh, LevelDev<T> &d, const Leve
                  const T *rfine_nodal, int rfine_ld) {
   d.n = lh.n;
   const int n = lh.n;
-  d.nslot = skew_size(n, n);
+  d.nslot = skew_size<T>(n, n);
   BLP_TRY(p->upload(&d.W, lh.tx.W));
   BLP_TRY(p->upload(&d.E, lh.tx.E));
   BLP_TRY(p->upload(&d.Dx, lh.tx.D));
@@ -486,25 +498,27 @@ int build_fine_prec(blp_problem *p, FineDev<T> &f) {
   BLP_TRY(p->alloc(&f.dh, p->n));
   k_diag_tables<T><<<grid2d(n1, n1), 256, 0, p->stream>>>(p->grid64(), (T *)nullptr, f.dh);
   const int m = n1 - h;
-  f.nslotI = skew_size(m, m);
+  f.nslotI = skew_size<T>(m, m);
   BLP_TRY(zalloc(p, &f.icI[0], f.nslotI));
   BLP_TRY(zalloc(p, &f.icI[1], f.nslotI));
   BLP_TRY(zalloc(p, &f.bI, f.nslotI));
   BLP_TRY(zalloc(p, &f.zI, f.nslotI));
-  const Skew<false> skf{h + 1, n1, h + 1, n1};
-  const Skew<true> skt{h + 1, n1, h + 1, n1};
+  const SkewT<T, false> skf{h + 1, n1, h + 1, n1};
+  const SkewT<T, true> skt{h + 1, n1, h + 1, n1};
   k_diag_skew<T, false><<<blocks1d(f.nslotI), 256, 0, p->stream>>>(p->grid64(), skf, f.icI[0], f.nslotI);
   k_diag_skew<T, true><<<blocks1d(f.nslotI), 256, 0, p->stream>>>(p->grid64(), skt, f.icI[1], f.nslotI);
-  BLP_TRY(zalloc(p, &f.bY, (size_t)m * h));
-  BLP_TRY(zalloc(p, &f.zY, (size_t)m * h));
+  for (int r = 0; r < 2; ++r) {
+    BLP_TRY(zalloc(p, &f.bL[r], (size_t)m * line_stride(h)));
+    BLP_TRY(zalloc(p, &f.zL[r], (size_t)m * line_stride(h)));
+  }
   HIP_TRY(hipGetLastError());
   return BLP_OK;
 }
 
 template <typename T>
 void level_diag(blp_problem *p, const LevelDev<double> &l64, LevelDev<T> &d) {
-  const Skew<false> sf{1, d.n, 1, d.n};
-  const Skew<true> st{1, d.n, 1, d.n};
+  const SkewT<T, false> sf{1, d.n, 1, d.n};
+  const SkewT<T, true> st{1, d.n, 1, d.n};
   k_diag_skew<T, false><<<blocks1d(d.nslot), 256, 0, p->stream>>>(l64.grid(), sf, d.ic[0], d.nslot);
   k_diag_skew<T, true><<<blocks1d(d.nslot), 256, 0, p->stream>>>(l64.grid(), st, d.ic[1], d.nslot);
 }
@@ -514,15 +528,17 @@ int build_preconditioner(blp_problem *p) {
   BLP_TRY(build_fine_prec(p, p->f64));
   BLP_TRY(build_fine_prec(p, p->f32));
   // ---- Thomas factors of the edge-layer lines (computed in FP64) ----------
-  const size_t fl = (size_t)(n1 - h) * h;
+  // (zero-filled: the padding nodes of a line keep zero factors)
+  const int hp = line_stride(h);
+  const size_t fl = (size_t)(n1 - h) * hp;
   for (int v = 0; v < 4; ++v) {
     for (int k = 0; k < 3; ++k) {
-      BLP_TRY(p->alloc(&p->f64.fac[v][k], fl));
-      BLP_TRY(p->alloc(&p->f32.fac[v][k], fl));
+      BLP_TRY(zalloc(p, &p->f64.fac[v][k], fl));
+      BLP_TRY(zalloc(p, &p->f32.fac[v][k], fl));
     }
     const int region = v % 2, tr = v / 2;
     k_line_factor<double><<<blocks1d(n1 - h, 64), 64, 0, p->stream>>>(
-        p->grid64(), h, n1, region, tr, p->f64.fac[v][0], p->f64.fac[v][1], p->f64.fac[v][2]);
+        p->grid64(), h, n1, hp, region, tr, p->f64.fac[v][0], p->f64.fac[v][1], p->f64.fac[v][2]);
     for (int k = 0; k < 3; ++k)
       k_convert<double, float><<<blocks1d(fl), 256, 0, p->stream>>>(p->f64.fac[v][k],
                                                                     p->f32.fac[v][k], fl);
@@ -582,7 +598,7 @@ int build_preconditioner(blp_problem *p) {
   if (!p->ctrl) {
     BLP_TRY(p->alloc(&p->ctrl, 1));
     HIP_TRY(hipMemsetAsync(p->ctrl, 0, sizeof(MgCtrl), p->stream));
-    BLP_TRY(p->alloc(&p->mg_partials, 256));
+    BLP_TRY(p->alloc(&p->mg_partials, kMgNormBlocks));
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(p->stream));

@@ -22,9 +22,8 @@ struct Grid {
   const T *r;           // nodal r, r[(j-1)*rld + (i-1)], or nullptr
   int rld;
   T rc;                 // constant r when r == nullptr
-  BLP_DEV T C(int i, int j) const {
-    return Dx[i] + Dy[j] + (r ? r[(size_t)(j - 1) * rld + (i - 1)] : rc);
-  }
+  BLP_DEV T rr(int i, int j) const { return r ? r[(size_t)(j - 1) * rld + (i - 1)] : rc; }
+  BLP_DEV T C(int i, int j) const { return Dx[i] + Dy[j] + rr(i, j); }
 };
 
 BLP_DEV size_t vidx(int i, int j, int ld) { return (size_t)(j - 1) * ld + (i - 1); }
@@ -73,15 +72,34 @@ BLP_DEV double block_sum(double v, double *sh) {
 }
 
 // "Last block" pattern: every block publishes its partial, then the last
-// block to arrive sees all partials.  Returns true in the whole last block.
+// block to arrive reads all partials.  Partials are stored and read through
+// to the device coherence point (relaxed agent-scope atomic accesses), and a
+// block's arrival is counted only after its own partial store has completed
+// (s_waitcnt vmcnt(0) before the counter increment), which orders the two
+// without a device-scope fence: on this GPU such a fence writes back the
+// whole L2 of the XCD, in every block.  Only thread 0 publishes.
+BLP_DEV void publish(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+BLP_DEV double collect(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Returns true in the whole last block.
 BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned int prev = atomicAdd(counter, 1u);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));  // vmcnt(0)
+    const unsigned int prev =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *sh_flag = (prev == gridDim.x * gridDim.y - 1);
+    __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   __syncthreads();
-  if (*sh_flag) __threadfence();
   return *sh_flag;
+}
+// Reset of an arrival counter by the last block (for the next launch).
+BLP_DEV void reset_counter(unsigned int *counter) {
+  __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

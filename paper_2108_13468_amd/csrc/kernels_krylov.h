@@ -49,24 +49,23 @@ __global__ __launch_bounds__(256) void k_arnoldi_dot(const TV *V, size_t ldv, in
       if (q < n) acc += (double)V[(size_t)v * ldv + q] * wl[e];
     }
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nd + v] = acc;
+    if (threadIdx.x == 0) publish(&partials[(size_t)blockIdx.x * nd + v], acc);
   }
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < KPT; ++e) acc += wl[e] * wl[e];
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nd + j + 1] = acc;
+  if (threadIdx.x == 0) publish(&partials[(size_t)blockIdx.x * nd + j + 1], acc);
   if (!arrive_last(&st->counter, &last)) return;
   for (int v = threadIdx.x; v < nd; v += blockDim.x) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += partials[(size_t)b * nd + v];
+    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[(size_t)b * nd + v]);
     if (v <= j) ko.h1(ks)[v] = s;
     else st->wn0 = sqrt(s);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    st->counter = 0;
-    __threadfence();
+    reset_counter(&st->counter);
   }
 }
 
@@ -113,32 +112,31 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv,
         if (q < n) acc += (double)V[(size_t)v * ldv + q] * wl[e];
       }
       acc = block_sum(acc, sh);
-      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nd + v] = acc;
+      if (threadIdx.x == 0) publish(&partials[(size_t)blockIdx.x * nd + v], acc);
     }
   } else {
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < KPT; ++e) acc += wl[e] * wl[e];
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+    if (threadIdx.x == 0) publish(&partials[blockIdx.x], acc);
   }
   if (!arrive_last(&st->counter, &last)) return;
   if (!NORM) {
     for (int v = threadIdx.x; v <= j; v += blockDim.x) {
       double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += partials[(size_t)b * nd + v];
+      for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[(size_t)b * nd + v]);
       ko.h2(ks)[v] = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      st->counter = 0;
-      __threadfence();
+      reset_counter(&st->counter);
     }
     return;
   }
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += partials[b];
+    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[b]);
     const double hn = sqrt(s);
     const int m = ko.m;
     double *H = ko.H(ks), *cs = ko.cs(ks), *sn = ko.sn(ks), *g = ko.g(ks);
@@ -167,8 +165,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv,
     st->est = fabs(g[j + 1]);
     st->hn = hn;
     st->happy = hn <= 1e-14 * st->wn0;
-    st->counter = 0;
-    __threadfence();
+    reset_counter(&st->counter);
   }
 }
 

@@ -50,14 +50,13 @@ __global__ __launch_bounds__(256) void k_stencil(Grid<double> g, const TX *__res
   if (!RESID) return;
   acc = block_sum(acc, sh);
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) partials[bid] = acc;
+  if (threadIdx.x == 0) publish(&partials[bid], acc);
   if (!arrive_last(&st->counter, &last)) return;
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < (int)(gridDim.x * gridDim.y); ++b) s += partials[b];
+    for (int b = 0; b < (int)(gridDim.x * gridDim.y); ++b) s += collect(&partials[b]);
     st->beta = sqrt(s);
-    st->counter = 0;
-    __threadfence();
+    reset_counter(&st->counter);
   }
 }
 
@@ -80,14 +79,13 @@ __global__ __launch_bounds__(256) void k_norm(Grid<double> g, const double *F, d
     acc += v * v;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+  if (threadIdx.x == 0) publish(&partials[blockIdx.x], acc);
   if (!arrive_last(&st->counter, &last)) return;
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += partials[b];
+    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[b]);
     st->beta = sqrt(s);
-    st->counter = 0;
-    __threadfence();
+    reset_counter(&st->counter);
   }
 }
 

@@ -61,9 +61,10 @@ BLP_DEV void scan_affine_up(T &A, T &M) {
   BLP_COMBINE(0x143, 0xC)
 }
 
-// Suffix version: lane l ends with the composition of lanes 63..l applied to
-// a zero value beyond lane 63 (only A is meaningful on exit).  In-row steps
-// by DPP row_shl; the three row totals cross rows through readlane.
+// Suffix version: lane l ends with the composition f_l o f_{l+1} o ... o
+// f_63 of the affine maps of lanes l..63 (A and M both valid).  In-row steps
+// by DPP row_shl; the row totals (held by lanes 16, 32, 48) cross rows
+// through readlane.
 template <typename T>
 BLP_DEV void scan_affine_down(T &A, T &M, int lane) {
   BLP_COMBINE(0x101, 0xF)
@@ -71,15 +72,18 @@ BLP_DEV void scan_affine_down(T &A, T &M, int lane) {
   BLP_COMBINE(0x104, 0xF)
   BLP_COMBINE(0x108, 0xF)
 #undef BLP_COMBINE
-  const T A48 = read_lane(A, 48);
+  const T A48 = read_lane(A, 48), M48 = read_lane(M, 48);
   const T A32 = read_lane(A, 32), M32 = read_lane(M, 32);
   const T A16 = read_lane(A, 16), M16 = read_lane(M, 16);
-  const T S3 = A48;
-  const T S2 = A32 + M32 * S3;
-  const T S1 = A16 + M16 * S2;
+  // suffix of the rows after row r: S3 = id, S2 = R3, S1 = R2 o R3, S0 = R1 o S1
+  const T SA2 = A48, SM2 = M48;
+  const T SA1 = A32 + M32 * SA2, SM1 = M32 * SM2;
+  const T SA0 = A16 + M16 * SA1, SM0 = M16 * SM1;
   const int row = lane >> 4;
-  const T Sin = row == 0 ? S1 : (row == 1 ? S2 : (row == 2 ? S3 : T(0)));
-  A = A + M * Sin;
+  const T SA = row == 0 ? SA0 : (row == 1 ? SA1 : (row == 2 ? SA2 : T(0)));
+  const T SM = row == 0 ? SM0 : (row == 1 ? SM1 : (row == 2 ? SM2 : T(1)));
+  A = A + M * SA;
+  M = M * SM;
 }
 
 // ---------------------------------------------------------------------------
@@ -88,30 +92,40 @@ BLP_DEV void scan_affine_down(T &A, T &M, int lane) {
 // A downstream sweep over the rectangle [i0,i1] x [j0,j1] visits column c
 // (c = 0 first: i1 - c forward, i0 + c transposed) and row t (t = 0 first:
 // j1 - t forward, j0 + t transposed).  Columns are grouped in bands of 64;
-// lane l = c mod 64 handles node (c, t) at step s = t + l.  In this layout
-// node (c, t) is stored at ((band * (mr + 64)) + t + l) * 64 + l, so the 64
-// lanes of a band read and write 64 consecutive words at every step.  Step
-// index mr + 63 of each band is never a node (a sink row for idle steps).
+// lane l = c mod 64 handles node (c, t) at step s = t + l.  Steps are grouped
+// in chunks of P = 16 / sizeof(word) (2 in FP64, 4 in FP32), and the P steps
+// of one lane in one chunk are contiguous:
+//   node (c, t) -> ((band * nck + s / P) * 64 + l) * P + s mod P,
+// so one 16-byte access per lane moves P steps of a band, and the 64 lanes of
+// a wave touch 1 KiB of consecutive bytes.  A band has nck = ceil((mr + 63) /
+// P) + 1 chunks; the last chunk holds no node (a sink for idle steps), and
+// neither do the slots with t < 0 or t >= mr (padding, kept at zero in
+// right-hand sides and inverse diagonals).
 // ---------------------------------------------------------------------------
-template <bool TR>
+template <bool TR, int P>
 struct Skew {
   int i0, i1, j0, j1;
   BLP_DEV int mc() const { return i1 - i0 + 1; }
   BLP_DEV int mr() const { return j1 - j0 + 1; }
+  BLP_DEV int nck() const { return (mr() + 62 + P) / P + 1; }
   BLP_DEV int col(int i) const { return TR ? i - i0 : i1 - i; }
   BLP_DEV int row(int j) const { return TR ? j - j0 : j1 - j; }
   BLP_DEV int icol(int c) const { return TR ? i0 + c : i1 - c; }
   BLP_DEV int jrow(int t) const { return TR ? j0 + t : j1 - t; }
+  // s >= 0
   BLP_DEV size_t slot(int band, int s, int lane) const {
-    return ((size_t)band * (mr() + 64) + s) * 64 + lane;
+    return (((size_t)band * nck() + s / P) * 64 + lane) * P + s % P;
   }
   BLP_DEV size_t at_ct(int c, int t) const { return slot(c >> 6, t + (c & 63), c & 63); }
   BLP_DEV size_t at(int i, int j) const { return at_ct(col(i), row(j)); }
   // slot index -> node; false on padding
   BLP_DEV bool decode(size_t q, int &i, int &j) const {
-    const int lane = (int)(q & 63);
-    const size_t r = q >> 6;
-    const int band = (int)(r / (size_t)(mr() + 64)), s = (int)(r % (size_t)(mr() + 64));
+    const int e = (int)(q % P);
+    const size_t r = q / P;
+    const int lane = (int)(r & 63);
+    const size_t r2 = r >> 6;
+    const int n = nck();
+    const int band = (int)(r2 / (size_t)n), s = (int)(r2 % (size_t)n) * P + e;
     const int c = band * 64 + lane, t = s - lane;
     if (c >= mc() || t < 0 || t >= mr()) return false;
     i = icol(c);
@@ -119,7 +133,15 @@ struct Skew {
     return true;
   }
 };
-inline size_t skew_size(int mc, int mr) { return (size_t)((mc + 63) / 64) * (mr + 64) * 64; }
+template <typename T>
+constexpr int kChunk = 16 / (int)sizeof(T);
+template <typename T, bool TR>
+using SkewT = Skew<TR, kChunk<T>>;
+template <typename T>
+inline size_t skew_size(int mc, int mr) {
+  constexpr int P = kChunk<T>;
+  return (size_t)((mc + 63) / 64) * ((mr + 62 + P) / P + 1) * 64 * P;
+}
 
 // ---------------------------------------------------------------------------
 // Downstream triangular sweep on a rectangle of a grid.
@@ -131,143 +153,187 @@ inline size_t skew_size(int mc, int mr) { return (size_t)((mc + 63) / 64) * (mr 
 // neighbour terms k_gs_rhs folds into rhs beforehand).  Transposed
 // (TR = true) solves the transpose from the bottom-left corner:
 //   C_ij z_ij + E_{i-1} z_{i-1,j} + N_{j-1} z_{i,j-1} = rhs_ij.
-// Values just outside the rectangle on its upstream sides come from zb (a
-// grid vector in natural layout, e.g. already-solved neighbouring regions)
-// when they lie inside the grid, else are zero.
+// Couplings to values outside the rectangle are already folded into rhs
+// (k_gather_skew), so the sweep sees zero boundary values.
 //
 // rhs, 1/C and z are in the skewed layout of the rectangle.  One workgroup;
 // wave w owns band w, lane l one column.  The upstream-column value comes
-// from lane l-1 by a DPP shift, the upstream-row value is the lane's own
-// previous result.  Band w runs LAG = 64 + K steps behind band w-1 and takes
-// the band-boundary column from an LDS ring; an LDS-only barrier every K
+// from lane l-1 by a DPP shift (lane 0: from the previous band, through an
+// LDS ring), the upstream-row value is the lane's own previous result.  Band
+// w runs LAG = 64 + K steps behind band w-1; an LDS-only barrier every K
 // steps (a superstep) orders the ring traffic.
 //
-// Memory pipelining: a wave that both loads and stores can only wait for all
-// of its outstanding memory operations at once, so work is organised by
-// supersteps with two register buffers: at the start of superstep m the wave
-// stores the results of superstep m-1 and issues the loads of superstep m+1,
-// then computes superstep m from registers.  Every operation outstanding at
-// the next wait was issued a whole superstep earlier.  Step offsets are
-// wave-uniform (scalar arithmetic); lanes add a constant lane offset.
+// Idle steps need no masking: padding slots hold rhs = 1/C = 0, so a lane
+// whose row is not yet reached computes exactly 0 (the ring starts at zero),
+// which is also the correct upstream value of the first row; steps past the
+// last row land in padding or in the sink chunk.
+//
+// Memory pipelining: every access is one 16-byte chunk per lane.  At the
+// start of superstep m the wave stores the results of superstep m-1 and
+// issues the loads of superstep m+D into the register buffer that superstep
+// m-1 used (D+1 buffers, rotated by full unrolling), then computes superstep
+// m.  A superstep issues 3K/P memory instructions, so the wait before
+// superstep m covers operations issued D supersteps earlier, as long as
+// 3DK/P stays within the 63 outstanding operations the counter can track.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SweepArgs {
   Grid<T> g;
   int i0, i1, j0, j1;
   const T *b;     // skewed rhs
-  const T *ic;    // skewed 1/C
-  T *z;           // skewed solution
-  const T *zb;    // natural-layout source of upstream boundary values, or null
+  const T *ic;    // skewed 1/C (zero in padding)
+  T *z;           // skewed result
   const int *gate;
 };
 
-constexpr int kSweepMaxRows = 1024;
+constexpr int kSweepMaxRows = 1024;  // also bounds the rows of the ycu table
+constexpr int kSweepMaxBands = 16;
 
 // Workgroup barrier that waits for this wave's LDS traffic only (global
 // loads and stores may stay in flight): s_waitcnt lgkmcnt(0) with vmcnt and
-// expcnt at their maxima (GFX9 encoding 0xC07F), then s_barrier.
+// expcnt at their maxima (GFX9 encoding 0xC07F), then s_barrier.  The empty
+// asm statements keep the compiler from moving memory accesses across it.
 BLP_DEV void lds_barrier() {
+  asm volatile("" ::: "memory");
   __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
 }
 
-template <typename T, bool TR, int K>
-__global__ __launch_bounds__(K > 8 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <>
+struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+
+template <typename T, bool TR, int K, int D>
+__global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
   if (a.gate && *a.gate) return;
-  constexpr int LAG = 64 + K, RING = 64;
-  __shared__ T ring[16][RING];
-  __shared__ T bnd[kSweepMaxRows];  // upstream boundary column, by row t
-  __shared__ T ycu[kSweepMaxRows];  // upstream y coupling, by row t
+  constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64;
+  static_assert(K % P == 0 && 64 % K == 0 && 2 * K < 64, "superstep length");
+  typedef typename Vec16<T>::type V;
+  // ring row w + 1 holds the last column of band w by step; row 0 stays zero
+  __shared__ T ring[kSweepMaxBands + 1][RING];
+  // upstream y coupling by row t, stored at t + 64 for t in [-64, mr + 64 +
+  // K) with zeros outside [0, mr), so that a superstep reads it without
+  // per-lane clamping
+  __shared__ T ycu[kSweepMaxRows + 128 + K];
   const Grid<T> &g = a.g;
-  const Skew<TR> sk{a.i0, a.i1, a.j0, a.j1};
-  const int mc = sk.mc(), mr = sk.mr();
-  const int ib = TR ? a.i0 - 1 : a.i1 + 1;
-  const bool ib_in = a.zb && ib >= 1 && ib <= g.nx;
-  for (int t = threadIdx.x; t < mr; t += blockDim.x) {
-    const int j = sk.jrow(t);
-    ycu[t] = TR ? g.N[j - 1] : g.N[j];
-    bnd[t] = ib_in ? a.zb[vidx(ib, j, g.nx)] : T(0);
+  const SkewT<T, TR> sk{a.i0, a.i1, a.j0, a.j1};
+  const int mc = sk.mc(), mr = sk.mr(), nck = sk.nck();
+  for (int t = (int)threadIdx.x - 64; t < mr + 64 + K; t += blockDim.x) {
+    T v = T(0);
+    if (t >= 0 && t < mr) {
+      const int j = sk.jrow(t);
+      v = TR ? g.N[j - 1] : g.N[j];
+    }
+    ycu[t + 64] = v;
   }
+  for (int q = threadIdx.x; q < (kSweepMaxBands + 1) * RING; q += blockDim.x) (&ring[0][0])[q] = T(0);
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
   const int band = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int nb = blockDim.x >> 6;
+  const int nb = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
   const int c = band * 64 + lane;
   const bool colok = c < mc;
   const int i = sk.icol(colok ? c : mc - 1);
   const T cu = colok ? (TR ? g.E[i - 1] : g.E[i]) : T(0);  // upstream x coupling
-  const int jb = TR ? a.j0 - 1 : a.j1 + 1;
-  T zrow = (colok && a.zb && jb >= 1 && jb <= g.ny) ? a.zb[vidx(i, jb, g.nx)] : T(0);
-  T zlast = T(0);
-  const int total = (nb - 1) * LAG + mr + 63;
-  const int smax = mr + 63;  // steps 0..smax-1 are the band's work, smax its sink row
-  // this band's storage; step s of lane l is element (s * 64 + l)
-  const T *__restrict__ bb = a.b + sk.slot(band, 0, 0);
-  const T *__restrict__ ib_ = a.ic + sk.slot(band, 0, 0);
-  T *__restrict__ zz = a.z + sk.slot(band, 0, 0);
-  auto clampstep = [&](int s) { return (s >= 0 && s < smax) ? s : smax; };
-
-  T Ab[K], Ai[K], Bb[K], Bi[K], res[K];
+  const int nsup = __builtin_amdgcn_readfirstlane(((nb - 1) * LAG + mr + 63 + K - 1) / K);
+  // this band's storage: chunk ck of this lane is element ck * 64
+  const V *__restrict__ bb = reinterpret_cast<const V *>(a.b + sk.slot(band, 0, 0)) + lane;
+  const V *__restrict__ bi = reinterpret_cast<const V *>(a.ic + sk.slot(band, 0, 0)) + lane;
+  V *__restrict__ zz = reinterpret_cast<V *>(a.z + sk.slot(band, 0, 0)) + lane;
+  T *__restrict__ ring_out = ring[band + 1];
+  const T *__restrict__ ring_in = ring[band];
+  const T *__restrict__ yc_lane = ycu + 64 - lane;  // yc_lane[s] = coupling of row s - lane
+  // last superstep start with a step that is not idle for every lane
+  const int shi = __builtin_amdgcn_readfirstlane((mr + 63) / K * K);
+  // chunk of local step s (a multiple of P, wave-uniform): its own, or the sink
+  auto chunk = [&](int s) {
+    const int ck = s / P;
+    return (s >= 0 && ck < nck - 1) ? ck : nck - 1;
+  };
+  auto load = [&](int s, T (&Bb)[K], T (&Bi)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int s = clampstep(k - band * LAG);
-    Ab[k] = bb[s * 64 + lane];
-    Ai[k] = ib_[s * 64 + lane];
-    res[k] = T(0);
-  }
-  int s_prev = -(1 << 20);  // first local step of the results held in res
-
-  // one superstep: store previous results, prefetch the next superstep into
-  // (Nb, Ni), compute from (Cb, Ci) into res
-  auto superstep = [&](int s0, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
-    const int sl = s0 - band * LAG;  // local step of k = 0
+    for (int q = 0; q < CK; ++q) {
+      const int ck = chunk(s + q * P);
+      const V vb = bb[ck * 64], vi = bi[ck * 64];
 #pragma unroll
-    for (int k = 0; k < K; ++k) zz[clampstep(s_prev + k) * 64 + lane] = res[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int s = clampstep(sl + K + k);
-      Nb[k] = bb[s * 64 + lane];
-      Ni[k] = ib_[s * 64 + lane];
+      for (int e = 0; e < P; ++e) {
+        Bb[q * P + e] = vb[e];
+        Bi[q * P + e] = vi[e];
+      }
     }
+  };
+  auto store = [&](int s, const T (&R)[K]) {
+#pragma unroll
+    for (int q = 0; q < CK; ++q) {
+      V v;
+#pragma unroll
+      for (int e = 0; e < P; ++e) v[e] = R[q * P + e];
+      zz[chunk(s + q * P) * 64] = v;
+    }
+  };
+
+  T buf_b[D + 1][K], buf_i[D + 1][K], res[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) res[k] = T(0);
+#pragma unroll
+  for (int u = 0; u < D; ++u) load(u * K - band * LAG, buf_b[u], buf_i[u]);
+  int s_prev = -(1 << 20);  // local step of the results held in res (none yet: sink)
+  T z = T(0);               // this lane's latest result (the next row's upstream value)
+
+  auto superstep = [&](int m, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
+    const int sl = __builtin_amdgcn_readfirstlane(m * K - band * LAG);  // local step of k = 0
+    store(s_prev, res);
+    load(sl + D * K, Nb, Ni);
     // LDS operands of the superstep, read up front so that no LDS latency
-    // sits on the step-to-step dependency chain (the ring rows read here were
-    // written at least one superstep earlier)
+    // sits on the step-to-step dependency chain.  Ring slot of local step s
+    // of the writer is (s + 1) mod 64, so lane 0 of this band, at local step
+    // s, needs slot s mod 64 (the writer's step s + 63); entries read here
+    // were written at least one superstep earlier.
     T yc[K], zb0[K];
+    const int r0 = sl & (RING - 1);
+    // supersteps before the band starts or after it ends are idle for every
+    // lane: any finite coupling will do there
+    const int sy = sl < 0 ? 0 : (sl > shi ? shi : sl);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int s = sl + k;
-      const int t = s - lane;
-      yc[k] = ycu[t < 0 ? 0 : (t >= mr ? mr - 1 : t)];
-      const int su = s < 0 ? 0 : (s >= mr ? mr - 1 : s);  // lane 0's row
-      zb0[k] = band == 0 ? bnd[su] : ring[band - 1][su & (RING - 1)];
+      yc[k] = yc_lane[sy + k];
+      zb0[k] = ring_in[r0 + k];
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int t = sl + k - lane;
-      // Values computed on idle steps only feed idle steps of the next lane,
-      // and land in padding slots; only the row carry needs masking.
-      T zin = wave_shr1(zlast);
-      zin = lane == 0 ? zb0[k] : zin;
-      const T t1 = Cb[k] - yc[k] * zrow;
-      const T zv = (t1 - cu * zin) * Ci[k];
-      zrow = (t >= 0) ? zv : zrow;
-      res[k] = zv;
-      // ring slot t mod 64: a slot is rewritten 64 rows later, i.e. 63 - K
-      // steps after its reader (band + 1) has read it
-      if (lane == 63) ring[band][t & (RING - 1)] = zv;
-      zlast = zv;
+      const T zin = dpp_mov<0x138>(zb0[k], z);  // lane l-1's value; lane 0: zb0
+      z = (Cb[k] - yc[k] * z - cu * zin) * Ci[k];
+      res[k] = z;
+    }
+    // a slot is read K + 1 steps after it is written and rewritten 64 steps
+    // after (2K < 64 keeps both in different supersteps)
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) ring_out[(sl + k + 1) & (RING - 1)] = res[k];
     }
     s_prev = sl;
     lds_barrier();
   };
-  for (int s0 = 0; s0 < total; s0 += 2 * K) {
-    superstep(s0, Ab, Ai, Bb, Bi);
-    if (s0 + K >= total) break;
-    superstep(s0 + K, Bb, Bi, Ab, Ai);
+  // whole groups of D + 1 supersteps (buffer roles fixed by unrolling), then
+  // the remaining supersteps outside the loop, so that no partially executed
+  // group reaches the loop back edge
+  int m = 0;
+  for (; m + D < nsup; m += D + 1) {
+#pragma unroll
+    for (int u = 0; u <= D; ++u)
+      superstep(m + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
   }
 #pragma unroll
-  for (int k = 0; k < K; ++k) zz[clampstep(s_prev + k) * 64 + lane] = res[k];
+  for (int u = 0; u < D; ++u) {
+    if (m + u < nsup)
+      superstep(m + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
+  }
+  store(s_prev, res);
 }
 
 // Gauss-Seidel right-hand side, folded before a smoothing sweep: with the
@@ -281,36 +347,52 @@ __global__ void k_gs_rhs(Grid<T> g, const T *b, const T *z, T *out, size_t nslot
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nslot) return;
   const int n = g.nx;
-  const Skew<TR> sk{1, n, 1, n};
+  const SkewT<T, TR> sk{1, n, 1, n};
   int i, j;
   if (!sk.decode(q, i, j)) {
     out[q] = T(0);
     return;
   }
   const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
-  T v = b[q];
-  if (id >= 1 && id <= n) v -= (TR ? g.W[i + 1] : g.W[i]) * z[sk.at(id, j)];
-  if (jd >= 1 && jd <= g.ny) v -= (TR ? g.S[j + 1] : g.S[j]) * z[sk.at(i, jd)];
-  out[q] = v;
+  double v = b[q];  // FP64 arithmetic: the terms largely cancel
+  if (id >= 1 && id <= n) v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)z[sk.at(id, j)];
+  if (jd >= 1 && jd <= g.ny) v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)z[sk.at(i, jd)];
+  out[q] = T(v);
 }
 
-// Natural <-> skewed copies of a rectangle of the fine grid; the gather can
-// multiply by dh (scaled-system input).  One thread per skewed slot.
+// Natural <-> skewed copies of a rectangle of the fine grid.  The gather can
+// multiply by dh (scaled-system input) and folds the couplings to the
+// already-solved values zb just outside the rectangle's upstream sides into
+// the right-hand side (forward: E_i z_{i+1,j} past column i1, N_j z_{i,j+1}
+// past row j1; transposed: E_{i-1} z_{i-1,j} before column i0, N_{j-1}
+// z_{i,j-1} before row j0), so that the sweep runs with zero boundary
+// values.  One thread per skewed slot; padding slots get zero.
 template <typename T, bool TR>
-__global__ void k_gather_skew(Skew<TR> sk, const T *v, const T *dh, int ld, T *out, size_t nslot) {
+__global__ void k_gather_skew(Grid<T> g, SkewT<T, TR> sk, const T *v, const T *dh, const T *zb,
+                              T *out, size_t nslot) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nslot) return;
+  const int ld = g.nx;
   int i, j;
   T val = T(0);
   if (sk.decode(q, i, j)) {
     const size_t o = vidx(i, j, ld);
     val = v[o];
     if (dh) val *= dh[o];
+    if (zb) {
+      if (!TR) {
+        if (i == sk.i1 && i < g.nx) val -= g.E[i] * zb[vidx(i + 1, j, ld)];
+        if (j == sk.j1 && j < g.ny) val -= g.N[j] * zb[vidx(i, j + 1, ld)];
+      } else {
+        if (i == sk.i0 && i > 1) val -= g.E[i - 1] * zb[vidx(i - 1, j, ld)];
+        if (j == sk.j0 && j > 1) val -= g.N[j - 1] * zb[vidx(i, j - 1, ld)];
+      }
+    }
   }
   out[q] = val;
 }
 template <typename T, bool TR>
-__global__ void k_scatter_skew(Skew<TR> sk, const T *in, T *z, int ld, size_t nslot) {
+__global__ void k_scatter_skew(SkewT<T, TR> sk, const T *in, T *z, int ld, size_t nslot) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nslot) return;
   int i, j;
@@ -319,7 +401,7 @@ __global__ void k_scatter_skew(Skew<TR> sk, const T *in, T *z, int ld, size_t ns
 
 // 1/C_ij in the skewed layout of a rectangle (setup).
 template <typename T, bool TR>
-__global__ void k_diag_skew(Grid<double> g, Skew<TR> sk, T *ic, size_t nslot) {
+__global__ void k_diag_skew(Grid<double> g, SkewT<T, TR> sk, T *ic, size_t nslot) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= nslot) return;
   int i, j;
@@ -331,190 +413,238 @@ __global__ void k_diag_skew(Grid<double> g, Skew<TR> sk, T *ic, size_t nslot) {
 // lines, each line a tridiagonal solve by the Thomas algorithm without
 // pivoting (Lemma diag_dom) with factors computed at setup.
 //
-// Region r has L = n1 - h lines of length h.  Line q couples to line q-1
-// (already solved) through a coefficient constant along the line, and, in
-// the forward direction, its last node couples to the interior region.
+// Region r (0 = Y, 1 = X) has L = n1 - h lines of length h; line q couples
+// to line q-1 through a coefficient constant along the line.
 //   Y forward:  line q <-> i = n1-q, node p <-> j = p+1; previous line i+1
-//               (E_i); last node couples to (i, h+1) through N_h.
+//               (E_i); node h-1 couples to (i, h+1) in I through N_h.
 //   X forward:  line q <-> j = n1-q, node p <-> i = p+1; previous line j+1
-//               (N_j); last node couples to (h+1, j) through E_h.
+//               (N_j); node h-1 couples to (h+1, j) in I through E_h.
 //   Y transposed: line q <-> i = h+1+q, previous line i-1 (E_{i-1}); line 0
-//               couples to the corner values (h, j).
+//               couples to the corner values (h, j) through E_h.
 //   X transposed: line q <-> j = h+1+q, previous line j-1 (N_{j-1}); line 0
-//               couples to the corner values (i, h).
+//               couples to the corner values (i, h) through N_h.
+// The couplings to the already-solved regions (I, resp. C) are folded into
+// the right-hand side by k_gather_lines, which also applies the scaled-system
+// factor and writes both regions line-major with row stride hp (h rounded up
+// to a multiple of 4, padding zero), so that the kernel only sees
+//   T_q z_q = b_q - c_q z_{q-1},  z_{-1} = 0.
 // Thomas factors per line: forward elimination y_p = rhs_p d_p + m_p y_{p-1},
 // back substitution z_p = y_p + w_p z_{p+1} (d = 1/pivot, m = -sub/pivot,
-// w = -super/pivot).
+// w = -super/pivot); zero in padding, so padding nodes give y = z = 0.
 //
-// Operand access: node (q, p) of region r is element off[r] + q*sq[r] + p of
-// b / z (Y lines are gathered into a line-major buffer first, X lines are
-// rows of the natural layout), so each line is contiguous.
-//
-// One wave per region; lane l holds the EP contiguous nodes p = l*EP + e.
-// Each of the two recurrences is an affine scan: a sequential pass over the
-// lane's nodes, a DPP wave scan across the 64 lanes, and a fix-up pass.
+// One workgroup of W waves per region; thread g holds the EP contiguous
+// nodes p = g EP + e (one or two 16-byte accesses per operand).  Each
+// recurrence is an affine scan: a sequential pass over the thread's nodes, a
+// DPP scan across the wave, the wave totals combined through LDS (one
+// barrier per scan), and a fix-up pass.  The operands of D lines ahead are in flight
+// (D + 1 register buffers rotated by unrolling); line q's results are stored
+// when line q+1 starts.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct LineArgs {
-  Grid<T> g;          // fine grid
-  int h, n1;
-  const T *b[2];      // operands per region
-  const T *dh[2];     // scaled-system input factor (same indexing as b) or null
-  T *z[2];            // outputs per region
-  long long off[2], sq[2];
-  const T *znat;      // natural-layout z: coupling values of C / I
-  const T *fd[2], *fm[2], *fw[2];  // factors [region 0 = Y, 1 = X], (lines x h)
+  Grid<T> g;          // fine grid (line couplings)
+  int h, n1, hp;
+  const T *b[2];      // gathered right-hand sides [region], line-major, stride hp
+  T *z[2];            // results [region], same layout
+  const T *fd[2], *fm[2], *fw[2];  // factors [region], same layout
   const int *gate;
 };
 
-// Operands of one line held in registers (raw loads).
 template <typename T, int EP>
-struct LineBuf {
-  T b[EP], d[EP], m[EP], w[EP], s[EP];
-  T zc;  // value of the already-solved node the line's last (forward) node couples to
+BLP_DEV void load_ep(const T *p, T (&x)[EP]) {
+  if constexpr (EP == 1) {
+    x[0] = p[0];
+  } else {
+    constexpr int VW = 16 / (int)sizeof(T) < EP ? 16 / (int)sizeof(T) : EP;
+    typedef T V __attribute__((ext_vector_type(VW)));
+#pragma unroll
+    for (int k = 0; k < EP / VW; ++k) {
+      const V v = reinterpret_cast<const V *>(p)[k];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) x[k * VW + e] = v[e];
+    }
+  }
+}
+template <typename T, int EP>
+BLP_DEV void store_ep(T *p, const T (&x)[EP]) {
+  if constexpr (EP == 1) {
+    p[0] = x[0];
+  } else {
+    constexpr int VW = 16 / (int)sizeof(T) < EP ? 16 / (int)sizeof(T) : EP;
+    typedef T V __attribute__((ext_vector_type(VW)));
+#pragma unroll
+    for (int k = 0; k < EP / VW; ++k) {
+      V v;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) v[e] = x[k * VW + e];
+      reinterpret_cast<V *>(p)[k] = v;
+    }
+  }
+}
+
+template <typename T, int EP>
+struct LineOps {
+  T b[EP], d[EP], m[EP], w[EP];
+  T c;  // coupling to the previous line
 };
 
-template <typename T, bool TR, int EP>
-BLP_DEV void line_load(const LineArgs<T> &a, int r, int q, int lane, LineBuf<T, EP> &B) {
-  const int h = a.h, n1 = a.n1;
-  const int line = TR ? h + 1 + q : n1 - q;
-  const T *fd = a.fd[r], *fm = a.fm[r], *fw = a.fw[r];
-  const long long lb = a.off[r] + (long long)q * a.sq[r];
-#pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    int p = lane * EP + e;
-    p = p < h ? p : h - 1;  // clamp: loads stay in bounds, values are masked later
-    B.b[e] = a.b[r][lb + p];
-    if (a.dh[r]) B.s[e] = a.dh[r][lb + p];
-    const size_t f = (size_t)q * h + p;
-    B.d[e] = fd[f];
-    B.m[e] = fm[f];
-    B.w[e] = fw[f];
-  }
-  if (!TR) B.zc = r == 0 ? a.znat[vidx(line, h + 1, n1)] : a.znat[vidx(h + 1, line, n1)];
-}
-
-template <typename T, bool TR, int EP>
-BLP_DEV void line_solve(const LineArgs<T> &a, int r, int q, int lane,
-                        const LineBuf<T, EP> &B, T (&zprev)[EP]) {
-  const int h = a.h, n1 = a.n1;
-  const Grid<T> &g = a.g;
-  const int line = TR ? h + 1 + q : n1 - q;
-  T cprev;  // coupling to the previous line (constant along the line)
-  if (r == 0) cprev = TR ? g.E[line - 1] : g.E[line];
-  else cprev = TR ? g.N[line - 1] : g.N[line];
-  T clast = T(0);  // coupling of the last node to the interior region (forward)
-  if (!TR) clast = r == 0 ? g.N[h] : g.E[h];
-  T av[EP], mv[EP], y[EP], wv[EP];
-  T A = T(0), M = T(1);
-#pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    const int p = lane * EP + e;
-    const bool on = p < h;
-    T rhs = B.b[e];
-    if (a.dh[r]) rhs *= B.s[e];
-    rhs -= cprev * zprev[e];
-    if (!TR && p == h - 1) rhs -= clast * B.zc;
-    av[e] = on ? rhs * B.d[e] : T(0);
-    mv[e] = on ? B.m[e] : T(0);
-    wv[e] = on ? B.w[e] : T(0);
-    A = av[e] + mv[e] * A;
-    M = mv[e] * M;
-  }
-  scan_affine_up(A, M);
-  T x = dpp_mov<0x138>(T(0), A);  // value before this lane's chunk
-#pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    x = av[e] + mv[e] * x;
-    y[e] = x;
-  }
-  A = T(0);
-  M = T(1);
-#pragma unroll
-  for (int e = EP - 1; e >= 0; --e) {
-    A = y[e] + wv[e] * A;
-    M = wv[e] * M;
-  }
-  scan_affine_down(A, M, lane);
-  T zn = dpp_mov<0x130>(T(0), A);  // value just after this lane's chunk
-#pragma unroll
-  for (int e = EP - 1; e >= 0; --e) {
-    zn = y[e] + wv[e] * zn;
-    zprev[e] = zn;
-  }
-}
-
-template <typename T, int EP>
-BLP_DEV void line_store(const LineArgs<T> &a, int r, int q, int lane, const T (&zl)[EP]) {
-  const long long lb = a.off[r] + (long long)q * a.sq[r];
-#pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    const int p = lane * EP + e;
-    if (p < a.h) a.z[r][lb + p] = zl[e];
-  }
-}
-
-// One wave per region (block 0: Y, block 1: X).  The operands of line q+1
-// are loaded while line q is solved (two register buffers, alternating), and
-// line q's results are stored when line q+1 starts: the wave both loads and
-// stores, so it can only wait for all of its outstanding memory operations at
-// once, and this order makes them all a full line old at every wait.
-template <typename T, bool TR, int EP>
-__global__ __launch_bounds__(64) void k_lines(LineArgs<T> a) {
+template <typename T, bool TR, int EP, int W, int D>
+__global__ __launch_bounds__(64 * W) void k_lines(LineArgs<T> a) {
   if (a.gate && *a.gate) return;
+  // wave totals of the forward and of the backward scan (separate, so that
+  // one barrier per scan orders every write after all reads of the previous
+  // use)
+  __shared__ T fwA[W], fwM[W], bwA[W], bwM[W];
   const int r = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int h = a.h, L = a.n1 - h;
-  T zprev[EP];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int h = a.h, hp = a.hp, L = a.n1 - h;
+  const Grid<T> &g = a.g;
+  // this thread's nodes; threads past the line read node 0 and are masked
+  const bool act = tid * EP < hp;
+  const size_t toff = act ? (size_t)tid * EP : 0;
+  const T *__restrict__ bp = a.b[r] + toff;
+  const T *__restrict__ dp = a.fd[r] + toff;
+  const T *__restrict__ mp = a.fm[r] + toff;
+  const T *__restrict__ wp = a.fw[r] + toff;
+  T *__restrict__ zp = a.z[r] + toff;
+  const T *cc = r == 0 ? g.E : g.N;  // previous-line coupling table
+
+  auto load = [&](int q, LineOps<T, EP> &B) {
+    const int qq = q < L ? q : L - 1;  // loads past the last line stay in bounds
+    const size_t o = (size_t)qq * hp;
+    load_ep<T, EP>(bp + o, B.b);
+    load_ep<T, EP>(dp + o, B.d);
+    load_ep<T, EP>(mp + o, B.m);
+    load_ep<T, EP>(wp + o, B.w);
+    const int line = TR ? h + 1 + qq : a.n1 - qq;
+    B.c = qq == 0 ? T(0) : (TR ? cc[line - 1] : cc[line]);
+  };
+  T zl[EP];  // results of the latest line (the next line's coupling values)
 #pragma unroll
-  for (int e = 0; e < EP; ++e) {
-    const int p = lane * EP + e;
-    zprev[e] = T(0);
-    // transposed: the first line couples to the corner region's edge
-    if (TR && p < h) zprev[e] = r == 0 ? a.znat[vidx(h, p + 1, a.n1)] : a.znat[vidx(p + 1, h, a.n1)];
-  }
-  LineBuf<T, EP> A_, B_;
-  line_load<T, TR, EP>(a, r, 0, lane, A_);
-  for (int q = 0; q < L; q += 2) {
-    if (q > 0) line_store<T, EP>(a, r, q - 1, lane, zprev);
-    if (q + 1 < L) line_load<T, TR, EP>(a, r, q + 1, lane, B_);
-    line_solve<T, TR, EP>(a, r, q, lane, A_, zprev);
-    if (q + 1 >= L) {
-      line_store<T, EP>(a, r, q, lane, zprev);
-      break;
+  for (int e = 0; e < EP; ++e) zl[e] = T(0);
+  int q_prev = -1;
+
+  auto solve = [&](int q, const LineOps<T, EP> &B) {
+    if (q_prev >= 0 && act) store_ep<T, EP>(zp + (size_t)q_prev * hp, zl);
+    T av[EP], y[EP];
+    T A = T(0), M = T(1);
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      av[e] = act ? (B.b[e] - B.c * zl[e]) * B.d[e] : T(0);
+      const T m = act ? B.m[e] : T(0);
+      A = av[e] + m * A;
+      M = m * M;
     }
-    line_store<T, EP>(a, r, q, lane, zprev);
-    if (q + 2 < L) line_load<T, TR, EP>(a, r, q + 2, lane, A_);
-    line_solve<T, TR, EP>(a, r, q + 1, lane, B_, zprev);
-    if (q + 2 >= L) line_store<T, EP>(a, r, q + 1, lane, zprev);
+    scan_affine_up(A, M);
+    T xin = dpp_mov<0x138>(T(0), A), xm = dpp_mov<0x138>(T(1), M);  // exclusive prefix
+    if constexpr (W > 1) {
+      if (lane == 63) {
+        fwA[wv] = A;
+        fwM[wv] = M;
+      }
+      lds_barrier();
+      T x0 = T(0);
+      for (int v = 0; v < wv; ++v) x0 = fwA[v] + fwM[v] * x0;
+      xin = xin + xm * x0;
+    }
+    T x = xin;
+#pragma unroll
+    for (int e = 0; e < EP; ++e) {
+      x = av[e] + (act ? B.m[e] : T(0)) * x;
+      y[e] = x;
+    }
+    A = T(0);
+    M = T(1);
+#pragma unroll
+    for (int e = EP - 1; e >= 0; --e) {
+      const T w = act ? B.w[e] : T(0);
+      A = y[e] + w * A;
+      M = w * M;
+    }
+    scan_affine_down(A, M, lane);
+    T zin = dpp_mov<0x130>(T(0), A), zm = dpp_mov<0x130>(T(1), M);  // exclusive suffix
+    if constexpr (W > 1) {
+      if (lane == 0) {
+        bwA[wv] = A;
+        bwM[wv] = M;
+      }
+      lds_barrier();
+      T zr = T(0);
+      for (int v = W - 1; v > wv; --v) zr = bwA[v] + bwM[v] * zr;
+      zin = zin + zm * zr;
+    }
+    T zn = zin;
+#pragma unroll
+    for (int e = EP - 1; e >= 0; --e) {
+      zn = y[e] + (act ? B.w[e] : T(0)) * zn;
+      zl[e] = zn;
+    }
+    q_prev = q;
+  };
+
+  LineOps<T, EP> buf[D + 1];
+#pragma unroll
+  for (int u = 0; u < D; ++u) load(u, buf[u]);
+  int q = 0;
+  for (; q + D < L; q += D + 1) {
+#pragma unroll
+    for (int u = 0; u <= D; ++u) {
+      load(q + u + D, buf[(u + D) % (D + 1)]);
+      solve(q + u, buf[u]);
+    }
   }
+#pragma unroll
+  for (int u = 0; u < D; ++u) {
+    if (q + u < L) {
+      load(q + u + D, buf[(u + D) % (D + 1)]);
+      solve(q + u, buf[u]);
+    }
+  }
+  if (act) store_ep<T, EP>(zp + (size_t)q_prev * hp, zl);
 }
 
-// Y-region lines <-> line-major buffer: element (q, p) <-> (i(q), p+1),
-// i(q) = n1-q (forward) or h+1+q (transposed); the gather multiplies by dh.
+// Natural layout -> line-major buffers of both edge regions (blockIdx.z =
+// region), scaled by dh, with the couplings to already-solved regions folded
+// in (see above); padding nodes p in [h, hp) get zero.
 template <typename T, bool TR>
-__global__ void k_gather_lines(const T *v, const T *dh, int h, int n1, T *out) {
+__global__ void k_gather_lines(Grid<T> g, const T *v, const T *dh, const T *z, int h, int n1,
+                               int hp, T *outY, T *outX) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  if (p >= h) return;
-  const int i = TR ? h + 1 + q : n1 - q;
-  const size_t o = vidx(i, p + 1, n1);
-  T val = v[o];
-  if (dh) val *= dh[o];
-  out[(size_t)q * h + p] = val;
+  const int q = blockIdx.y, r = blockIdx.z;
+  if (p >= hp) return;
+  T *out = r == 0 ? outY : outX;
+  const size_t o = (size_t)q * hp + p;
+  if (p >= h) {
+    out[o] = T(0);
+    return;
+  }
+  const int line = TR ? h + 1 + q : n1 - q;
+  const int i = r == 0 ? line : p + 1, j = r == 0 ? p + 1 : line;
+  const size_t k = vidx(i, j, n1);
+  T val = v[k];
+  if (dh) val *= dh[k];
+  if (!TR) {
+    if (p == h - 1) val -= r == 0 ? g.N[h] * z[vidx(i, h + 1, n1)] : g.E[h] * z[vidx(h + 1, j, n1)];
+  } else if (q == 0) {
+    val -= r == 0 ? g.E[h] * z[vidx(h, j, n1)] : g.N[h] * z[vidx(i, h, n1)];
+  }
+  out[o] = val;
 }
 template <typename T, bool TR>
-__global__ void k_scatter_lines(const T *in, int h, int n1, T *z) {
+__global__ void k_scatter_lines(const T *inY, const T *inX, int h, int n1, int hp, T *z) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
+  const int q = blockIdx.y, r = blockIdx.z;
   if (p >= h) return;
-  const int i = TR ? h + 1 + q : n1 - q;
-  z[vidx(i, p + 1, n1)] = in[(size_t)q * h + p];
+  const int line = TR ? h + 1 + q : n1 - q;
+  const int i = r == 0 ? line : p + 1, j = r == 0 ? p + 1 : line;
+  z[vidx(i, j, n1)] = (r == 0 ? inY : inX)[(size_t)q * hp + p];
 }
 
-// Thomas factorisation of every line (setup).  One thread per line.
+// Thomas factorisation of every line (setup), row stride hp; the padding
+// stays as allocated (zero).  One thread per line.
 template <typename T>
-__global__ void k_line_factor(Grid<T> g, int h, int n1, int region, int tr, T *fd,
+__global__ void k_line_factor(Grid<T> g, int h, int n1, int hp, int region, int tr, T *fd,
                               T *fm, T *fw) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int L = n1 - h;
@@ -535,7 +665,7 @@ __global__ void k_line_factor(Grid<T> g, int h, int n1, int region, int tr, T *f
     const T den = g.C(i, j) - sub * cp;
     const T inv = T(1) / den;
     cp = sup * inv;
-    const size_t f = (size_t)q * h + p;
+    const size_t f = (size_t)q * hp + p;
     fd[f] = inv;
     fm[f] = -sub * inv;
     fw[f] = -cp;
@@ -573,20 +703,26 @@ struct MgLevel {
   size_t nslot;
 };
 
-template <bool TR>
-BLP_DEV Skew<TR> level_skew(int n) { return Skew<TR>{1, n, 1, n}; }
-
-// (A z)_ij (forward) or (A^T z)_ij (transposed) on a level, z skewed.
 template <typename T, bool TR>
-BLP_DEV T level_apply(const Grid<T> &g, const Skew<TR> &sk, const T *z, int i, int j) {
+BLP_DEV SkewT<T, TR> level_skew(int n) { return SkewT<T, TR>{1, n, 1, n}; }
+
+// (A z)_ij (forward) or (A^T z)_ij (transposed) on a level, z skewed, in
+// FP64 arithmetic whatever the storage precision (residuals of the FP32
+// cycle would otherwise lose the digits that cancel in b - A z).
+template <typename T, bool TR>
+BLP_DEV double level_apply(const Grid<T> &g, const SkewT<T, TR> &sk, const T *z, int i, int j) {
   const int n = g.nx;
-  const T zc = z[sk.at(i, j)];
-  const T zw = i > 1 ? z[sk.at(i - 1, j)] : T(0);
-  const T ze = i < n ? z[sk.at(i + 1, j)] : T(0);
-  const T zs = j > 1 ? z[sk.at(i, j - 1)] : T(0);
-  const T zn = j < g.ny ? z[sk.at(i, j + 1)] : T(0);
-  if (!TR) return g.C(i, j) * zc + g.W[i] * zw + g.E[i] * ze + g.S[j] * zs + g.N[j] * zn;
-  return g.C(i, j) * zc + g.E[i - 1] * zw + g.W[i + 1] * ze + g.N[j - 1] * zs + g.S[j + 1] * zn;
+  const double zc = z[sk.at(i, j)];
+  const double zw = i > 1 ? (double)z[sk.at(i - 1, j)] : 0.0;
+  const double ze = i < n ? (double)z[sk.at(i + 1, j)] : 0.0;
+  const double zs = j > 1 ? (double)z[sk.at(i, j - 1)] : 0.0;
+  const double zn = j < g.ny ? (double)z[sk.at(i, j + 1)] : 0.0;
+  const double C = (double)g.Dx[i] + (double)g.Dy[j] + (double)g.rr(i, j);
+  if (!TR)
+    return C * zc + (double)g.W[i] * zw + (double)g.E[i] * ze + (double)g.S[j] * zs +
+           (double)g.N[j] * zn;
+  return C * zc + (double)g.E[i - 1] * zw + (double)g.W[i + 1] * ze + (double)g.N[j - 1] * zs +
+         (double)g.S[j + 1] * zn;
 }
 
 // t = b - A z (forward) or b - A^T z (transposed) on a level.
@@ -595,10 +731,10 @@ __global__ void k_mg_resid(MgLevel<T> L, const int *gate) {
   if (gate && *gate) return;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.nslot) return;
-  const Skew<TR> sk = level_skew<TR>(L.g.nx);
+  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
   int i, j;
   if (!sk.decode(q, i, j)) return;
-  L.t[q] = L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j);
+  L.t[q] = T((double)L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j));
 }
 
 // One-dimensional transfer weight from fine node i to coarse node k
@@ -618,7 +754,7 @@ __global__ void k_mg_restrict(MgLevel<T> F, MgLevel<T> Cc, const int *gate) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Cc.nslot) return;
   const int nc = Cc.g.nx, nf = F.g.nx;
-  const Skew<TR> skc = level_skew<TR>(nc), skf = level_skew<TR>(nf);
+  const SkewT<T, TR> skc = level_skew<T, TR>(nc), skf = level_skew<T, TR>(nf);
   int k, m;
   if (!skc.decode(q, k, m)) return;
   T s = T(0);
@@ -644,7 +780,7 @@ __global__ void k_mg_prolong(MgLevel<T> F, MgLevel<T> Cc, const int *gate) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= F.nslot) return;
   const int nc = Cc.g.nx, nf = F.g.nx;
-  const Skew<TR> skc = level_skew<TR>(nc), skf = level_skew<TR>(nf);
+  const SkewT<T, TR> skc = level_skew<T, TR>(nc), skf = level_skew<T, TR>(nf);
   int i, j;
   if (!skf.decode(q, i, j)) return;
   int kx[2], ky[2];
@@ -681,7 +817,7 @@ __global__ void k_mg_coarsest(MgLevel<T> L, int zero_init, const int *gate) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const Grid<T> &g = L.g;
   const int n = g.nx;
-  const Skew<TR> sk = level_skew<TR>(n);
+  const SkewT<T, TR> sk = level_skew<T, TR>(n);
   if (zero_init)
     for (int j = 1; j <= g.ny; ++j)
       for (int i = 1; i <= n; ++i) L.z[sk.at(i, j)] = T(0);
@@ -713,24 +849,26 @@ __global__ __launch_bounds__(256) void k_mg_norm(MgLevel<T> L, MgCtrl *ctrl, int
   __shared__ double sh[16];
   __shared__ bool last;
   if (ctrl->gate) return;  // uniform across the grid
-  const Skew<TR> sk = level_skew<TR>(L.g.nx);
+  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
   double acc = 0.0;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < L.nslot;
        q += (size_t)gridDim.x * blockDim.x) {
     int i, j;
     if (!sk.decode(q, i, j)) continue;
     double v = (double)L.b[q];
-    if (mode == 1) v -= (double)level_apply<T, TR>(L.g, sk, L.z, i, j);
+    if (mode == 1) v -= level_apply<T, TR>(L.g, sk, L.z, i, j);
     if (!TR) v *= (double)L.hbx[i] * (double)L.hby[j];
     acc += v * v;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+  if (threadIdx.x == 0) publish(&partials[blockIdx.x], acc);
   if (!arrive_last(&ctrl->counter, &last)) return;
+  // last block: fixed-order sum of the partials (deterministic)
+  double s = 0.0;
+  for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += blockDim.x) s += collect(&partials[b2]);
+  s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b2 = 0; b2 < (int)gridDim.x; ++b2) s += partials[b2];
-    ctrl->counter = 0;
+    reset_counter(&ctrl->counter);
     if (mode == 0) {
       ctrl->bnorm2 = s;
       if (s == 0.0) ctrl->gate = 1;  // zero right-hand side: z = 0, no cycle
@@ -739,7 +877,6 @@ __global__ __launch_bounds__(256) void k_mg_norm(MgLevel<T> L, MgCtrl *ctrl, int
       ctrl->res2 = s;
       if (s <= ctrl->rtol2 * ctrl->bnorm2 || ctrl->cycles >= ctrl->maxcyc) ctrl->gate = 1;
     }
-    __threadfence();
   }
 }
 
@@ -773,7 +910,7 @@ __global__ void k_corner_rhs(Grid<T> g, int h, int n1, const T *b, const T *dh,
     if (i == h) v -= g.E[h] * z[vidx(h + 1, j, n1)];
     if (j == h) v -= g.N[h] * z[vidx(i, h + 1, n1)];
   }
-  b0[level_skew<TR>(h).at(i, j)] = v;
+  b0[level_skew<T, TR>(h).at(i, j)] = v;
 }
 
 template <typename T, bool TR>
@@ -781,7 +918,7 @@ __global__ void k_corner_copy(int h, int n1, const T *z0, T *z) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
   const int j = blockIdx.y + 1;
   if (i > h) return;
-  z[vidx(i, j, n1)] = z0[level_skew<TR>(h).at(i, j)];
+  z[vidx(i, j, n1)] = z0[level_skew<T, TR>(h).at(i, j)];
 }
 
 // Sample a nodal field at every f-th node: rc(k, m) = rf(f k, f m), natural

@@ -78,7 +78,13 @@ def test_operator_parity(N, eps):
         assert err <= 1e-14, (name, err)
 
 
-@pytest.mark.parametrize("N,eps", CASES)
+# Larger meshes cover every line-kernel shape (threads holding 1, 2 and 4
+# nodes, 1 to 4 waves, edge lengths h = N/2 that are not multiples of 4) and
+# sweeps over several bands with ragged last bands.
+PREC_CASES = CASES + [(202, 1e-6), (600, 1e-6), (1024, 1e-6), (1100, 1e-8)]
+
+
+@pytest.mark.parametrize("N,eps", PREC_CASES)
 def test_preconditioner_parity_fixed_cycles(N, eps):
     say("preconditioner parity N=%d eps=%g" % (N, eps))
     inst = inputs.plain(N, eps, seed=N + 1)
@@ -89,7 +95,17 @@ def test_preconditioner_parity_fixed_cycles(N, eps):
         ref = op.M_inv(b, transpose=tr, mg_fixed=2)
         z = host(gp.apply(name, dev(b)))
         err = np.abs(z - ref).max() / np.abs(ref).max()
+        say("  %s rel err %.3e" % (name, err))
         assert err <= 1e-11, (name, err)
+    # The FP32 preconditioner (mixed mode) against the same FP64 map.  The
+    # corner cycles amplify rounding: the FP64 comparison above shows up to
+    # ~3e4 units of 2^-53 at N = 1024, so FP32 (2^-24) may differ by up to
+    # ~3e4 * 6e-8 = 2e-3 there; the edge and interior regions stay near 1e-6.
+    ref = op.M_inv(b, mg_fixed=2)
+    z = host(gp.apply("MINV32", dev(b)))
+    err = np.abs(z - ref).max() / np.abs(ref).max()
+    say("  MINV32 rel err %.3e" % err)
+    assert err <= 2e-3, ("MINV32", err)
 
 
 @pytest.mark.parametrize("N,eps", [(64, 1e-2), (130, 1e-4), (256, 1e-6)])
