@@ -214,12 +214,17 @@ class Problem:
         self.last_cycles = cyc.value
         return y
 
-    def sine_rhs(self, a):
+    def sine_rhs(self, a, out=None):
+        """F from sine coefficients a (L x K); with out, written into that
+        contiguous float64 device vector of length (N-1)^2."""
         a = _f64(a)
         L, K = a.shape
-        F = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device)
-        _check(lib().blp_sine_rhs(self._h, K, L, a.ctypes.data_as(_dp), C.c_void_p(F.data_ptr())),
-               "blp_sine_rhs")
+        F = self.torch.empty(self.n, dtype=self.torch.float64, device=self.device) if out is None \
+            else out
+        if F.numel() != self.n:
+            raise ValueError("out must hold (N-1)^2 values")
+        _check(lib().blp_sine_rhs(self._h, K, L, a.ctypes.data_as(_dp),
+                                  C.c_void_p(self._vec(F).data_ptr())), "blp_sine_rhs")
         return F
 
     def sine_project(self, w, K, L):
