@@ -8,6 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <memory>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -68,9 +71,9 @@ struct LevelDev {
   T *W, *E, *Dx, *S, *N, *Dy, *r, rc;
   T *ic[2];      // skewed 1/C for the forward (0) and transposed (1) cycle
   T *hbx, *hby, *wlx, *wrx, *wly, *wry;
-  T *z, *b, *t;  // skewed work vectors
   Grid<T> grid() const { return Grid<T>{n, n, W, E, Dx, S, N, Dy, r, n, rc}; }
-  MgLevel<T> view(bool tr) const {
+  // the level with one system's work vectors (skewed z, b, t)
+  MgLevel<T> view(bool tr, T *z, T *b, T *t) const {
     return MgLevel<T>{grid(), ic[tr ? 1 : 0], hbx, hby, wlx, wrx, wly, wry, z, b, t, nslot};
   }
 };
@@ -81,10 +84,10 @@ struct FineDev {
   T *dh;          // sqrt(C), natural layout (scaled-system input)
   T *fac[4][3];   // line factors [Y fwd, X fwd, Y tr, X tr] x [d, m, w]
   T *icI[2];      // skewed 1/C of the interior region, per direction
-  T *bI, *zI;     // skewed work vectors of the interior region
-  T *bL[2], *zL[2];  // line-major work vectors of the edge regions [Y, X], stride hp
-  size_t nslotI;
+  size_t nslotI;  // skewed size of the interior region
 };
+
+struct Batch;
 
 }  // namespace
 
@@ -103,23 +106,13 @@ struct blp_problem {
   blp_prec_opts popts{0, 1e-3, 20};
   std::vector<LevelDev<double>> l64;
   std::vector<LevelDev<float>> l32;
-  MgCtrl *ctrl = nullptr;
-  MgCtrl *ctrl_h = nullptr;       // pinned host mirror
-  KrylovStatus *st = nullptr;
-  KrylovStatus *st_h = nullptr;   // pinned host mirror
-  double *mg_partials = nullptr;
-  double *partials = nullptr;     // Krylov reduction partials
-  size_t partials_len = 0;
-  // Krylov workspace (sized at first solve, grown on demand)
-  int ws_m = 0;
-  int ws_prec = -1;
-  void *V = nullptr, *Z = nullptr;
-  double *w = nullptr, *ks = nullptr;
+  // solves run as a batch of systems over this problem (rebuilt when the
+  // number of right-hand sides changes); FP32 staging of the test hook
+  Batch *own = nullptr;
+  int own_S = 0;
   float *tmp32a = nullptr, *tmp32b = nullptr;
   std::vector<void *> allocs;
   long long bytes = 0;
-  std::vector<void *> ws_allocs;
-  long long ws_bytes = 0;
   // kernel timing (blp_timing): event pairs per class, resolved on demand
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -138,11 +131,11 @@ struct blp_problem {
   }
 
   template <typename T>
-  int alloc(T **p, size_t count, bool ws = false) {
+  int alloc(T **p, size_t count) {
     void *q = nullptr;
     if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return BLP_E_NOMEM;
-    (ws ? ws_allocs : allocs).push_back(q);
-    (ws ? ws_bytes : bytes) += (long long)(count * sizeof(T));
+    allocs.push_back(q);
+    bytes += (long long)(count * sizeof(T));
     *p = (T *)q;
     return BLP_OK;
   }
@@ -172,7 +165,7 @@ struct KScope {
   double bytes;
   hipEvent_t a = nullptr;
   KScope(blp_problem *p_, int c, double b) : p(p_), cls(c), bytes(b) {
-    if (p->timing && (a = p->ev_next())) (void)hipEventRecord(a, p->stream);
+    if (p && p->timing && (a = p->ev_next())) (void)hipEventRecord(a, p->stream);
   }
   void end() {
     if (!a) return;
@@ -208,6 +201,10 @@ Grid<double> fine_grid<double>(blp_problem *p) { return p->grid64(); }
 template <>
 Grid<float> fine_grid<float>(blp_problem *p) { return p->grid32(); }
 
+// Row stride of the line-major edge-region buffers: h rounded up to a
+// multiple of 4, so that every thread's nodes are 16-byte aligned.
+inline int line_stride(int h) { return (h + 3) / 4 * 4; }
+
 inline dim3 grid2d(int nx, int ny, int bx = 256) { return dim3((nx + bx - 1) / bx, ny); }
 inline unsigned blocks1d(size_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
@@ -229,209 +226,6 @@ void axis_mesh(int N, double tau, std::vector<double> &nodes, std::vector<double
   const double hl = 2.0 * tau / N, hi = 2.0 * (1.0 - tau) / N;
   for (int k = 0; k <= N; ++k) nodes[k] = k <= N / 2 ? k * hl : tau + (k - N / 2) * hi;
   for (int k = 1; k <= N; ++k) w[k] = k <= N / 2 ? hl : hi;
-}
-
-// ------------------------------------------------------------------------ //
-// Preconditioner apply                                                      //
-// ------------------------------------------------------------------------ //
-
-template <typename T, bool TR>
-void launch_sweep(blp_problem *p, const Grid<T> &g, int i0, int i1, int j0, int j1, const T *b,
-                  const T *ic, T *z, const int *gate) {
-  const int nb = (i1 - i0 + 1 + 63) / 64;
-  SweepArgs<T> a{g, i0, i1, j0, j1, b, ic, z, gate};
-  const double pts = (double)(i1 - i0 + 1) * (j1 - j0 + 1);
-  KScope ks(p, KC_SWEEP, pts * 2 * sizeof(T));
-  // superstep of K steps = 4 chunks of 16 bytes per lane; D supersteps of
-  // loads in flight (D + 1 register buffers of 2K words); more than 8 waves
-  // leave registers for D = 1 only
-  constexpr int K = 4 * kChunk<T>;
-  if (nb <= 8)
-    k_sweep<T, TR, K, 4><<<1, 64 * nb, 0, p->stream>>>(a);
-  else
-    k_sweep<T, TR, K, 1><<<1, 64 * nb, 0, p->stream>>>(a);
-}
-
-// Row stride of the line-major edge-region buffers: h rounded up to a
-// multiple of 4, so that every thread's nodes are 16-byte aligned.
-inline int line_stride(int h) { return (h + 3) / 4 * 4; }
-
-template <typename T, bool TR, int EP, int W>
-void launch_lines_k(blp_problem *p, const LineArgs<T> &a) {
-  // D lines of operands in flight: 4 EP words per line and wave, within the
-  // 63 outstanding memory operations a wave can track and its registers
-  constexpr int D = EP >= 4 ? 4 : 6;
-  k_lines<T, TR, EP, W, D><<<2, 64 * W, 0, p->stream>>>(a);
-}
-
-template <typename T, bool TR>
-void launch_lines(blp_problem *p, const T *v, const T *dh, T *z) {
-  FineDev<T> &f = fine<T>(p);
-  const int h = p->h, n1 = p->n1, hp = line_stride(h);
-  LineArgs<T> a;
-  a.g = fine_grid<T>(p);
-  a.h = h;
-  a.n1 = n1;
-  a.hp = hp;
-  const int base = TR ? 2 : 0;
-  for (int r = 0; r < 2; ++r) {
-    a.b[r] = f.bL[r];
-    a.z[r] = f.zL[r];
-    a.fd[r] = f.fac[base + r][0];
-    a.fm[r] = f.fac[base + r][1];
-    a.fw[r] = f.fac[base + r][2];
-  }
-  a.gate = nullptr;
-  const dim3 gl((hp + 255) / 256, n1 - h, 2);
-  {
-    KScope ks(p, KC_LAYOUT, 0.0);
-    k_gather_lines<T, TR><<<gl, 256, 0, p->stream>>>(a.g, v, dh, z, h, n1, hp, f.bL[0], f.bL[1]);
-  }
-  KScope ks(p, KC_LINES, 2.0 * (n1 - h) * h * 4 * sizeof(T));
-  // threads hold EP contiguous nodes; up to 4 waves per region
-  if (hp <= 64)
-    launch_lines_k<T, TR, 1, 1>(p, a);
-  else if (hp <= 128)
-    launch_lines_k<T, TR, 1, 2>(p, a);
-  else if (hp <= 256)
-    launch_lines_k<T, TR, 1, 4>(p, a);
-  else if (hp <= 512)
-    launch_lines_k<T, TR, 2, 4>(p, a);
-  else
-    launch_lines_k<T, TR, 4, 4>(p, a);
-  ks.end();
-  KScope ks2(p, KC_LAYOUT, 0.0);
-  k_scatter_lines<T, TR><<<gl, 256, 0, p->stream>>>(f.zL[0], f.zL[1], h, n1, hp, z);
-}
-
-// Interior region: gather into the skewed layout, sweep, scatter back.
-template <typename T, bool TR>
-void interior_solve(blp_problem *p, const T *v, const T *dh, T *z) {
-  FineDev<T> &f = fine<T>(p);
-  const int h = p->h, n1 = p->n1;
-  const SkewT<T, TR> sk{h + 1, n1, h + 1, n1};
-  const unsigned nb = blocks1d(f.nslotI);
-  {
-    KScope ks(p, KC_LAYOUT, 0.0);
-    k_gather_skew<T, TR><<<nb, 256, 0, p->stream>>>(fine_grid<T>(p), sk, v, dh, z, f.bI, f.nslotI);
-  }
-  launch_sweep<T, TR>(p, fine_grid<T>(p), h + 1, n1, h + 1, n1, f.bI, f.icI[TR ? 1 : 0], f.zI,
-                      nullptr);
-  KScope ks(p, KC_LAYOUT, 0.0);
-  k_scatter_skew<T, TR><<<nb, 256, 0, p->stream>>>(sk, f.zI, z, n1, f.nslotI);
-}
-
-// Gauss-Seidel rhs of a level into its t vector (t is free at that point).
-template <typename T, bool TR>
-void gs_rhs(blp_problem *p, const LevelDev<T> &lv, const int *gate) {
-  KScope ks(p, KC_GSRHS, (double)lv.n * lv.n * 3 * sizeof(T));
-  k_gs_rhs<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.grid(), lv.b, lv.z, lv.t, lv.nslot,
-                                                             gate);
-}
-
-// One V(1,1) cycle on level l (Sec. 3.2).  zero_init: the level iterate is
-// zero on entry, so the pre-smoothing sweep is the plain triangular solve.
-template <typename T, bool TR>
-void vcycle(blp_problem *p, int l, bool zero_init, const int *gate) {
-  std::vector<LevelDev<T>> &L = levels<T>(p);
-  const LevelDev<T> &lv = L[l];
-  const int n = lv.n;
-  if (l == (int)L.size() - 1) {
-    KScope ks(p, KC_MG, (double)n * n * 2 * sizeof(T));
-    k_mg_coarsest<T, TR><<<1, 64, 0, p->stream>>>(lv.view(TR), zero_init ? 1 : 0, gate);
-    return;
-  }
-  const LevelDev<T> &cv = L[l + 1];
-  const T *ic = lv.ic[TR ? 1 : 0];
-  if (zero_init) {
-    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.b, ic, lv.z, gate);
-  } else {
-    gs_rhs<T, TR>(p, lv, gate);
-    launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, gate);
-  }
-  {
-    KScope ks(p, KC_MG, (double)n * n * 3 * sizeof(T));
-    k_mg_resid<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), gate);
-  }
-  {
-    KScope ks(p, KC_MG, ((double)n * n + (double)cv.n * cv.n) * sizeof(T));
-    k_mg_restrict<T, TR><<<blocks1d(cv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
-  }
-  vcycle<T, TR>(p, l + 1, true, gate);
-  {
-    KScope ks(p, KC_MG, ((double)n * n * 2 + (double)cv.n * cv.n) * sizeof(T));
-    k_mg_prolong<T, TR><<<blocks1d(lv.nslot), 256, 0, p->stream>>>(lv.view(TR), cv.view(TR), gate);
-  }
-  gs_rhs<T, TR>(p, lv, gate);
-  launch_sweep<T, TR>(p, lv.grid(), 1, n, 1, n, lv.t, ic, lv.z, gate);
-}
-
-// blocks of the corner residual-norm reduction (one partial each)
-constexpr int kMgNormBlocks = 256;
-
-// Corner solve M_CC^{-1} b_0 (level 0 b and z).  Cycles are counted in ctrl.
-template <typename T, bool TR>
-int corner_solve(blp_problem *p) {
-  std::vector<LevelDev<T>> &L = levels<T>(p);
-  const LevelDev<T> &l0 = L[0];
-  const blp_prec_opts &o = p->popts;
-  const int nblk = std::min(kMgNormBlocks, (int)blocks1d(l0.nslot));
-  if (o.mg_fixed > 0) {
-    for (int c = 0; c < o.mg_fixed; ++c) {
-      vcycle<T, TR>(p, 0, c == 0, nullptr);
-      k_mg_count<<<1, 1, 0, p->stream>>>(p->ctrl);
-    }
-    return BLP_OK;
-  }
-  const int *gate = &p->ctrl->gate;
-  k_mg_norm<T, TR><<<nblk, 256, 0, p->stream>>>(l0.view(TR), p->ctrl, 0, p->mg_partials);
-  const int first = std::min(o.mg_maxcyc, 5);
-  int enq = 0;
-  for (; enq < first; ++enq) {
-    vcycle<T, TR>(p, 0, enq == 0, gate);
-    k_mg_norm<T, TR><<<nblk, 256, 0, p->stream>>>(l0.view(TR), p->ctrl, 1, p->mg_partials);
-  }
-  while (enq < o.mg_maxcyc) {
-    HIP_TRY(hipMemcpyAsync(p->ctrl_h, p->ctrl, sizeof(MgCtrl), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    if (p->ctrl_h->gate) break;
-    vcycle<T, TR>(p, 0, false, gate);
-    k_mg_norm<T, TR><<<nblk, 256, 0, p->stream>>>(l0.view(TR), p->ctrl, 1, p->mg_partials);
-    ++enq;
-  }
-  return BLP_OK;
-}
-
-// z = M^{-1} (dh .* v) (forward) or M^{-T} (dh .* v) (transposed); dh may
-// be null (unscaled input).  All of z is written.
-template <typename T, bool TR>
-int prec_apply(blp_problem *p, const T *v, const T *dh, T *z) {
-  std::vector<LevelDev<T>> &L = levels<T>(p);
-  const Grid<T> g = fine_grid<T>(p);
-  const int h = p->h, n1 = p->n1;
-  const T rtol = (T)p->popts.mg_rtol;
-  if (!TR) {
-    interior_solve<T, false>(p, v, dh, z);
-    launch_lines<T, false>(p, v, dh, z);
-    k_corner_rhs<T, false><<<grid2d(h, h), 256, 0, p->stream>>>(g, h, n1, v, dh, z, L[0].b,
-                                                                 p->ctrl, p->popts.mg_maxcyc, rtol);
-    BLP_TRY((corner_solve<T, false>(p)));
-    k_corner_copy<T, false><<<grid2d(h, h), 256, 0, p->stream>>>(h, n1, L[0].z, z);
-  } else {
-    k_corner_rhs<T, true><<<grid2d(h, h), 256, 0, p->stream>>>(g, h, n1, v, dh, z, L[0].b,
-                                                                p->ctrl, p->popts.mg_maxcyc, rtol);
-    BLP_TRY((corner_solve<T, true>(p)));
-    k_corner_copy<T, true><<<grid2d(h, h), 256, 0, p->stream>>>(h, n1, L[0].z, z);
-    launch_lines<T, true>(p, v, dh, z);
-    interior_solve<T, true>(p, v, dh, z);
-  }
-  HIP_TRY(hipGetLastError());
-  return BLP_OK;
-}
-
-template <typename T>
-int prec_apply_dir(blp_problem *p, bool tr, const T *v, const T *dh, T *z) {
-  return tr ? prec_apply<T, true>(p, v, dh, z) : prec_apply<T, false>(p, v, dh, z);
 }
 
 // ------------------------------------------------------------------------ //
@@ -482,12 +276,9 @@ int upload_level(blp_problem *p, const LevelHost &lh, LevelDev<T> &d, const Leve
     else
       k_sample<T><<<grid2d(n, n), 256, 0, p->stream>>>(rfine_nodal, rfine_ld, 1, d.r, n);
   }
-  // skewed storage: zero-filled so that padding slots always hold finite values
+  // skewed inverse diagonals: zero in the padding slots
   BLP_TRY(zalloc(p, &d.ic[0], d.nslot));
   BLP_TRY(zalloc(p, &d.ic[1], d.nslot));
-  BLP_TRY(zalloc(p, &d.z, d.nslot));
-  BLP_TRY(zalloc(p, &d.b, d.nslot));
-  BLP_TRY(zalloc(p, &d.t, d.nslot));
   HIP_TRY(hipGetLastError());
   return BLP_OK;
 }
@@ -501,16 +292,10 @@ int build_fine_prec(blp_problem *p, FineDev<T> &f) {
   f.nslotI = skew_size<T>(m, m);
   BLP_TRY(zalloc(p, &f.icI[0], f.nslotI));
   BLP_TRY(zalloc(p, &f.icI[1], f.nslotI));
-  BLP_TRY(zalloc(p, &f.bI, f.nslotI));
-  BLP_TRY(zalloc(p, &f.zI, f.nslotI));
   const SkewT<T, false> skf{h + 1, n1, h + 1, n1};
   const SkewT<T, true> skt{h + 1, n1, h + 1, n1};
   k_diag_skew<T, false><<<blocks1d(f.nslotI), 256, 0, p->stream>>>(p->grid64(), skf, f.icI[0], f.nslotI);
   k_diag_skew<T, true><<<blocks1d(f.nslotI), 256, 0, p->stream>>>(p->grid64(), skt, f.icI[1], f.nslotI);
-  for (int r = 0; r < 2; ++r) {
-    BLP_TRY(zalloc(p, &f.bL[r], (size_t)m * line_stride(h)));
-    BLP_TRY(zalloc(p, &f.zL[r], (size_t)m * line_stride(h)));
-  }
   HIP_TRY(hipGetLastError());
   return BLP_OK;
 }
@@ -595,206 +380,95 @@ int build_preconditioner(blp_problem *p) {
     level_diag<double>(p, p->l64[l], p->l64[l]);
     level_diag<float>(p, p->l64[l], p->l32[l]);
   }
-  if (!p->ctrl) {
-    BLP_TRY(p->alloc(&p->ctrl, 1));
-    HIP_TRY(hipMemsetAsync(p->ctrl, 0, sizeof(MgCtrl), p->stream));
-    BLP_TRY(p->alloc(&p->mg_partials, kMgNormBlocks));
-  }
+  BLP_TRY(p->alloc(&p->tmp32a, p->n));
+  BLP_TRY(p->alloc(&p->tmp32b, p->n));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(p->stream));
-  return BLP_OK;
-}
-
-// ------------------------------------------------------------------------ //
-// FGMRES driver                                                             //
-// ------------------------------------------------------------------------ //
-
-int ensure_workspace(blp_problem *p, int m, int prec) {
-  if (p->ws_m >= m && p->ws_prec == prec) return BLP_OK;
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  for (void *q : p->ws_allocs) (void)hipFree(q);
-  p->ws_allocs.clear();
-  p->ws_bytes = 0;
-  const size_t n = p->n;
-  const size_t es = prec == BLP_MIXED ? sizeof(float) : sizeof(double);
-  char *V = nullptr, *Z = nullptr;
-  BLP_TRY(p->alloc(&V, (size_t)(m + 1) * n * es, true));
-  BLP_TRY(p->alloc(&Z, (size_t)m * n * es, true));
-  p->V = V;
-  p->Z = Z;
-  BLP_TRY(p->alloc(&p->w, n, true));
-  BLP_TRY(p->alloc(&p->ks, (size_t)(m + 1) * m + 2 * m + 3 * (m + 1) + m, true));
-  const size_t nblk = (n + KCHUNK - 1) / KCHUNK;
-  const size_t nstencil = (size_t)((p->n1 + 255) / 256) * ((p->n1 + 15) / 16);
-  p->partials_len = std::max(nblk * (size_t)(m + 2), std::max(nstencil, (size_t)1024));
-  BLP_TRY(p->alloc(&p->partials, p->partials_len, true));
-  BLP_TRY(p->alloc(&p->tmp32a, n, true));
-  BLP_TRY(p->alloc(&p->tmp32b, n, true));
-  p->ws_m = m;
-  p->ws_prec = prec;
   return BLP_OK;
 }
 
 constexpr int kRows = 16;  // rows per block of the stencil kernels
 
-template <bool TR, bool SCALE>
-void launch_residual(blp_problem *p, const double *F, const double *u, double *r) {
-  KScope ks(p, KC_SPMV, (double)p->n * 3 * sizeof(double));
-  dim3 gr((p->n1 + 255) / 256, (p->n1 + kRows - 1) / kRows);
-  k_stencil<double, double, TR, SCALE, true><<<gr, 256, 0, p->stream>>>(p->grid64(), u, r, F, kRows,
-                                                                         p->partials, p->st);
-}
+}  // namespace
 
-template <typename TX, bool TR, bool SCALE>
-void launch_spmv(blp_problem *p, const TX *x, double *y) {
-  KScope ks(p, KC_SPMV, (double)p->n * (sizeof(TX) + sizeof(double)));
-  dim3 gr((p->n1 + 255) / 256, (p->n1 + kRows - 1) / kRows);
-  k_stencil<TX, double, TR, SCALE, false><<<gr, 256, 0, p->stream>>>(p->grid64(), x, y, nullptr,
-                                                                      kRows, nullptr, nullptr);
-}
+namespace {
+#include "engine.h"
 
-int read_status(blp_problem *p) {
-  HIP_TRY(hipMemcpyAsync(p->st_h, p->st, sizeof(KrylovStatus), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->ctrl_h, p->ctrl, sizeof(MgCtrl), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
+// The problem's own batch of nrhs systems (created on first use).
+int own_batch(blp_problem *p, int nrhs, Batch **out) {
+  if (!p->prec_ready) return BLP_E_STATE;
+  if (!p->own || p->own_S != nrhs) {
+    delete p->own;
+    p->own = nullptr;
+    p->own_S = 0;
+    std::vector<blp_problem *> probs(nrhs, p);
+    std::unique_ptr<Batch> B;
+    BLP_TRY(batch_create(p->stream, probs.data(), nrhs, B));
+    B->timer = p;
+    p->own = B.release();
+    p->own_S = nrhs;
+  }
+  *out = p->own;
   return BLP_OK;
-}
-
-struct CycleStats {
-  long total = 0;
-  int mn = 1 << 30, mx = 0, applies = 0;
-  void add(int c) {
-    total += c;
-    mn = std::min(mn, c);
-    mx = std::max(mx, c);
-    ++applies;
-  }
-};
-
-// Right-preconditioned FGMRES(m) from u = 0 (Saad).  In scaled mode the
-// Krylov space is that of D^{-1/2} A D^{-1/2}; the preconditioned vectors Z
-// are kept in the unscaled variables, so u += Z y needs no rescaling.
-// TV = double: FP64 throughout.  TV = float (mixed): V, Z and the
-// preconditioner in FP32, SpMV arithmetic, Hessenberg/Givens, u and the
-// restart-boundary true residuals in FP64; each restart cycle reduces the
-// residual by at most inner_rtol before an FP64 residual is taken.
-template <typename TV, bool TR, bool SCALE>
-int fgmres(blp_problem *p, const double *F, double *u, const blp_solve_opts *o,
-           blp_solve_info *info, double *hist) {
-  const size_t n = p->n;
-  const int m = o->restart;
-  const double inner_rtol = std::is_same<TV, float>::value ? 1e-4 : 0.0;
-  TV *V = (TV *)p->V, *Z = (TV *)p->Z;
-  FineDev<TV> &f = fine<TV>(p);
-  const TV *dh = SCALE ? f.dh : nullptr;
-  KOffsets ko{m};
-  CycleStats cs;
-  auto t0 = std::chrono::steady_clock::now();
-
-  k_norm<SCALE><<<256, 256, 0, p->stream>>>(p->grid64(), F, p->partials, p->st);
-  BLP_TRY(read_status(p));
-  const double nF = p->st_h->beta;
-  if (!std::isfinite(nF)) return BLP_E_NUMERIC;
-  const double target = o->absolute ? o->tol : o->tol * nF;
-  HIP_TRY(hipMemsetAsync(u, 0, n * sizeof(double), p->stream));
-  launch_residual<TR, SCALE>(p, F, u, p->w);
-  BLP_TRY(read_status(p));
-  double beta = p->st_h->beta;
-  if (hist) hist[0] = beta;
-  int it = 0, restarts = 0;
-  bool conv = beta <= target;
-  while (!conv && it < o->maxit) {
-    if (!std::isfinite(beta)) return BLP_E_NUMERIC;
-    k_normalize<TV><<<blocks1d(n), 256, 0, p->stream>>>(p->w, V, n, p->st, 1);
-    k_krylov_init<<<1, 64, 0, p->stream>>>(p->ks, ko, p->st);
-    const double cyc_target = std::max(target, inner_rtol * beta);
-    int ncol = 0;
-    for (int j = 0; j < m && it < o->maxit; ++j) {
-      TV *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
-      if (o->precond) {
-        BLP_TRY(prec_apply_dir<TV>(p, TR, vj, dh, zj));
-      } else if (SCALE) {
-        // identity preconditioner of the scaled system; Z keeps the unscaled
-        // variables, z = v / sqrt(C)
-        k_div<TV><<<blocks1d(n), 256, 0, p->stream>>>(vj, f.dh, zj, n);
-      } else {
-        HIP_TRY(hipMemcpyAsync(zj, vj, n * sizeof(TV), hipMemcpyDeviceToDevice, p->stream));
-      }
-      launch_spmv<TV, TR, SCALE>(p, zj, p->w);
-      const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
-      // CGS2: four passes over the j+1 basis vectors plus w traffic
-      KScope ks(p, KC_KRYLOV, (double)n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
-      k_arnoldi_dot<TV><<<nb, 256, 0, p->stream>>>(V, n, j, p->w, n, p->partials, p->ks, ko, p->st);
-      k_arnoldi_update<TV, false><<<nb, 256, 0, p->stream>>>(V, n, j, p->w, n, p->partials, p->ks, ko,
-                                                              p->st);
-      k_arnoldi_update<TV, true><<<nb, 256, 0, p->stream>>>(V, n, j, p->w, n, p->partials, p->ks, ko,
-                                                             p->st);
-      ks.end();
-      BLP_TRY(read_status(p));
-      ++it;
-      ncol = j + 1;
-      if (o->precond) cs.add(p->ctrl_h->cycles);
-      const double est = p->st_h->est;
-      if (hist && !std::is_same<TV, float>::value) hist[it] = est;
-      if (!std::isfinite(est)) return BLP_E_NUMERIC;
-      const bool happy = p->st_h->happy != 0;
-      if (!happy && j + 1 < m)
-        k_normalize<TV><<<blocks1d(n), 256, 0, p->stream>>>(p->w, V + (size_t)(j + 1) * n, n, p->st, 0);
-      if (est <= cyc_target || happy) break;
-    }
-    k_update_solution<TV><<<blocks1d(n), 256, 0, p->stream>>>(Z, n, ncol, p->ks, ko, u, n);
-    launch_residual<TR, SCALE>(p, F, u, p->w);
-    BLP_TRY(read_status(p));
-    beta = p->st_h->beta;
-    ++restarts;
-    if (hist && std::is_same<TV, float>::value) hist[std::min(it, o->maxit)] = beta;
-    if (beta <= target) conv = true;
-  }
-  HIP_TRY(hipGetLastError());
-  auto t1 = std::chrono::steady_clock::now();
-  if (info) {
-    info->iterations = it;
-    info->restarts = restarts;
-    info->converged = conv ? 1 : 0;
-    info->res = beta;
-    info->norm_F = nF;
-    info->mg_cycles_total = cs.total;
-    info->mg_cycles_min = cs.applies ? cs.mn : 0;
-    info->mg_cycles_max = cs.mx;
-    info->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  }
-  if (!std::isfinite(beta)) return BLP_E_NUMERIC;
-  return conv ? BLP_OK : BLP_W_NOCONV;
 }
 
 int solve_common(blp_problem *p, bool tr, int nrhs, const double *F, double *U,
                  const blp_solve_opts *o, blp_solve_info *info, double *hist) {
   if (!p || !o || !F || !U || nrhs < 1) return BLP_E_INVAL;
   if (o->precond && !p->prec_ready) return BLP_E_STATE;
-  if (!(o->tol > 0) || o->restart < 1 || o->restart > 60 || o->maxit < 1) return BLP_E_INVAL;
-  if (o->precision != BLP_FP64 && o->precision != BLP_MIXED) return BLP_E_INVAL;
-  BLP_TRY(ensure_workspace(p, o->restart, o->precision));
-  int worst = BLP_OK;
-  for (int k = 0; k < nrhs; ++k) {
-    const double *Fk = F + (size_t)k * p->n;
-    double *Uk = U + (size_t)k * p->n;
-    blp_solve_info *ik = info ? info + k : nullptr;
-    double *hk = hist ? hist + (size_t)k * (o->maxit + 1) : nullptr;
-    int rc;
-    const bool mixed = o->precision == BLP_MIXED, sc = o->scaled != 0;
-#define BLP_DISPATCH(TV, TRB, SCB) rc = fgmres<TV, TRB, SCB>(p, Fk, Uk, o, ik, hk)
-    if (mixed) {
-      if (tr) { if (sc) BLP_DISPATCH(float, true, true); else BLP_DISPATCH(float, true, false); }
-      else { if (sc) BLP_DISPATCH(float, false, true); else BLP_DISPATCH(float, false, false); }
-    } else {
-      if (tr) { if (sc) BLP_DISPATCH(double, true, true); else BLP_DISPATCH(double, true, false); }
-      else { if (sc) BLP_DISPATCH(double, false, true); else BLP_DISPATCH(double, false, false); }
-    }
-#undef BLP_DISPATCH
-    if (rc < 0) return rc;
-    if (rc > worst) worst = rc;
+  if (!p->prec_ready) {
+    // unpreconditioned solves still run on the engine's systems
+    BLP_TRY(build_preconditioner(p));
+    p->prec_ready = true;
   }
-  return worst;
+  Batch *B = nullptr;
+  BLP_TRY(own_batch(p, nrhs, &B));
+  std::vector<const double *> Fs(nrhs);
+  std::vector<double *> Us(nrhs), Hs(nrhs, nullptr);
+  for (int k = 0; k < nrhs; ++k) {
+    Fs[k] = F + (size_t)k * p->n;
+    Us[k] = U + (size_t)k * p->n;
+    if (hist) Hs[k] = hist + (size_t)k * (o->maxit + 1);
+  }
+  return batch_solve(*B, tr, Fs.data(), Us.data(), o, info, hist ? Hs.data() : nullptr);
+}
+
+// M^{-1} x (or M^{-T} x) for one vector, through a one-off plan on the
+// problem's first system.
+template <typename T, bool TR>
+int apply_prec(blp_problem *p, const T *x, T *y, int *cycles) {
+  Batch *B = nullptr;
+  BLP_TRY(own_batch(p, std::max(p->own_S, 1), &B));
+  std::vector<System *> sys{B->sys[0].get()};
+  std::vector<IOSpec> io{IOSpec{x, 0, y, 0}};
+  PrecPlan<T, TR> P;
+  BLP_TRY((build_prec_plan<T, TR>(p->stream, sys, io, false, P)));
+  const Ctx c{p->stream, p};
+  HIP_TRY(hipMemsetAsync(B->gate, 0, sizeof(int), p->stream));
+  prec_part1<T, TR>(c, P, nullptr, p->popts);
+  BLP_TRY((corner_finish<T, TR>(c, P, p->popts, kFirstCycles, B->ctrl, B->ctrl_h, 1)));
+  prec_part2<T, TR>(c, P, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(B->ctrl_h, B->ctrl, sizeof(MgCtrl), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (cycles) *cycles = B->ctrl_h[0].cycles;
+  return BLP_OK;
+}
+
+// y = A x or A^T x.
+template <bool TR>
+int apply_op(blp_problem *p, const double *x, double *y) {
+  SpmvArgs<double> a{p->grid64(), x, 0, y, nullptr, nullptr, nullptr, nullptr};
+  Alloc mem;
+  SpmvArgs<double> *d = nullptr;
+  BLP_TRY(mem.put(&d, &a, 1, p->stream));
+  KScope ks(p, KC_SPMV, (double)p->n * 2 * sizeof(double));
+  k_stencil<double, TR, false, false>
+      <<<dim3((p->n1 + 255) / 256, (p->n1 + kRows - 1) / kRows, 1), 256, 0, p->stream>>>(d, nullptr, kRows);
+  ks.end();
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return BLP_OK;
 }
 
 int check_field(const blp_field *f, int N, bool allow_nodal, double lo, bool strict) {
@@ -907,11 +581,6 @@ int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2, co
     }
     k_convert<double, float><<<blocks1d(p->n), 256, 0, p->stream>>>(p->f64.r, p->f32.r, p->n);
   }
-  if ((rc = p->alloc(&p->st, 1))) return fail(rc);
-  if (hipMemsetAsync(p->st, 0, sizeof(KrylovStatus), p->stream) != hipSuccess) return fail(BLP_E_HIP);
-  if (hipHostMalloc((void **)&p->st_h, sizeof(KrylovStatus), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&p->ctrl_h, sizeof(MgCtrl), hipHostMallocDefault) != hipSuccess)
-    return fail(BLP_E_NOMEM);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(p->stream) != hipSuccess)
     return fail(BLP_E_HIP);
   *out = p;
@@ -949,31 +618,21 @@ int blp_solve_adjoint(blp_problem *p, int nrhs, const double *G, double *L,
 
 int blp_apply(blp_problem *p, int op, const double *x, double *y, int *cycles) {
   if (!p || !x || !y) return BLP_E_INVAL;
-  if (op == BLP_OP_A || op == BLP_OP_AT) {
-    if (op == BLP_OP_A) launch_spmv<double, false, false>(p, x, y);
-    else launch_spmv<double, true, false>(p, x, y);
-  } else if (op == BLP_OP_MINV || op == BLP_OP_MINVT || op == BLP_OP_MINV32) {
-    if (!p->prec_ready) return BLP_E_STATE;
-    if (op == BLP_OP_MINV32) {
-      BLP_TRY(ensure_workspace(p, std::max(p->ws_m, 1), p->ws_prec < 0 ? BLP_FP64 : p->ws_prec));
-      k_convert<double, float><<<blocks1d(p->n), 256, 0, p->stream>>>(x, p->tmp32a, p->n);
-      BLP_TRY((prec_apply<float, false>(p, p->tmp32a, nullptr, p->tmp32b)));
-      k_convert<float, double><<<blocks1d(p->n), 256, 0, p->stream>>>(p->tmp32b, y, p->n);
-    } else {
-      BLP_TRY(prec_apply_dir<double>(p, op == BLP_OP_MINVT, x, nullptr, y));
-    }
+  if (cycles) *cycles = 0;
+  if (op == BLP_OP_A) return apply_op<false>(p, x, y);
+  if (op == BLP_OP_AT) return apply_op<true>(p, x, y);
+  if (op != BLP_OP_MINV && op != BLP_OP_MINVT && op != BLP_OP_MINV32) return BLP_E_INVAL;
+  if (!p->prec_ready) return BLP_E_STATE;
+  if (op == BLP_OP_MINV32) {
+    k_convert<double, float><<<blocks1d(p->n), 256, 0, p->stream>>>(x, p->tmp32a, p->n);
+    BLP_TRY((apply_prec<float, false>(p, p->tmp32a, p->tmp32b, cycles)));
+    k_convert<float, double><<<blocks1d(p->n), 256, 0, p->stream>>>(p->tmp32b, y, p->n);
+  } else if (op == BLP_OP_MINVT) {
+    BLP_TRY((apply_prec<double, true>(p, x, y, cycles)));
   } else {
-    return BLP_E_INVAL;
+    BLP_TRY((apply_prec<double, false>(p, x, y, cycles)));
   }
   HIP_TRY(hipGetLastError());
-  if (cycles) {
-    *cycles = 0;
-    if (p->ctrl && op >= BLP_OP_MINV) {
-      HIP_TRY(hipMemcpyAsync(p->ctrl_h, p->ctrl, sizeof(MgCtrl), hipMemcpyDeviceToHost, p->stream));
-      HIP_TRY(hipStreamSynchronize(p->stream));
-      *cycles = p->ctrl_h->cycles;
-    }
-  }
   HIP_TRY(hipStreamSynchronize(p->stream));
   return BLP_OK;
 }
@@ -1087,16 +746,16 @@ int blp_timing(blp_problem *p, int enable, double *ms, long long *launches, doub
   return BLP_OK;
 }
 
-long long blp_footprint(const blp_problem *p) { return p ? p->bytes + p->ws_bytes : 0; }
+long long blp_footprint(const blp_problem *p) {
+  return p ? p->bytes + (p->own ? batch_bytes(*p->own) : 0) : 0;
+}
 
 void blp_destroy(blp_problem *p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->stream);
   for (void *q : p->allocs) (void)hipFree(q);
-  for (void *q : p->ws_allocs) (void)hipFree(q);
+  delete p->own;
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-  if (p->st_h) (void)hipHostFree(p->st_h);
-  if (p->ctrl_h) (void)hipHostFree(p->ctrl_h);
   delete p;
 }
 

@@ -84,15 +84,15 @@ BLP_DEV void publish(double *p, double v) {
 BLP_DEV double collect(const double *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Returns true in the whole last block.
-BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag) {
+// Returns true in the whole last of nblocks arriving blocks.
+BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag, unsigned int nblocks) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));  // vmcnt(0)
     const unsigned int prev =
         __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *sh_flag = (prev == gridDim.x * gridDim.y - 1);
+    *sh_flag = (prev == nblocks - 1);
     __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
@@ -102,4 +102,22 @@ BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag) {
 // Reset of an arrival counter by the last block (for the next launch).
 BLP_DEV void reset_counter(unsigned int *counter) {
   __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Batched launches: blockIdx.z (or the block's system slot) selects one
+// system's argument record in a device array.  Vectors that change with the
+// Krylov step are addressed as base + j * ld, with j read from device memory
+// (jp; null means j = 0), so that the same launches (and captured graphs)
+// serve every step.
+BLP_DEV long long step_of(const int *jp) { return jp ? (long long)*jp : 0; }
+// Per-system gate: nonzero means the system takes no part in the launch.
+BLP_DEV bool gated(const int *g) { return g && *g; }
+
+// Pointers read from argument records in memory carry no address space, so
+// the compiler would access them with FLAT instructions (which also count
+// against the LDS counter).  Hot loops cast them to the global space.
+#define BLP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+BLP_DEV BLP_GLOBAL T *gptr(T *p) {
+  return (BLP_GLOBAL T *)p;
 }

@@ -1,0 +1,844 @@
+// Execution engine: systems, launch plans and the batched FGMRES driver.
+//
+// A *system* is one right-hand side being solved with one problem's
+// operator and preconditioner data; it owns its work vectors (region
+// buffers, corner-level vectors, Krylov basis).  A *batch* is a set of
+// systems solved together: every kernel launch covers all systems of one
+// mesh size (a class) at once, each workgroup reading its system's argument
+// record from a device array (a launch plan, built once).  Vectors that move
+// with the Krylov step are addressed as base + j * ld with j in device
+// memory, so one launch sequence -- which can be captured in a HIP graph --
+// serves every step.  Systems leave a restart cycle (converged, happy
+// breakdown, cycle length) through a per-system gate that every kernel
+// checks; a new cycle starts for all active systems together.  A single
+// solve is a batch of one.
+//
+// Included once, from blp.hip, inside its anonymous namespace.
+#pragma once
+
+// ------------------------------------------------------------------------ //
+// Device memory ownership                                                   //
+// ------------------------------------------------------------------------ //
+
+struct Alloc {
+  std::vector<void *> ptrs;
+  long long bytes = 0;
+  template <typename T>
+  int get(T **p, size_t count, hipStream_t s = nullptr, bool zero = false) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) return BLP_E_NOMEM;
+    ptrs.push_back(q);
+    bytes += (long long)(count * sizeof(T));
+    *p = (T *)q;
+    if (zero && hipMemsetAsync(q, 0, std::max<size_t>(count, 1) * sizeof(T), s) != hipSuccess)
+      return BLP_E_HIP;
+    return BLP_OK;
+  }
+  template <typename T>
+  int put(T **p, const T *host, size_t count, hipStream_t s) {
+    BLP_TRY(get(p, count));
+    if (hipMemcpyAsync(*p, host, count * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
+      return BLP_E_HIP;
+    return BLP_OK;
+  }
+  void release() {
+    for (void *q : ptrs) (void)hipFree(q);
+    ptrs.clear();
+    bytes = 0;
+  }
+  ~Alloc() { release(); }
+};
+
+// ------------------------------------------------------------------------ //
+// Systems                                                                   //
+// ------------------------------------------------------------------------ //
+
+template <typename T>
+struct SysWork {
+  T *bI = nullptr, *zI = nullptr;                    // interior region, skewed
+  T *bL[2] = {nullptr, nullptr}, *zL[2] = {nullptr, nullptr};  // edge lines [Y, X]
+  std::vector<T *> z, b, t;                          // corner levels, skewed
+};
+
+struct System {
+  blp_problem *p = nullptr;  // operator and preconditioner data (not owned)
+  SysWork<double> w64;
+  SysWork<float> w32;
+  MgCtrl *ctrl = nullptr;        // device, in the batch's array
+  KrylovStatus *st = nullptr;    // device, in the batch's array
+  int *gate = nullptr;           // device, in the batch's array
+  double *mg_partials = nullptr;
+  // Krylov workspace
+  int ws_m = 0, ws_prec = -1;
+  void *V = nullptr, *Z = nullptr;
+  double *w = nullptr, *ks = nullptr, *partials = nullptr;
+  Alloc mem, kmem;
+};
+
+template <typename T>
+SysWork<T> &work(System &s);
+template <>
+SysWork<double> &work<double>(System &s) { return s.w64; }
+template <>
+SysWork<float> &work<float>(System &s) { return s.w32; }
+
+template <typename T>
+int alloc_work(System &s, hipStream_t st, SysWork<T> &w, const FineDev<T> &f,
+               const std::vector<LevelDev<T>> &L) {
+  blp_problem *p = s.p;
+  const int h = p->h, m = p->n1 - h, hp = line_stride(h);
+  BLP_TRY(s.mem.get(&w.bI, f.nslotI, st, true));
+  BLP_TRY(s.mem.get(&w.zI, f.nslotI, st, true));
+  for (int r = 0; r < 2; ++r) {
+    BLP_TRY(s.mem.get(&w.bL[r], (size_t)m * hp, st, true));
+    BLP_TRY(s.mem.get(&w.zL[r], (size_t)m * hp, st, true));
+  }
+  w.z.assign(L.size(), nullptr);
+  w.b.assign(L.size(), nullptr);
+  w.t.assign(L.size(), nullptr);
+  for (size_t l = 0; l < L.size(); ++l) {
+    // zero-filled: padding slots of right-hand sides must hold zero
+    BLP_TRY(s.mem.get(&w.z[l], L[l].nslot, st, true));
+    BLP_TRY(s.mem.get(&w.b[l], L[l].nslot, st, true));
+    BLP_TRY(s.mem.get(&w.t[l], L[l].nslot, st, true));
+  }
+  return BLP_OK;
+}
+
+// Krylov workspace of a system for restart length m and precision prec.
+int ensure_krylov(System &s, hipStream_t st, int m, int prec) {
+  if (s.ws_m >= m && s.ws_prec == prec) return BLP_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  s.kmem.release();
+  const size_t n = s.p->n;
+  const size_t es = prec == BLP_MIXED ? sizeof(float) : sizeof(double);
+  char *V = nullptr, *Z = nullptr;
+  BLP_TRY(s.kmem.get(&V, (size_t)(m + 1) * n * es));
+  BLP_TRY(s.kmem.get(&Z, (size_t)m * n * es));
+  s.V = V;
+  s.Z = Z;
+  BLP_TRY(s.kmem.get(&s.w, n));
+  BLP_TRY(s.kmem.get(&s.ks, (size_t)(m + 1) * m + 2 * m + 3 * (m + 1) + m, st, true));
+  const size_t nblk = (n + KCHUNK - 1) / KCHUNK;
+  const size_t nstencil = (size_t)((s.p->n1 + 255) / 256) * ((s.p->n1 + kRows - 1) / kRows);
+  BLP_TRY(s.kmem.get(&s.partials, std::max(nblk * (size_t)(m + 2), std::max(nstencil, (size_t)256))));
+  s.ws_m = m;
+  s.ws_prec = prec;
+  return BLP_OK;
+}
+
+// ------------------------------------------------------------------------ //
+// Launch plans: device arrays of per-system argument records                //
+// ------------------------------------------------------------------------ //
+
+// Where the preconditioner of one system reads its input and writes its
+// output: v + j ldv and z + j ldz (ld = 0: fixed vectors).
+struct IOSpec {
+  const void *v;
+  long long ldv;
+  void *z;
+  long long ldz;
+};
+
+template <typename T, bool TR>
+struct PrecPlan {
+  int S = 0, N = 0, h = 0, n1 = 0, hp = 0, nbI = 0;
+  size_t nslotI = 0;
+  std::vector<int> ln;        // level sizes
+  std::vector<size_t> lslot;  // level skewed sizes
+  bool scaled = false;
+  SkewIO<T, TR> *ioI = nullptr;
+  SweepArgs<T> *swI = nullptr;
+  LineIO<T> *ioL = nullptr;
+  LineArgs<T> *lnA = nullptr;
+  CornerIO<T> *cr = nullptr;
+  std::vector<MgArgs<T> *> mg;
+  std::vector<SweepArgs<T> *> swb, swt;  // per level: sweep from b, from t
+  Alloc mem;
+};
+
+template <typename T, bool TR>
+int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std::vector<IOSpec> &io,
+                    bool scaled, PrecPlan<T, TR> &P) {
+  const int S = (int)sys.size();
+  blp_problem *p0 = sys[0]->p;
+  P.S = S;
+  P.N = p0->N;
+  P.h = p0->h;
+  P.n1 = p0->n1;
+  P.hp = line_stride(P.h);
+  P.scaled = scaled;
+  const std::vector<LevelDev<T>> &L0 = levels<T>(p0);
+  const int nl = (int)L0.size();
+  P.ln.resize(nl);
+  P.lslot.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    P.ln[l] = L0[l].n;
+    P.lslot[l] = L0[l].nslot;
+  }
+  P.nslotI = fine<T>(p0).nslotI;
+  P.nbI = (P.n1 - P.h + 63) / 64;
+  std::vector<SkewIO<T, TR>> ioI(S);
+  std::vector<SweepArgs<T>> swI(S);
+  std::vector<LineIO<T>> ioL(S);
+  std::vector<LineArgs<T>> lnA(S);
+  std::vector<CornerIO<T>> cr(S);
+  std::vector<std::vector<MgArgs<T>>> mg(nl, std::vector<MgArgs<T>>(S));
+  std::vector<std::vector<SweepArgs<T>>> swb(nl, std::vector<SweepArgs<T>>(S)), swt = swb;
+  const int h = P.h, n1 = P.n1, hp = P.hp;
+  for (int s = 0; s < S; ++s) {
+    System &y = *sys[s];
+    blp_problem *p = y.p;
+    const FineDev<T> &f = fine<T>(p);
+    const std::vector<LevelDev<T>> &L = levels<T>(p);
+    SysWork<T> &w = work<T>(y);
+    const Grid<T> g = fine_grid<T>(p);
+    const T *v = (const T *)io[s].v;
+    T *z = (T *)io[s].z;
+    const T *dh = scaled ? f.dh : nullptr;
+    ioI[s] = SkewIO<T, TR>{g, SkewT<T, TR>{h + 1, n1, h + 1, n1}, v, io[s].ldv, dh, z, io[s].ldz,
+                           w.bI, w.zI, P.nslotI, y.gate};
+    swI[s] = SweepArgs<T>{g, h + 1, n1, h + 1, n1, w.bI, f.icI[TR ? 1 : 0], w.zI, y.gate};
+    ioL[s] = LineIO<T>{g, h, n1, hp, v, io[s].ldv, dh, z, io[s].ldz, {w.bL[0], w.bL[1]},
+                       {w.zL[0], w.zL[1]}, y.gate};
+    LineArgs<T> la;
+    la.g = g;
+    la.h = h;
+    la.n1 = n1;
+    la.hp = hp;
+    const int base = TR ? 2 : 0;
+    for (int r = 0; r < 2; ++r) {
+      la.b[r] = w.bL[r];
+      la.z[r] = w.zL[r];
+      la.fd[r] = f.fac[base + r][0];
+      la.fm[r] = f.fac[base + r][1];
+      la.fw[r] = f.fac[base + r][2];
+    }
+    la.gate = y.gate;
+    lnA[s] = la;
+    cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.b[0], w.z[0], y.ctrl,
+                        p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate};
+    for (int l = 0; l < nl; ++l) {
+      const MgLevel<T> lv = L[l].view(TR, w.z[l], w.b[l], w.t[l]);
+      const MgLevel<T> cv =
+          l + 1 < nl ? L[l + 1].view(TR, w.z[l + 1], w.b[l + 1], w.t[l + 1]) : MgLevel<T>{};
+      mg[l][s] = MgArgs<T>{lv, cv, y.ctrl, y.mg_partials};
+      const T *ic = L[l].ic[TR ? 1 : 0];
+      swb[l][s] = SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.b[l], ic, w.z[l], &y.ctrl->gate};
+      swt[l][s] = SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.t[l], ic, w.z[l], &y.ctrl->gate};
+    }
+  }
+  BLP_TRY(P.mem.put(&P.ioI, ioI.data(), S, st));
+  BLP_TRY(P.mem.put(&P.swI, swI.data(), S, st));
+  BLP_TRY(P.mem.put(&P.ioL, ioL.data(), S, st));
+  BLP_TRY(P.mem.put(&P.lnA, lnA.data(), S, st));
+  BLP_TRY(P.mem.put(&P.cr, cr.data(), S, st));
+  P.mg.assign(nl, nullptr);
+  P.swb.assign(nl, nullptr);
+  P.swt.assign(nl, nullptr);
+  for (int l = 0; l < nl; ++l) {
+    BLP_TRY(P.mem.put(&P.mg[l], mg[l].data(), S, st));
+    BLP_TRY(P.mem.put(&P.swb[l], swb[l].data(), S, st));
+    BLP_TRY(P.mem.put(&P.swt[l], swt[l].data(), S, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));  // host staging vectors go out of scope
+  return BLP_OK;
+}
+
+// Launch context: stream and the (optional) kernel timer.
+struct Ctx {
+  hipStream_t stream;
+  blp_problem *timer;  // records per-class kernel times when its timing is on
+};
+
+template <typename T, bool TR>
+void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A) {
+  const int nb = (ncols + 63) / 64;
+  // superstep of K steps = 4 chunks of 16 bytes per lane; D supersteps of
+  // loads in flight (D + 1 register buffers of 2K words); more than 8 waves
+  // leave registers for D = 1 only
+  constexpr int K = 4 * kChunk<T>;
+  if (nb <= 8)
+    k_sweep<T, TR, K, 4><<<S, 64 * nb, 0, c.stream>>>(A);
+  else
+    k_sweep<T, TR, K, 1><<<S, 64 * nb, 0, c.stream>>>(A);
+}
+
+template <typename T, bool TR, int EP, int W>
+void lines_launch_k(const Ctx &c, int S, const LineArgs<T> *A) {
+  // D lines of operands in flight: 4 EP words per line and wave, within the
+  // 63 outstanding memory operations a wave can track and its registers
+  constexpr int D = EP >= 4 ? 4 : 6;
+  k_lines<T, TR, EP, W, D><<<2 * S, 64 * W, 0, c.stream>>>(A);
+}
+
+template <typename T, bool TR>
+void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A) {
+  // threads hold EP contiguous nodes; up to 4 waves per region
+  if (hp <= 64)
+    lines_launch_k<T, TR, 1, 1>(c, S, A);
+  else if (hp <= 128)
+    lines_launch_k<T, TR, 1, 2>(c, S, A);
+  else if (hp <= 256)
+    lines_launch_k<T, TR, 1, 4>(c, S, A);
+  else if (hp <= 512)
+    lines_launch_k<T, TR, 2, 4>(c, S, A);
+  else
+    lines_launch_k<T, TR, 4, 4>(c, S, A);
+}
+
+template <typename T, bool TR>
+void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
+  const int S = P.S, m = P.n1 - P.h;
+  const dim3 gg(blocks1d(P.nslotI), S);
+  {
+    KScope ks(c.timer, KC_LAYOUT, 0.0);
+    k_gather_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
+  }
+  {
+    KScope ks(c.timer, KC_SWEEP, (double)S * m * m * 2 * sizeof(T));
+    sweep_launch<T, TR>(c, S, m, P.swI);
+  }
+  KScope ks(c.timer, KC_LAYOUT, 0.0);
+  k_scatter_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
+}
+
+template <typename T, bool TR>
+void lines_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
+  const int S = P.S, L = P.n1 - P.h;
+  const dim3 gl((P.hp + 255) / 256, L, 2 * S);
+  {
+    KScope ks(c.timer, KC_LAYOUT, 0.0);
+    k_gather_lines<T, TR><<<gl, 256, 0, c.stream>>>(P.ioL, jp);
+  }
+  {
+    KScope ks(c.timer, KC_LINES, (double)S * 2.0 * L * P.h * 4 * sizeof(T));
+    lines_launch<T, TR>(c, S, P.hp, P.lnA);
+  }
+  KScope ks(c.timer, KC_LAYOUT, 0.0);
+  k_scatter_lines<T, TR><<<gl, 256, 0, c.stream>>>(P.ioL, jp);
+}
+
+// One V(1,1) cycle on level l for every system (Sec. 3.2).  zero_init: the
+// level iterate is zero on entry, so the pre-smoothing sweep is the plain
+// triangular solve.
+template <typename T, bool TR>
+void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
+  const int S = P.S, n = P.ln[l], nl = (int)P.ln.size();
+  const double nn = (double)S * n * n;
+  if (l == nl - 1) {
+    KScope ks(c.timer, KC_MG, nn * 2 * sizeof(T));
+    k_mg_coarsest<T, TR><<<S, 64, 0, c.stream>>>(P.mg[l], zero_init ? 1 : 0);
+    return;
+  }
+  const dim3 gl(blocks1d(P.lslot[l]), S), gc(blocks1d(P.lslot[l + 1]), S);
+  const double cc = (double)S * P.ln[l + 1] * P.ln[l + 1];
+  if (zero_init) {
+    KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
+    sweep_launch<T, TR>(c, S, n, P.swb[l]);
+  } else {
+    {
+      KScope ks(c.timer, KC_GSRHS, nn * 3 * sizeof(T));
+      k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
+    }
+    KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
+    sweep_launch<T, TR>(c, S, n, P.swt[l]);
+  }
+  {
+    KScope ks(c.timer, KC_MG, nn * 3 * sizeof(T));
+    k_mg_resid<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
+  }
+  {
+    KScope ks(c.timer, KC_MG, (nn + cc) * sizeof(T));
+    k_mg_restrict<T, TR><<<gc, 256, 0, c.stream>>>(P.mg[l]);
+  }
+  vcycle_run<T, TR>(c, P, l + 1, true);
+  {
+    KScope ks(c.timer, KC_MG, (2 * nn + cc) * sizeof(T));
+    k_mg_prolong<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
+  }
+  {
+    KScope ks(c.timer, KC_GSRHS, nn * 3 * sizeof(T));
+    k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
+  }
+  KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
+  sweep_launch<T, TR>(c, S, n, P.swt[l]);
+}
+
+// blocks of the corner residual-norm reduction (one partial each)
+constexpr int kMgNormBlocks = 256;
+
+template <typename T, bool TR>
+void mg_norm_run(const Ctx &c, const PrecPlan<T, TR> &P, int mode) {
+  const int nblk = std::min(kMgNormBlocks, (int)blocks1d(P.lslot[0]));
+  KScope ks(c.timer, KC_MG, (double)P.S * P.ln[0] * P.ln[0] * 2 * sizeof(T));
+  k_mg_norm<T, TR><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.mg[0], mode);
+}
+
+// The corner right-hand side and the first cycles: fixed mode runs all its
+// cycles; the adaptive rule (Sec. 3.2) enqueues the initial norm and up to
+// `first` cycles with their norms, each gated per system on device.
+template <typename T, bool TR>
+void corner_begin(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const blp_prec_opts &o,
+                  int first) {
+  const int h = P.h;
+  {
+    KScope ks(c.timer, KC_LAYOUT, 0.0);
+    k_corner_rhs<T, TR><<<dim3((h + 255) / 256, h, P.S), 256, 0, c.stream>>>(P.cr, jp);
+  }
+  if (o.mg_fixed > 0) {
+    for (int k = 0; k < o.mg_fixed; ++k) {
+      vcycle_run<T, TR>(c, P, 0, k == 0);
+      k_mg_count<T><<<P.S, 64, 0, c.stream>>>(P.mg[0]);
+    }
+    return;
+  }
+  mg_norm_run<T, TR>(c, P, 0);
+  for (int k = 0; k < std::min(first, o.mg_maxcyc); ++k) {
+    vcycle_run<T, TR>(c, P, 0, k == 0);
+    mg_norm_run<T, TR>(c, P, 1);
+  }
+}
+
+// Further adaptive cycles while any system's corner gate is open; ctrl_h
+// mirrors the systems' control blocks (contiguous device array ctrl).
+template <typename T, bool TR>
+int corner_finish(const Ctx &c, const PrecPlan<T, TR> &P, const blp_prec_opts &o, int done,
+                  const MgCtrl *ctrl, MgCtrl *ctrl_h, int S) {
+  if (o.mg_fixed > 0) return BLP_OK;
+  for (int k = done; k < o.mg_maxcyc; ++k) {
+    HIP_TRY(hipMemcpyAsync(ctrl_h, ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost, c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    bool open = false;
+    for (int s = 0; s < S; ++s) open = open || !ctrl_h[s].gate;
+    if (!open) break;
+    vcycle_run<T, TR>(c, P, 0, false);
+    mg_norm_run<T, TR>(c, P, 1);
+  }
+  return BLP_OK;
+}
+
+template <typename T, bool TR>
+void corner_end(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
+  KScope ks(c.timer, KC_LAYOUT, 0.0);
+  k_corner_copy<T, TR><<<dim3((P.h + 255) / 256, P.h, P.S), 256, 0, c.stream>>>(P.cr, jp);
+}
+
+// Cycles the adaptive rule enqueues before it looks at the corner residuals.
+constexpr int kFirstCycles = 5;
+
+// Preconditioner part before the corner-cycle check: forward I, edges,
+// corner right-hand side and the first cycles; transposed (M^T, block lower
+// triangular) the corner right-hand side and first cycles only.
+template <typename T, bool TR>
+void prec_part1(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const blp_prec_opts &o) {
+  if (!TR) {
+    interior_run<T, TR>(c, P, jp);
+    lines_run<T, TR>(c, P, jp);
+  }
+  corner_begin<T, TR>(c, P, jp, o, kFirstCycles);
+}
+// ... and after it: corner copy-back, then (transposed) edges and interior.
+template <typename T, bool TR>
+void prec_part2(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
+  corner_end<T, TR>(c, P, jp);
+  if (TR) {
+    lines_run<T, TR>(c, P, jp);
+    interior_run<T, TR>(c, P, jp);
+  }
+}
+
+// ------------------------------------------------------------------------ //
+// Batches                                                                   //
+// ------------------------------------------------------------------------ //
+
+// Operator / Krylov plans of one class for one precision and direction.
+template <typename TV, bool TR, bool SCALE>
+struct SolvePlan {
+  int S = 0;
+  PrecPlan<TV, TR> prec;
+  SpmvArgs<TV> *spmv = nullptr;     // x = Z_j -> w
+  SpmvArgs<double> *resid = nullptr;  // w = F - A u (scaled if SCALE), ||w||
+  NormArgs *norm = nullptr;         // ||F|| (scaled if SCALE)
+  KArgs<TV> *kr = nullptr;
+  Alloc mem;
+  std::vector<const double *> F;    // right-hand sides the plan was built for
+  std::vector<double *> U;
+};
+
+struct PlanBase {
+  virtual ~PlanBase() {}
+};
+template <typename TV, bool TR, bool SCALE>
+struct PlanHolder : PlanBase {
+  SolvePlan<TV, TR, SCALE> plan;
+};
+
+struct Batch {
+  hipStream_t stream = nullptr;
+  std::vector<std::unique_ptr<System>> sys;
+  std::vector<std::vector<int>> classes;  // system indices by mesh size
+  MgCtrl *ctrl = nullptr, *ctrl_h = nullptr;
+  KrylovStatus *st = nullptr, *st_h = nullptr;
+  int *gate = nullptr, *gate_h = nullptr;
+  int *jdev = nullptr;
+  int *ncol = nullptr, *ncol_h = nullptr;
+  blp_problem *timer = nullptr;
+  Alloc mem;
+  // cached plans per class and kind (key: class, TV, TR, SCALE, m)
+  std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<PlanBase>> plans;
+  ~Batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    plans.clear();
+    sys.clear();
+    if (ctrl_h) (void)hipHostFree(ctrl_h);
+    if (st_h) (void)hipHostFree(st_h);
+    if (gate_h) (void)hipHostFree(gate_h);
+    if (ncol_h) (void)hipHostFree(ncol_h);
+  }
+};
+
+// A batch over the given (preconditioned) problems, one system each.
+int batch_create(hipStream_t stream, blp_problem *const *probs, int S, std::unique_ptr<Batch> &out) {
+  std::unique_ptr<Batch> B(new (std::nothrow) Batch());
+  if (!B) return BLP_E_NOMEM;
+  B->stream = stream;
+  BLP_TRY(B->mem.get(&B->ctrl, S, stream, true));
+  BLP_TRY(B->mem.get(&B->st, S, stream, true));
+  BLP_TRY(B->mem.get(&B->gate, S, stream, true));
+  BLP_TRY(B->mem.get(&B->jdev, 1, stream, true));
+  BLP_TRY(B->mem.get(&B->ncol, S, stream, true));
+  if (hipHostMalloc((void **)&B->ctrl_h, S * sizeof(MgCtrl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&B->st_h, S * sizeof(KrylovStatus), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&B->gate_h, S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&B->ncol_h, S * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return BLP_E_NOMEM;
+  std::map<int, std::vector<int>> byN;
+  for (int s = 0; s < S; ++s) {
+    blp_problem *p = probs[s];
+    if (!p || !p->prec_ready) return BLP_E_STATE;
+    std::unique_ptr<System> y(new (std::nothrow) System());
+    if (!y) return BLP_E_NOMEM;
+    y->p = p;
+    y->ctrl = B->ctrl + s;
+    y->st = B->st + s;
+    y->gate = B->gate + s;
+    BLP_TRY(y->mem.get(&y->mg_partials, kMgNormBlocks, stream, true));
+    BLP_TRY(alloc_work<double>(*y, stream, y->w64, p->f64, p->l64));
+    BLP_TRY(alloc_work<float>(*y, stream, y->w32, p->f32, p->l32));
+    B->sys.push_back(std::move(y));
+    byN[p->N].push_back(s);
+  }
+  // largest meshes first: their launches start first in every step
+  for (auto it = byN.rbegin(); it != byN.rend(); ++it) B->classes.push_back(it->second);
+  HIP_TRY(hipStreamSynchronize(stream));
+  out = std::move(B);
+  return BLP_OK;
+}
+
+long long batch_bytes(const Batch &B) {
+  long long b = B.mem.bytes;
+  for (const auto &y : B.sys) b += y->mem.bytes + y->kmem.bytes;
+  return b;
+}
+
+template <typename TV, bool TR, bool SCALE>
+int build_solve_plan(Batch &B, const std::vector<int> &cls, int m, const double *const *F,
+                     double *const *U, SolvePlan<TV, TR, SCALE> &P) {
+  hipStream_t st = B.stream;
+  const int S = (int)cls.size();
+  P.S = S;
+  std::vector<System *> sys;
+  std::vector<IOSpec> io;
+  std::vector<SpmvArgs<TV>> sp(S);
+  std::vector<SpmvArgs<double>> rs(S);
+  std::vector<NormArgs> nm(S);
+  std::vector<KArgs<TV>> kr(S);
+  P.F.clear();
+  P.U.clear();
+  for (int k = 0; k < S; ++k) {
+    System &y = *B.sys[cls[k]];
+    blp_problem *p = y.p;
+    const size_t n = p->n;
+    sys.push_back(&y);
+    io.push_back(IOSpec{y.V, (long long)n, y.Z, (long long)n});
+    const Grid<double> g = p->grid64();
+    sp[k] = SpmvArgs<TV>{g, (const TV *)y.Z, (long long)n, y.w, nullptr, nullptr, nullptr, y.gate};
+    rs[k] = SpmvArgs<double>{g, U[cls[k]], 0, y.w, F[cls[k]], y.partials, y.st, y.gate};
+    nm[k] = NormArgs{g, F[cls[k]], y.partials, y.st, nullptr};
+    kr[k] = KArgs<TV>{(TV *)y.V, (TV *)y.Z, n, y.w, y.partials, y.ks, y.st, U[cls[k]], y.gate};
+    P.F.push_back(F[cls[k]]);
+    P.U.push_back(U[cls[k]]);
+  }
+  BLP_TRY((build_prec_plan<TV, TR>(st, sys, io, SCALE, P.prec)));
+  BLP_TRY(P.mem.put(&P.spmv, sp.data(), S, st));
+  BLP_TRY(P.mem.put(&P.resid, rs.data(), S, st));
+  BLP_TRY(P.mem.put(&P.norm, nm.data(), S, st));
+  BLP_TRY(P.mem.put(&P.kr, kr.data(), S, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return BLP_OK;
+}
+
+template <typename TV, bool TR, bool SCALE>
+int get_solve_plan(Batch &B, int c, int m, const double *const *F, double *const *U,
+                   SolvePlan<TV, TR, SCALE> **out) {
+  const auto key = std::make_tuple(c, (int)sizeof(TV), (int)TR, (int)SCALE, m);
+  auto it = B.plans.find(key);
+  if (it != B.plans.end()) {
+    auto *h = static_cast<PlanHolder<TV, TR, SCALE> *>(it->second.get());
+    bool same = true;
+    for (size_t k = 0; k < B.classes[c].size(); ++k)
+      same = same && h->plan.F[k] == F[B.classes[c][k]] && h->plan.U[k] == U[B.classes[c][k]];
+    if (same) {
+      *out = &h->plan;
+      return BLP_OK;
+    }
+    B.plans.erase(it);
+  }
+  std::unique_ptr<PlanHolder<TV, TR, SCALE>> h(new (std::nothrow) PlanHolder<TV, TR, SCALE>());
+  if (!h) return BLP_E_NOMEM;
+  BLP_TRY((build_solve_plan<TV, TR, SCALE>(B, B.classes[c], m, F, U, h->plan)));
+  *out = &h->plan;
+  B.plans[key] = std::move(h);
+  return BLP_OK;
+}
+
+int upload_gates(Batch &B) {
+  HIP_TRY(hipMemcpyAsync(B.gate, B.gate_h, B.sys.size() * sizeof(int), hipMemcpyHostToDevice,
+                         B.stream));
+  return BLP_OK;
+}
+int read_all(Batch &B) {
+  const size_t S = B.sys.size();
+  HIP_TRY(hipMemcpyAsync(B.st_h, B.st, S * sizeof(KrylovStatus), hipMemcpyDeviceToHost, B.stream));
+  HIP_TRY(hipMemcpyAsync(B.ctrl_h, B.ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost, B.stream));
+  HIP_TRY(hipStreamSynchronize(B.stream));
+  return BLP_OK;
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+struct CycleStats {
+  long total = 0;
+  int mn = 1 << 30, mx = 0, applies = 0;
+  void add(int c) {
+    total += c;
+    mn = std::min(mn, c);
+    mx = std::max(mx, c);
+    ++applies;
+  }
+};
+
+// Right-preconditioned FGMRES(m) from u = 0 (Saad) for every system of the
+// batch.  In scaled mode the Krylov space is that of D^{-1/2} A D^{-1/2}; the
+// preconditioned vectors Z are kept in the unscaled variables, so u += Z y
+// needs no rescaling.  TV = double: FP64 throughout.  TV = float (mixed): V,
+// Z and the preconditioner in FP32; SpMV arithmetic, Hessenberg/Givens, u and
+// the restart-boundary true residuals in FP64; each restart cycle reduces the
+// residual by at most inner_rtol before an FP64 residual is taken.
+template <typename TV, bool TR, bool SCALE>
+int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_solve_opts *o,
+                 blp_solve_info *info, double *const *hist) {
+  const int S = (int)B.sys.size(), m = o->restart, NC = (int)B.classes.size();
+  const double inner_rtol = std::is_same<TV, float>::value ? 1e-4 : 0.0;
+  const KOffsets ko{m};
+  const Ctx c{B.stream, B.timer};
+  auto t0 = std::chrono::steady_clock::now();
+  for (auto &y : B.sys) BLP_TRY(ensure_krylov(*y, B.stream, m, o->precision));
+  std::vector<SolvePlan<TV, TR, SCALE> *> P(NC);
+  for (int k = 0; k < NC; ++k) BLP_TRY((get_solve_plan<TV, TR, SCALE>(B, k, m, F, U, &P[k])));
+  const blp_prec_opts &po = B.sys[0]->p->popts;
+
+  std::vector<double> nF(S), target(S), beta(S), cyc_target(S);
+  std::vector<int> it(S, 0), restarts(S, 0), ncol(S, 0);
+  std::vector<char> active(S, 1), conv(S, 0), incyc(S, 0);
+  std::vector<CycleStats> cs(S);
+  auto set_gates = [&](const std::vector<char> &on) {
+    for (int s = 0; s < S; ++s) B.gate_h[s] = on[s] ? 0 : 1;
+    return upload_gates(B);
+  };
+  // ||F||, u = 0, r = F
+  for (int s = 0; s < S; ++s) B.gate_h[s] = 0;
+  BLP_TRY(upload_gates(B));
+  for (int k = 0; k < NC; ++k) {
+    const int nblk = 256;
+    k_norm<SCALE><<<dim3(nblk, P[k]->S), 256, 0, B.stream>>>(P[k]->norm);
+  }
+  BLP_TRY(read_all(B));
+  for (int s = 0; s < S; ++s) {
+    nF[s] = B.st_h[s].beta;
+    if (!std::isfinite(nF[s])) return BLP_E_NUMERIC;
+    target[s] = o->absolute ? o->tol : o->tol * nF[s];
+    HIP_TRY(hipMemsetAsync(U[s], 0, B.sys[s]->p->n * sizeof(double), B.stream));
+  }
+  auto residual = [&]() {
+    for (int k = 0; k < NC; ++k) {
+      const int n1 = B.sys[B.classes[k][0]]->p->n1;
+      KScope ks(c.timer, KC_SPMV, (double)P[k]->S * n1 * n1 * 3 * sizeof(double));
+      k_stencil<double, TR, SCALE, true>
+          <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, P[k]->S), 256, 0, B.stream>>>(
+              P[k]->resid, nullptr, kRows);
+    }
+    return read_all(B);
+  };
+  BLP_TRY(residual());
+  for (int s = 0; s < S; ++s) {
+    beta[s] = B.st_h[s].beta;
+    if (hist && hist[s]) hist[s][0] = beta[s];
+    conv[s] = beta[s] <= target[s];
+    active[s] = !conv[s] && it[s] < o->maxit;
+  }
+  while (std::any_of(active.begin(), active.end(), [](char a) { return a != 0; })) {
+    for (int s = 0; s < S; ++s) {
+      if (active[s] && !std::isfinite(beta[s])) return BLP_E_NUMERIC;
+      incyc[s] = active[s];
+      cyc_target[s] = std::max(target[s], inner_rtol * beta[s]);
+      ncol[s] = 0;
+    }
+    BLP_TRY(set_gates(incyc));
+    for (int k = 0; k < NC; ++k) {
+      const size_t n = B.sys[B.classes[k][0]]->p->n;
+      k_normalize<TV><<<dim3(blocks1d(n), P[k]->S), 256, 0, B.stream>>>(P[k]->kr, nullptr, 1);
+      k_krylov_init<TV><<<P[k]->S, 64, 0, B.stream>>>(P[k]->kr, ko);
+    }
+    for (int j = 0; j < m; ++j) {
+      k_set_int<<<1, 1, 0, B.stream>>>(B.jdev, j);
+      // preconditioner, first part (for every class), corner check, rest
+      if (o->precond) {
+        for (int k = 0; k < NC; ++k) prec_part1<TV, TR>(c, P[k]->prec, B.jdev, po);
+        if (po.mg_fixed == 0) {
+          // more cycles while any corner gate is open (all classes)
+          for (int extra = kFirstCycles; extra < po.mg_maxcyc; ++extra) {
+            HIP_TRY(hipMemcpyAsync(B.ctrl_h, B.ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost,
+                                   B.stream));
+            HIP_TRY(hipStreamSynchronize(B.stream));
+            bool open = false;
+            for (int s = 0; s < S; ++s) open = open || !B.ctrl_h[s].gate;
+            if (!open) break;
+            for (int k = 0; k < NC; ++k) {
+              vcycle_run<TV, TR>(c, P[k]->prec, 0, false);
+              mg_norm_run<TV, TR>(c, P[k]->prec, 1);
+            }
+          }
+        }
+        for (int k = 0; k < NC; ++k) prec_part2<TV, TR>(c, P[k]->prec, B.jdev);
+      } else {
+        for (int k = 0; k < NC; ++k) {
+          const size_t n = B.sys[B.classes[k][0]]->p->n;
+          for (int q = 0; q < P[k]->S; ++q) {
+            System &y = *B.sys[B.classes[k][q]];
+            TV *vj = (TV *)y.V + (size_t)j * n, *zj = (TV *)y.Z + (size_t)j * n;
+            if (!incyc[B.classes[k][q]]) continue;
+            if (SCALE)
+              k_div<TV><<<blocks1d(n), 256, 0, B.stream>>>(vj, fine<TV>(y.p).dh, zj, n);
+            else
+              HIP_TRY(hipMemcpyAsync(zj, vj, n * sizeof(TV), hipMemcpyDeviceToDevice, B.stream));
+          }
+        }
+      }
+      for (int k = 0; k < NC; ++k) {
+        const int n1 = B.sys[B.classes[k][0]]->p->n1;
+        const size_t n = (size_t)n1 * n1;
+        const int Sk = P[k]->S;
+        {
+          KScope ks(c.timer, KC_SPMV, (double)Sk * n * (sizeof(TV) + sizeof(double)));
+          k_stencil<TV, TR, SCALE, false>
+              <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, Sk), 256, 0, B.stream>>>(
+                  P[k]->spmv, B.jdev, kRows);
+        }
+        const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
+        // CGS2: four passes over the j+1 basis vectors plus w traffic
+        KScope ks(c.timer, KC_KRYLOV, (double)Sk * n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
+        k_arnoldi_dot<TV><<<dim3(nb, Sk), 256, 0, B.stream>>>(P[k]->kr, B.jdev, ko);
+        k_arnoldi_update<TV, false><<<dim3(nb, Sk), 256, 0, B.stream>>>(P[k]->kr, B.jdev, ko);
+        k_arnoldi_update<TV, true><<<dim3(nb, Sk), 256, 0, B.stream>>>(P[k]->kr, B.jdev, ko);
+      }
+      BLP_TRY(read_all(B));
+      bool any = false;
+      for (int s = 0; s < S; ++s) {
+        if (!incyc[s]) continue;
+        ++it[s];
+        ncol[s] = j + 1;
+        if (o->precond) cs[s].add(B.ctrl_h[s].cycles);
+        const double est = B.st_h[s].est;
+        if (hist && hist[s] && !std::is_same<TV, float>::value) hist[s][it[s]] = est;
+        if (!std::isfinite(est)) return BLP_E_NUMERIC;
+        const bool happy = B.st_h[s].happy != 0;
+        if (est <= cyc_target[s] || happy || j + 1 >= m || it[s] >= o->maxit) incyc[s] = 0;
+        any = any || incyc[s];
+      }
+      if (!any) break;
+      BLP_TRY(set_gates(incyc));
+      for (int k = 0; k < NC; ++k) {
+        const size_t n = B.sys[B.classes[k][0]]->p->n;
+        k_normalize<TV><<<dim3(blocks1d(n), P[k]->S), 256, 0, B.stream>>>(P[k]->kr, B.jdev, 0);
+      }
+    }
+    // u += Z y and the true residual of every system of the cycle
+    BLP_TRY(set_gates(active));
+    // column counts in class order (the kernel indexes its class-local slot)
+    {
+      int off = 0;
+      for (int k = 0; k < NC; ++k)
+        for (int q = 0; q < P[k]->S; ++q) B.ncol_h[off++] = ncol[B.classes[k][q]];
+      HIP_TRY(hipMemcpyAsync(B.ncol, B.ncol_h, S * sizeof(int), hipMemcpyHostToDevice, B.stream));
+      off = 0;
+      for (int k = 0; k < NC; ++k) {
+        const size_t n = B.sys[B.classes[k][0]]->p->n;
+        k_update_solution<TV>
+            <<<dim3(blocks1d(n), P[k]->S), 256, 0, B.stream>>>(P[k]->kr, B.ncol + off, ko);
+        off += P[k]->S;
+      }
+    }
+    BLP_TRY(residual());
+    for (int s = 0; s < S; ++s) {
+      if (!active[s]) continue;
+      beta[s] = B.st_h[s].beta;
+      ++restarts[s];
+      if (hist && hist[s] && std::is_same<TV, float>::value)
+        hist[s][std::min(it[s], o->maxit)] = beta[s];
+      if (beta[s] <= target[s]) conv[s] = 1;
+      if (!std::isfinite(beta[s])) return BLP_E_NUMERIC;
+      active[s] = !conv[s] && it[s] < o->maxit;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  auto t1 = std::chrono::steady_clock::now();
+  int rc = BLP_OK;
+  for (int s = 0; s < S; ++s) {
+    if (info) {
+      blp_solve_info &I = info[s];
+      I.iterations = it[s];
+      I.restarts = restarts[s];
+      I.converged = conv[s] ? 1 : 0;
+      I.res = beta[s];
+      I.norm_F = nF[s];
+      I.mg_cycles_total = cs[s].total;
+      I.mg_cycles_min = cs[s].applies ? cs[s].mn : 0;
+      I.mg_cycles_max = cs[s].mx;
+      I.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (!conv[s]) rc = BLP_W_NOCONV;
+  }
+  return rc;
+}
+
+int batch_solve(Batch &B, bool tr, const double *const *F, double *const *U, const blp_solve_opts *o,
+                blp_solve_info *info, double *const *hist) {
+  if (!o || !(o->tol > 0) || o->restart < 1 || o->restart > 60 || o->maxit < 1) return BLP_E_INVAL;
+  if (o->precision != BLP_FP64 && o->precision != BLP_MIXED) return BLP_E_INVAL;
+  for (size_t s = 0; s < B.sys.size(); ++s)
+    if (!F[s] || !U[s]) return BLP_E_INVAL;
+  const bool mixed = o->precision == BLP_MIXED, sc = o->scaled != 0;
+  int rc;
+#define BLP_DISPATCH(TV, TRB, SCB) rc = fgmres_batch<TV, TRB, SCB>(B, F, U, o, info, hist)
+  if (mixed) {
+    if (tr) { if (sc) BLP_DISPATCH(float, true, true); else BLP_DISPATCH(float, true, false); }
+    else { if (sc) BLP_DISPATCH(float, false, true); else BLP_DISPATCH(float, false, false); }
+  } else {
+    if (tr) { if (sc) BLP_DISPATCH(double, true, true); else BLP_DISPATCH(double, true, false); }
+    else { if (sc) BLP_DISPATCH(double, false, true); else BLP_DISPATCH(double, false, false); }
+  }
+#undef BLP_DISPATCH
+  return rc;
+}

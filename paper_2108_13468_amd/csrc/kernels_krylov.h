@@ -25,20 +25,38 @@ struct KOffsets {
 constexpr int KCHUNK = 4096;  // elements per block in the basis kernels
 constexpr int KPT = KCHUNK / 256;
 
+// One system's Krylov state (batched: blockIdx.y selects the record).  The
+// step index j is read from device memory (jp), so one launch sequence
+// serves every step.
+template <typename TV>
+struct KArgs {
+  TV *V, *Z;          // bases, column stride n
+  size_t n;
+  double *w;          // FP64 work vector
+  double *partials;   // per-block reduction partials
+  double *ks;         // Hessenberg / Givens state (KOffsets)
+  KrylovStatus *st;
+  double *u;          // iterate
+  const int *gate;    // nonzero: the system is outside the current cycle
+};
+
 // h1[i] = V_i . w (i = 0..j) and wn0 = ||w||.
 template <typename TV>
-__global__ __launch_bounds__(256) void k_arnoldi_dot(const TV *V, size_t ldv, int j,
-                                                     const double *w, size_t n,
-                                                     double *partials, double *ks,
-                                                     KOffsets ko, KrylovStatus *st) {
+__global__ __launch_bounds__(256) void k_arnoldi_dot(const KArgs<TV> *A, const int *jp, KOffsets ko) {
   __shared__ double sh[16];
   __shared__ bool last;
+  const KArgs<TV> a = A[blockIdx.y];
+  if (gated(a.gate)) return;
+  const int j = (int)step_of(jp);
+  const size_t n = a.n;
+  const BLP_GLOBAL TV *V = gptr(a.V);
+  const BLP_GLOBAL double *wv = gptr(a.w);
   const size_t base = (size_t)blockIdx.x * KCHUNK + threadIdx.x;
   double wl[KPT];
 #pragma unroll
   for (int e = 0; e < KPT; ++e) {
     const size_t q = base + (size_t)e * 256;
-    wl[e] = q < n ? w[q] : 0.0;
+    wl[e] = q < n ? wv[q] : 0.0;
   }
   const int nd = j + 2;  // j+1 dots and ||w||^2
   for (int v = 0; v <= j; ++v) {
@@ -46,39 +64,43 @@ __global__ __launch_bounds__(256) void k_arnoldi_dot(const TV *V, size_t ldv, in
 #pragma unroll
     for (int e = 0; e < KPT; ++e) {
       const size_t q = base + (size_t)e * 256;
-      if (q < n) acc += (double)V[(size_t)v * ldv + q] * wl[e];
+      if (q < n) acc += (double)V[(size_t)v * n + q] * wl[e];
     }
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) publish(&partials[(size_t)blockIdx.x * nd + v], acc);
+    if (threadIdx.x == 0) publish(&a.partials[(size_t)blockIdx.x * nd + v], acc);
   }
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < KPT; ++e) acc += wl[e] * wl[e];
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) publish(&partials[(size_t)blockIdx.x * nd + j + 1], acc);
-  if (!arrive_last(&st->counter, &last)) return;
+  if (threadIdx.x == 0) publish(&a.partials[(size_t)blockIdx.x * nd + j + 1], acc);
+  if (!arrive_last(&a.st->counter, &last, gridDim.x)) return;
   for (int v = threadIdx.x; v < nd; v += blockDim.x) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[(size_t)b * nd + v]);
-    if (v <= j) ko.h1(ks)[v] = s;
-    else st->wn0 = sqrt(s);
+    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[(size_t)b * nd + v]);
+    if (v <= j) ko.h1(a.ks)[v] = s;
+    else a.st->wn0 = sqrt(s);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    reset_counter(&st->counter);
-  }
+  if (threadIdx.x == 0) reset_counter(&a.st->counter);
 }
 
 // w -= sum_i V_i h[i]; then either h2 = V^T w (NORM = false) or
 // hn = ||w|| with the Hessenberg/Givens update (NORM = true).
 template <typename TV, bool NORM>
-__global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv, int j,
-                                                        double *w, size_t n, double *partials,
-                                                        double *ks, KOffsets ko,
-                                                        KrylovStatus *st) {
+__global__ __launch_bounds__(256) void k_arnoldi_update(const KArgs<TV> *A, const int *jp,
+                                                        KOffsets ko) {
   __shared__ double sh[16];
   __shared__ bool last;
   __shared__ double hs[64];
+  const KArgs<TV> a = A[blockIdx.y];
+  if (gated(a.gate)) return;
+  const int j = (int)step_of(jp);
+  const size_t n = a.n;
+  const BLP_GLOBAL TV *V = gptr(a.V);
+  BLP_GLOBAL double *w = gptr(a.w);
+  double *ks = a.ks;
+  KrylovStatus *st = a.st;
   const double *hin = NORM ? ko.h2(ks) : ko.h1(ks);
   for (int v = threadIdx.x; v <= j; v += blockDim.x) hs[v] = hin[v];
   __syncthreads();
@@ -94,7 +116,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv,
 #pragma unroll
     for (int e = 0; e < KPT; ++e) {
       const size_t q = base + (size_t)e * 256;
-      if (q < n) wl[e] -= (double)V[(size_t)v * ldv + q] * hv;
+      if (q < n) wl[e] -= (double)V[(size_t)v * n + q] * hv;
     }
   }
 #pragma unroll
@@ -109,34 +131,32 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv,
 #pragma unroll
       for (int e = 0; e < KPT; ++e) {
         const size_t q = base + (size_t)e * 256;
-        if (q < n) acc += (double)V[(size_t)v * ldv + q] * wl[e];
+        if (q < n) acc += (double)V[(size_t)v * n + q] * wl[e];
       }
       acc = block_sum(acc, sh);
-      if (threadIdx.x == 0) publish(&partials[(size_t)blockIdx.x * nd + v], acc);
+      if (threadIdx.x == 0) publish(&a.partials[(size_t)blockIdx.x * nd + v], acc);
     }
   } else {
     double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < KPT; ++e) acc += wl[e] * wl[e];
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) publish(&partials[blockIdx.x], acc);
+    if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
   }
-  if (!arrive_last(&st->counter, &last)) return;
+  if (!arrive_last(&st->counter, &last, gridDim.x)) return;
   if (!NORM) {
     for (int v = threadIdx.x; v <= j; v += blockDim.x) {
       double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[(size_t)b * nd + v]);
+      for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[(size_t)b * nd + v]);
       ko.h2(ks)[v] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      reset_counter(&st->counter);
-    }
+    if (threadIdx.x == 0) reset_counter(&st->counter);
     return;
   }
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[b]);
+    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[b]);
     const double hn = sqrt(s);
     const int m = ko.m;
     double *H = ko.H(ks), *cs = ko.cs(ks), *sn = ko.sn(ks), *g = ko.g(ks);
@@ -145,18 +165,18 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv,
     for (int v = 0; v <= j; ++v) H[v * m + j] = h1[v] + hs[v];
     H[(j + 1) * m + j] = hn;
     for (int v = 0; v < j; ++v) {
-      const double a = H[v * m + j], b = H[(v + 1) * m + j];
-      H[v * m + j] = cs[v] * a + sn[v] * b;
-      H[(v + 1) * m + j] = -sn[v] * a + cs[v] * b;
+      const double a0 = H[v * m + j], b0 = H[(v + 1) * m + j];
+      H[v * m + j] = cs[v] * a0 + sn[v] * b0;
+      H[(v + 1) * m + j] = -sn[v] * a0 + cs[v] * b0;
     }
-    const double a = H[j * m + j], b = H[(j + 1) * m + j];
-    const double rho = hypot(a, b);
+    const double a0 = H[j * m + j], b0 = H[(j + 1) * m + j];
+    const double rho = hypot(a0, b0);
     if (rho == 0.0) {
       cs[j] = 1.0;
       sn[j] = 0.0;
     } else {
-      cs[j] = a / rho;
-      sn[j] = b / rho;
+      cs[j] = a0 / rho;
+      sn[j] = b0 / rho;
     }
     H[j * m + j] = rho;
     H[(j + 1) * m + j] = 0.0;
@@ -169,32 +189,40 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const TV *V, size_t ldv,
   }
 }
 
-// V_{j+1} = w / hn (or V_0 = w / beta), FP64 in, TV out.
+// V_{j+1} = w / hn (use_beta = 0) or V_0 = w / beta (use_beta = 1), FP64 in,
+// TV out.  Batched over blockIdx.y.
 template <typename TV>
-__global__ void k_normalize(const double *w, TV *v, size_t n, const KrylovStatus *st,
-                            int use_beta) {
+__global__ void k_normalize(const KArgs<TV> *A, const int *jp, int use_beta) {
+  const KArgs<TV> a = A[blockIdx.y];
+  if (gated(a.gate)) return;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const double s = use_beta ? st->beta : st->hn;
-  v[q] = (TV)(w[q] / s);
+  if (q >= a.n) return;
+  const double s = use_beta ? a.st->beta : a.st->hn;
+  BLP_GLOBAL TV *v = gptr(a.V + (use_beta ? 0 : (size_t)(step_of(jp) + 1) * a.n));
+  v[q] = (TV)(gptr(a.w)[q] / s);
 }
 
-// Start of a restart cycle: g = (beta, 0, ..., 0).
-__global__ void k_krylov_init(double *ks, KOffsets ko, const KrylovStatus *st) {
-  double *g = ko.g(ks);
-  for (int v = threadIdx.x; v <= ko.m; v += blockDim.x) g[v] = v == 0 ? st->beta : 0.0;
+// Start of a restart cycle: g = (beta, 0, ..., 0).  One block per system.
+template <typename TV>
+__global__ void k_krylov_init(const KArgs<TV> *A, KOffsets ko) {
+  const KArgs<TV> a = A[blockIdx.x];
+  if (gated(a.gate)) return;
+  double *g = ko.g(a.ks);
+  for (int v = threadIdx.x; v <= ko.m; v += blockDim.x) g[v] = v == 0 ? a.st->beta : 0.0;
 }
 
-// u += Z y, with H y = g solved (upper triangular, ncol columns) by each
-// block into shared memory.
-template <typename TZ>
-__global__ __launch_bounds__(256) void k_update_solution(const TZ *Z, size_t ldz, int ncol,
-                                                         const double *ks, KOffsets ko,
-                                                         double *u, size_t n) {
+// u += Z y, with H y = g solved (upper triangular, ncol[s] columns) by each
+// block into shared memory.  Batched over blockIdx.y.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_update_solution(const KArgs<TV> *A, const int *ncolv,
+                                                         KOffsets ko) {
   __shared__ double y[64];
+  const KArgs<TV> a = A[blockIdx.y];
+  if (gated(a.gate)) return;
+  const int ncol = ncolv[blockIdx.y];
   if (threadIdx.x == 0) {
     const int m = ko.m;
-    const double *H = ks, *g = ks + (m + 1) * m + 2 * m;
+    const double *H = ko.H(a.ks), *g = ko.g(a.ks);
     for (int v = ncol - 1; v >= 0; --v) {
       double s = g[v];
       for (int k = v + 1; k < ncol; ++k) s -= H[v * m + k] * y[k];
@@ -203,8 +231,10 @@ __global__ __launch_bounds__(256) void k_update_solution(const TZ *Z, size_t ldz
   }
   __syncthreads();
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
+  if (q >= a.n) return;
+  BLP_GLOBAL double *u = gptr(a.u);
+  const BLP_GLOBAL TV *Z = gptr(a.Z);
   double s = u[q];
-  for (int v = 0; v < ncol; ++v) s += y[v] * (double)Z[(size_t)v * ldz + q];
+  for (int v = 0; v < ncol; ++v) s += y[v] * (double)Z[(size_t)v * a.n + q];
   u[q] = s;
 }

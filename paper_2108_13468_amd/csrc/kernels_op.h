@@ -10,38 +10,56 @@
 //   y = A x            (TR = false)   or   y = A^T x   (TR = true)
 //   RESID: y = F - (A x)
 //   SCALE: y *= 1/sqrt(C_ij)        (symmetric Jacobi scaling of the output)
-// Arithmetic in FP64 whatever the storage types.  With RESID the kernel also
-// reduces ||y||^2 (last block writes st->beta = ||y||).
-template <typename TX, typename TO, bool TR, bool SCALE, bool RESID>
-__global__ __launch_bounds__(256) void k_stencil(Grid<double> g, const TX *__restrict__ x,
-                                                 TO *__restrict__ y,
-                                                 const double *__restrict__ F, int rows,
-                                                 double *partials, KrylovStatus *st) {
+// Arithmetic in FP64 whatever the storage type of x.  With RESID the kernel
+// also reduces ||y||^2 (the last block writes st->beta = ||y||).  Batched:
+// blockIdx.z selects the system; x is x + j * ldx.
+template <typename TX>
+struct SpmvArgs {
+  Grid<double> g;
+  const TX *x;
+  long long ldx;
+  double *y;
+  const double *F;    // RESID
+  double *partials;   // RESID: one per block of the system
+  KrylovStatus *st;   // RESID
+  const int *gate;
+};
+
+template <typename TX, bool TR, bool SCALE, bool RESID>
+__global__ __launch_bounds__(256) void k_stencil(const SpmvArgs<TX> *A, const int *jp, int rows) {
   __shared__ double sh[16];
   __shared__ bool last;
+  const SpmvArgs<TX> a = A[blockIdx.z];
+  if (gated(a.gate)) return;
+  const Grid<double> &g = a.g;
+  const BLP_GLOBAL TX *__restrict__ x = gptr(a.x + step_of(jp) * a.ldx);
+  BLP_GLOBAL double *__restrict__ y = gptr(a.y);
+  const BLP_GLOBAL double *__restrict__ Fv = gptr(a.F);
   const int n = g.nx;
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
   const int j0 = blockIdx.y * rows + 1;
   const int j1 = min(j0 + rows - 1, g.ny);
   double acc = 0.0;
+  const BLP_GLOBAL double *gW = gptr(g.W), *gE = gptr(g.E), *gS = gptr(g.S), *gN = gptr(g.N),
+                         *gDy = gptr(g.Dy), *gr = gptr(g.r);
   if (i <= n) {
-    const double cw = TR ? g.E[i - 1] : g.W[i];
-    const double ce = TR ? g.W[i + 1] : g.E[i];
-    const double dx = g.Dx[i];
+    const double cw = TR ? gE[i - 1] : gW[i];
+    const double ce = TR ? gW[i + 1] : gE[i];
+    const double dx = gptr(g.Dx)[i];
     double xs = j0 > 1 ? (double)x[vidx(i, j0 - 1, n)] : 0.0;
     double xc = (double)x[vidx(i, j0, n)];
     for (int j = j0; j <= j1; ++j) {
       const double xn = j < g.ny ? (double)x[vidx(i, j + 1, n)] : 0.0;
       const double xw = i > 1 ? (double)x[vidx(i - 1, j, n)] : 0.0;
       const double xe = i < n ? (double)x[vidx(i + 1, j, n)] : 0.0;
-      const double cs = TR ? g.N[j - 1] : g.S[j];
-      const double cn = TR ? g.S[j + 1] : g.N[j];
+      const double cs = TR ? gN[j - 1] : gS[j];
+      const double cn = TR ? gS[j + 1] : gN[j];
       const size_t q = vidx(i, j, n);
-      const double C = dx + g.Dy[j] + (g.r ? g.r[q] : g.rc);
+      const double C = dx + gDy[j] + (gr ? gr[q] : g.rc);
       double v = C * xc + cw * xw + ce * xe + cs * xs + cn * xn;
-      if (RESID) v = F[q] - v;
+      if (RESID) v = Fv[q] - v;
       if (SCALE) v /= sqrt(C);
-      y[q] = (TO)v;
+      y[q] = v;
       if (RESID) acc += v * v;
       xs = xc;
       xc = xn;
@@ -49,29 +67,40 @@ __global__ __launch_bounds__(256) void k_stencil(Grid<double> g, const TX *__res
   }
   if (!RESID) return;
   acc = block_sum(acc, sh);
+  const unsigned int nblk = gridDim.x * gridDim.y;
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) publish(&partials[bid], acc);
-  if (!arrive_last(&st->counter, &last)) return;
+  if (threadIdx.x == 0) publish(&a.partials[bid], acc);
+  if (!arrive_last(&a.st->counter, &last, nblk)) return;
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < (int)(gridDim.x * gridDim.y); ++b) s += collect(&partials[b]);
-    st->beta = sqrt(s);
-    reset_counter(&st->counter);
+    for (int b = 0; b < (int)nblk; ++b) s += collect(&a.partials[b]);
+    a.st->beta = sqrt(s);
+    reset_counter(&a.st->counter);
   }
 }
 
-// ||F|| (or ||F / sqrt(C)|| when SCALE) into st->beta.
+// ||F|| (or ||F / sqrt(C)|| when SCALE) into st->beta.  Batched over
+// blockIdx.y.
+struct NormArgs {
+  Grid<double> g;
+  const double *F;
+  double *partials;
+  KrylovStatus *st;
+  const int *gate;
+};
 template <bool SCALE>
-__global__ __launch_bounds__(256) void k_norm(Grid<double> g, const double *F, double *partials,
-                                              KrylovStatus *st) {
+__global__ __launch_bounds__(256) void k_norm(const NormArgs *A) {
   __shared__ double sh[16];
   __shared__ bool last;
+  const NormArgs a = A[blockIdx.y];
+  if (gated(a.gate)) return;
+  const Grid<double> &g = a.g;
   const int n = g.nx;
   const size_t tot = (size_t)n * g.ny;
   double acc = 0.0;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot;
        q += (size_t)gridDim.x * blockDim.x) {
-    double v = F[q];
+    double v = a.F[q];
     if (SCALE) {
       const int i = (int)(q % n) + 1, j = (int)(q / n) + 1;
       v /= sqrt(g.C(i, j));
@@ -79,13 +108,13 @@ __global__ __launch_bounds__(256) void k_norm(Grid<double> g, const double *F, d
     acc += v * v;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) publish(&partials[blockIdx.x], acc);
-  if (!arrive_last(&st->counter, &last)) return;
+  if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
+  if (!arrive_last(&a.st->counter, &last, gridDim.x)) return;
   if (threadIdx.x == 0) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&partials[b]);
-    st->beta = sqrt(s);
-    reset_counter(&st->counter);
+    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[b]);
+    a.st->beta = sqrt(s);
+    reset_counter(&a.st->counter);
   }
 }
 

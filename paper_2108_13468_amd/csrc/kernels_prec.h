@@ -208,8 +208,9 @@ template <>
 struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
 
 template <typename T, bool TR, int K, int D>
-__global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
-  if (a.gate && *a.gate) return;
+__global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T> *A) {
+  const SweepArgs<T> a = A[blockIdx.x];  // one workgroup per system
+  if (gated(a.gate)) return;
   constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64;
   static_assert(K % P == 0 && 64 % K == 0 && 2 * K < 64, "superstep length");
   typedef typename Vec16<T>::type V;
@@ -242,9 +243,9 @@ __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
   const T cu = colok ? (TR ? g.E[i - 1] : g.E[i]) : T(0);  // upstream x coupling
   const int nsup = __builtin_amdgcn_readfirstlane(((nb - 1) * LAG + mr + 63 + K - 1) / K);
   // this band's storage: chunk ck of this lane is element ck * 64
-  const V *__restrict__ bb = reinterpret_cast<const V *>(a.b + sk.slot(band, 0, 0)) + lane;
-  const V *__restrict__ bi = reinterpret_cast<const V *>(a.ic + sk.slot(band, 0, 0)) + lane;
-  V *__restrict__ zz = reinterpret_cast<V *>(a.z + sk.slot(band, 0, 0)) + lane;
+  const BLP_GLOBAL V *__restrict__ bb = gptr(reinterpret_cast<const V *>(a.b + sk.slot(band, 0, 0)) + lane);
+  const BLP_GLOBAL V *__restrict__ bi = gptr(reinterpret_cast<const V *>(a.ic + sk.slot(band, 0, 0)) + lane);
+  BLP_GLOBAL V *__restrict__ zz = gptr(reinterpret_cast<V *>(a.z + sk.slot(band, 0, 0)) + lane);
   T *__restrict__ ring_out = ring[band + 1];
   const T *__restrict__ ring_in = ring[band];
   const T *__restrict__ yc_lane = ycu + 64 - lane;  // yc_lane[s] = coupling of row s - lane
@@ -336,67 +337,63 @@ __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(SweepArgs<T> a) {
   store(s_prev, res);
 }
 
-// Gauss-Seidel right-hand side, folded before a smoothing sweep: with the
-// current iterate z (skewed), rhs = b - (downstream couplings) * z, i.e.
-// forward b - W_i z_{i-1,j} - S_j z_{i,j-1}, transposed
-// b - W_{i+1} z_{i+1,j} - S_{j+1} z_{i,j+1}; the sweep then solves the
-// triangular system with this rhs, which is one Gauss-Seidel sweep.
+// Natural <-> skewed copies of a rectangle of the fine grid (batched over
+// blockIdx.y).  The gather reads v + j ldv, can multiply by dh (scaled-system
+// input) and folds the couplings to the already-solved values of z + j ldz
+// just outside the rectangle's upstream sides into the right-hand side
+// (forward: E_i z_{i+1,j} past column i1, N_j z_{i,j+1} past row j1;
+// transposed: E_{i-1} z_{i-1,j} before column i0, N_{j-1} z_{i,j-1} before
+// row j0), so that the sweep runs with zero boundary values.  One thread per
+// skewed slot; padding slots get zero.  The scatter writes the rectangle of
+// z + j ldz from the skewed result.
 template <typename T, bool TR>
-__global__ void k_gs_rhs(Grid<T> g, const T *b, const T *z, T *out, size_t nslot, const int *gate) {
-  if (gate && *gate) return;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nslot) return;
-  const int n = g.nx;
-  const SkewT<T, TR> sk{1, n, 1, n};
-  int i, j;
-  if (!sk.decode(q, i, j)) {
-    out[q] = T(0);
-    return;
-  }
-  const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
-  double v = b[q];  // FP64 arithmetic: the terms largely cancel
-  if (id >= 1 && id <= n) v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)z[sk.at(id, j)];
-  if (jd >= 1 && jd <= g.ny) v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)z[sk.at(i, jd)];
-  out[q] = T(v);
-}
-
-// Natural <-> skewed copies of a rectangle of the fine grid.  The gather can
-// multiply by dh (scaled-system input) and folds the couplings to the
-// already-solved values zb just outside the rectangle's upstream sides into
-// the right-hand side (forward: E_i z_{i+1,j} past column i1, N_j z_{i,j+1}
-// past row j1; transposed: E_{i-1} z_{i-1,j} before column i0, N_{j-1}
-// z_{i,j-1} before row j0), so that the sweep runs with zero boundary
-// values.  One thread per skewed slot; padding slots get zero.
+struct SkewIO {
+  Grid<T> g;
+  SkewT<T, TR> sk;
+  const T *v;
+  long long ldv;
+  const T *dh;
+  T *z;
+  long long ldz;
+  T *bbuf;        // skewed right-hand side (gather output)
+  const T *zbuf;  // skewed result (scatter input)
+  size_t nslot;
+  const int *gate;
+};
 template <typename T, bool TR>
-__global__ void k_gather_skew(Grid<T> g, SkewT<T, TR> sk, const T *v, const T *dh, const T *zb,
-                              T *out, size_t nslot) {
+__global__ void k_gather_skew(const SkewIO<T, TR> *A, const int *jp) {
+  const SkewIO<T, TR> a = A[blockIdx.y];
+  if (gated(a.gate)) return;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nslot) return;
+  if (q >= a.nslot) return;
+  const Grid<T> &g = a.g;
   const int ld = g.nx;
+  const T *v = a.v + step_of(jp) * a.ldv;
+  const T *zb = a.z + step_of(jp) * a.ldz;
   int i, j;
   T val = T(0);
-  if (sk.decode(q, i, j)) {
+  if (a.sk.decode(q, i, j)) {
     const size_t o = vidx(i, j, ld);
     val = v[o];
-    if (dh) val *= dh[o];
-    if (zb) {
-      if (!TR) {
-        if (i == sk.i1 && i < g.nx) val -= g.E[i] * zb[vidx(i + 1, j, ld)];
-        if (j == sk.j1 && j < g.ny) val -= g.N[j] * zb[vidx(i, j + 1, ld)];
-      } else {
-        if (i == sk.i0 && i > 1) val -= g.E[i - 1] * zb[vidx(i - 1, j, ld)];
-        if (j == sk.j0 && j > 1) val -= g.N[j - 1] * zb[vidx(i, j - 1, ld)];
-      }
+    if (a.dh) val *= a.dh[o];
+    if (!TR) {
+      if (i == a.sk.i1 && i < g.nx) val -= g.E[i] * zb[vidx(i + 1, j, ld)];
+      if (j == a.sk.j1 && j < g.ny) val -= g.N[j] * zb[vidx(i, j + 1, ld)];
+    } else {
+      if (i == a.sk.i0 && i > 1) val -= g.E[i - 1] * zb[vidx(i - 1, j, ld)];
+      if (j == a.sk.j0 && j > 1) val -= g.N[j - 1] * zb[vidx(i, j - 1, ld)];
     }
   }
-  out[q] = val;
+  a.bbuf[q] = val;
 }
 template <typename T, bool TR>
-__global__ void k_scatter_skew(SkewT<T, TR> sk, const T *in, T *z, int ld, size_t nslot) {
+__global__ void k_scatter_skew(const SkewIO<T, TR> *A, const int *jp) {
+  const SkewIO<T, TR> a = A[blockIdx.y];
+  if (gated(a.gate)) return;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nslot) return;
+  if (q >= a.nslot) return;
   int i, j;
-  if (sk.decode(q, i, j)) z[vidx(i, j, ld)] = in[q];
+  if (a.sk.decode(q, i, j)) (a.z + step_of(jp) * a.ldz)[vidx(i, j, a.g.nx)] = a.zbuf[q];
 }
 
 // 1/C_ij in the skewed layout of a rectangle (setup).
@@ -451,7 +448,7 @@ struct LineArgs {
 };
 
 template <typename T, int EP>
-BLP_DEV void load_ep(const T *p, T (&x)[EP]) {
+BLP_DEV void load_ep(const BLP_GLOBAL T *p, T (&x)[EP]) {
   if constexpr (EP == 1) {
     x[0] = p[0];
   } else {
@@ -459,14 +456,14 @@ BLP_DEV void load_ep(const T *p, T (&x)[EP]) {
     typedef T V __attribute__((ext_vector_type(VW)));
 #pragma unroll
     for (int k = 0; k < EP / VW; ++k) {
-      const V v = reinterpret_cast<const V *>(p)[k];
+      const V v = reinterpret_cast<const BLP_GLOBAL V *>(p)[k];
 #pragma unroll
       for (int e = 0; e < VW; ++e) x[k * VW + e] = v[e];
     }
   }
 }
 template <typename T, int EP>
-BLP_DEV void store_ep(T *p, const T (&x)[EP]) {
+BLP_DEV void store_ep(BLP_GLOBAL T *p, const T (&x)[EP]) {
   if constexpr (EP == 1) {
     p[0] = x[0];
   } else {
@@ -477,7 +474,7 @@ BLP_DEV void store_ep(T *p, const T (&x)[EP]) {
       V v;
 #pragma unroll
       for (int e = 0; e < VW; ++e) v[e] = x[k * VW + e];
-      reinterpret_cast<V *>(p)[k] = v;
+      reinterpret_cast<BLP_GLOBAL V *>(p)[k] = v;
     }
   }
 }
@@ -489,13 +486,14 @@ struct LineOps {
 };
 
 template <typename T, bool TR, int EP, int W, int D>
-__global__ __launch_bounds__(64 * W) void k_lines(LineArgs<T> a) {
-  if (a.gate && *a.gate) return;
+__global__ __launch_bounds__(64 * W) void k_lines(const LineArgs<T> *A) {
+  const LineArgs<T> a = A[blockIdx.x >> 1];  // two workgroups (regions) per system
+  if (gated(a.gate)) return;
   // wave totals of the forward and of the backward scan (separate, so that
   // one barrier per scan orders every write after all reads of the previous
   // use)
   __shared__ T fwA[W], fwM[W], bwA[W], bwM[W];
-  const int r = blockIdx.x;
+  const int r = blockIdx.x & 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int h = a.h, hp = a.hp, L = a.n1 - h;
@@ -503,12 +501,12 @@ __global__ __launch_bounds__(64 * W) void k_lines(LineArgs<T> a) {
   // this thread's nodes; threads past the line read node 0 and are masked
   const bool act = tid * EP < hp;
   const size_t toff = act ? (size_t)tid * EP : 0;
-  const T *__restrict__ bp = a.b[r] + toff;
-  const T *__restrict__ dp = a.fd[r] + toff;
-  const T *__restrict__ mp = a.fm[r] + toff;
-  const T *__restrict__ wp = a.fw[r] + toff;
-  T *__restrict__ zp = a.z[r] + toff;
-  const T *cc = r == 0 ? g.E : g.N;  // previous-line coupling table
+  const BLP_GLOBAL T *__restrict__ bp = gptr(a.b[r] + toff);
+  const BLP_GLOBAL T *__restrict__ dp = gptr(a.fd[r] + toff);
+  const BLP_GLOBAL T *__restrict__ mp = gptr(a.fm[r] + toff);
+  const BLP_GLOBAL T *__restrict__ wp = gptr(a.fw[r] + toff);
+  BLP_GLOBAL T *__restrict__ zp = gptr(a.z[r] + toff);
+  const BLP_GLOBAL T *cc = gptr(r == 0 ? g.E : g.N);  // previous-line coupling table
 
   auto load = [&](int q, LineOps<T, EP> &B) {
     const int qq = q < L ? q : L - 1;  // loads past the last line stay in bounds
@@ -604,26 +602,46 @@ __global__ __launch_bounds__(64 * W) void k_lines(LineArgs<T> a) {
   if (act) store_ep<T, EP>(zp + (size_t)q_prev * hp, zl);
 }
 
-// Natural layout -> line-major buffers of both edge regions (blockIdx.z =
-// region), scaled by dh, with the couplings to already-solved regions folded
-// in (see above); padding nodes p in [h, hp) get zero.
+// Natural layout -> line-major buffers of both edge regions, and back
+// (blockIdx.z = 2 * system + region).  The gather reads v + j ldv, scales by
+// dh and folds in the couplings to already-solved regions (see above), read
+// from z + j ldz; padding nodes p in [h, hp) get zero.  The scatter writes
+// the edge regions of z + j ldz.
+template <typename T>
+struct LineIO {
+  Grid<T> g;
+  int h, n1, hp;
+  const T *v;
+  long long ldv;
+  const T *dh;
+  T *z;
+  long long ldz;
+  T *bL[2];        // gathered right-hand sides [Y, X]
+  const T *zL[2];  // line results [Y, X]
+  const int *gate;
+};
 template <typename T, bool TR>
-__global__ void k_gather_lines(Grid<T> g, const T *v, const T *dh, const T *z, int h, int n1,
-                               int hp, T *outY, T *outX) {
+__global__ void k_gather_lines(const LineIO<T> *A, const int *jp) {
+  const LineIO<T> a = A[blockIdx.z >> 1];
+  if (gated(a.gate)) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y, r = blockIdx.z;
+  const int q = blockIdx.y, r = blockIdx.z & 1;
+  const int h = a.h, n1 = a.n1, hp = a.hp;
   if (p >= hp) return;
-  T *out = r == 0 ? outY : outX;
+  T *out = a.bL[r];
   const size_t o = (size_t)q * hp + p;
   if (p >= h) {
     out[o] = T(0);
     return;
   }
+  const Grid<T> &g = a.g;
+  const T *v = a.v + step_of(jp) * a.ldv;
+  const T *z = a.z + step_of(jp) * a.ldz;
   const int line = TR ? h + 1 + q : n1 - q;
   const int i = r == 0 ? line : p + 1, j = r == 0 ? p + 1 : line;
   const size_t k = vidx(i, j, n1);
   T val = v[k];
-  if (dh) val *= dh[k];
+  if (a.dh) val *= a.dh[k];
   if (!TR) {
     if (p == h - 1) val -= r == 0 ? g.N[h] * z[vidx(i, h + 1, n1)] : g.E[h] * z[vidx(h + 1, j, n1)];
   } else if (q == 0) {
@@ -632,13 +650,16 @@ __global__ void k_gather_lines(Grid<T> g, const T *v, const T *dh, const T *z, i
   out[o] = val;
 }
 template <typename T, bool TR>
-__global__ void k_scatter_lines(const T *inY, const T *inX, int h, int n1, int hp, T *z) {
+__global__ void k_scatter_lines(const LineIO<T> *A, const int *jp) {
+  const LineIO<T> a = A[blockIdx.z >> 1];
+  if (gated(a.gate)) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y, r = blockIdx.z;
+  const int q = blockIdx.y, r = blockIdx.z & 1;
+  const int h = a.h, n1 = a.n1;
   if (p >= h) return;
   const int line = TR ? h + 1 + q : n1 - q;
   const int i = r == 0 ? line : p + 1, j = r == 0 ? p + 1 : line;
-  z[vidx(i, j, n1)] = (r == 0 ? inY : inX)[(size_t)q * hp + p];
+  (a.z + step_of(jp) * a.ldz)[vidx(i, j, n1)] = a.zL[r][(size_t)q * a.hp + p];
 }
 
 // Thomas factorisation of every line (setup), row stride hp; the padding
@@ -703,6 +724,17 @@ struct MgLevel {
   size_t nslot;
 };
 
+// One system's view of a level for the batched cycle kernels
+// (blockIdx.y selects the record): the level, the next coarser level
+// (transfers), the corner control block (its gate switches every kernel of
+// the cycle off) and the norm partials.
+template <typename T>
+struct MgArgs {
+  MgLevel<T> L, Cc;
+  MgCtrl *ctrl;
+  double *partials;
+};
+
 template <typename T, bool TR>
 BLP_DEV SkewT<T, TR> level_skew(int n) { return SkewT<T, TR>{1, n, 1, n}; }
 
@@ -725,10 +757,40 @@ BLP_DEV double level_apply(const Grid<T> &g, const SkewT<T, TR> &sk, const T *z,
          (double)g.S[j + 1] * zn;
 }
 
+// Gauss-Seidel right-hand side, folded before a smoothing sweep: with the
+// current iterate z (skewed), t = b - (downstream couplings) * z, i.e.
+// forward b - W_i z_{i-1,j} - S_j z_{i,j-1}, transposed
+// b - W_{i+1} z_{i+1,j} - S_{j+1} z_{i,j+1}; the sweep then solves the
+// triangular system with this right-hand side, which is one Gauss-Seidel
+// sweep.  FP64 arithmetic (the terms largely cancel); padding slots get 0.
+template <typename T, bool TR>
+__global__ void k_gs_rhs(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const MgLevel<T> &L = a.L;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.nslot) return;
+  const Grid<T> &g = L.g;
+  const int n = g.nx;
+  const SkewT<T, TR> sk = level_skew<T, TR>(n);
+  int i, j;
+  if (!sk.decode(q, i, j)) {
+    L.t[q] = T(0);
+    return;
+  }
+  const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
+  double v = L.b[q];
+  if (id >= 1 && id <= n) v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)L.z[sk.at(id, j)];
+  if (jd >= 1 && jd <= g.ny) v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)L.z[sk.at(i, jd)];
+  L.t[q] = T(v);
+}
+
 // t = b - A z (forward) or b - A^T z (transposed) on a level.
 template <typename T, bool TR>
-__global__ void k_mg_resid(MgLevel<T> L, const int *gate) {
-  if (gate && *gate) return;
+__global__ void k_mg_resid(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const MgLevel<T> &L = a.L;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.nslot) return;
   const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
@@ -749,8 +811,10 @@ BLP_DEV T w1d(const T *wl, const T *wr, int i, int k) {
 // Coarse right-hand side: forward b_c = S_c^{-1} P^T S_f t_f (FE rescaling,
 // Sec. 3.2), transposed b_c = P^T t_f.  Gathers the 3x3 fine neighbourhood.
 template <typename T, bool TR>
-__global__ void k_mg_restrict(MgLevel<T> F, MgLevel<T> Cc, const int *gate) {
-  if (gate && *gate) return;
+__global__ void k_mg_restrict(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const MgLevel<T> &F = a.L, &Cc = a.Cc;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= Cc.nslot) return;
   const int nc = Cc.g.nx, nf = F.g.nx;
@@ -775,8 +839,10 @@ __global__ void k_mg_restrict(MgLevel<T> F, MgLevel<T> Cc, const int *gate) {
 // Coarse-grid correction: forward z_f += P z_c; transposed
 // z_f += S_f P S_c^{-1} z_c.
 template <typename T, bool TR>
-__global__ void k_mg_prolong(MgLevel<T> F, MgLevel<T> Cc, const int *gate) {
-  if (gate && *gate) return;
+__global__ void k_mg_prolong(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const MgLevel<T> &F = a.L, &Cc = a.Cc;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= F.nslot) return;
   const int nc = Cc.g.nx, nf = F.g.nx;
@@ -808,13 +874,15 @@ __global__ void k_mg_prolong(MgLevel<T> F, MgLevel<T> Cc, const int *gate) {
 }
 
 // Coarsest level: four downstream Gauss-Seidel sweeps (transposed: the
-// transposed sweep on A^T), by one thread, from z = 0 when zero_init (a
-// coarse level) or from the current iterate (when the corner block itself is
-// the coarsest level).
+// transposed sweep on A^T), by one thread per system, from z = 0 when
+// zero_init (a coarse level) or from the current iterate (when the corner
+// block itself is the coarsest level).
 template <typename T, bool TR>
-__global__ void k_mg_coarsest(MgLevel<T> L, int zero_init, const int *gate) {
-  if (gate && *gate) return;
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_mg_coarsest(const MgArgs<T> *A, int zero_init) {
+  const MgArgs<T> a = A[blockIdx.x];
+  if (a.ctrl->gate) return;
+  if (threadIdx.x != 0) return;
+  const MgLevel<T> &L = a.L;
   const Grid<T> &g = L.g;
   const int n = g.nx;
   const SkewT<T, TR> sk = level_skew<T, TR>(n);
@@ -842,13 +910,15 @@ __global__ void k_mg_coarsest(MgLevel<T> L, int zero_init, const int *gate) {
 // Corner stopping rule (Sec. 3.2): norm of the residual of the system the
 // cycle works on -- forward ||S (b - A z)||, transposed ||b - A^T z|| -- with
 // mode 0 measuring ||S b|| (resp. ||b||) before the first cycle.  The last
-// block compares against rtol and sets the gate.
+// block of each system compares against rtol and sets its gate.
 template <typename T, bool TR>
-__global__ __launch_bounds__(256) void k_mg_norm(MgLevel<T> L, MgCtrl *ctrl, int mode,
-                                                 double *partials) {
+__global__ __launch_bounds__(256) void k_mg_norm(const MgArgs<T> *A, int mode) {
   __shared__ double sh[16];
   __shared__ bool last;
-  if (ctrl->gate) return;  // uniform across the grid
+  const MgArgs<T> a = A[blockIdx.y];
+  MgCtrl *ctrl = a.ctrl;
+  if (ctrl->gate) return;  // uniform across the system's blocks
+  const MgLevel<T> &L = a.L;
   const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
   double acc = 0.0;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < L.nslot;
@@ -861,11 +931,11 @@ __global__ __launch_bounds__(256) void k_mg_norm(MgLevel<T> L, MgCtrl *ctrl, int
     acc += v * v;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) publish(&partials[blockIdx.x], acc);
-  if (!arrive_last(&ctrl->counter, &last)) return;
+  if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
+  if (!arrive_last(&ctrl->counter, &last, gridDim.x)) return;
   // last block: fixed-order sum of the partials (deterministic)
   double s = 0.0;
-  for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += blockDim.x) s += collect(&partials[b2]);
+  for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += blockDim.x) s += collect(&a.partials[b2]);
   s = block_sum(s, sh);
   if (threadIdx.x == 0) {
     reset_counter(&ctrl->counter);
@@ -880,45 +950,75 @@ __global__ __launch_bounds__(256) void k_mg_norm(MgLevel<T> L, MgCtrl *ctrl, int
   }
 }
 
-// Count a fixed-mode cycle (no norm evaluation).
-__global__ void k_mg_count(MgCtrl *ctrl) { ctrl->cycles += 1; }
+// Count a fixed-mode cycle (no norm evaluation).  One thread per system.
+template <typename T>
+__global__ void k_mg_count(const MgArgs<T> *A) {
+  MgCtrl *c = A[blockIdx.x].ctrl;
+  if (threadIdx.x == 0 && !c->gate) c->cycles += 1;
+}
 
 // ---------------------------------------------------------------------------
-// Corner block: right-hand side and copy-back.
+// Corner block: right-hand side and copy-back (blockIdx.z = system).
 // Forward: b_C = b_C - A_CX z_X - A_CY z_Y, the couplings sitting on the
 // transition column (E_h to (h+1, j) in Y) and row (N_h to (i, h+1) in X).
-// b_0 is written in the skewed layout of level 0.  The kernel also resets the
-// corner control block.
+// b_0 is written in the skewed layout of level 0.  The right-hand-side kernel
+// also resets the corner control block; for a gated system it closes the
+// corner gate, which switches the whole cycle off.
 // ---------------------------------------------------------------------------
+template <typename T>
+struct CornerIO {
+  Grid<T> g;
+  int h, n1;
+  const T *v;
+  long long ldv;
+  const T *dh;
+  T *z;
+  long long ldz;
+  T *b0;        // level-0 right-hand side (skewed)
+  const T *z0;  // level-0 result (skewed)
+  MgCtrl *ctrl;
+  int maxcyc;
+  double rtol;
+  const int *gate;
+};
 template <typename T, bool TR>
-__global__ void k_corner_rhs(Grid<T> g, int h, int n1, const T *b, const T *dh,
-                             const T *z, T *b0, MgCtrl *ctrl, int maxcyc, T rtol) {
+__global__ void k_corner_rhs(const CornerIO<T> *A, const int *jp) {
+  const CornerIO<T> a = A[blockIdx.z];
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
   const int j = blockIdx.y + 1;
-  if (i == 1 && j == 1 && ctrl) {
-    ctrl->gate = 0;
-    ctrl->cycles = 0;
-    ctrl->maxcyc = maxcyc;
-    ctrl->rtol2 = (double)rtol * (double)rtol;
-    ctrl->counter = 0;
+  const bool off = gated(a.gate);
+  if (i == 1 && j == 1) {
+    MgCtrl *c = a.ctrl;
+    c->gate = off ? 1 : 0;
+    c->cycles = 0;
+    c->maxcyc = a.maxcyc;
+    c->rtol2 = a.rtol * a.rtol;
+    c->counter = 0;
   }
+  if (off) return;
+  const int h = a.h, n1 = a.n1;
   if (i > h) return;
   const size_t q = vidx(i, j, n1);
-  T v = b[q];
-  if (dh) v *= dh[q];
+  const T *v = a.v + step_of(jp) * a.ldv;
+  const T *z = a.z + step_of(jp) * a.ldz;
+  T val = v[q];
+  if (a.dh) val *= a.dh[q];
   if (!TR) {
-    if (i == h) v -= g.E[h] * z[vidx(h + 1, j, n1)];
-    if (j == h) v -= g.N[h] * z[vidx(i, h + 1, n1)];
+    if (i == h) val -= a.g.E[h] * z[vidx(h + 1, j, n1)];
+    if (j == h) val -= a.g.N[h] * z[vidx(i, h + 1, n1)];
   }
-  b0[level_skew<T, TR>(h).at(i, j)] = v;
+  a.b0[level_skew<T, TR>(h).at(i, j)] = val;
 }
 
 template <typename T, bool TR>
-__global__ void k_corner_copy(int h, int n1, const T *z0, T *z) {
+__global__ void k_corner_copy(const CornerIO<T> *A, const int *jp) {
+  const CornerIO<T> a = A[blockIdx.z];
+  if (gated(a.gate)) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
   const int j = blockIdx.y + 1;
+  const int h = a.h;
   if (i > h) return;
-  z[vidx(i, j, n1)] = z0[level_skew<T, TR>(h).at(i, j)];
+  (a.z + step_of(jp) * a.ldz)[vidx(i, j, a.n1)] = a.z0[level_skew<T, TR>(h).at(i, j)];
 }
 
 // Sample a nodal field at every f-th node: rc(k, m) = rf(f k, f m), natural
