@@ -164,6 +164,42 @@ int blp_solve_adjoint(blp_problem *p, int nrhs, const double *G, double *Lambda,
                       const blp_solve_opts *opts, blp_solve_info *info,
                       double *hist);
 
+/* Batched solves: S independent systems A_s U_s = F_s solved together
+ * (the method of blp_solve for each; a batch is an execution schedule, not
+ * a different method).  probs[s] is the assembled and preconditioned
+ * problem of system s; one problem may appear several times (several
+ * right-hand sides).  The batch owns each system's work vectors and Krylov
+ * basis; the problems must outlive it and are only read.  All work runs on
+ * `stream` (a hipStream_t, or NULL for the default stream).  Every kernel
+ * launch covers all systems of one mesh size; the restart cycles of all
+ * active systems start together and each system leaves a cycle (and the
+ * launches) through its own gate when its estimate reaches the cycle
+ * target, so each system follows exactly the iteration of its single solve.
+ * opts (may be NULL): graphs = 1 replays the launches of one Krylov step from
+ * HIP graphs captured on first use; autotune = 1 times the candidate kernel
+ * variants of each mesh size once and keeps the fastest.
+ * Errors: BLP_E_INVAL (S < 1, NULL problem), BLP_E_STATE (a problem not
+ * preconditioned), BLP_E_NOMEM, BLP_E_HIP. */
+typedef struct blp_batch blp_batch;
+typedef struct {
+  int graphs;
+  int autotune;
+} blp_batch_opts;
+int blp_batch_create(blp_problem *const *probs, int S, void *hip_stream,
+                     const blp_batch_opts *opts, blp_batch **out);
+
+/* F[s], U[s]: device vectors of system s ((N_s-1)^2 doubles; F and U host
+ * arrays of S pointers).  info: host, S entries (may be NULL).  Same solve
+ * options and errors as blp_solve (BLP_W_NOCONV if any system hit maxit). */
+int blp_batch_solve(blp_batch *b, const double *const *F, double *const *U,
+                    const blp_solve_opts *opts, blp_solve_info *info);
+/* Adjoint systems A_s^T L_s = G_s, as blp_solve_adjoint. */
+int blp_batch_solve_adjoint(blp_batch *b, const double *const *G, double *const *L,
+                            const blp_solve_opts *opts, blp_solve_info *info);
+/* Device bytes held by the batch (work vectors, bases, launch plans). */
+long long blp_batch_footprint(const blp_batch *b);
+void blp_batch_destroy(blp_batch *b);
+
 /* Single operator applications on one vector (device in/out, (N-1)^2
  * doubles), for tests: BLP_OP_A (y = A x), BLP_OP_AT (y = A^T x),
  * BLP_OP_MINV (y = M^{-1} x), BLP_OP_MINVT (y = M^{-T} x), and the FP32

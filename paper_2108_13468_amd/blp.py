@@ -23,7 +23,8 @@ OPS = {"A": 0, "AT": 1, "MINV": 2, "MINVT": 3, "MINV32": 4}
 EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_solve",
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
            "blp_bilinear_project", "blp_mul", "blp_timing", "blp_footprint", "blp_destroy",
-           "blp_strerror")
+           "blp_strerror", "blp_batch_create", "blp_batch_solve", "blp_batch_solve_adjoint",
+           "blp_batch_footprint", "blp_batch_destroy")
 NCLASS = 7
 CLASSES = ("sweep", "gs_rhs", "lines", "mg_other", "spmv", "krylov", "layout")
 
@@ -46,6 +47,10 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("absolute", C.c_int), ("scaled", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int), ("precision", C.c_int),
                 ("precond", C.c_int)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("graphs", C.c_int), ("autotune", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -98,6 +103,14 @@ def lib():
         L.blp_destroy.argtypes = [vp]
         L.blp_strerror.restype = C.c_char_p
         L.blp_strerror.argtypes = [C.c_int]
+        L.blp_batch_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.POINTER(BatchOpts),
+                                       C.POINTER(vp)]
+        for f in ("blp_batch_solve", "blp_batch_solve_adjoint"):
+            getattr(L, f).argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
+                                      C.POINTER(SolveInfo)]
+        L.blp_batch_footprint.restype = C.c_longlong
+        L.blp_batch_footprint.argtypes = [vp]
+        L.blp_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -275,3 +288,61 @@ def from_instance(inst, nodal_r=None):
         r = float(inst.r_const)
     return Problem(inst.N, inst.eps, ("axis", inst.c1_at(x)), ("axis", inst.c2_at(y)), r,
                    sigma=inst.sigma, clow=inst.clow)
+
+
+class Batch:
+    """Independent systems solved together (blp_batch_*): one system per
+    entry of `problems` (preconditioned Problems; a Problem may appear
+    several times, once per right-hand side).  Runs on torch's current
+    stream at creation."""
+
+    def __init__(self, problems, graphs=False, autotune=False):
+        import torch
+        self.torch = torch
+        self.problems = list(problems)  # kept alive while the batch exists
+        S = len(self.problems)
+        arr = (C.c_void_p * S)(*[p._h for p in self.problems])
+        stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().blp_batch_create(arr, S, C.c_void_p(stream.cuda_stream),
+                                      C.byref(BatchOpts(int(graphs), int(autotune))), C.byref(h)),
+               "blp_batch_create")
+        self._h = h
+        self.S = S
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().blp_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _solve(self, fn, F, U, tol, scaled, restart, maxit, precision, precond, absolute):
+        if len(F) != self.S:
+            raise ValueError("one right-hand side per system")
+        F = [p._vec(f) for p, f in zip(self.problems, F)]
+        U = [self.torch.empty_like(f) for f in F] if U is None else [p._vec(u) for p, u in
+                                                                        zip(self.problems, U)]
+        o = SolveOpts(tol, int(absolute), int(scaled), restart, maxit,
+                      BLP_MIXED if precision == "mixed" else BLP_FP64, int(precond))
+        infos = (SolveInfo * self.S)()
+        fa = (C.c_void_p * self.S)(*[f.data_ptr() for f in F])
+        ua = (C.c_void_p * self.S)(*[u.data_ptr() for u in U])
+        rc = _check(fn(self._h, fa, ua, C.byref(o), infos), "batch solve")
+        out = [i.as_dict() for i in infos]
+        for d in out:
+            d["status"] = rc
+        return U, out
+
+    def solve(self, F, U=None, tol=1e-8, scaled=True, restart=50, maxit=1000, precision="fp64",
+              precond=True, absolute=False):
+        return self._solve(lib().blp_batch_solve, F, U, tol, scaled, restart, maxit, precision,
+                           precond, absolute)
+
+    def solve_adjoint(self, G, L=None, tol=1e-8, scaled=True, restart=50, maxit=1000,
+                      precision="fp64", precond=True, absolute=False):
+        return self._solve(lib().blp_batch_solve_adjoint, G, L, tol, scaled, restart, maxit,
+                           precision, precond, absolute)
+
+    def footprint(self):
+        return int(lib().blp_batch_footprint(self._h))

@@ -91,6 +91,10 @@ struct Batch;
 
 }  // namespace
 
+struct blp_batch {
+  std::unique_ptr<Batch> B;
+};
+
 struct blp_problem {
   int N, n1, h;
   size_t n;
@@ -615,6 +619,46 @@ int blp_solve_adjoint(blp_problem *p, int nrhs, const double *G, double *L,
                       const blp_solve_opts *o, blp_solve_info *info, double *hist) {
   return solve_common(p, true, nrhs, G, L, o, info, hist);
 }
+
+int blp_batch_create(blp_problem *const *probs, int S, void *stream, const blp_batch_opts *o,
+                     blp_batch **out) {
+  if (!out) return BLP_E_INVAL;
+  *out = nullptr;
+  if (!probs || S < 1) return BLP_E_INVAL;
+  for (int s = 0; s < S; ++s) {
+    if (!probs[s]) return BLP_E_INVAL;
+    if (!probs[s]->prec_ready) return BLP_E_STATE;
+  }
+  blp_batch *b = new (std::nothrow) blp_batch();
+  if (!b) return BLP_E_NOMEM;
+  const int rc = batch_create((hipStream_t)stream, probs, S, b->B);
+  if (rc < 0) {
+    delete b;
+    return rc;
+  }
+  if (o) {
+    b->B->graphs = o->graphs != 0;
+    b->B->autotune = o->autotune != 0;
+  }
+  *out = b;
+  return BLP_OK;
+}
+
+int blp_batch_solve(blp_batch *b, const double *const *F, double *const *U,
+                    const blp_solve_opts *o, blp_solve_info *info) {
+  if (!b || !F || !U) return BLP_E_INVAL;
+  return batch_solve(*b->B, false, F, U, o, info, nullptr);
+}
+
+int blp_batch_solve_adjoint(blp_batch *b, const double *const *G, double *const *L,
+                            const blp_solve_opts *o, blp_solve_info *info) {
+  if (!b || !G || !L) return BLP_E_INVAL;
+  return batch_solve(*b->B, true, G, L, o, info, nullptr);
+}
+
+long long blp_batch_footprint(const blp_batch *b) { return b ? batch_bytes(*b->B) : 0; }
+
+void blp_batch_destroy(blp_batch *b) { delete b; }
 
 int blp_apply(blp_problem *p, int op, const double *x, double *y, int *cycles) {
   if (!p || !x || !y) return BLP_E_INVAL;

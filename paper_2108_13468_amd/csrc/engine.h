@@ -484,6 +484,7 @@ struct Batch {
   int *jdev = nullptr;
   int *ncol = nullptr, *ncol_h = nullptr;
   blp_problem *timer = nullptr;
+  int graphs = 0, autotune = 0;  // blp_batch_opts
   Alloc mem;
   // cached plans per class and kind (key: class, TV, TR, SCALE, m)
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<PlanBase>> plans;

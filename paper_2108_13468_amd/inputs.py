@@ -59,11 +59,11 @@ def headline_case(eps=1e-6, seed=1):
     return plain(1024, eps, seed)
 
 
-def batch_cases(count=64, seed=2):
-    """Uneven batch: N ~ U{128,256,512,1024}, log10 eps ~ U(-8,-2),
-    c = (1 + a x, 1 + b y) with a, b ~ U(0,1), r ~ U(0.5, 2) constant,
-    3x3 sine series with a_kl ~ U(-1,1).  Per instance the draw order is
-    a_kl (row-major), r, a, b, N, eps."""
+def batch_cases(count=64, seed=2, sizes=(128, 256, 512, 1024)):
+    """Uneven batch: N ~ U{sizes} (the workload: {128,256,512,1024}),
+    log10 eps ~ U(-8,-2), c = (1 + a x, 1 + b y) with a, b ~ U(0,1),
+    r ~ U(0.5, 2) constant, 3x3 sine series with a_kl ~ U(-1,1).  Per
+    instance the draw order is a_kl (row-major), r, a, b, N, eps."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
@@ -71,7 +71,7 @@ def batch_cases(count=64, seed=2):
         r = rng.uniform(0.5, 2.0)
         ca = rng.uniform(0.0, 1.0)
         cb = rng.uniform(0.0, 1.0)
-        N = int(rng.choice([128, 256, 512, 1024]))
+        N = int(rng.choice(list(sizes)))
         eps = float(10.0 ** rng.uniform(-8.0, -2.0))
         out.append(Instance(N=N, eps=eps, c1=(1.0, ca, 0.0), c2=(1.0, cb, 0.0),
                             r_const=r, a=akl))
