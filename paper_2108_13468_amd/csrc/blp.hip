@@ -640,6 +640,18 @@ int blp_batch_create(blp_problem *const *probs, int S, void *stream, const blp_b
     b->B->graphs = o->graphs != 0;
     b->B->autotune = o->autotune != 0;
   }
+  if (b->B->graphs) {
+    // graphs are captured on a stream of the batch's own (capture is not
+    // possible on the legacy default stream); default priority
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return BLP_E_HIP;
+    }
+    b->B->user = b->B->stream;
+    b->B->stream = st;
+    b->B->own_stream = true;
+  }
   *out = b;
   return BLP_OK;
 }

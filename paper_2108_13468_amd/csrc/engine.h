@@ -464,6 +464,13 @@ struct SolvePlan {
   Alloc mem;
   std::vector<const double *> F;    // right-hand sides the plan was built for
   std::vector<double *> U;
+  // captured step (graphs mode): part 1 of the preconditioner; the rest of
+  // the step (corner copy-back, remaining regions, SpMV, Arnoldi)
+  hipGraphExec_t g1 = nullptr, g2 = nullptr;
+  ~SolvePlan() {
+    if (g1) (void)hipGraphExecDestroy(g1);
+    if (g2) (void)hipGraphExecDestroy(g2);
+  }
 };
 
 struct PlanBase {
@@ -485,6 +492,8 @@ struct Batch {
   int *ncol = nullptr, *ncol_h = nullptr;
   blp_problem *timer = nullptr;
   int graphs = 0, autotune = 0;  // blp_batch_opts
+  hipStream_t user = nullptr;     // caller's stream when the batch runs on its own
+  bool own_stream = false;
   Alloc mem;
   // cached plans per class and kind (key: class, TV, TR, SCALE, m)
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<PlanBase>> plans;
@@ -492,6 +501,8 @@ struct Batch {
     if (stream) (void)hipStreamSynchronize(stream);
     plans.clear();
     sys.clear();
+    mem.release();
+    if (own_stream) (void)hipStreamDestroy(stream);
     if (ctrl_h) (void)hipHostFree(ctrl_h);
     if (st_h) (void)hipHostFree(st_h);
     if (gate_h) (void)hipHostFree(gate_h);
@@ -619,6 +630,41 @@ int read_all(Batch &B) {
 
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
+// Capture the launches `body` issues on stream s into an executable graph.
+// The captured kernels take their step index and gates from device memory,
+// so one graph serves every step; it holds kernel nodes only (no memsets).
+template <typename Body>
+int capture(hipStream_t s, hipGraphExec_t *out, Body &&body) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  body();
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || !g) return BLP_E_HIP;
+  const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e2 == hipSuccess ? BLP_OK : BLP_E_HIP;
+}
+
+// SpMV on Z_j and the CGS2 Arnoldi kernels of one class (step j in jdev).
+template <typename TV, bool TR, bool SCALE>
+void krylov_step(const Ctx &c, const SolvePlan<TV, TR, SCALE> &P, int n1, int j, const int *jdev,
+                 const KOffsets &ko) {
+  const size_t n = (size_t)n1 * n1;
+  const int Sk = P.S;
+  {
+    KScope ks(c.timer, KC_SPMV, (double)Sk * n * (sizeof(TV) + sizeof(double)));
+    k_stencil<TV, TR, SCALE, false>
+        <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, Sk), 256, 0, c.stream>>>(P.spmv, jdev,
+                                                                                   kRows);
+  }
+  const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
+  // CGS2: four passes over the j+1 basis vectors plus w traffic
+  KScope ks(c.timer, KC_KRYLOV, (double)Sk * n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
+  k_arnoldi_dot<TV><<<dim3(nb, Sk), 256, 0, c.stream>>>(P.kr, jdev, ko);
+  k_arnoldi_update<TV, false><<<dim3(nb, Sk), 256, 0, c.stream>>>(P.kr, jdev, ko);
+  k_arnoldi_update<TV, true><<<dim3(nb, Sk), 256, 0, c.stream>>>(P.kr, jdev, ko);
+}
+
 struct CycleStats {
   long total = 0;
   int mn = 1 << 30, mx = 0, applies = 0;
@@ -649,6 +695,8 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
   std::vector<SolvePlan<TV, TR, SCALE> *> P(NC);
   for (int k = 0; k < NC; ++k) BLP_TRY((get_solve_plan<TV, TR, SCALE>(B, k, m, F, U, &P[k])));
   const blp_prec_opts &po = B.sys[0]->p->popts;
+  // kernel timing records events between launches: no graphs then
+  const bool use_graphs = B.graphs && !(c.timer && c.timer->timing);
 
   std::vector<double> nF(S), target(S), beta(S), cyc_target(S);
   std::vector<int> it(S, 0), restarts(S, 0), ncol(S, 0);
@@ -704,11 +752,20 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
     }
     for (int j = 0; j < m; ++j) {
       k_set_int<<<1, 1, 0, B.stream>>>(B.jdev, j);
-      // preconditioner, first part (for every class), corner check, rest
       if (o->precond) {
-        for (int k = 0; k < NC; ++k) prec_part1<TV, TR>(c, P[k]->prec, B.jdev, po);
+        // part 1 for every class, the corner check (further cycles while any
+        // system's corner gate is open), then the rest of the step
+        for (int k = 0; k < NC; ++k) {
+          if (use_graphs) {
+            if (!P[k]->g1)
+              BLP_TRY(capture(B.stream, &P[k]->g1,
+                              [&]() { prec_part1<TV, TR>(c, P[k]->prec, B.jdev, po); }));
+            HIP_TRY(hipGraphLaunch(P[k]->g1, B.stream));
+          } else {
+            prec_part1<TV, TR>(c, P[k]->prec, B.jdev, po);
+          }
+        }
         if (po.mg_fixed == 0) {
-          // more cycles while any corner gate is open (all classes)
           for (int extra = kFirstCycles; extra < po.mg_maxcyc; ++extra) {
             HIP_TRY(hipMemcpyAsync(B.ctrl_h, B.ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost,
                                    B.stream));
@@ -722,7 +779,6 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
             }
           }
         }
-        for (int k = 0; k < NC; ++k) prec_part2<TV, TR>(c, P[k]->prec, B.jdev);
       } else {
         for (int k = 0; k < NC; ++k) {
           const size_t n = B.sys[B.classes[k][0]]->p->n;
@@ -738,21 +794,16 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
         }
       }
       for (int k = 0; k < NC; ++k) {
-        const int n1 = B.sys[B.classes[k][0]]->p->n1;
-        const size_t n = (size_t)n1 * n1;
-        const int Sk = P[k]->S;
-        {
-          KScope ks(c.timer, KC_SPMV, (double)Sk * n * (sizeof(TV) + sizeof(double)));
-          k_stencil<TV, TR, SCALE, false>
-              <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, Sk), 256, 0, B.stream>>>(
-                  P[k]->spmv, B.jdev, kRows);
+        auto rest = [&]() {
+          if (o->precond) prec_part2<TV, TR>(c, P[k]->prec, B.jdev);
+          krylov_step<TV, TR, SCALE>(c, *P[k], B.sys[B.classes[k][0]]->p->n1, j, B.jdev, ko);
+        };
+        if (use_graphs && o->precond) {
+          if (!P[k]->g2) BLP_TRY(capture(B.stream, &P[k]->g2, rest));
+          HIP_TRY(hipGraphLaunch(P[k]->g2, B.stream));
+        } else {
+          rest();
         }
-        const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
-        // CGS2: four passes over the j+1 basis vectors plus w traffic
-        KScope ks(c.timer, KC_KRYLOV, (double)Sk * n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
-        k_arnoldi_dot<TV><<<dim3(nb, Sk), 256, 0, B.stream>>>(P[k]->kr, B.jdev, ko);
-        k_arnoldi_update<TV, false><<<dim3(nb, Sk), 256, 0, B.stream>>>(P[k]->kr, B.jdev, ko);
-        k_arnoldi_update<TV, true><<<dim3(nb, Sk), 256, 0, B.stream>>>(P[k]->kr, B.jdev, ko);
       }
       BLP_TRY(read_all(B));
       bool any = false;
@@ -830,6 +881,9 @@ int batch_solve(Batch &B, bool tr, const double *const *F, double *const *U, con
   if (o->precision != BLP_FP64 && o->precision != BLP_MIXED) return BLP_E_INVAL;
   for (size_t s = 0; s < B.sys.size(); ++s)
     if (!F[s] || !U[s]) return BLP_E_INVAL;
+  // a batch on its own stream starts after the caller's pending work (the
+  // right-hand sides) and has finished when this returns
+  if (B.own_stream) HIP_TRY(hipStreamSynchronize(B.user));
   const bool mixed = o->precision == BLP_MIXED, sc = o->scaled != 0;
   int rc;
 #define BLP_DISPATCH(TV, TRB, SCB) rc = fgmres_batch<TV, TRB, SCB>(B, F, U, o, info, hist)

@@ -34,20 +34,26 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_batch_matches_single_solves(precision):
+@pytest.mark.parametrize("precision,graphs", [("fp64", False), ("mixed", False), ("fp64", True),
+                                              ("mixed", True)])
+def test_batch_matches_single_solves(precision, graphs):
+    """With graphs, every Krylov step replays the two captured graphs of each
+    mesh size (eager launches, memcpys and host decisions in between): each
+    replay must reproduce the eager single solve."""
     from paper_2108_13468_amd import blp
     insts = inputs.batch_cases(count=6, seed=31, sizes=(64, 96, 130))
-    say("batch of %d, sizes %s, %s" % (len(insts), [i.N for i in insts], precision))
+    say("batch of %d, sizes %s, %s, graphs=%s" % (len(insts), [i.N for i in insts], precision,
+                                                  graphs))
     ps, F = _problems(insts)
     opts = dict(tol=1e-10, scaled=True, precision=precision, maxit=800)
     single = [p.solve(f, **opts) for p, f in zip(ps, F)]
-    b = blp.Batch(ps)
-    U, info = b.solve(F, **opts)
-    for s in range(len(ps)):
-        assert info[s]["converged"] == 1
-        assert info[s]["iterations"] == single[s][1][0]["iterations"], s
-        assert _rel(U[s], single[s][0]) <= 1e-13, s
+    b = blp.Batch(ps, graphs=graphs)
+    for rep in range(2):  # the second solve replays graphs captured by the first
+        U, info = b.solve(F, **opts)
+        for s in range(len(ps)):
+            assert info[s]["converged"] == 1
+            assert info[s]["iterations"] == single[s][1][0]["iterations"], (rep, s)
+            assert _rel(U[s], single[s][0]) <= 1e-13, (rep, s)
 
 
 def test_batch_adjoint_matches_single():
