@@ -198,6 +198,10 @@ int blp_batch_solve_adjoint(blp_batch *b, const double *const *G, double *const 
                             const blp_solve_opts *opts, blp_solve_info *info);
 /* Device bytes held by the batch (work vectors, bases, launch plans). */
 long long blp_batch_footprint(const blp_batch *b);
+/* Text summary (NUL-terminated, truncated to len-1 bytes) of the batch's mesh
+ * classes and of the kernel variants its launch plans use (the autotuner's
+ * choices).  Returns the full length, or BLP_E_INVAL. */
+int blp_batch_describe(const blp_batch *b, char *buf, int len);
 void blp_batch_destroy(blp_batch *b);
 
 /* Single operator applications on one vector (device in/out, (N-1)^2

@@ -124,9 +124,10 @@ class Problem:
         self.h = N // 2
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().orc_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and _lib is not None:  # (at interpreter exit the library may be gone)
+            _lib.orc_destroy(h)
 
     @property
     def levels(self):

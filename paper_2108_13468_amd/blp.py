@@ -24,7 +24,7 @@ EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_sol
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
            "blp_bilinear_project", "blp_mul", "blp_timing", "blp_footprint", "blp_destroy",
            "blp_strerror", "blp_batch_create", "blp_batch_solve", "blp_batch_solve_adjoint",
-           "blp_batch_footprint", "blp_batch_destroy")
+           "blp_batch_footprint", "blp_batch_describe", "blp_batch_destroy")
 NCLASS = 7
 CLASSES = ("sweep", "gs_rhs", "lines", "mg_other", "spmv", "krylov", "layout")
 
@@ -108,6 +108,7 @@ def lib():
         for f in ("blp_batch_solve", "blp_batch_solve_adjoint"):
             getattr(L, f).argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
                                       C.POINTER(SolveInfo)]
+        L.blp_batch_describe.argtypes = [vp, C.c_char_p, C.c_int]
         L.blp_batch_footprint.restype = C.c_longlong
         L.blp_batch_footprint.argtypes = [vp]
         L.blp_batch_destroy.argtypes = [vp]
@@ -166,9 +167,10 @@ class Problem:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().blp_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and _lib is not None:  # (at interpreter exit the library may be gone)
+            _lib.blp_destroy(h)
 
     __del__ = close
 
@@ -311,9 +313,10 @@ class Batch:
         self.S = S
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().blp_batch_destroy(self._h)
-            self._h = None
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and _lib is not None:
+            _lib.blp_batch_destroy(h)
 
     __del__ = close
 
@@ -346,3 +349,9 @@ class Batch:
 
     def footprint(self):
         return int(lib().blp_batch_footprint(self._h))
+
+    def describe(self):
+        """Mesh classes and the kernel variants of the launch plans."""
+        buf = C.create_string_buffer(8192)
+        _check(lib().blp_batch_describe(self._h, buf, len(buf)), "blp_batch_describe")
+        return buf.value.decode()

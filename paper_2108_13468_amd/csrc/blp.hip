@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <string>
 #include <tuple>
 #include <chrono>
 #include <cmath>
@@ -669,6 +670,15 @@ int blp_batch_solve_adjoint(blp_batch *b, const double *const *G, double *const 
 }
 
 long long blp_batch_footprint(const blp_batch *b) { return b ? batch_bytes(*b->B) : 0; }
+
+int blp_batch_describe(const blp_batch *b, char *buf, int len) {
+  if (!b || !buf || len < 1) return BLP_E_INVAL;
+  const std::string s = describe(*b->B);
+  const int n = std::min((int)s.size(), len - 1);
+  std::memcpy(buf, s.data(), n);
+  buf[n] = 0;
+  return (int)s.size();
+}
 
 void blp_batch_destroy(blp_batch *b) { delete b; }
 

@@ -120,7 +120,8 @@ int ensure_krylov(System &s, hipStream_t st, int m, int prec) {
   BLP_TRY(s.kmem.get(&s.w, n));
   BLP_TRY(s.kmem.get(&s.ks, (size_t)(m + 1) * m + 2 * m + 3 * (m + 1) + m, st, true));
   const size_t nblk = (n + KCHUNK - 1) / KCHUNK;
-  const size_t nstencil = (size_t)((s.p->n1 + 255) / 256) * ((s.p->n1 + kRows - 1) / kRows);
+  // stencil partials: one per block at the smallest strip height tried (8 rows)
+  const size_t nstencil = (size_t)((s.p->n1 + 255) / 256) * ((s.p->n1 + 7) / 8);
   BLP_TRY(s.kmem.get(&s.partials, std::max(nblk * (size_t)(m + 2), std::max(nstencil, (size_t)256))));
   s.ws_m = m;
   s.ws_prec = prec;
@@ -154,6 +155,9 @@ struct PrecPlan {
   CornerIO<T> *cr = nullptr;
   std::vector<MgArgs<T> *> mg;
   std::vector<SweepArgs<T> *> swb, swt;  // per level: sweep from b, from t
+  // kernel variants (autotuner; 0 = default)
+  int varI = 0, varLines = 0;
+  std::vector<int> varL;
   Alloc mem;
 };
 
@@ -178,6 +182,7 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   }
   P.nslotI = fine<T>(p0).nslotI;
   P.nbI = (P.n1 - P.h + 63) / 64;
+  P.varL.assign(nl, 0);
   std::vector<SkewIO<T, TR>> ioI(S);
   std::vector<SweepArgs<T>> swI(S);
   std::vector<LineIO<T>> ioL(S);
@@ -251,17 +256,29 @@ struct Ctx {
   blp_problem *timer;  // records per-class kernel times when its timing is on
 };
 
+// Kernel variants the autotuner chooses between (all compute the same
+// arithmetic in the same order per lane; they differ in scheduling only).
+// Sweep: superstep K = 4 or 2 chunks of 16 bytes per lane, D supersteps of
+// loads in flight (D + 1 register buffers of 2K words); more than 8 waves
+// leave registers for D = 1 only.
+inline int sweep_variants(int ncols) { return (ncols + 63) / 64 <= 8 ? 4 : 2; }
+
 template <typename T, bool TR>
-void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A) {
+void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A, int var = 0) {
   const int nb = (ncols + 63) / 64;
-  // superstep of K steps = 4 chunks of 16 bytes per lane; D supersteps of
-  // loads in flight (D + 1 register buffers of 2K words); more than 8 waves
-  // leave registers for D = 1 only
-  constexpr int K = 4 * kChunk<T>;
-  if (nb <= 8)
-    k_sweep<T, TR, K, 4><<<S, 64 * nb, 0, c.stream>>>(A);
-  else
-    k_sweep<T, TR, K, 1><<<S, 64 * nb, 0, c.stream>>>(A);
+  constexpr int P = kChunk<T>;
+  const dim3 grid(S), block(64 * nb);
+  if (nb <= 8) {
+    switch (var) {
+      case 1: k_sweep<T, TR, 4 * P, 2><<<grid, block, 0, c.stream>>>(A); break;
+      case 2: k_sweep<T, TR, 2 * P, 4><<<grid, block, 0, c.stream>>>(A); break;
+      case 3: k_sweep<T, TR, 2 * P, 2><<<grid, block, 0, c.stream>>>(A); break;
+      default: k_sweep<T, TR, 4 * P, 4><<<grid, block, 0, c.stream>>>(A); break;
+    }
+  } else {
+    if (var == 1) k_sweep<T, TR, 2 * P, 1><<<grid, block, 0, c.stream>>>(A);
+    else k_sweep<T, TR, 4 * P, 1><<<grid, block, 0, c.stream>>>(A);
+  }
 }
 
 template <typename T, bool TR, int EP, int W>
@@ -272,19 +289,30 @@ void lines_launch_k(const Ctx &c, int S, const LineArgs<T> *A) {
   k_lines<T, TR, EP, W, D><<<2 * S, 64 * W, 0, c.stream>>>(A);
 }
 
+// Line solves: threads hold EP contiguous nodes, W waves per region (EP x
+// 64 W >= hp); the variants trade scan depth within threads against waves.
+inline int lines_variants(int hp) {
+  return hp <= 64 ? 1 : (hp <= 256 ? 2 : (hp <= 512 ? 3 : 2));
+}
+
 template <typename T, bool TR>
-void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A) {
-  // threads hold EP contiguous nodes; up to 4 waves per region
-  if (hp <= 64)
+void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A, int var = 0) {
+  if (hp <= 64) {
     lines_launch_k<T, TR, 1, 1>(c, S, A);
-  else if (hp <= 128)
-    lines_launch_k<T, TR, 1, 2>(c, S, A);
-  else if (hp <= 256)
-    lines_launch_k<T, TR, 1, 4>(c, S, A);
-  else if (hp <= 512)
-    lines_launch_k<T, TR, 2, 4>(c, S, A);
-  else
-    lines_launch_k<T, TR, 4, 4>(c, S, A);
+  } else if (hp <= 128) {
+    if (var == 1) lines_launch_k<T, TR, 2, 1>(c, S, A);
+    else lines_launch_k<T, TR, 1, 2>(c, S, A);
+  } else if (hp <= 256) {
+    if (var == 1) lines_launch_k<T, TR, 2, 2>(c, S, A);
+    else lines_launch_k<T, TR, 1, 4>(c, S, A);
+  } else if (hp <= 512) {
+    if (var == 1) lines_launch_k<T, TR, 4, 2>(c, S, A);
+    else if (var == 2) lines_launch_k<T, TR, 1, 8>(c, S, A);
+    else lines_launch_k<T, TR, 2, 4>(c, S, A);
+  } else {
+    if (var == 1) lines_launch_k<T, TR, 2, 8>(c, S, A);
+    else lines_launch_k<T, TR, 4, 4>(c, S, A);
+  }
 }
 
 template <typename T, bool TR>
@@ -297,7 +325,7 @@ void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   }
   {
     KScope ks(c.timer, KC_SWEEP, (double)S * m * m * 2 * sizeof(T));
-    sweep_launch<T, TR>(c, S, m, P.swI);
+    sweep_launch<T, TR>(c, S, m, P.swI, P.varI);
   }
   KScope ks(c.timer, KC_LAYOUT, 0.0);
   k_scatter_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
@@ -313,7 +341,7 @@ void lines_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   }
   {
     KScope ks(c.timer, KC_LINES, (double)S * 2.0 * L * P.h * 4 * sizeof(T));
-    lines_launch<T, TR>(c, S, P.hp, P.lnA);
+    lines_launch<T, TR>(c, S, P.hp, P.lnA, P.varLines);
   }
   KScope ks(c.timer, KC_LAYOUT, 0.0);
   k_scatter_lines<T, TR><<<gl, 256, 0, c.stream>>>(P.ioL, jp);
@@ -335,14 +363,14 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   const double cc = (double)S * P.ln[l + 1] * P.ln[l + 1];
   if (zero_init) {
     KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
-    sweep_launch<T, TR>(c, S, n, P.swb[l]);
+    sweep_launch<T, TR>(c, S, n, P.swb[l], P.varL[l]);
   } else {
     {
       KScope ks(c.timer, KC_GSRHS, nn * 3 * sizeof(T));
       k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
     }
     KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
-    sweep_launch<T, TR>(c, S, n, P.swt[l]);
+    sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
   }
   {
     KScope ks(c.timer, KC_MG, nn * 3 * sizeof(T));
@@ -362,7 +390,7 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
     k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
   }
   KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
-  sweep_launch<T, TR>(c, S, n, P.swt[l]);
+  sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
 }
 
 // blocks of the corner residual-norm reduction (one partial each)
@@ -461,6 +489,8 @@ struct SolvePlan {
   SpmvArgs<double> *resid = nullptr;  // w = F - A u (scaled if SCALE), ||w||
   NormArgs *norm = nullptr;         // ||F|| (scaled if SCALE)
   KArgs<TV> *kr = nullptr;
+  int rows = kRows;  // stencil strip height (autotuner)
+  bool tuned = false;
   Alloc mem;
   std::vector<const double *> F;    // right-hand sides the plan was built for
   std::vector<double *> U;
@@ -494,6 +524,10 @@ struct Batch {
   int graphs = 0, autotune = 0;  // blp_batch_opts
   hipStream_t user = nullptr;     // caller's stream when the batch runs on its own
   bool own_stream = false;
+  // one stream per mesh class when there are several (default priority)
+  std::vector<hipStream_t> cstream;
+  std::vector<hipEvent_t> cevent;
+  hipEvent_t fork_ev = nullptr;
   Alloc mem;
   // cached plans per class and kind (key: class, TV, TR, SCALE, m)
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<PlanBase>> plans;
@@ -502,6 +536,12 @@ struct Batch {
     plans.clear();
     sys.clear();
     mem.release();
+    for (hipStream_t q : cstream) {
+      (void)hipStreamSynchronize(q);
+      (void)hipStreamDestroy(q);
+    }
+    for (hipEvent_t e : cevent) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (own_stream) (void)hipStreamDestroy(stream);
     if (ctrl_h) (void)hipHostFree(ctrl_h);
     if (st_h) (void)hipHostFree(st_h);
@@ -591,6 +631,70 @@ int build_solve_plan(Batch &B, const std::vector<int> &cls, int m, const double 
   return BLP_OK;
 }
 
+// Average time of reps launches issued by f (after one untimed launch).
+template <typename Fn>
+float time_launches(hipStream_t s, Fn &&f, int reps) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 1e30f;
+  f();
+  (void)hipEventRecord(a, s);
+  for (int r = 0; r < reps; ++r) f();
+  (void)hipEventRecord(b, s);
+  float ms = 1e30f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    ms = 1e30f;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms / reps;
+}
+
+// Autotuner: for one class, time every variant of the interior sweep, of
+// each corner level's sweep, of the line solves and of the stencil strip
+// height on the plan's own data and keep the fastest.  The variants compute
+// the same values (sweeps bit for bit); only the schedule differs.  Runs
+// once per plan, with every gate of the class open (the work vectors it
+// overwrites are rewritten by the next apply).
+template <typename TV, bool TR, bool SCALE>
+int tune_plan(Batch &B, int cls, SolvePlan<TV, TR, SCALE> &P) {
+  const hipStream_t st = B.stream;
+  HIP_TRY(hipMemsetAsync(B.gate, 0, B.sys.size() * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(B.ctrl, 0, B.sys.size() * sizeof(MgCtrl), st));
+  const Ctx c{st, nullptr};
+  PrecPlan<TV, TR> &Q = P.prec;
+  const int S = Q.S, m = Q.n1 - Q.h, reps = 4;
+  auto pick = [&](int nvar, auto &&launch) {
+    int best = 0;
+    float tbest = 1e30f;
+    for (int v = 0; v < nvar; ++v) {
+      const float t = time_launches(st, [&]() { launch(v); }, reps);
+      if (t < tbest) {
+        tbest = t;
+        best = v;
+      }
+    }
+    return best;
+  };
+  Q.varI = pick(sweep_variants(m), [&](int v) { sweep_launch<TV, TR>(c, S, m, Q.swI, v); });
+  for (size_t l = 0; l + 1 < Q.ln.size(); ++l) {
+    const int n = Q.ln[l];
+    Q.varL[l] = pick(sweep_variants(n), [&](int v) { sweep_launch<TV, TR>(c, S, n, Q.swb[l], v); });
+  }
+  Q.varLines = pick(lines_variants(Q.hp), [&](int v) { lines_launch<TV, TR>(c, S, Q.hp, Q.lnA, v); });
+  const int n1 = Q.n1;
+  const int rows_c[3] = {8, 16, 32};
+  const int r = pick(3, [&](int v) {
+    const int rows = rows_c[v];
+    k_stencil<TV, TR, SCALE, false>
+        <<<dim3((n1 + 255) / 256, (n1 + rows - 1) / rows, S), 256, 0, st>>>(P.spmv, B.jdev, rows);
+  });
+  P.rows = rows_c[r];
+  P.tuned = true;
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  (void)cls;
+  return BLP_OK;
+}
+
 template <typename TV, bool TR, bool SCALE>
 int get_solve_plan(Batch &B, int c, int m, const double *const *F, double *const *U,
                    SolvePlan<TV, TR, SCALE> **out) {
@@ -610,8 +714,43 @@ int get_solve_plan(Batch &B, int c, int m, const double *const *F, double *const
   std::unique_ptr<PlanHolder<TV, TR, SCALE>> h(new (std::nothrow) PlanHolder<TV, TR, SCALE>());
   if (!h) return BLP_E_NOMEM;
   BLP_TRY((build_solve_plan<TV, TR, SCALE>(B, B.classes[c], m, F, U, h->plan)));
+  if (B.autotune) BLP_TRY((tune_plan<TV, TR, SCALE>(B, c, h->plan)));
   *out = &h->plan;
   B.plans[key] = std::move(h);
+  return BLP_OK;
+}
+
+// Class streams: created on first use when the batch has several classes.
+int ensure_class_streams(Batch &B) {
+  const int NC = (int)B.classes.size();
+  if (NC < 2 || (int)B.cstream.size() == NC) return BLP_OK;
+  HIP_TRY(hipEventCreateWithFlags(&B.fork_ev, hipEventDisableTiming));
+  for (int k = 0; k < NC; ++k) {
+    hipStream_t q = nullptr;
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    B.cstream.push_back(q);
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    B.cevent.push_back(e);
+  }
+  return BLP_OK;
+}
+hipStream_t class_stream(const Batch &B, int k) {
+  return B.cstream.empty() ? B.stream : B.cstream[k];
+}
+// Class streams wait for the work enqueued on the batch stream so far.
+int fork(Batch &B) {
+  if (B.cstream.empty()) return BLP_OK;
+  HIP_TRY(hipEventRecord(B.fork_ev, B.stream));
+  for (hipStream_t q : B.cstream) HIP_TRY(hipStreamWaitEvent(q, B.fork_ev, 0));
+  return BLP_OK;
+}
+// The batch stream waits for the work enqueued on every class stream.
+int join(Batch &B) {
+  for (size_t k = 0; k < B.cstream.size(); ++k) {
+    HIP_TRY(hipEventRecord(B.cevent[k], B.cstream[k]));
+    HIP_TRY(hipStreamWaitEvent(B.stream, B.cevent[k], 0));
+  }
   return BLP_OK;
 }
 
@@ -654,8 +793,8 @@ void krylov_step(const Ctx &c, const SolvePlan<TV, TR, SCALE> &P, int n1, int j,
   {
     KScope ks(c.timer, KC_SPMV, (double)Sk * n * (sizeof(TV) + sizeof(double)));
     k_stencil<TV, TR, SCALE, false>
-        <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, Sk), 256, 0, c.stream>>>(P.spmv, jdev,
-                                                                                   kRows);
+        <<<dim3((n1 + 255) / 256, (n1 + P.rows - 1) / P.rows, Sk), 256, 0, c.stream>>>(P.spmv, jdev,
+                                                                                     P.rows);
   }
   const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
   // CGS2: four passes over the j+1 basis vectors plus w traffic
@@ -683,51 +822,70 @@ struct CycleStats {
 // Z and the preconditioner in FP32; SpMV arithmetic, Hessenberg/Givens, u and
 // the restart-boundary true residuals in FP64; each restart cycle reduces the
 // residual by at most inner_rtol before an FP64 residual is taken.
+//
+// Streams: host-side decisions (gates, step index, status reads) go through
+// the batch stream; with several mesh classes each class runs on a stream
+// of its own between a fork (classes wait for the batch stream) and a join
+// (the batch stream waits for every class), so that the classes' launches
+// overlap on the GPU.  Classes without a flagged system are not launched.
 template <typename TV, bool TR, bool SCALE>
 int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_solve_opts *o,
                  blp_solve_info *info, double *const *hist) {
   const int S = (int)B.sys.size(), m = o->restart, NC = (int)B.classes.size();
   const double inner_rtol = std::is_same<TV, float>::value ? 1e-4 : 0.0;
   const KOffsets ko{m};
-  const Ctx c{B.stream, B.timer};
   auto t0 = std::chrono::steady_clock::now();
   for (auto &y : B.sys) BLP_TRY(ensure_krylov(*y, B.stream, m, o->precision));
+  BLP_TRY(ensure_class_streams(B));
   std::vector<SolvePlan<TV, TR, SCALE> *> P(NC);
   for (int k = 0; k < NC; ++k) BLP_TRY((get_solve_plan<TV, TR, SCALE>(B, k, m, F, U, &P[k])));
   const blp_prec_opts &po = B.sys[0]->p->popts;
   // kernel timing records events between launches: no graphs then
-  const bool use_graphs = B.graphs && !(c.timer && c.timer->timing);
+  const bool use_graphs = B.graphs && !(B.timer && B.timer->timing);
+  std::vector<Ctx> cx(NC);
+  for (int k = 0; k < NC; ++k) cx[k] = Ctx{class_stream(B, k), B.timer};
 
   std::vector<double> nF(S), target(S), beta(S), cyc_target(S);
   std::vector<int> it(S, 0), restarts(S, 0), ncol(S, 0);
   std::vector<char> active(S, 1), conv(S, 0), incyc(S, 0);
   std::vector<CycleStats> cs(S);
+  // classes with at least one system flagged (launches of other classes are skipped)
+  auto live = [&](int k, const std::vector<char> &on) {
+    for (int s : B.classes[k])
+      if (on[s]) return true;
+    return false;
+  };
   auto set_gates = [&](const std::vector<char> &on) {
     for (int s = 0; s < S; ++s) B.gate_h[s] = on[s] ? 0 : 1;
     return upload_gates(B);
   };
-  // ||F||, u = 0, r = F
+  // ||F||, u = 0
   for (int s = 0; s < S; ++s) B.gate_h[s] = 0;
   BLP_TRY(upload_gates(B));
-  for (int k = 0; k < NC; ++k) {
-    const int nblk = 256;
-    k_norm<SCALE><<<dim3(nblk, P[k]->S), 256, 0, B.stream>>>(P[k]->norm);
-  }
+  for (int s = 0; s < S; ++s)
+    HIP_TRY(hipMemsetAsync(U[s], 0, B.sys[s]->p->n * sizeof(double), B.stream));
+  BLP_TRY(fork(B));
+  for (int k = 0; k < NC; ++k)
+    k_norm<SCALE><<<dim3(256, P[k]->S), 256, 0, cx[k].stream>>>(P[k]->norm);
+  BLP_TRY(join(B));
   BLP_TRY(read_all(B));
   for (int s = 0; s < S; ++s) {
     nF[s] = B.st_h[s].beta;
     if (!std::isfinite(nF[s])) return BLP_E_NUMERIC;
     target[s] = o->absolute ? o->tol : o->tol * nF[s];
-    HIP_TRY(hipMemsetAsync(U[s], 0, B.sys[s]->p->n * sizeof(double), B.stream));
   }
+  // true residual of the active systems (gates = active)
   auto residual = [&]() {
+    BLP_TRY(fork(B));
     for (int k = 0; k < NC; ++k) {
+      if (!live(k, active)) continue;
       const int n1 = B.sys[B.classes[k][0]]->p->n1;
-      KScope ks(c.timer, KC_SPMV, (double)P[k]->S * n1 * n1 * 3 * sizeof(double));
+      KScope ks(cx[k].timer, KC_SPMV, (double)P[k]->S * n1 * n1 * 3 * sizeof(double));
       k_stencil<double, TR, SCALE, true>
-          <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, P[k]->S), 256, 0, B.stream>>>(
+          <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, P[k]->S), 256, 0, cx[k].stream>>>(
               P[k]->resid, nullptr, kRows);
     }
+    BLP_TRY(join(B));
     return read_all(B);
   };
   BLP_TRY(residual());
@@ -745,37 +903,45 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       ncol[s] = 0;
     }
     BLP_TRY(set_gates(incyc));
+    BLP_TRY(fork(B));
     for (int k = 0; k < NC; ++k) {
+      if (!live(k, incyc)) continue;
       const size_t n = B.sys[B.classes[k][0]]->p->n;
-      k_normalize<TV><<<dim3(blocks1d(n), P[k]->S), 256, 0, B.stream>>>(P[k]->kr, nullptr, 1);
-      k_krylov_init<TV><<<P[k]->S, 64, 0, B.stream>>>(P[k]->kr, ko);
+      k_normalize<TV><<<dim3(blocks1d(n), P[k]->S), 256, 0, cx[k].stream>>>(P[k]->kr, nullptr, 1);
+      k_krylov_init<TV><<<P[k]->S, 64, 0, cx[k].stream>>>(P[k]->kr, ko);
     }
+    BLP_TRY(join(B));
     for (int j = 0; j < m; ++j) {
       k_set_int<<<1, 1, 0, B.stream>>>(B.jdev, j);
+      BLP_TRY(fork(B));
       if (o->precond) {
         // part 1 for every class, the corner check (further cycles while any
         // system's corner gate is open), then the rest of the step
         for (int k = 0; k < NC; ++k) {
+          if (!live(k, incyc)) continue;
           if (use_graphs) {
             if (!P[k]->g1)
-              BLP_TRY(capture(B.stream, &P[k]->g1,
-                              [&]() { prec_part1<TV, TR>(c, P[k]->prec, B.jdev, po); }));
-            HIP_TRY(hipGraphLaunch(P[k]->g1, B.stream));
+              BLP_TRY(capture(cx[k].stream, &P[k]->g1,
+                              [&]() { prec_part1<TV, TR>(cx[k], P[k]->prec, B.jdev, po); }));
+            HIP_TRY(hipGraphLaunch(P[k]->g1, cx[k].stream));
           } else {
-            prec_part1<TV, TR>(c, P[k]->prec, B.jdev, po);
+            prec_part1<TV, TR>(cx[k], P[k]->prec, B.jdev, po);
           }
         }
         if (po.mg_fixed == 0) {
           for (int extra = kFirstCycles; extra < po.mg_maxcyc; ++extra) {
+            BLP_TRY(join(B));
             HIP_TRY(hipMemcpyAsync(B.ctrl_h, B.ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost,
                                    B.stream));
             HIP_TRY(hipStreamSynchronize(B.stream));
             bool open = false;
             for (int s = 0; s < S; ++s) open = open || !B.ctrl_h[s].gate;
+            BLP_TRY(fork(B));
             if (!open) break;
             for (int k = 0; k < NC; ++k) {
-              vcycle_run<TV, TR>(c, P[k]->prec, 0, false);
-              mg_norm_run<TV, TR>(c, P[k]->prec, 1);
+              if (!live(k, incyc)) continue;
+              vcycle_run<TV, TR>(cx[k], P[k]->prec, 0, false);
+              mg_norm_run<TV, TR>(cx[k], P[k]->prec, 1);
             }
           }
         }
@@ -787,24 +953,26 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
             TV *vj = (TV *)y.V + (size_t)j * n, *zj = (TV *)y.Z + (size_t)j * n;
             if (!incyc[B.classes[k][q]]) continue;
             if (SCALE)
-              k_div<TV><<<blocks1d(n), 256, 0, B.stream>>>(vj, fine<TV>(y.p).dh, zj, n);
+              k_div<TV><<<blocks1d(n), 256, 0, cx[k].stream>>>(vj, fine<TV>(y.p).dh, zj, n);
             else
-              HIP_TRY(hipMemcpyAsync(zj, vj, n * sizeof(TV), hipMemcpyDeviceToDevice, B.stream));
+              HIP_TRY(hipMemcpyAsync(zj, vj, n * sizeof(TV), hipMemcpyDeviceToDevice, cx[k].stream));
           }
         }
       }
       for (int k = 0; k < NC; ++k) {
+        if (!live(k, incyc)) continue;
         auto rest = [&]() {
-          if (o->precond) prec_part2<TV, TR>(c, P[k]->prec, B.jdev);
-          krylov_step<TV, TR, SCALE>(c, *P[k], B.sys[B.classes[k][0]]->p->n1, j, B.jdev, ko);
+          if (o->precond) prec_part2<TV, TR>(cx[k], P[k]->prec, B.jdev);
+          krylov_step<TV, TR, SCALE>(cx[k], *P[k], B.sys[B.classes[k][0]]->p->n1, j, B.jdev, ko);
         };
         if (use_graphs && o->precond) {
-          if (!P[k]->g2) BLP_TRY(capture(B.stream, &P[k]->g2, rest));
-          HIP_TRY(hipGraphLaunch(P[k]->g2, B.stream));
+          if (!P[k]->g2) BLP_TRY(capture(cx[k].stream, &P[k]->g2, rest));
+          HIP_TRY(hipGraphLaunch(P[k]->g2, cx[k].stream));
         } else {
           rest();
         }
       }
+      BLP_TRY(join(B));
       BLP_TRY(read_all(B));
       bool any = false;
       for (int s = 0; s < S; ++s) {
@@ -821,26 +989,33 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       }
       if (!any) break;
       BLP_TRY(set_gates(incyc));
+      BLP_TRY(fork(B));
       for (int k = 0; k < NC; ++k) {
+        if (!live(k, incyc)) continue;
         const size_t n = B.sys[B.classes[k][0]]->p->n;
-        k_normalize<TV><<<dim3(blocks1d(n), P[k]->S), 256, 0, B.stream>>>(P[k]->kr, B.jdev, 0);
+        k_normalize<TV><<<dim3(blocks1d(n), P[k]->S), 256, 0, cx[k].stream>>>(P[k]->kr, B.jdev, 0);
       }
+      BLP_TRY(join(B));
     }
-    // u += Z y and the true residual of every system of the cycle
+    // u += Z y and the true residual of every system of the cycle; column
+    // counts in class order (the kernel indexes its class-local slot)
     BLP_TRY(set_gates(active));
-    // column counts in class order (the kernel indexes its class-local slot)
     {
       int off = 0;
       for (int k = 0; k < NC; ++k)
         for (int q = 0; q < P[k]->S; ++q) B.ncol_h[off++] = ncol[B.classes[k][q]];
       HIP_TRY(hipMemcpyAsync(B.ncol, B.ncol_h, S * sizeof(int), hipMemcpyHostToDevice, B.stream));
+      BLP_TRY(fork(B));
       off = 0;
       for (int k = 0; k < NC; ++k) {
-        const size_t n = B.sys[B.classes[k][0]]->p->n;
-        k_update_solution<TV>
-            <<<dim3(blocks1d(n), P[k]->S), 256, 0, B.stream>>>(P[k]->kr, B.ncol + off, ko);
+        if (live(k, active)) {
+          const size_t n = B.sys[B.classes[k][0]]->p->n;
+          k_update_solution<TV>
+              <<<dim3(blocks1d(n), P[k]->S), 256, 0, cx[k].stream>>>(P[k]->kr, B.ncol + off, ko);
+        }
         off += P[k]->S;
       }
+      BLP_TRY(join(B));
     }
     BLP_TRY(residual());
     for (int s = 0; s < S; ++s) {
@@ -896,4 +1071,47 @@ int batch_solve(Batch &B, bool tr, const double *const *F, double *const *U, con
   }
 #undef BLP_DISPATCH
   return rc;
+}
+
+// Text summary of the batch's classes and the kernel variants of its plans.
+struct PlanInfo {
+  int N, S, prec, tr, rows, varI, varLines;
+  std::vector<int> varL;
+};
+template <typename TV, bool TR, bool SCALE>
+bool plan_info(PlanBase *b, PlanInfo &I) {
+  auto *h = dynamic_cast<PlanHolder<TV, TR, SCALE> *>(b);
+  if (!h) return false;
+  const auto &P = h->plan;
+  I = PlanInfo{P.prec.N, P.S, (int)sizeof(TV), (int)TR, P.rows, P.prec.varI, P.prec.varLines,
+               P.prec.varL};
+  return true;
+}
+std::string describe(const Batch &B) {
+  std::string out;
+  char buf[256];
+  for (size_t k = 0; k < B.classes.size(); ++k) {
+    snprintf(buf, sizeof buf, "class %zu: N=%d systems=%zu\n", k, B.sys[B.classes[k][0]]->p->N,
+             B.classes[k].size());
+    out += buf;
+  }
+  for (const auto &kv : B.plans) {
+    PlanInfo I;
+    PlanBase *b = kv.second.get();
+    if (!(plan_info<double, false, true>(b, I) || plan_info<double, false, false>(b, I) ||
+          plan_info<double, true, true>(b, I) || plan_info<double, true, false>(b, I) ||
+          plan_info<float, false, true>(b, I) || plan_info<float, false, false>(b, I) ||
+          plan_info<float, true, true>(b, I) || plan_info<float, true, false>(b, I)))
+      continue;
+    snprintf(buf, sizeof buf, "plan N=%d systems=%d %s%s: interior sweep v%d, lines v%d, stencil rows %d, levels",
+             I.N, I.S, I.prec == 8 ? "fp64" : "fp32", I.tr ? " transposed" : "", I.varI, I.varLines,
+             I.rows);
+    out += buf;
+    for (int v : I.varL) {
+      snprintf(buf, sizeof buf, " v%d", v);
+      out += buf;
+    }
+    out += "\n";
+  }
+  return out;
 }

@@ -34,26 +34,31 @@ def _rel(a, b):
     return np.abs(a - b).max() / np.abs(b).max()
 
 
-@pytest.mark.parametrize("precision,graphs", [("fp64", False), ("mixed", False), ("fp64", True),
-                                              ("mixed", True)])
-def test_batch_matches_single_solves(precision, graphs):
+@pytest.mark.parametrize("precision,graphs,tune", [("fp64", False, False), ("mixed", False, False),
+                                                   ("fp64", True, False), ("mixed", True, True)])
+def test_batch_matches_single_solves(precision, graphs, tune):
     """With graphs, every Krylov step replays the two captured graphs of each
     mesh size (eager launches, memcpys and host decisions in between): each
     replay must reproduce the eager single solve."""
     from paper_2108_13468_amd import blp
     insts = inputs.batch_cases(count=6, seed=31, sizes=(64, 96, 130))
-    say("batch of %d, sizes %s, %s, graphs=%s" % (len(insts), [i.N for i in insts], precision,
-                                                  graphs))
+    say("batch of %d, sizes %s, %s, graphs=%s, autotune=%s" % (
+        len(insts), [i.N for i in insts], precision, graphs, tune))
     ps, F = _problems(insts)
     opts = dict(tol=1e-10, scaled=True, precision=precision, maxit=800)
     single = [p.solve(f, **opts) for p, f in zip(ps, F)]
-    b = blp.Batch(ps, graphs=graphs)
+    b = blp.Batch(ps, graphs=graphs, autotune=tune)
     for rep in range(2):  # the second solve replays graphs captured by the first
         U, info = b.solve(F, **opts)
         for s in range(len(ps)):
             assert info[s]["converged"] == 1
             assert info[s]["iterations"] == single[s][1][0]["iterations"], (rep, s)
-            assert _rel(U[s], single[s][0]) <= 1e-13, (rep, s)
+            # identical schedules agree to rounding; a tuned line-solve variant
+            # groups its scans differently (other rounding in the preconditioner),
+            # which moves the result well inside the solve tolerance
+            assert _rel(U[s], single[s][0]) <= (1e-9 if tune else 1e-13), (rep, s)
+    if tune:
+        say(b.describe())
 
 
 def test_batch_adjoint_matches_single():
