@@ -202,6 +202,10 @@ long long blp_batch_footprint(const blp_batch *b);
  * classes and of the kernel variants its launch plans use (the autotuner's
  * choices).  Returns the full length, or BLP_E_INVAL. */
 int blp_batch_describe(const blp_batch *b, char *buf, int len);
+/* Per-kernel-class timing of a batch's launches, as blp_timing (events on
+ * the streams the launches run on; graphs are not replayed while it is on). */
+int blp_batch_timing(blp_batch *b, int enable, double *ms, long long *launches,
+                     double *bytes);
 void blp_batch_destroy(blp_batch *b);
 
 /* Single operator applications on one vector (device in/out, (N-1)^2

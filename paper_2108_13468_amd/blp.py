@@ -24,7 +24,7 @@ EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_sol
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
            "blp_bilinear_project", "blp_mul", "blp_timing", "blp_footprint", "blp_destroy",
            "blp_strerror", "blp_batch_create", "blp_batch_solve", "blp_batch_solve_adjoint",
-           "blp_batch_footprint", "blp_batch_describe", "blp_batch_destroy")
+           "blp_batch_footprint", "blp_batch_describe", "blp_batch_timing", "blp_batch_destroy")
 NCLASS = 7
 CLASSES = ("sweep", "gs_rhs", "lines", "mg_other", "spmv", "krylov", "layout")
 
@@ -109,6 +109,7 @@ def lib():
             getattr(L, f).argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveOpts),
                                       C.POINTER(SolveInfo)]
         L.blp_batch_describe.argtypes = [vp, C.c_char_p, C.c_int]
+        L.blp_batch_timing.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_longlong), _dp]
         L.blp_batch_footprint.restype = C.c_longlong
         L.blp_batch_footprint.argtypes = [vp]
         L.blp_batch_destroy.argtypes = [vp]
@@ -349,6 +350,17 @@ class Batch:
 
     def footprint(self):
         return int(lib().blp_batch_footprint(self._h))
+
+    def timing(self, enable):
+        """As Problem.timing, for the batch's launches."""
+        ms = np.zeros(NCLASS)
+        nl = (C.c_longlong * NCLASS)()
+        by = np.zeros(NCLASS)
+        _check(lib().blp_batch_timing(self._h, int(bool(enable)), ms.ctypes.data_as(_dp), nl,
+                                      by.ctypes.data_as(_dp)), "blp_batch_timing")
+        if enable:
+            return None
+        return {c: (float(ms[k]), int(nl[k]), float(by[k])) for k, c in enumerate(CLASSES)}
 
     def describe(self):
         """Mesh classes and the kernel variants of the launch plans."""

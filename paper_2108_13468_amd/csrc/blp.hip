@@ -90,6 +90,55 @@ struct FineDev {
 
 struct Batch;
 
+// Kernel timing: an event pair around each timed launch (recorded on the
+// launch's stream), resolved into per-class sums on demand.
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int cls; hipEvent_t a, b; double bytes; };
+  std::vector<Rec> recs;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      // timestamps only: no system-scope fence (the streams are synchronised
+      // before the times are read), so recording does not flush caches
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void start() {
+    recs.clear();
+    used = 0;
+    on = true;
+  }
+  // per-class sums (ms, launches, bytes); the streams must be synchronised
+  int stop(double *ms, long long *launches, double *bytes, int ncls) {
+    on = false;
+    std::vector<double> sm(ncls, 0.0), sb(ncls, 0.0);
+    std::vector<long long> sl(ncls, 0);
+    for (const auto &r : recs) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return BLP_E_HIP;
+      sm[r.cls] += t;
+      sb[r.cls] += r.bytes;
+      sl[r.cls] += 1;
+    }
+    for (int k = 0; k < ncls; ++k) {
+      if (ms) ms[k] = sm[k];
+      if (launches) launches[k] = sl[k];
+      if (bytes) bytes[k] = sb[k];
+    }
+    recs.clear();
+    used = 0;
+    return BLP_OK;
+  }
+  ~Timer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace
 
 struct blp_batch {
@@ -118,22 +167,7 @@ struct blp_problem {
   float *tmp32a = nullptr, *tmp32b = nullptr;
   std::vector<void *> allocs;
   long long bytes = 0;
-  // kernel timing (blp_timing): event pairs per class, resolved on demand
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  struct Rec { int cls; hipEvent_t a, b; double bytes; };
-  std::vector<Rec> recs;
-  hipEvent_t ev_next() {
-    if (ev_used == ev_pool.size()) {
-      hipEvent_t e;
-      // timestamps only: no system-scope fence (the stream is synchronised
-      // before the times are read), so recording does not flush caches
-      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
-      ev_pool.push_back(e);
-    }
-    return ev_pool[ev_used++];
-  }
+  Timer timer;  // kernel timing (blp_timing)
 
   template <typename T>
   int alloc(T **p, size_t count) {
@@ -162,22 +196,29 @@ struct blp_problem {
 
 namespace {
 
-// Records an event pair around the launches issued during its lifetime when
-// timing is enabled.
+// Launch context: stream and the (optional) kernel timer.
+struct Ctx {
+  hipStream_t stream;
+  Timer *timer;
+};
+
+// Records an event pair around the launches issued on the context's stream
+// during its lifetime when timing is enabled.
 struct KScope {
-  blp_problem *p;
+  Timer *t;
+  hipStream_t s;
   int cls;
   double bytes;
   hipEvent_t a = nullptr;
-  KScope(blp_problem *p_, int c, double b) : p(p_), cls(c), bytes(b) {
-    if (p && p->timing && (a = p->ev_next())) (void)hipEventRecord(a, p->stream);
+  KScope(const Ctx &c, int k, double b) : t(c.timer), s(c.stream), cls(k), bytes(b) {
+    if (t && t->on && (a = t->next())) (void)hipEventRecord(a, s);
   }
   void end() {
     if (!a) return;
-    hipEvent_t b = p->ev_next();
+    hipEvent_t b = t->next();
     if (b) {
-      (void)hipEventRecord(b, p->stream);
-      p->recs.push_back({cls, a, b, bytes});
+      (void)hipEventRecord(b, s);
+      t->recs.push_back({cls, a, b, bytes});
     }
     a = nullptr;
   }
@@ -409,7 +450,7 @@ int own_batch(blp_problem *p, int nrhs, Batch **out) {
     std::vector<blp_problem *> probs(nrhs, p);
     std::unique_ptr<Batch> B;
     BLP_TRY(batch_create(p->stream, probs.data(), nrhs, B));
-    B->timer = p;
+    B->timer = &p->timer;
     p->own = B.release();
     p->own_S = nrhs;
   }
@@ -448,7 +489,7 @@ int apply_prec(blp_problem *p, const T *x, T *y, int *cycles) {
   std::vector<IOSpec> io{IOSpec{x, 0, y, 0}};
   PrecPlan<T, TR> P;
   BLP_TRY((build_prec_plan<T, TR>(p->stream, sys, io, false, P)));
-  const Ctx c{p->stream, p};
+  const Ctx c{p->stream, &p->timer};
   HIP_TRY(hipMemsetAsync(B->gate, 0, sizeof(int), p->stream));
   prec_part1<T, TR>(c, P, nullptr, p->popts);
   BLP_TRY((corner_finish<T, TR>(c, P, p->popts, kFirstCycles, B->ctrl, B->ctrl_h, 1)));
@@ -467,7 +508,7 @@ int apply_op(blp_problem *p, const double *x, double *y) {
   Alloc mem;
   SpmvArgs<double> *d = nullptr;
   BLP_TRY(mem.put(&d, &a, 1, p->stream));
-  KScope ks(p, KC_SPMV, (double)p->n * 2 * sizeof(double));
+  KScope ks(Ctx{p->stream, &p->timer}, KC_SPMV, (double)p->n * 2 * sizeof(double));
   k_stencil<double, TR, false, false>
       <<<dim3((p->n1 + 255) / 256, (p->n1 + kRows - 1) / kRows, 1), 256, 0, p->stream>>>(d, nullptr, kRows);
   ks.end();
@@ -637,6 +678,7 @@ int blp_batch_create(blp_problem *const *probs, int S, void *stream, const blp_b
     delete b;
     return rc;
   }
+  b->B->timer = &b->B->own_timer;
   if (o) {
     b->B->graphs = o->graphs != 0;
     b->B->autotune = o->autotune != 0;
@@ -670,6 +712,18 @@ int blp_batch_solve_adjoint(blp_batch *b, const double *const *G, double *const 
 }
 
 long long blp_batch_footprint(const blp_batch *b) { return b ? batch_bytes(*b->B) : 0; }
+
+int blp_batch_timing(blp_batch *b, int enable, double *ms, long long *launches, double *bytes) {
+  if (!b) return BLP_E_INVAL;
+  Batch &B = *b->B;
+  HIP_TRY(hipStreamSynchronize(B.stream));
+  for (hipStream_t q : B.cstream) HIP_TRY(hipStreamSynchronize(q));
+  if (enable) {
+    B.own_timer.start();
+    return BLP_OK;
+  }
+  return B.own_timer.stop(ms, launches, bytes, BLP_NCLASS);
+}
 
 int blp_batch_describe(const blp_batch *b, char *buf, int len) {
   if (!b || !buf || len < 1) return BLP_E_INVAL;
@@ -784,32 +838,12 @@ int blp_mul(blp_problem *p, const double *a, const double *b, double *out) {
 
 int blp_timing(blp_problem *p, int enable, double *ms, long long *launches, double *bytes) {
   if (!p) return BLP_E_INVAL;
+  HIP_TRY(hipStreamSynchronize(p->stream));
   if (enable) {
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    p->recs.clear();
-    p->ev_used = 0;
-    p->timing = true;
+    p->timer.start();
     return BLP_OK;
   }
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  p->timing = false;
-  double sm[BLP_NCLASS] = {0}, sb[BLP_NCLASS] = {0};
-  long long sl[BLP_NCLASS] = {0};
-  for (const auto &r : p->recs) {
-    float t = 0.f;
-    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
-    sm[r.cls] += t;
-    sb[r.cls] += r.bytes;
-    sl[r.cls] += 1;
-  }
-  for (int k = 0; k < BLP_NCLASS; ++k) {
-    if (ms) ms[k] = sm[k];
-    if (launches) launches[k] = sl[k];
-    if (bytes) bytes[k] = sb[k];
-  }
-  p->recs.clear();
-  p->ev_used = 0;
-  return BLP_OK;
+  return p->timer.stop(ms, launches, bytes, BLP_NCLASS);
 }
 
 long long blp_footprint(const blp_problem *p) {
@@ -821,7 +855,6 @@ void blp_destroy(blp_problem *p) {
   (void)hipStreamSynchronize(p->stream);
   for (void *q : p->allocs) (void)hipFree(q);
   delete p->own;
-  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   delete p;
 }
 

@@ -250,12 +250,6 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   return BLP_OK;
 }
 
-// Launch context: stream and the (optional) kernel timer.
-struct Ctx {
-  hipStream_t stream;
-  blp_problem *timer;  // records per-class kernel times when its timing is on
-};
-
 // Kernel variants the autotuner chooses between (all compute the same
 // arithmetic in the same order per lane; they differ in scheduling only).
 // Sweep: superstep K = 4 or 2 chunks of 16 bytes per lane, D supersteps of
@@ -320,14 +314,14 @@ void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   const int S = P.S, m = P.n1 - P.h;
   const dim3 gg(blocks1d(P.nslotI), S);
   {
-    KScope ks(c.timer, KC_LAYOUT, 0.0);
+    KScope ks(c, KC_LAYOUT, 0.0);
     k_gather_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
   }
   {
-    KScope ks(c.timer, KC_SWEEP, (double)S * m * m * 2 * sizeof(T));
+    KScope ks(c, KC_SWEEP, (double)S * m * m * 2 * sizeof(T));
     sweep_launch<T, TR>(c, S, m, P.swI, P.varI);
   }
-  KScope ks(c.timer, KC_LAYOUT, 0.0);
+  KScope ks(c, KC_LAYOUT, 0.0);
   k_scatter_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
 }
 
@@ -336,14 +330,14 @@ void lines_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   const int S = P.S, L = P.n1 - P.h;
   const dim3 gl((P.hp + 255) / 256, L, 2 * S);
   {
-    KScope ks(c.timer, KC_LAYOUT, 0.0);
+    KScope ks(c, KC_LAYOUT, 0.0);
     k_gather_lines<T, TR><<<gl, 256, 0, c.stream>>>(P.ioL, jp);
   }
   {
-    KScope ks(c.timer, KC_LINES, (double)S * 2.0 * L * P.h * 4 * sizeof(T));
+    KScope ks(c, KC_LINES, (double)S * 2.0 * L * P.h * 4 * sizeof(T));
     lines_launch<T, TR>(c, S, P.hp, P.lnA, P.varLines);
   }
-  KScope ks(c.timer, KC_LAYOUT, 0.0);
+  KScope ks(c, KC_LAYOUT, 0.0);
   k_scatter_lines<T, TR><<<gl, 256, 0, c.stream>>>(P.ioL, jp);
 }
 
@@ -355,41 +349,41 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   const int S = P.S, n = P.ln[l], nl = (int)P.ln.size();
   const double nn = (double)S * n * n;
   if (l == nl - 1) {
-    KScope ks(c.timer, KC_MG, nn * 2 * sizeof(T));
+    KScope ks(c, KC_MG, nn * 2 * sizeof(T));
     k_mg_coarsest<T, TR><<<S, 64, 0, c.stream>>>(P.mg[l], zero_init ? 1 : 0);
     return;
   }
   const dim3 gl(blocks1d(P.lslot[l]), S), gc(blocks1d(P.lslot[l + 1]), S);
   const double cc = (double)S * P.ln[l + 1] * P.ln[l + 1];
   if (zero_init) {
-    KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
+    KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
     sweep_launch<T, TR>(c, S, n, P.swb[l], P.varL[l]);
   } else {
     {
-      KScope ks(c.timer, KC_GSRHS, nn * 3 * sizeof(T));
+      KScope ks(c, KC_GSRHS, nn * 3 * sizeof(T));
       k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
     }
-    KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
+    KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
     sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
   }
   {
-    KScope ks(c.timer, KC_MG, nn * 3 * sizeof(T));
+    KScope ks(c, KC_MG, nn * 3 * sizeof(T));
     k_mg_resid<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
   }
   {
-    KScope ks(c.timer, KC_MG, (nn + cc) * sizeof(T));
+    KScope ks(c, KC_MG, (nn + cc) * sizeof(T));
     k_mg_restrict<T, TR><<<gc, 256, 0, c.stream>>>(P.mg[l]);
   }
   vcycle_run<T, TR>(c, P, l + 1, true);
   {
-    KScope ks(c.timer, KC_MG, (2 * nn + cc) * sizeof(T));
+    KScope ks(c, KC_MG, (2 * nn + cc) * sizeof(T));
     k_mg_prolong<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
   }
   {
-    KScope ks(c.timer, KC_GSRHS, nn * 3 * sizeof(T));
+    KScope ks(c, KC_GSRHS, nn * 3 * sizeof(T));
     k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
   }
-  KScope ks(c.timer, KC_SWEEP, nn * 2 * sizeof(T));
+  KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
   sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
 }
 
@@ -399,7 +393,7 @@ constexpr int kMgNormBlocks = 256;
 template <typename T, bool TR>
 void mg_norm_run(const Ctx &c, const PrecPlan<T, TR> &P, int mode) {
   const int nblk = std::min(kMgNormBlocks, (int)blocks1d(P.lslot[0]));
-  KScope ks(c.timer, KC_MG, (double)P.S * P.ln[0] * P.ln[0] * 2 * sizeof(T));
+  KScope ks(c, KC_MG, (double)P.S * P.ln[0] * P.ln[0] * 2 * sizeof(T));
   k_mg_norm<T, TR><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.mg[0], mode);
 }
 
@@ -411,7 +405,7 @@ void corner_begin(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const b
                   int first) {
   const int h = P.h;
   {
-    KScope ks(c.timer, KC_LAYOUT, 0.0);
+    KScope ks(c, KC_LAYOUT, 0.0);
     k_corner_rhs<T, TR><<<dim3((h + 255) / 256, h, P.S), 256, 0, c.stream>>>(P.cr, jp);
   }
   if (o.mg_fixed > 0) {
@@ -448,7 +442,7 @@ int corner_finish(const Ctx &c, const PrecPlan<T, TR> &P, const blp_prec_opts &o
 
 template <typename T, bool TR>
 void corner_end(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
-  KScope ks(c.timer, KC_LAYOUT, 0.0);
+  KScope ks(c, KC_LAYOUT, 0.0);
   k_corner_copy<T, TR><<<dim3((P.h + 255) / 256, P.h, P.S), 256, 0, c.stream>>>(P.cr, jp);
 }
 
@@ -520,7 +514,8 @@ struct Batch {
   int *gate = nullptr, *gate_h = nullptr;
   int *jdev = nullptr;
   int *ncol = nullptr, *ncol_h = nullptr;
-  blp_problem *timer = nullptr;
+  Timer *timer = nullptr;  // the problem's timer (own batches) or own_timer
+  Timer own_timer;
   int graphs = 0, autotune = 0;  // blp_batch_opts
   hipStream_t user = nullptr;     // caller's stream when the batch runs on its own
   bool own_stream = false;
@@ -791,14 +786,14 @@ void krylov_step(const Ctx &c, const SolvePlan<TV, TR, SCALE> &P, int n1, int j,
   const size_t n = (size_t)n1 * n1;
   const int Sk = P.S;
   {
-    KScope ks(c.timer, KC_SPMV, (double)Sk * n * (sizeof(TV) + sizeof(double)));
+    KScope ks(c, KC_SPMV, (double)Sk * n * (sizeof(TV) + sizeof(double)));
     k_stencil<TV, TR, SCALE, false>
         <<<dim3((n1 + 255) / 256, (n1 + P.rows - 1) / P.rows, Sk), 256, 0, c.stream>>>(P.spmv, jdev,
                                                                                      P.rows);
   }
   const unsigned nb = (unsigned)((n + KCHUNK - 1) / KCHUNK);
   // CGS2: four passes over the j+1 basis vectors plus w traffic
-  KScope ks(c.timer, KC_KRYLOV, (double)Sk * n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
+  KScope ks(c, KC_KRYLOV, (double)Sk * n * ((4.0 * (j + 1)) * sizeof(TV) + 6 * sizeof(double)));
   k_arnoldi_dot<TV><<<dim3(nb, Sk), 256, 0, c.stream>>>(P.kr, jdev, ko);
   k_arnoldi_update<TV, false><<<dim3(nb, Sk), 256, 0, c.stream>>>(P.kr, jdev, ko);
   k_arnoldi_update<TV, true><<<dim3(nb, Sk), 256, 0, c.stream>>>(P.kr, jdev, ko);
@@ -841,7 +836,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
   for (int k = 0; k < NC; ++k) BLP_TRY((get_solve_plan<TV, TR, SCALE>(B, k, m, F, U, &P[k])));
   const blp_prec_opts &po = B.sys[0]->p->popts;
   // kernel timing records events between launches: no graphs then
-  const bool use_graphs = B.graphs && !(B.timer && B.timer->timing);
+  const bool use_graphs = B.graphs && !(B.timer && B.timer->on);
   std::vector<Ctx> cx(NC);
   for (int k = 0; k < NC; ++k) cx[k] = Ctx{class_stream(B, k), B.timer};
 
@@ -880,7 +875,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
     for (int k = 0; k < NC; ++k) {
       if (!live(k, active)) continue;
       const int n1 = B.sys[B.classes[k][0]]->p->n1;
-      KScope ks(cx[k].timer, KC_SPMV, (double)P[k]->S * n1 * n1 * 3 * sizeof(double));
+      KScope ks(cx[k], KC_SPMV, (double)P[k]->S * n1 * n1 * 3 * sizeof(double));
       k_stencil<double, TR, SCALE, true>
           <<<dim3((n1 + 255) / 256, (n1 + kRows - 1) / kRows, P[k]->S), 256, 0, cx[k].stream>>>(
               P[k]->resid, nullptr, kRows);
