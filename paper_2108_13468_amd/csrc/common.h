@@ -71,6 +71,15 @@ BLP_DEV double block_sum(double v, double *sh) {
   return s;
 }
 
+// Pointers read from argument records in memory carry no address space, so
+// the compiler would access them with FLAT instructions (which also count
+// against the LDS counter).  Hot loops cast them to the global space.
+#define BLP_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+BLP_DEV BLP_GLOBAL T *gptr(T *p) {
+  return (BLP_GLOBAL T *)p;
+}
+
 // "Last block" pattern: every block publishes its partial, then the last
 // block to arrive reads all partials.  Partials are stored and read through
 // to the device coherence point (relaxed agent-scope atomic accesses), and a
@@ -79,10 +88,10 @@ BLP_DEV double block_sum(double v, double *sh) {
 // without a device-scope fence: on this GPU such a fence writes back the
 // whole L2 of the XCD, in every block.  Only thread 0 publishes.
 BLP_DEV void publish(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 BLP_DEV double collect(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Returns true in the whole last of nblocks arriving blocks.
 BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag, unsigned int nblocks) {
@@ -91,7 +100,7 @@ BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag, unsigned int nblo
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));  // vmcnt(0)
     const unsigned int prev =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gptr(counter), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *sh_flag = (prev == nblocks - 1);
     __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xf << 8));
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -101,7 +110,7 @@ BLP_DEV bool arrive_last(unsigned int *counter, bool *sh_flag, unsigned int nblo
 }
 // Reset of an arrival counter by the last block (for the next launch).
 BLP_DEV void reset_counter(unsigned int *counter) {
-  __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gptr(counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Batched launches: blockIdx.z (or the block's system slot) selects one
@@ -113,11 +122,20 @@ BLP_DEV long long step_of(const int *jp) { return jp ? (long long)*jp : 0; }
 // Per-system gate: nonzero means the system takes no part in the launch.
 BLP_DEV bool gated(const int *g) { return g && *g; }
 
-// Pointers read from argument records in memory carry no address space, so
-// the compiler would access them with FLAT instructions (which also count
-// against the LDS counter).  Hot loops cast them to the global space.
-#define BLP_GLOBAL __attribute__((address_space(1)))
+
+
+// Grid with its tables in the global space (device-side view).
 template <typename T>
-BLP_DEV BLP_GLOBAL T *gptr(T *p) {
-  return (BLP_GLOBAL T *)p;
+struct GridG {
+  int nx, ny;
+  const BLP_GLOBAL T *W, *E, *Dx, *S, *N, *Dy, *r;
+  int rld;
+  T rc;
+  BLP_DEV T rr(int i, int j) const { return r ? r[(size_t)(j - 1) * rld + (i - 1)] : rc; }
+  BLP_DEV T C(int i, int j) const { return Dx[i] + Dy[j] + rr(i, j); }
+};
+template <typename T>
+BLP_DEV GridG<T> gview(const Grid<T> &g) {
+  return GridG<T>{g.nx,       g.ny,       gptr(g.W), gptr(g.E), gptr(g.Dx), gptr(g.S),
+                  gptr(g.N), gptr(g.Dy), gptr(g.r), g.rld,     g.rc};
 }

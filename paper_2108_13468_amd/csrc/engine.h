@@ -158,6 +158,9 @@ struct PrecPlan {
   // kernel variants (autotuner; 0 = default)
   int varI = 0, varLines = 0;
   std::vector<int> varL;
+  // fused cycle below level lc (at most kFuseN nodes per axis); -1: none
+  int lc = -1;
+  CoarseArgs<T> *coarse = nullptr;
   Alloc mem;
 };
 
@@ -232,6 +235,22 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
       swb[l][s] = SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.b[l], ic, w.z[l], &y.ctrl->gate};
       swt[l][s] = SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.t[l], ic, w.z[l], &y.ctrl->gate};
     }
+  }
+  // the coarse levels run as one fused cycle per system
+  P.lc = -1;
+  for (int l = 0; l < nl; ++l)
+    if (P.ln[l] <= kFuseN) {
+      if (nl - l <= kCoarseMax) P.lc = l;
+      break;
+    }
+  if (P.lc >= 0) {
+    std::vector<CoarseArgs<T>> ca(S);
+    for (int q = 0; q < S; ++q) {
+      ca[q].nlev = nl - P.lc;
+      for (int l = P.lc; l < nl; ++l) ca[q].L[l - P.lc] = mg[l][q].L;
+      ca[q].ctrl = mg[0][q].ctrl;
+    }
+    BLP_TRY(P.mem.put(&P.coarse, ca.data(), S, st));
   }
   BLP_TRY(P.mem.put(&P.ioI, ioI.data(), S, st));
   BLP_TRY(P.mem.put(&P.swI, swI.data(), S, st));
@@ -348,6 +367,13 @@ template <typename T, bool TR>
 void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   const int S = P.S, n = P.ln[l], nl = (int)P.ln.size();
   const double nn = (double)S * n * n;
+  if (l == P.lc) {
+    double pts = 0.0;
+    for (int k = l; k < nl; ++k) pts += (double)S * P.ln[k] * P.ln[k];
+    KScope ks(c, KC_MG, pts * 12 * sizeof(T));
+    k_mg_coarse<T, TR><<<S, kCoarseThreads, 0, c.stream>>>(P.coarse, zero_init ? 1 : 0);
+    return;
+  }
   if (l == nl - 1) {
     KScope ks(c, KC_MG, nn * 2 * sizeof(T));
     k_mg_coarsest<T, TR><<<S, 64, 0, c.stream>>>(P.mg[l], zero_init ? 1 : 0);

@@ -154,39 +154,52 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const KArgs<TV> *A, cons
     if (threadIdx.x == 0) reset_counter(&st->counter);
     return;
   }
+  // last block: hn = ||w|| (block-wide fixed-order sum of the partials), then
+  // the Hessenberg column h1 + h2 with the previous rotations applied, the new
+  // rotation and the residual estimate.  The column and the rotations are
+  // staged in shared memory by the whole block; thread 0 applies them.
+  __shared__ double col[66], rc[64], rs[64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s += collect(&a.partials[b]);
+  s = block_sum(s, sh);
+  const int m = ko.m;
+  BLP_GLOBAL double *H = gptr(ko.H(ks)), *cs = gptr(ko.cs(ks)), *sn = gptr(ko.sn(ks)),
+                    *g = gptr(ko.g(ks));
+  const BLP_GLOBAL double *h1 = gptr(ko.h1(ks));
+  for (int v = threadIdx.x; v <= j; v += blockDim.x) {
+    col[v] = h1[v] + hs[v];
+    if (v < j) {
+      rc[v] = cs[v];
+      rs[v] = sn[v];
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[b]);
     const double hn = sqrt(s);
-    const int m = ko.m;
-    double *H = ko.H(ks), *cs = ko.cs(ks), *sn = ko.sn(ks), *g = ko.g(ks);
-    const double *h1 = ko.h1(ks);
-    // Hessenberg column j = h1 + h2 (the two Gram-Schmidt passes)
-    for (int v = 0; v <= j; ++v) H[v * m + j] = h1[v] + hs[v];
-    H[(j + 1) * m + j] = hn;
+    col[j + 1] = hn;
     for (int v = 0; v < j; ++v) {
-      const double a0 = H[v * m + j], b0 = H[(v + 1) * m + j];
-      H[v * m + j] = cs[v] * a0 + sn[v] * b0;
-      H[(v + 1) * m + j] = -sn[v] * a0 + cs[v] * b0;
+      const double a0 = col[v], b0 = col[v + 1];
+      col[v] = rc[v] * a0 + rs[v] * b0;
+      col[v + 1] = -rs[v] * a0 + rc[v] * b0;
     }
-    const double a0 = H[j * m + j], b0 = H[(j + 1) * m + j];
+    const double a0 = col[j], b0 = col[j + 1];
     const double rho = hypot(a0, b0);
-    if (rho == 0.0) {
-      cs[j] = 1.0;
-      sn[j] = 0.0;
-    } else {
-      cs[j] = a0 / rho;
-      sn[j] = b0 / rho;
-    }
-    H[j * m + j] = rho;
-    H[(j + 1) * m + j] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    st->est = fabs(g[j + 1]);
-    st->hn = hn;
-    st->happy = hn <= 1e-14 * st->wn0;
+    const double c = rho == 0.0 ? 1.0 : a0 / rho, sj = rho == 0.0 ? 0.0 : b0 / rho;
+    cs[j] = c;
+    sn[j] = sj;
+    col[j] = rho;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = c * gj;
+    BLP_GLOBAL KrylovStatus *gs = gptr(st);
+    gs->est = fabs(sj * gj);
+    gs->hn = hn;
+    gs->happy = hn <= 1e-14 * gs->wn0;
     reset_counter(&st->counter);
   }
+  __syncthreads();
+  for (int v = threadIdx.x; v <= j + 1; v += blockDim.x) H[(size_t)v * m + j] = col[v];
 }
 
 // V_{j+1} = w / hn (use_beta = 0) or V_0 = w / beta (use_beta = 1), FP64 in,

@@ -207,50 +207,65 @@ struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); 
 template <>
 struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
 
-template <typename T, bool TR, int K, int D>
-__global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T> *A) {
-  const SweepArgs<T> a = A[blockIdx.x];  // one workgroup per system
-  if (gated(a.gate)) return;
+// The sweep of one workgroup (wave w = band w of nb), or, SOLO, of a single
+// wave on a rectangle of at most 64 columns inside a larger kernel (no
+// barriers: with one band there is no ring traffic).  ring holds (nb + 1) x
+// 64 words and ycu rows + 128 + K words of LDS, both provided by the caller.
+template <typename T, bool TR, int K, int D, bool SOLO>
+BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nthreads) {
   constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64;
   static_assert(K % P == 0 && 64 % K == 0 && 2 * K < 64, "superstep length");
   typedef typename Vec16<T>::type V;
-  // ring row w + 1 holds the last column of band w by step; row 0 stays zero
-  __shared__ T ring[kSweepMaxBands + 1][RING];
-  // upstream y coupling by row t, stored at t + 64 for t in [-64, mr + 64 +
-  // K) with zeros outside [0, mr), so that a superstep reads it without
+  // ring row w + 1 holds the last column of band w by step; row 0 stays zero.
+  // ycu: upstream y coupling by row t, stored at t + 64 for t in [-64, mr +
+  // 64 + K) with zeros outside [0, mr), so that a superstep reads it without
   // per-lane clamping
-  __shared__ T ycu[kSweepMaxRows + 128 + K];
   const Grid<T> &g = a.g;
   const SkewT<T, TR> sk{a.i0, a.i1, a.j0, a.j1};
   const int mc = sk.mc(), mr = sk.mr(), nck = sk.nck();
-  for (int t = (int)threadIdx.x - 64; t < mr + 64 + K; t += blockDim.x) {
-    T v = T(0);
-    if (t >= 0 && t < mr) {
-      const int j = sk.jrow(t);
-      v = TR ? g.N[j - 1] : g.N[j];
-    }
-    ycu[t + 64] = v;
-  }
-  for (int q = threadIdx.x; q < (kSweepMaxBands + 1) * RING; q += blockDim.x) (&ring[0][0])[q] = T(0);
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63;
-  const int band = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  const int nb = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+  const int nb = SOLO ? 1 : __builtin_amdgcn_readfirstlane(nthreads >> 6);
+  const int lane = tid & 63;
+  const int band = SOLO ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int c = band * 64 + lane;
   const bool colok = c < mc;
   const int i = sk.icol(colok ? c : mc - 1);
-  const T cu = colok ? (TR ? g.E[i - 1] : g.E[i]) : T(0);  // upstream x coupling
-  const int nsup = __builtin_amdgcn_readfirstlane(((nb - 1) * LAG + mr + 63 + K - 1) / K);
+  // upstream x coupling, read through a global (not generic) pointer before
+  // the barrier below: a generic load still in flight at the first use inside
+  // the step loop would make every iteration wait for all loads in flight
+  const BLP_GLOBAL T *gE = gptr(g.E), *gN = gptr(g.N);
+  const T cu = colok ? (TR ? gE[i - 1] : gE[i]) : T(0);
+  for (int t = tid - 64; t < mr + 64 + K; t += nthreads) {
+    T v = T(0);
+    if (t >= 0 && t < mr) {
+      const int j = sk.jrow(t);
+      v = TR ? gN[j - 1] : gN[j];
+    }
+    ycu[t + 64] = v;
+  }
+  for (int q = tid; q < (nb + 1) * RING; q += nthreads) ring[q] = T(0);
+  if (SOLO) {
+    // one wave: its LDS accesses are processed in order
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
+  }
+
+  // the last band holds mcl columns, so its last node is at local step
+  // mr + mcl - 2; earlier bands finish earlier
+  const int mcl = mc - (nb - 1) * 64;
+  const int nsup = __builtin_amdgcn_readfirstlane(((nb - 1) * LAG + mr + mcl - 1 + K - 1) / K);
   // this band's storage: chunk ck of this lane is element ck * 64
   const BLP_GLOBAL V *__restrict__ bb = gptr(reinterpret_cast<const V *>(a.b + sk.slot(band, 0, 0)) + lane);
   const BLP_GLOBAL V *__restrict__ bi = gptr(reinterpret_cast<const V *>(a.ic + sk.slot(band, 0, 0)) + lane);
   BLP_GLOBAL V *__restrict__ zz = gptr(reinterpret_cast<V *>(a.z + sk.slot(band, 0, 0)) + lane);
-  T *__restrict__ ring_out = ring[band + 1];
-  const T *__restrict__ ring_in = ring[band];
+  T *__restrict__ ring_out = ring + (band + 1) * RING;
+  const T *__restrict__ ring_in = ring + band * RING;
   const T *__restrict__ yc_lane = ycu + 64 - lane;  // yc_lane[s] = coupling of row s - lane
-  // last superstep start with a step that is not idle for every lane
-  const int shi = __builtin_amdgcn_readfirstlane((mr + 63) / K * K);
+  // last local step of this band that holds a node (its last column's last
+  // row), and the last superstep start below it
+  const int lastl = __builtin_amdgcn_readfirstlane(mr - 2 + (band == nb - 1 ? mcl : 64));
+  const int shi = __builtin_amdgcn_readfirstlane(lastl / K * K);
   // chunk of local step s (a multiple of P, wave-uniform): its own, or the sink
   auto chunk = [&](int s) {
     const int ck = s / P;
@@ -281,13 +296,18 @@ __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T>
   T buf_b[D + 1][K], buf_i[D + 1][K], res[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) res[k] = T(0);
-#pragma unroll
-  for (int u = 0; u < D; ++u) load(u * K - band * LAG, buf_b[u], buf_i[u]);
   int s_prev = -(1 << 20);  // local step of the results held in res (none yet: sink)
   T z = T(0);               // this lane's latest result (the next row's upstream value)
-
-  auto superstep = [&](int m, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
-    const int sl = __builtin_amdgcn_readfirstlane(m * K - band * LAG);  // local step of k = 0
+  auto barrier = [&]() {
+    if (SOLO) {
+      asm volatile("" ::: "memory");
+    } else {
+      lds_barrier();
+    }
+  };
+  // superstep ml of this band: local steps ml K .. ml K + K - 1
+  auto superstep = [&](int ml, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
+    const int sl = __builtin_amdgcn_readfirstlane(ml * K);
     store(s_prev, res);
     load(sl + D * K, Nb, Ni);
     // LDS operands of the superstep, read up front so that no LDS latency
@@ -297,9 +317,9 @@ __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T>
     // were written at least one superstep earlier.
     T yc[K], zb0[K];
     const int r0 = sl & (RING - 1);
-    // supersteps before the band starts or after it ends are idle for every
-    // lane: any finite coupling will do there
-    const int sy = sl < 0 ? 0 : (sl > shi ? shi : sl);
+    // the last superstep may pass the last row of every lane: any finite
+    // coupling will do there
+    const int sy = sl > shi ? shi : sl;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       yc[k] = yc_lane[sy + k];
@@ -318,23 +338,51 @@ __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T>
       for (int k = 0; k < K; ++k) ring_out[(sl + k + 1) & (RING - 1)] = res[k];
     }
     s_prev = sl;
-    lds_barrier();
+    barrier();
   };
+  // Band w runs LAG / K supersteps behind band w - 1 and works only on its
+  // own supersteps [m0, m0 + nact) of the workgroup's nsup: before and after
+  // those it only takes part in the barriers (no memory traffic).  Its
+  // first D supersteps of operands are requested D barriers before it starts,
+  // and the step loop follows those loads directly, so that the compiler's
+  // wait counts keep the D supersteps of loads in flight.
+  static_assert(LAG % K == 0 && LAG / K >= D, "lag in whole supersteps, at least D");
+  const int m0 = band * (LAG / K);
+  const int nact = __builtin_amdgcn_readfirstlane((lastl + K) / K);
+  if (m0 > 0) {
+    for (int m = 0; m < m0 - D; ++m) barrier();
+  }
+#pragma unroll
+  for (int u = 0; u < D; ++u) load(u * K, buf_b[u], buf_i[u]);
+  if (m0 > 0) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) barrier();
+  }
   // whole groups of D + 1 supersteps (buffer roles fixed by unrolling), then
   // the remaining supersteps outside the loop, so that no partially executed
   // group reaches the loop back edge
-  int m = 0;
-  for (; m + D < nsup; m += D + 1) {
+  int ml = 0;
+  for (; ml + D < nact; ml += D + 1) {
 #pragma unroll
     for (int u = 0; u <= D; ++u)
-      superstep(m + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
+      superstep(ml + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
   }
 #pragma unroll
   for (int u = 0; u < D; ++u) {
-    if (m + u < nsup)
-      superstep(m + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
+    if (ml + u < nact)
+      superstep(ml + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
   }
   store(s_prev, res);
+  for (int m = m0 + nact; m < nsup; ++m) barrier();
+}
+
+template <typename T, bool TR, int K, int D>
+__global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T> *A) {
+  const SweepArgs<T> a = A[blockIdx.x];  // one workgroup per system
+  if (gated(a.gate)) return;
+  __shared__ T ring[(kSweepMaxBands + 1) * 64];
+  __shared__ T ycu[kSweepMaxRows + 128 + K];
+  sweep_body<T, TR, K, D, false>(a, ring, ycu, threadIdx.x, blockDim.x);
 }
 
 // Natural <-> skewed copies of a rectangle of the fine grid (batched over
@@ -735,6 +783,19 @@ struct MgArgs {
   double *partials;
 };
 
+// A level with its pointers in the global space (device-side view).
+template <typename T>
+struct MgLevelG {
+  GridG<T> g;
+  const BLP_GLOBAL T *ic, *hbx, *hby, *wlx, *wrx, *wly, *wry;
+  BLP_GLOBAL T *z, *b, *t;
+};
+template <typename T>
+BLP_DEV MgLevelG<T> lview(const MgLevel<T> &L) {
+  return MgLevelG<T>{gview(L.g),  gptr(L.ic),  gptr(L.hbx), gptr(L.hby), gptr(L.wlx), gptr(L.wrx),
+                     gptr(L.wly), gptr(L.wry), gptr(L.z),   gptr(L.b),   gptr(L.t)};
+}
+
 template <typename T, bool TR>
 BLP_DEV SkewT<T, TR> level_skew(int n) { return SkewT<T, TR>{1, n, 1, n}; }
 
@@ -742,7 +803,8 @@ BLP_DEV SkewT<T, TR> level_skew(int n) { return SkewT<T, TR>{1, n, 1, n}; }
 // FP64 arithmetic whatever the storage precision (residuals of the FP32
 // cycle would otherwise lose the digits that cancel in b - A z).
 template <typename T, bool TR>
-BLP_DEV double level_apply(const Grid<T> &g, const SkewT<T, TR> &sk, const T *z, int i, int j) {
+BLP_DEV double level_apply(const GridG<T> &g, const SkewT<T, TR> &sk, const BLP_GLOBAL T *z, int i,
+                           int j) {
   const int n = g.nx;
   const double zc = z[sk.at(i, j)];
   const double zw = i > 1 ? (double)z[sk.at(i - 1, j)] : 0.0;
@@ -764,45 +826,57 @@ BLP_DEV double level_apply(const Grid<T> &g, const SkewT<T, TR> &sk, const T *z,
 // triangular system with this right-hand side, which is one Gauss-Seidel
 // sweep.  FP64 arithmetic (the terms largely cancel); padding slots get 0.
 template <typename T, bool TR>
-__global__ void k_gs_rhs(const MgArgs<T> *A) {
-  const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
-  const MgLevel<T> &L = a.L;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= L.nslot) return;
-  const Grid<T> &g = L.g;
+BLP_DEV void gs_rhs_node(const MgLevelG<T> &L, const SkewT<T, TR> &sk, int i, int j, size_t q) {
+  const GridG<T> &g = L.g;
   const int n = g.nx;
-  const SkewT<T, TR> sk = level_skew<T, TR>(n);
-  int i, j;
-  if (!sk.decode(q, i, j)) {
-    L.t[q] = T(0);
-    return;
-  }
   const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
   double v = L.b[q];
   if (id >= 1 && id <= n) v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)L.z[sk.at(id, j)];
   if (jd >= 1 && jd <= g.ny) v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)L.z[sk.at(i, jd)];
   L.t[q] = T(v);
 }
+template <typename T, bool TR>
+BLP_DEV void gs_rhs_slot(const MgLevelG<T> &L, size_t q) {
+  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
+  int i, j;
+  if (!sk.decode(q, i, j)) {
+    L.t[q] = T(0);
+    return;
+  }
+  gs_rhs_node<T, TR>(L, sk, i, j, q);
+}
+template <typename T, bool TR>
+__global__ void k_gs_rhs(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < a.L.nslot) gs_rhs_slot<T, TR>(lview(a.L), q);
+}
 
 // t = b - A z (forward) or b - A^T z (transposed) on a level.
+template <typename T, bool TR>
+BLP_DEV void resid_node(const MgLevelG<T> &L, const SkewT<T, TR> &sk, int i, int j, size_t q) {
+  L.t[q] = T((double)L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j));
+}
+template <typename T, bool TR>
+BLP_DEV void resid_slot(const MgLevelG<T> &L, size_t q) {
+  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
+  int i, j;
+  if (!sk.decode(q, i, j)) return;
+  resid_node<T, TR>(L, sk, i, j, q);
+}
 template <typename T, bool TR>
 __global__ void k_mg_resid(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
   if (a.ctrl->gate) return;
-  const MgLevel<T> &L = a.L;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= L.nslot) return;
-  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
-  int i, j;
-  if (!sk.decode(q, i, j)) return;
-  L.t[q] = T((double)L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j));
+  if (q < a.L.nslot) resid_slot<T, TR>(lview(a.L), q);
 }
 
 // One-dimensional transfer weight from fine node i to coarse node k
 // (i in {2k-1, 2k, 2k+1}).
 template <typename T>
-BLP_DEV T w1d(const T *wl, const T *wr, int i, int k) {
+BLP_DEV T w1d(const BLP_GLOBAL T *wl, const BLP_GLOBAL T *wr, int i, int k) {
   if (i == 2 * k) return T(1);
   if (i == 2 * k - 1) return wr[i];
   return wl[i];  // i == 2k+1
@@ -811,16 +885,9 @@ BLP_DEV T w1d(const T *wl, const T *wr, int i, int k) {
 // Coarse right-hand side: forward b_c = S_c^{-1} P^T S_f t_f (FE rescaling,
 // Sec. 3.2), transposed b_c = P^T t_f.  Gathers the 3x3 fine neighbourhood.
 template <typename T, bool TR>
-__global__ void k_mg_restrict(const MgArgs<T> *A) {
-  const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
-  const MgLevel<T> &F = a.L, &Cc = a.Cc;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= Cc.nslot) return;
-  const int nc = Cc.g.nx, nf = F.g.nx;
-  const SkewT<T, TR> skc = level_skew<T, TR>(nc), skf = level_skew<T, TR>(nf);
-  int k, m;
-  if (!skc.decode(q, k, m)) return;
+BLP_DEV void restrict_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skf,
+                           int k, int m, size_t q) {
+  const int nf = F.g.nx;
   T s = T(0);
   for (int jj = 2 * m - 1; jj <= 2 * m + 1; ++jj) {
     if (jj < 1 || jj > nf) continue;
@@ -835,20 +902,26 @@ __global__ void k_mg_restrict(const MgArgs<T> *A) {
   if (!TR) s /= Cc.hbx[k] * Cc.hby[m];
   Cc.b[q] = s;
 }
+template <typename T, bool TR>
+BLP_DEV void restrict_slot(const MgLevelG<T> &F, const MgLevelG<T> &Cc, size_t q) {
+  const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
+  int k, m;
+  if (!skc.decode(q, k, m)) return;
+  restrict_node<T, TR>(F, Cc, skf, k, m, q);
+}
+template <typename T, bool TR>
+__global__ void k_mg_restrict(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < a.Cc.nslot) restrict_slot<T, TR>(lview(a.L), lview(a.Cc), q);
+}
 
 // Coarse-grid correction: forward z_f += P z_c; transposed
 // z_f += S_f P S_c^{-1} z_c.
 template <typename T, bool TR>
-__global__ void k_mg_prolong(const MgArgs<T> *A) {
-  const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
-  const MgLevel<T> &F = a.L, &Cc = a.Cc;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= F.nslot) return;
-  const int nc = Cc.g.nx, nf = F.g.nx;
-  const SkewT<T, TR> skc = level_skew<T, TR>(nc), skf = level_skew<T, TR>(nf);
-  int i, j;
-  if (!skf.decode(q, i, j)) return;
+BLP_DEV void prolong_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skc,
+                          int i, int j, size_t q) {
   int kx[2], ky[2];
   T wx[2], wy[2];
   int nxk = 0, nyk = 0;
@@ -872,18 +945,28 @@ __global__ void k_mg_prolong(const MgArgs<T> *A) {
   if (TR) s *= F.hbx[i] * F.hby[j];
   F.z[q] += s;
 }
+template <typename T, bool TR>
+BLP_DEV void prolong_slot(const MgLevelG<T> &F, const MgLevelG<T> &Cc, size_t q) {
+  const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
+  int i, j;
+  if (!skf.decode(q, i, j)) return;
+  prolong_node<T, TR>(F, Cc, skc, i, j, q);
+}
+template <typename T, bool TR>
+__global__ void k_mg_prolong(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < a.L.nslot) prolong_slot<T, TR>(lview(a.L), lview(a.Cc), q);
+}
 
 // Coarsest level: four downstream Gauss-Seidel sweeps (transposed: the
 // transposed sweep on A^T), by one thread per system, from z = 0 when
 // zero_init (a coarse level) or from the current iterate (when the corner
 // block itself is the coarsest level).
 template <typename T, bool TR>
-__global__ void k_mg_coarsest(const MgArgs<T> *A, int zero_init) {
-  const MgArgs<T> a = A[blockIdx.x];
-  if (a.ctrl->gate) return;
-  if (threadIdx.x != 0) return;
-  const MgLevel<T> &L = a.L;
-  const Grid<T> &g = L.g;
+BLP_DEV void coarsest_body(const MgLevelG<T> &L, int zero_init) {
+  const GridG<T> &g = L.g;
   const int n = g.nx;
   const SkewT<T, TR> sk = level_skew<T, TR>(n);
   if (zero_init)
@@ -893,7 +976,7 @@ __global__ void k_mg_coarsest(const MgArgs<T> *A, int zero_init) {
     for (int jj = 0; jj < g.ny; ++jj)
       for (int ii = 0; ii < n; ++ii) {
         const int i = TR ? ii + 1 : n - ii, j = TR ? jj + 1 : g.ny - jj;
-        const T *z = L.z;
+        const BLP_GLOBAL T *z = L.z;
         const T zw = i > 1 ? z[sk.at(i - 1, j)] : T(0);
         const T ze = i < n ? z[sk.at(i + 1, j)] : T(0);
         const T zs = j > 1 ? z[sk.at(i, j - 1)] : T(0);
@@ -904,6 +987,83 @@ __global__ void k_mg_coarsest(const MgArgs<T> *A, int zero_init) {
         const size_t q = sk.at(i, j);
         L.z[q] = (L.b[q] - off) * L.ic[q];
       }
+  }
+}
+template <typename T, bool TR>
+__global__ void k_mg_coarsest(const MgArgs<T> *A, int zero_init) {
+  const MgArgs<T> a = A[blockIdx.x];
+  if (a.ctrl->gate) return;
+  if (threadIdx.x == 0) coarsest_body<T, TR>(lview(a.L), zero_init);
+}
+
+// ---------------------------------------------------------------------------
+// The V-cycle below a level with at most kFuseN nodes per axis, in one
+// workgroup per system: the same steps and order as the level-by-level
+// launches (pre-smoothing sweep, residual, restriction, the coarser cycle,
+// prolongation, Gauss-Seidel right-hand side, post-smoothing sweep; four
+// sweeps on the coarsest level), each a block-wide loop over the level's
+// slots followed by a barrier; the sweeps run on wave 0 (one band).  Replaces
+// about ten launches per level and cycle.
+// ---------------------------------------------------------------------------
+constexpr int kFuseN = 64;
+constexpr int kCoarseMax = 8;
+template <typename T>
+struct CoarseArgs {
+  int nlev;                  // levels held (the last is the coarsest)
+  MgLevel<T> L[kCoarseMax];  // consecutive levels, finest first
+  MgCtrl *ctrl;
+};
+
+constexpr int kCoarseThreads = 512;
+
+template <typename T, bool TR>
+__global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T> *A, int zero_init) {
+  constexpr int K = 4 * kChunk<T>, D = 2;
+  __shared__ T ring[2 * 64];
+  __shared__ T ycu[kFuseN + 128 + K];
+  const CoarseArgs<T> &a = A[blockIdx.x];
+  if (a.ctrl->gate) return;
+  const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x;
+  // smoothing sweep on level l with right-hand side t (use_t) or b
+  auto sweep = [&](int l, bool use_t) __attribute__((always_inline)) {
+    if (tid < 64) {
+      const MgLevel<T> &R = a.L[l];
+      const SweepArgs<T> sa{R.g, 1, R.g.nx, 1, R.g.nx, use_t ? R.t : R.b, R.ic, R.z, nullptr};
+      sweep_body<T, TR, K, D, true>(sa, ring, ycu, tid, 64);
+    }
+    __syncthreads();
+  };
+  // block-wide loop over the n x n nodes of a level (slot from the node)
+  auto nodes = [&](const MgLevelG<T> &L, auto &&f) {
+    const int n = L.g.nx;
+    const SkewT<T, TR> sk = level_skew<T, TR>(n);
+#pragma unroll 4
+    for (int idx = tid; idx < n * n; idx += nt) {
+      const int i = idx % n + 1, j = idx / n + 1;
+      f(sk, i, j, sk.at(i, j));
+    }
+    __syncthreads();
+  };
+  for (int l = 0; l + 1 < nl; ++l) {
+    const MgLevelG<T> L = lview(a.L[l]), Cc = lview(a.L[l + 1]);
+    if (l == 0 && !zero_init) {
+      nodes(L, [&](const SkewT<T, TR> &sk, int i, int j, size_t q) { gs_rhs_node<T, TR>(L, sk, i, j, q); });
+      sweep(l, true);
+    } else {
+      sweep(l, false);
+    }
+    nodes(L, [&](const SkewT<T, TR> &sk, int i, int j, size_t q) { resid_node<T, TR>(L, sk, i, j, q); });
+    const SkewT<T, TR> skf = level_skew<T, TR>(L.g.nx);
+    nodes(Cc, [&](const SkewT<T, TR> &, int k, int m, size_t q) { restrict_node<T, TR>(L, Cc, skf, k, m, q); });
+  }
+  if (tid == 0) coarsest_body<T, TR>(lview(a.L[nl - 1]), nl > 1 ? 1 : zero_init);
+  __syncthreads();
+  for (int l = nl - 2; l >= 0; --l) {
+    const MgLevelG<T> L = lview(a.L[l]), Cc = lview(a.L[l + 1]);
+    const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx);
+    nodes(L, [&](const SkewT<T, TR> &, int i, int j, size_t q) { prolong_node<T, TR>(L, Cc, skc, i, j, q); });
+    nodes(L, [&](const SkewT<T, TR> &sk, int i, int j, size_t q) { gs_rhs_node<T, TR>(L, sk, i, j, q); });
+    sweep(l, true);
   }
 }
 
@@ -918,10 +1078,11 @@ __global__ __launch_bounds__(256) void k_mg_norm(const MgArgs<T> *A, int mode) {
   const MgArgs<T> a = A[blockIdx.y];
   MgCtrl *ctrl = a.ctrl;
   if (ctrl->gate) return;  // uniform across the system's blocks
-  const MgLevel<T> &L = a.L;
+  const MgLevelG<T> L = lview(a.L);
   const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
+  const size_t nslot = a.L.nslot;
   double acc = 0.0;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < L.nslot;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nslot;
        q += (size_t)gridDim.x * blockDim.x) {
     int i, j;
     if (!sk.decode(q, i, j)) continue;
