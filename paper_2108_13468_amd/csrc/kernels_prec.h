@@ -97,17 +97,20 @@ BLP_DEV void scan_affine_down(T &A, T &M, int lane) {
 // of one lane in one chunk are contiguous:
 //   node (c, t) -> ((band * nck + s / P) * 64 + l) * P + s mod P,
 // so one 16-byte access per lane moves P steps of a band, and the 64 lanes of
-// a wave touch 1 KiB of consecutive bytes.  A band has nck = ceil((mr + 63) /
-// P) + 1 chunks; the last chunk holds no node (a sink for idle steps), and
-// neither do the slots with t < 0 or t >= mr (padding, kept at zero in
-// right-hand sides and inverse diagonals).
+// a wave touch 1 KiB of consecutive bytes.  A band has nck chunks, a whole
+// number of groups of kSkewGroup = 4 chunks: those of steps 0 .. mr + 62 (the
+// last node of the band is at step mr - 1 + 63), then at least one whole
+// group that holds no node (the sink that the sweep's loads past the band's
+// last step read).  Slots with t < 0 or t >= mr are padding, kept at zero in
+// right-hand sides and inverse diagonals.
 // ---------------------------------------------------------------------------
+constexpr int kSkewGroup = 4;
 template <bool TR, int P>
 struct Skew {
   int i0, i1, j0, j1;
   BLP_DEV int mc() const { return i1 - i0 + 1; }
   BLP_DEV int mr() const { return j1 - j0 + 1; }
-  BLP_DEV int nck() const { return (mr() + 62 + P) / P + 1; }
+  BLP_DEV int nck() const { return ((mr() + 62) / (kSkewGroup * P) + 2) * kSkewGroup; }
   BLP_DEV int col(int i) const { return TR ? i - i0 : i1 - i; }
   BLP_DEV int row(int j) const { return TR ? j - j0 : j1 - j; }
   BLP_DEV int icol(int c) const { return TR ? i0 + c : i1 - c; }
@@ -140,7 +143,7 @@ using SkewT = Skew<TR, kChunk<T>>;
 template <typename T>
 inline size_t skew_size(int mc, int mr) {
   constexpr int P = kChunk<T>;
-  return (size_t)((mc + 63) / 64) * ((mr + 62 + P) / P + 1) * 64 * P;
+  return (size_t)((mc + 63) / 64) * (((mr + 62) / (kSkewGroup * P) + 2) * kSkewGroup) * 64 * P;
 }
 
 // ---------------------------------------------------------------------------
@@ -166,15 +169,25 @@ inline size_t skew_size(int mc, int mr) {
 // Idle steps need no masking: padding slots hold rhs = 1/C = 0, so a lane
 // whose row is not yet reached computes exactly 0 (the ring starts at zero),
 // which is also the correct upstream value of the first row; steps past the
-// last row land in padding or in the sink chunk.
+// last row land in padding.  A band works only on its own supersteps (local
+// steps 0 .. its last node's step, rounded up to whole supersteps) and only
+// joins the barriers before and after them.
 //
-// Memory pipelining: every access is one 16-byte chunk per lane.  At the
-// start of superstep m the wave stores the results of superstep m-1 and
-// issues the loads of superstep m+D into the register buffer that superstep
-// m-1 used (D+1 buffers, rotated by full unrolling), then computes superstep
-// m.  A superstep issues 3K/P memory instructions, so the wait before
-// superstep m covers operations issued D supersteps earlier, as long as
-// 3DK/P stays within the 63 outstanding operations the counter can track.
+// Memory pipelining: every access is one 16-byte chunk per lane; the K/P
+// chunks of a superstep are consecutive, so one address per array and
+// superstep serves them all (immediate offsets).  At the start of superstep m
+// the wave stores the results of superstep m-1 and issues the loads of
+// superstep m+D (clamped to the sink group) into the register buffer that
+// superstep m-1 used (D+1 buffers, rotated by full unrolling), then computes
+// superstep m.  A superstep issues 3K/P memory instructions, so the wait
+// before superstep m covers operations issued D supersteps earlier, as long
+// as 3DK/P stays within the 63 outstanding operations the counter can track.
+//
+// The wave issues one instruction at a time, so the schedule keeps the
+// instructions per step few: aligned 16-byte LDS accesses for the ring and
+// for the row-coupling table (held in P copies shifted by one word each, so
+// that every lane's K consecutive entries start on a 16-byte boundary in one
+// of them), and no per-chunk address arithmetic.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct SweepArgs {
@@ -186,8 +199,15 @@ struct SweepArgs {
   const int *gate;
 };
 
-constexpr int kSweepMaxRows = 1024;  // also bounds the rows of the ycu table
+constexpr int kSweepMaxRows = 1024;  // also bounds the rows of the coupling table
 constexpr int kSweepMaxBands = 16;
+
+// Words per copy of the row-coupling table for rows rows (entries -64 ..
+// rows + 63 + K of the row index, rounded up to whole chunks).
+template <typename T, int K>
+BLP_DEV constexpr int yc_stride(int rows) {
+  return (rows + 128 + K + kChunk<T> - 1) / kChunk<T> * kChunk<T>;
+}
 
 // Workgroup barrier that waits for this wave's LDS traffic only (global
 // loads and stores may stay in flight): s_waitcnt lgkmcnt(0) with vmcnt and
@@ -209,17 +229,15 @@ struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
 
 // The sweep of one workgroup (wave w = band w of nb), or, SOLO, of a single
 // wave on a rectangle of at most 64 columns inside a larger kernel (no
-// barriers: with one band there is no ring traffic).  ring holds (nb + 1) x
-// 64 words and ycu rows + 128 + K words of LDS, both provided by the caller.
+// barriers and no ring: with one band there is no upstream band).  ring holds
+// (nb + 1) x 64 words and ycs kChunk<T> x yc_stride<T, K>(rows) words of LDS,
+// both 16-byte aligned and provided by the caller.
 template <typename T, bool TR, int K, int D, bool SOLO>
-BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nthreads) {
+BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nthreads) {
   constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64;
-  static_assert(K % P == 0 && 64 % K == 0 && 2 * K < 64, "superstep length");
+  static_assert(K % P == 0 && 64 % K == 0 && 2 * K + P <= 64 && CK <= kSkewGroup, "superstep length");
+  static_assert(LAG % K == 0 && LAG / K >= D, "lag in whole supersteps, at least D");
   typedef typename Vec16<T>::type V;
-  // ring row w + 1 holds the last column of band w by step; row 0 stays zero.
-  // ycu: upstream y coupling by row t, stored at t + 64 for t in [-64, mr +
-  // 64 + K) with zeros outside [0, mr), so that a superstep reads it without
-  // per-lane clamping
   const Grid<T> &g = a.g;
   const SkewT<T, TR> sk{a.i0, a.i1, a.j0, a.j1};
   const int mc = sk.mc(), mr = sk.mr(), nck = sk.nck();
@@ -234,15 +252,33 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
   // the step loop would make every iteration wait for all loads in flight
   const BLP_GLOBAL T *gE = gptr(g.E), *gN = gptr(g.N);
   const T cu = colok ? (TR ? gE[i - 1] : gE[i]) : T(0);
-  for (int t = tid - 64; t < mr + 64 + K; t += nthreads) {
-    T v = T(0);
-    if (t >= 0 && t < mr) {
-      const int j = sk.jrow(t);
-      v = TR ? gN[j - 1] : gN[j];
+  // row-coupling table: copy q (q < P) holds at word w the upstream y
+  // coupling of row w + q - 64 (zero outside rows 0 .. mr - 1).  One load
+  // per row, four in flight per thread, each value stored into every copy.
+  const int ys = yc_stride<T, K>(mr);
+  for (int x0 = tid; x0 < ys + P - 1; x0 += 4 * nthreads) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = x0 + u * nthreads - 64;
+      v[u] = T(0);
+      if (t >= 0 && t < mr) {
+        const int j = sk.jrow(t);
+        v[u] = TR ? gN[j - 1] : gN[j];
+      }
     }
-    ycu[t + 64] = v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int x = x0 + u * nthreads;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int w = x - q;
+        if (w >= 0 && w < ys) ycs[q * ys + w] = v[u];
+      }
+    }
   }
-  for (int q = tid; q < (nb + 1) * RING; q += nthreads) ring[q] = T(0);
+  if (!SOLO)
+    for (int q = tid; q < (nb + 1) * RING; q += nthreads) ring[q] = T(0);
   if (SOLO) {
     // one wave: its LDS accesses are processed in order
     asm volatile("" ::: "memory");
@@ -259,23 +295,26 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
   const BLP_GLOBAL V *__restrict__ bb = gptr(reinterpret_cast<const V *>(a.b + sk.slot(band, 0, 0)) + lane);
   const BLP_GLOBAL V *__restrict__ bi = gptr(reinterpret_cast<const V *>(a.ic + sk.slot(band, 0, 0)) + lane);
   BLP_GLOBAL V *__restrict__ zz = gptr(reinterpret_cast<V *>(a.z + sk.slot(band, 0, 0)) + lane);
-  T *__restrict__ ring_out = ring + (band + 1) * RING;
-  const T *__restrict__ ring_in = ring + band * RING;
-  const T *__restrict__ yc_lane = ycu + 64 - lane;  // yc_lane[s] = coupling of row s - lane
+  const V *ring_in = SOLO ? nullptr : reinterpret_cast<const V *>(ring + band * RING);
+  V *ring_out = SOLO ? nullptr : reinterpret_cast<V *>(ring + (band + 1) * RING);
   // last local step of this band that holds a node (its last column's last
-  // row), and the last superstep start below it
+  // row), and the last superstep start at or below it
   const int lastl = __builtin_amdgcn_readfirstlane(mr - 2 + (band == nb - 1 ? mcl : 64));
   const int shi = __builtin_amdgcn_readfirstlane(lastl / K * K);
-  // chunk of local step s (a multiple of P, wave-uniform): its own, or the sink
-  auto chunk = [&](int s) {
-    const int ck = s / P;
-    return (s >= 0 && ck < nck - 1) ? ck : nck - 1;
-  };
-  auto load = [&](int s, T (&Bb)[K], T (&Bi)[K]) {
+  // the coupling of this lane at local step s is that of row s - lane, word
+  // s + 64 - lane of copy 0, i.e. word s + 64 - lane - q of copy q with
+  // q = (64 - lane) mod P: a multiple of P for every s that is
+  const int yq = (64 - lane) & (P - 1);
+  const V *yc_base = reinterpret_cast<const V *>(ycs + yq * ys + 64 - lane - yq);
+  // group of K / P chunks that holds no node (loads past the band's end)
+  const int sink = __builtin_amdgcn_readfirstlane(nck / CK - 1);
+
+  auto load = [&](int u, T (&Bb)[K], T (&Bi)[K]) {  // superstep u's operands
+    const int ck = (u < sink ? u : sink) * CK;
+    const BLP_GLOBAL V *pb = bb + ck * 64, *pi = bi + ck * 64;
 #pragma unroll
     for (int q = 0; q < CK; ++q) {
-      const int ck = chunk(s + q * P);
-      const V vb = bb[ck * 64], vi = bi[ck * 64];
+      const V vb = pb[q * 64], vi = pi[q * 64];
 #pragma unroll
       for (int e = 0; e < P; ++e) {
         Bb[q * P + e] = vb[e];
@@ -283,21 +322,21 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
       }
     }
   };
-  auto store = [&](int s, const T (&R)[K]) {
+  auto store = [&](int u, const T (&R)[K]) {  // superstep u's results (u < 0: sink)
+    BLP_GLOBAL V *pz = zz + (u < 0 ? sink : u) * CK * 64;
 #pragma unroll
     for (int q = 0; q < CK; ++q) {
       V v;
 #pragma unroll
       for (int e = 0; e < P; ++e) v[e] = R[q * P + e];
-      zz[chunk(s + q * P) * 64] = v;
+      pz[q * 64] = v;
     }
   };
 
   T buf_b[D + 1][K], buf_i[D + 1][K], res[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) res[k] = T(0);
-  int s_prev = -(1 << 20);  // local step of the results held in res (none yet: sink)
-  T z = T(0);               // this lane's latest result (the next row's upstream value)
+  T z = T(0);  // this lane's latest result (the next row's upstream value)
   auto barrier = [&]() {
     if (SOLO) {
       asm volatile("" ::: "memory");
@@ -307,23 +346,37 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
   };
   // superstep ml of this band: local steps ml K .. ml K + K - 1
   auto superstep = [&](int ml, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
-    const int sl = __builtin_amdgcn_readfirstlane(ml * K);
-    store(s_prev, res);
-    load(sl + D * K, Nb, Ni);
+    const int sl = ml * K;
+    store(ml - 1, res);
+    load(ml + D, Nb, Ni);
     // LDS operands of the superstep, read up front so that no LDS latency
-    // sits on the step-to-step dependency chain.  Ring slot of local step s
-    // of the writer is (s + 1) mod 64, so lane 0 of this band, at local step
-    // s, needs slot s mod 64 (the writer's step s + 63); entries read here
-    // were written at least one superstep earlier.
+    // sits on the step-to-step dependency chain.  The writer band stores
+    // its local step s (lane 63) in ring slot s mod 64; lane 0 of this band,
+    // at local step s, needs the writer's step s + 63, slot (s - 1) mod 64,
+    // written at least one superstep earlier.  The last superstep may pass
+    // the last row of every lane: any finite coupling will do there.
     T yc[K], zb0[K];
-    const int r0 = sl & (RING - 1);
-    // the last superstep may pass the last row of every lane: any finite
-    // coupling will do there
-    const int sy = sl > shi ? shi : sl;
+    const V *yr = yc_base + (sl > shi ? shi : sl) / P;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      yc[k] = yc_lane[sy + k];
-      zb0[k] = ring_in[r0 + k];
+    for (int q = 0; q < CK; ++q) {
+      const V v = yr[q];
+#pragma unroll
+      for (int e = 0; e < P; ++e) yc[q * P + e] = v[e];
+    }
+    if (SOLO) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) zb0[k] = T(0);
+    } else {
+      const int r0 = (sl & (RING - 1)) / P;
+      const V pv = ring_in[(r0 + RING / P - 1) & (RING / P - 1)];
+      zb0[0] = pv[P - 1];
+#pragma unroll
+      for (int q = 0; q < CK; ++q) {
+        const V v = ring_in[r0 + q];
+#pragma unroll
+        for (int e = 0; e < P; ++e)
+          if (q * P + e + 1 < K) zb0[q * P + e + 1] = v[e];
+      }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -331,13 +384,19 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
       z = (Cb[k] - yc[k] * z - cu * zin) * Ci[k];
       res[k] = z;
     }
-    // a slot is read K + 1 steps after it is written and rewritten 64 steps
-    // after (2K < 64 keeps both in different supersteps)
-    if (lane == 63) {
+    // the slots written here (steps sl .. sl + K - 1) and the slots the
+    // next band reads in the same superstep (steps sl - K - P .. sl - 1 of
+    // this band, mod 64) are disjoint: 2K + P <= 64
+    if (!SOLO && lane == 63) {
+      const int r0 = (sl & (RING - 1)) / P;
 #pragma unroll
-      for (int k = 0; k < K; ++k) ring_out[(sl + k + 1) & (RING - 1)] = res[k];
+      for (int q = 0; q < CK; ++q) {
+        V v;
+#pragma unroll
+        for (int e = 0; e < P; ++e) v[e] = res[q * P + e];
+        ring_out[r0 + q] = v;
+      }
     }
-    s_prev = sl;
     barrier();
   };
   // Band w runs LAG / K supersteps behind band w - 1 and works only on its
@@ -346,14 +405,13 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
   // first D supersteps of operands are requested D barriers before it starts,
   // and the step loop follows those loads directly, so that the compiler's
   // wait counts keep the D supersteps of loads in flight.
-  static_assert(LAG % K == 0 && LAG / K >= D, "lag in whole supersteps, at least D");
   const int m0 = band * (LAG / K);
   const int nact = __builtin_amdgcn_readfirstlane((lastl + K) / K);
   if (m0 > 0) {
     for (int m = 0; m < m0 - D; ++m) barrier();
   }
 #pragma unroll
-  for (int u = 0; u < D; ++u) load(u * K, buf_b[u], buf_i[u]);
+  for (int u = 0; u < D; ++u) load(u, buf_b[u], buf_i[u]);
   if (m0 > 0) {
 #pragma unroll
     for (int u = 0; u < D; ++u) barrier();
@@ -372,7 +430,7 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycu, int tid, int nth
     if (ml + u < nact)
       superstep(ml + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
   }
-  store(s_prev, res);
+  store(nact - 1, res);
   for (int m = m0 + nact; m < nsup; ++m) barrier();
 }
 
@@ -380,9 +438,9 @@ template <typename T, bool TR, int K, int D>
 __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T> *A) {
   const SweepArgs<T> a = A[blockIdx.x];  // one workgroup per system
   if (gated(a.gate)) return;
-  __shared__ T ring[(kSweepMaxBands + 1) * 64];
-  __shared__ T ycu[kSweepMaxRows + 128 + K];
-  sweep_body<T, TR, K, D, false>(a, ring, ycu, threadIdx.x, blockDim.x);
+  __shared__ __align__(16) T ring[(kSweepMaxBands + 1) * 64];
+  __shared__ __align__(16) T ycs[kChunk<T> * yc_stride<T, K>(kSweepMaxRows)];
+  sweep_body<T, TR, K, D, false>(a, ring, ycs, threadIdx.x, blockDim.x);
 }
 
 // Natural <-> skewed copies of a rectangle of the fine grid (batched over
@@ -1019,8 +1077,7 @@ constexpr int kCoarseThreads = 512;
 template <typename T, bool TR>
 __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T> *A, int zero_init) {
   constexpr int K = 4 * kChunk<T>, D = 2;
-  __shared__ T ring[2 * 64];
-  __shared__ T ycu[kFuseN + 128 + K];
+  __shared__ __align__(16) T ycs[kChunk<T> * yc_stride<T, K>(kFuseN)];
   const CoarseArgs<T> &a = A[blockIdx.x];
   if (a.ctrl->gate) return;
   const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x;
@@ -1029,7 +1086,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
     if (tid < 64) {
       const MgLevel<T> &R = a.L[l];
       const SweepArgs<T> sa{R.g, 1, R.g.nx, 1, R.g.nx, use_t ? R.t : R.b, R.ic, R.z, nullptr};
-      sweep_body<T, TR, K, D, true>(sa, ring, ycu, tid, 64);
+      sweep_body<T, TR, K, D, true>(sa, nullptr, ycs, tid, 64);
     }
     __syncthreads();
   };
