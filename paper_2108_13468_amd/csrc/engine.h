@@ -298,14 +298,17 @@ template <typename T, bool TR, int EP, int W>
 void lines_launch_k(const Ctx &c, int S, const LineArgs<T> *A) {
   // D lines of operands in flight: 4 EP words per line and wave, within the
   // 63 outstanding memory operations a wave can track and its registers
-  constexpr int D = EP >= 4 ? 4 : 6;
+  constexpr int D = EP >= 16 ? (sizeof(T) == 8 ? 1 : 2) : (EP >= 4 ? 4 : 6);
   k_lines<T, TR, EP, W, D><<<2 * S, 64 * W, 0, c.stream>>>(A);
 }
 
 // Line solves: threads hold EP contiguous nodes, W waves per region (EP x
-// 64 W >= hp); the variants trade scan depth within threads against waves.
+// 64 W >= hp).  A line is a chain of dependent scans, so its latency sets the
+// pace: one wave (no workgroup barriers between the scan phases) is the
+// default; variants with more waves and fewer nodes per thread remain for
+// the autotuner.
 inline int lines_variants(int hp) {
-  return hp <= 64 ? 1 : (hp <= 256 ? 2 : (hp <= 512 ? 3 : 2));
+  return hp <= 64 ? 1 : (hp <= 128 ? 2 : (hp <= 256 ? 3 : 4));
 }
 
 template <typename T, bool TR>
@@ -313,18 +316,22 @@ void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A, int var = 0
   if (hp <= 64) {
     lines_launch_k<T, TR, 1, 1>(c, S, A);
   } else if (hp <= 128) {
-    if (var == 1) lines_launch_k<T, TR, 2, 1>(c, S, A);
-    else lines_launch_k<T, TR, 1, 2>(c, S, A);
+    if (var == 1) lines_launch_k<T, TR, 1, 2>(c, S, A);
+    else lines_launch_k<T, TR, 2, 1>(c, S, A);
   } else if (hp <= 256) {
     if (var == 1) lines_launch_k<T, TR, 2, 2>(c, S, A);
-    else lines_launch_k<T, TR, 1, 4>(c, S, A);
+    else if (var == 2) lines_launch_k<T, TR, 1, 4>(c, S, A);
+    else lines_launch_k<T, TR, 4, 1>(c, S, A);
   } else if (hp <= 512) {
     if (var == 1) lines_launch_k<T, TR, 4, 2>(c, S, A);
-    else if (var == 2) lines_launch_k<T, TR, 1, 8>(c, S, A);
-    else lines_launch_k<T, TR, 2, 4>(c, S, A);
+    else if (var == 2) lines_launch_k<T, TR, 2, 4>(c, S, A);
+    else if (var == 3) lines_launch_k<T, TR, 1, 8>(c, S, A);
+    else lines_launch_k<T, TR, 8, 1>(c, S, A);
   } else {
-    if (var == 1) lines_launch_k<T, TR, 2, 8>(c, S, A);
-    else lines_launch_k<T, TR, 4, 4>(c, S, A);
+    if (var == 1) lines_launch_k<T, TR, 8, 2>(c, S, A);
+    else if (var == 2) lines_launch_k<T, TR, 4, 4>(c, S, A);
+    else if (var == 3) lines_launch_k<T, TR, 2, 8>(c, S, A);
+    else lines_launch_k<T, TR, 16, 1>(c, S, A);
   }
 }
 
