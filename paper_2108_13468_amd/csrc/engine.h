@@ -158,8 +158,10 @@ struct PrecPlan {
   // kernel variants (autotuner; 0 = default)
   int varI = 0, varLines = 0;
   std::vector<int> varL;
-  // fused cycle below level lc (at most kFuseN nodes per axis); -1: none
+  // fused cycle below level lc (at most kLdsN<T> nodes per axis, held in
+  // coarse_lds bytes of LDS); -1: none
   int lc = -1;
+  size_t coarse_lds = 0;
   CoarseArgs<T> *coarse = nullptr;
   Alloc mem;
 };
@@ -239,18 +241,30 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   // the coarse levels run as one fused cycle per system
   P.lc = -1;
   for (int l = 0; l < nl; ++l)
-    if (P.ln[l] <= kFuseN) {
+    if (P.ln[l] <= kLdsN<T>) {
       if (nl - l <= kCoarseMax) P.lc = l;
       break;
     }
   if (P.lc >= 0) {
+    bool nodal = false;
+    for (int q = 0; q < S; ++q) nodal = nodal || mg[P.lc][q].L.g.r != nullptr;
+    P.coarse_lds = coarse_lds_bytes<T>(P.ln[P.lc], nl - P.lc, nodal);
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mg_coarse<T, TR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.coarse_lds));
+    // constant LDS images, one per system (zero padding rows)
+    const size_t iw = (size_t)lds_image_words<T>(P.ln[P.lc], nl - P.lc, nodal);
+    T *img = nullptr;
+    BLP_TRY(P.mem.get(&img, iw * S, st, true));
     std::vector<CoarseArgs<T>> ca(S);
     for (int q = 0; q < S; ++q) {
       ca[q].nlev = nl - P.lc;
       for (int l = P.lc; l < nl; ++l) ca[q].L[l - P.lc] = mg[l][q].L;
       ca[q].ctrl = mg[0][q].ctrl;
+      ca[q].image = img + iw * q;
     }
     BLP_TRY(P.mem.put(&P.coarse, ca.data(), S, st));
+    k_coarse_image<T, TR><<<S, 256, 0, st>>>(P.coarse);
+    HIP_TRY(hipGetLastError());
   }
   BLP_TRY(P.mem.put(&P.ioI, ioI.data(), S, st));
   BLP_TRY(P.mem.put(&P.swI, swI.data(), S, st));
@@ -378,7 +392,7 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
     double pts = 0.0;
     for (int k = l; k < nl; ++k) pts += (double)S * P.ln[k] * P.ln[k];
     KScope ks(c, KC_MG, pts * 12 * sizeof(T));
-    k_mg_coarse<T, TR><<<S, kCoarseThreads, 0, c.stream>>>(P.coarse, zero_init ? 1 : 0);
+    k_mg_coarse<T, TR><<<S, kCoarseThreads, P.coarse_lds, c.stream>>>(P.coarse, zero_init ? 1 : 0);
     return;
   }
   if (l == nl - 1) {

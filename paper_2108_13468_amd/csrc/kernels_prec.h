@@ -1055,73 +1055,387 @@ __global__ void k_mg_coarsest(const MgArgs<T> *A, int zero_init) {
 }
 
 // ---------------------------------------------------------------------------
-// The V-cycle below a level with at most kFuseN nodes per axis, in one
-// workgroup per system: the same steps and order as the level-by-level
+// The V-cycle below a level with at most kLdsN<T> nodes per axis, in one
+// workgroup per system with every level held in LDS in the natural layout
+// (node (i, j) at word (j - 1) n + i - 1, plus a zero padding row j = 0 and
+// j = n + 1 in the iterate, right-hand side, residual and inverse diagonal):
+// the axis and transfer tables, the inverse diagonal and nodal r (when
+// present) of every level form a constant image, laid out once per system in
+// global memory (k_coarse_image) and copied into LDS at the start of each
+// cycle.  The steps and their arithmetic are those of the level-by-level
 // launches (pre-smoothing sweep, residual, restriction, the coarser cycle,
 // prolongation, Gauss-Seidel right-hand side, post-smoothing sweep; four
-// sweeps on the coarsest level), each a block-wide loop over the level's
-// slots followed by a barrier; the sweeps run on wave 0 (one band).  Replaces
-// about ten launches per level and cycle.
+// Gauss-Seidel sweeps on the coarsest level); node loops use the whole
+// workgroup, sweeps one wave (the levels have at most 64 columns).  Only the
+// finest fused level touches the work vectors in global memory: its
+// right-hand side (and iterate, when not zero) is read at the start and its
+// iterate written back at the end, in the skewed layout of the other kernels.
 // ---------------------------------------------------------------------------
-constexpr int kFuseN = 64;
+template <typename T>
+constexpr int kLdsN = sizeof(T) == 4 ? 64 : 32;
 constexpr int kCoarseMax = 8;
 template <typename T>
 struct CoarseArgs {
   int nlev;                  // levels held (the last is the coarsest)
   MgLevel<T> L[kCoarseMax];  // consecutive levels, finest first
   MgCtrl *ctrl;
+  T *image;                  // constant image (k_coarse_image)
 };
 
 constexpr int kCoarseThreads = 512;
 
+// Array sizes in words, rounded up to whole 16-byte chunks: tables (n + 2),
+// padded node arrays (n + 2 rows), plain node arrays (nodal r).
+template <typename T>
+__host__ __device__ inline int lds_round(int w) {
+  constexpr int P = 16 / (int)sizeof(T);
+  return (w + P - 1) / P * P;
+}
+// constant words of one level: twelve tables, the inverse diagonal, nodal r
+template <typename T>
+__host__ __device__ inline int lds_const_words(int n, bool nodal) {
+  return 12 * lds_round<T>(n + 2) + lds_round<T>((n + 2) * n) + (nodal ? lds_round<T>(n * n) : 0);
+}
+// work words of one level: iterate, right-hand side, residual
+template <typename T>
+__host__ __device__ inline int lds_work_words(int n) {
+  return 3 * lds_round<T>((n + 2) * n);
+}
+template <typename T>
+__host__ __device__ inline int lds_image_words(int n0, int nl, bool nodal) {
+  int w = 0;
+  for (int l = 0; l < nl; ++l) w += lds_const_words<T>(n0 >> l, nodal);
+  return w;
+}
+
+template <typename T>
+struct LdsLevel {
+  int n;
+  T *z, *b, *t, *ic;  // node (1, 1); rows j = 0 and j = n + 1 are padding
+  T *r;               // nodal r (no padding), or nullptr: constant rc
+  T *W, *E, *S, *N, *Dx, *Dy, *hbx, *hby, *wlx, *wrx, *wly, *wry;
+  T rc;
+  BLP_DEV int at(int i, int j) const { return (j - 1) * n + (i - 1); }
+  BLP_DEV T rr(int i, int j) const { return r ? r[at(i, j)] : rc; }
+};
+
+// Level l of the fused hierarchy (n0 >> l nodes per axis): constant part in
+// cbase (the image layout), work part in wbase.
+template <typename T>
+BLP_DEV LdsLevel<T> lds_level(T *cbase, T *wbase, int n0, int l, bool nodal, T rc) {
+  int co = 0, wo = 0;
+  for (int k = 0; k < l; ++k) {
+    co += lds_const_words<T>(n0 >> k, nodal);
+    wo += lds_work_words<T>(n0 >> k);
+  }
+  const int n = n0 >> l, a1 = lds_round<T>(n + 2), ap = lds_round<T>((n + 2) * n);
+  LdsLevel<T> v;
+  v.n = n;
+  v.rc = rc;
+  T *p = cbase + co;
+  T **tab[12] = {&v.W, &v.E, &v.S, &v.N, &v.Dx, &v.Dy, &v.hbx, &v.hby, &v.wlx, &v.wrx, &v.wly, &v.wry};
+#pragma unroll
+  for (int k = 0; k < 12; ++k) { *tab[k] = p; p += a1; }
+  v.ic = p + n; p += ap;
+  v.r = nodal ? p : nullptr;
+  T *q = wbase + wo;
+  v.z = q + n;
+  v.b = q + ap + n;
+  v.t = q + 2 * ap + n;
+  return v;
+}
+
+// Constant image of one system's fused levels (setup; one block per system).
+// The buffer is zero on entry (padding rows stay zero).
+template <typename T, bool TR>
+__global__ void k_coarse_image(const CoarseArgs<T> *A) {
+  const CoarseArgs<T> &a = A[blockIdx.x];
+  const int n0 = a.L[0].g.nx;
+  const bool nodal = a.L[0].g.r != nullptr;
+  for (int l = 0; l < a.nlev; ++l) {
+    const LdsLevel<T> V = lds_level<T>(a.image, nullptr, n0, l, nodal, T(0));
+    const MgLevel<T> &G = a.L[l];
+    const int n = V.n;
+    const T *src[12] = {G.g.W, G.g.E, G.g.S, G.g.N, G.g.Dx, G.g.Dy, G.hbx, G.hby, G.wlx, G.wrx, G.wly, G.wry};
+    T *dst[12] = {V.W, V.E, V.S, V.N, V.Dx, V.Dy, V.hbx, V.hby, V.wlx, V.wrx, V.wly, V.wry};
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+      for (int x = threadIdx.x; x < n + 2; x += blockDim.x) dst[k][x] = src[k][x];
+    const SkewT<T, TR> sk = level_skew<T, TR>(n);
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+      const int i = idx % n + 1, j = idx / n + 1;
+      V.ic[idx] = G.ic[sk.at(i, j)];
+      if (nodal) V.r[idx] = G.g.r[(size_t)(j - 1) * G.g.rld + (i - 1)];
+    }
+  }
+}
+
+// (A z)_ij or (A^T z)_ij in FP64 arithmetic (as level_apply).
+template <typename T, bool TR>
+BLP_DEV double lds_apply(const LdsLevel<T> &L, int i, int j) {
+  const int n = L.n;
+  const T *z = L.z;
+  const double zc = z[L.at(i, j)];
+  const double zw = i > 1 ? (double)z[L.at(i - 1, j)] : 0.0;
+  const double ze = i < n ? (double)z[L.at(i + 1, j)] : 0.0;
+  const double zs = j > 1 ? (double)z[L.at(i, j - 1)] : 0.0;
+  const double zn = j < n ? (double)z[L.at(i, j + 1)] : 0.0;
+  const double C = (double)L.Dx[i] + (double)L.Dy[j] + (double)L.rr(i, j);
+  if (!TR)
+    return C * zc + (double)L.W[i] * zw + (double)L.E[i] * ze + (double)L.S[j] * zs +
+           (double)L.N[j] * zn;
+  return C * zc + (double)L.E[i - 1] * zw + (double)L.W[i + 1] * ze + (double)L.N[j - 1] * zs +
+         (double)L.S[j + 1] * zn;
+}
+
+// Downstream sweep on an LDS level by one wave (lane = column, as the
+// skewed sweep): z = solution of the triangular system with right-hand side
+// rhs (the level's b or t).  Row t of a lane's column (t = 0 first) is clamped
+// to the padding rows -1 and n outside 0 .. n - 1, where rhs and the inverse
+// diagonal are zero: those steps compute z = 0, the upstream value of the
+// first row, and store it into the iterate's padding.  Lane 0 has no
+// upstream column.
+template <typename T, bool TR>
+BLP_DEV void lds_sweep(const LdsLevel<T> &L, const T *rhs, int lane) {
+  constexpr int K = 8;
+  const int n = L.n;
+  const bool col = lane < n;
+  const int c = col ? lane : 0;
+  const int i = TR ? 1 + c : n - c;
+  const T cu = col ? (TR ? L.E[i - 1] : L.E[i]) : T(0);
+  // row t sits at j = 1 + t (transposed) or n - t: word o0 + t dq
+  const int o0 = TR ? i - 1 : (n - 1) * n + i - 1, dq = TR ? n : -n;
+  const int lofs = col ? lane : 4 * n;  // lanes without a column stay in the padding
+  T z = T(0);
+  for (int s0 = 0; s0 < 2 * n - 1; s0 += K) {
+    T bv[K], iv[K], yv[K];
+    int o[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int t = min(max(s0 + k - lofs, -1), n);
+      o[k] = o0 + t * dq;
+      bv[k] = rhs[o[k]];
+      iv[k] = L.ic[o[k]];
+      const int ty = min(max(t, 0), n - 1);
+      yv[k] = TR ? L.N[ty] : L.N[n - ty];  // N_{j-1} with j = 1 + t, or N_j with j = n - t
+    }
+    T res[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const T zin = dpp_mov<0x138>(T(0), z);  // lane l-1's value; lane 0: none
+      z = (bv[k] - yv[k] * z - cu * zin) * iv[k];
+      res[k] = z;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) L.z[o[k]] = res[k];
+  }
+}
+
+template <typename T>
+BLP_DEV T lds_w1d(const T *wl, const T *wr, int i, int k) {
+  if (i == 2 * k) return T(1);
+  if (i == 2 * k - 1) return wr[i];
+  return wl[i];  // i == 2k+1
+}
+
 template <typename T, bool TR>
 __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T> *A, int zero_init) {
-  constexpr int K = 4 * kChunk<T>, D = 2;
-  __shared__ __align__(16) T ycs[kChunk<T> * yc_stride<T, K>(kFuseN)];
+  extern __shared__ __align__(16) unsigned char blp_lds[];
+  typedef typename Vec16<T>::type V16;
+  constexpr int P = 16 / (int)sizeof(T);
+  T *cbase = reinterpret_cast<T *>(blp_lds);
   const CoarseArgs<T> &a = A[blockIdx.x];
   if (a.ctrl->gate) return;
-  const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x;
-  // smoothing sweep on level l with right-hand side t (use_t) or b
-  auto sweep = [&](int l, bool use_t) __attribute__((always_inline)) {
-    if (tid < 64) {
-      const MgLevel<T> &R = a.L[l];
-      const SweepArgs<T> sa{R.g, 1, R.g.nx, 1, R.g.nx, use_t ? R.t : R.b, R.ic, R.z, nullptr};
-      sweep_body<T, TR, K, D, true>(sa, nullptr, ycs, tid, 64);
+  const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+  const int n0 = a.L[0].g.nx;
+  const bool nodal = a.L[0].g.r != nullptr;
+  const T rc = a.L[0].g.rc;
+  const int cw = lds_image_words<T>(n0, nl, nodal);
+  T *wbase = cbase + cw;
+  auto lev = [&](int l) { return lds_level<T>(cbase, wbase, n0, l, nodal, rc); };
+
+  // ---- constant image into LDS (eight 16-byte loads in flight per thread)
+  {
+    const BLP_GLOBAL V16 *src = gptr(reinterpret_cast<const V16 *>(a.image));
+    V16 *dst = reinterpret_cast<V16 *>(cbase);
+    const int nv = cw / P;
+    for (int v0 = tid; v0 < nv; v0 += 8 * nt) {
+      V16 tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tmp[u] = src[min(v0 + u * nt, nv - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (v0 + u * nt < nv) dst[v0 + u * nt] = tmp[u];
     }
-    __syncthreads();
-  };
-  // block-wide loop over the n x n nodes of a level (slot from the node)
-  auto nodes = [&](const MgLevelG<T> &L, auto &&f) {
-    const int n = L.g.nx;
-    const SkewT<T, TR> sk = level_skew<T, TR>(n);
-#pragma unroll 4
-    for (int idx = tid; idx < n * n; idx += nt) {
-      const int i = idx % n + 1, j = idx / n + 1;
-      f(sk, i, j, sk.at(i, j));
-    }
-    __syncthreads();
-  };
-  for (int l = 0; l + 1 < nl; ++l) {
-    const MgLevelG<T> L = lview(a.L[l]), Cc = lview(a.L[l + 1]);
-    if (l == 0 && !zero_init) {
-      nodes(L, [&](const SkewT<T, TR> &sk, int i, int j, size_t q) { gs_rhs_node<T, TR>(L, sk, i, j, q); });
-      sweep(l, true);
-    } else {
-      sweep(l, false);
-    }
-    nodes(L, [&](const SkewT<T, TR> &sk, int i, int j, size_t q) { resid_node<T, TR>(L, sk, i, j, q); });
-    const SkewT<T, TR> skf = level_skew<T, TR>(L.g.nx);
-    nodes(Cc, [&](const SkewT<T, TR> &, int k, int m, size_t q) { restrict_node<T, TR>(L, Cc, skf, k, m, q); });
   }
-  if (tid == 0) coarsest_body<T, TR>(lview(a.L[nl - 1]), nl > 1 ? 1 : zero_init);
+  // ---- zero padding rows of every level's right-hand side and residual
+  for (int l = 0; l < nl; ++l) {
+    const LdsLevel<T> Vl = lev(l);
+    const int n = Vl.n;
+    for (int x = tid; x < 4 * n; x += nt) {
+      const int r2 = x / n, i = x - r2 * n;
+      T *arr = (r2 & 1) ? Vl.t : Vl.b;
+      arr[(r2 < 2 ? -n : n * n) + i] = T(0);
+    }
+  }
+  // ---- finest level's right-hand side (and iterate): skewed -> natural
+  {
+    const LdsLevel<T> V0 = lev(0);
+    const MgLevelG<T> G = lview(a.L[0]);
+    const int n = V0.n, nn = n * n;
+    const SkewT<T, TR> sk = level_skew<T, TR>(n);
+    for (int b0 = tid; b0 < nn; b0 += 8 * nt) {
+      T vb[8], vz[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = min(b0 + u * nt, nn - 1);
+        const size_t q = sk.at(idx % n + 1, idx / n + 1);
+        vb[u] = G.b[q];
+        vz[u] = zero_init ? T(0) : G.z[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (b0 + u * nt < nn) {
+          V0.b[b0 + u * nt] = vb[u];
+          V0.z[b0 + u * nt] = vz[u];
+        }
+    }
+  }
+  __syncthreads();
+
+  // block-wide loop over the nodes of level V: out[node] = f(i, j)
+  auto nodes = [&](const LdsLevel<T> &V, T *out, auto &&f) __attribute__((always_inline)) {
+    const int n = V.n, nn = n * n;
+    for (int idx = tid; idx < nn; idx += nt) {
+      const int i = idx % n + 1, j = idx / n + 1;
+      out[idx] = f(i, j);
+    }
+    __syncthreads();
+  };
+  auto sweep = [&](const LdsLevel<T> &V, const T *rhs) __attribute__((always_inline)) {
+    if (tid < 64) lds_sweep<T, TR>(V, rhs, lane);
+    __syncthreads();
+  };
+  // Gauss-Seidel right-hand side: the downstream couplings folded in
+  auto gs_rhs = [&](const LdsLevel<T> &V) __attribute__((always_inline)) {
+    const int n = V.n;
+    nodes(V, V.t, [&](int i, int j) {
+      const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
+      double v = V.b[V.at(i, j)];
+      if (id >= 1 && id <= n) v -= (double)(TR ? V.W[i + 1] : V.W[i]) * (double)V.z[V.at(id, j)];
+      if (jd >= 1 && jd <= n) v -= (double)(TR ? V.S[j + 1] : V.S[j]) * (double)V.z[V.at(i, jd)];
+      return T(v);
+    });
+  };
+
+  for (int l = 0; l + 1 < nl; ++l) {
+    const LdsLevel<T> F = lev(l), Cc = lev(l + 1);
+    if (l == 0 && !zero_init) {
+      gs_rhs(F);
+      sweep(F, F.t);
+    } else {
+      sweep(F, F.b);
+    }
+    nodes(F, F.t, [&](int i, int j) { return T((double)F.b[F.at(i, j)] - lds_apply<T, TR>(F, i, j)); });
+    // coarse right-hand side (as restrict_node)
+    const int nf = F.n;
+    nodes(Cc, Cc.b, [&](int k, int m) {
+      T s2 = T(0);
+      for (int jj = 2 * m - 1; jj <= 2 * m + 1; ++jj) {
+        if (jj < 1 || jj > nf) continue;
+        const T wy = lds_w1d(F.wly, F.wry, jj, m);
+        for (int ii = 2 * k - 1; ii <= 2 * k + 1; ++ii) {
+          if (ii < 1 || ii > nf) continue;
+          T v = F.t[F.at(ii, jj)] * lds_w1d(F.wlx, F.wrx, ii, k) * wy;
+          if (!TR) v *= F.hbx[ii] * F.hby[jj];
+          s2 += v;
+        }
+      }
+      if (!TR) s2 /= Cc.hbx[k] * Cc.hby[m];
+      return s2;
+    });
+  }
+  // coarsest level: four Gauss-Seidel sweeps by one thread (as coarsest_body)
+  if (tid == 0) {
+    const LdsLevel<T> V = lev(nl - 1);
+    const int n = V.n;
+    if (nl > 1 || zero_init)
+      for (int idx = 0; idx < n * n; ++idx) V.z[idx] = T(0);
+    for (int sw = 0; sw < 4; ++sw) {
+      for (int jj = 0; jj < n; ++jj)
+        for (int ii = 0; ii < n; ++ii) {
+          const int i = TR ? ii + 1 : n - ii, j = TR ? jj + 1 : n - jj;
+          const T *z = V.z;
+          const T zw = i > 1 ? z[V.at(i - 1, j)] : T(0);
+          const T ze = i < n ? z[V.at(i + 1, j)] : T(0);
+          const T zs = j > 1 ? z[V.at(i, j - 1)] : T(0);
+          const T zn = j < n ? z[V.at(i, j + 1)] : T(0);
+          T off;
+          if (!TR) off = V.W[i] * zw + V.E[i] * ze + V.S[j] * zs + V.N[j] * zn;
+          else off = V.E[i - 1] * zw + V.W[i + 1] * ze + V.N[j - 1] * zs + V.S[j + 1] * zn;
+          const int q = V.at(i, j);
+          V.z[q] = (V.b[q] - off) * V.ic[q];
+        }
+    }
+  }
   __syncthreads();
   for (int l = nl - 2; l >= 0; --l) {
-    const MgLevelG<T> L = lview(a.L[l]), Cc = lview(a.L[l + 1]);
-    const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx);
-    nodes(L, [&](const SkewT<T, TR> &, int i, int j, size_t q) { prolong_node<T, TR>(L, Cc, skc, i, j, q); });
-    nodes(L, [&](const SkewT<T, TR> &sk, int i, int j, size_t q) { gs_rhs_node<T, TR>(L, sk, i, j, q); });
-    sweep(l, true);
+    const LdsLevel<T> F = lev(l), Cc = lev(l + 1);
+    // coarse-grid correction (as prolong_node)
+    nodes(F, F.z, [&](int i, int j) {
+      // up to two coarse neighbours per axis: (k0, w0) and, if two, (k1, w1)
+      auto axis = [](int x, const T *wl, const T *wr, int &k0, T &w0, int &k1, T &w1) {
+        if (x % 2 == 0) { k0 = x / 2; w0 = T(1); return false; }
+        if ((x - 1) / 2 >= 1) {
+          k0 = (x - 1) / 2; w0 = wl[x];
+          k1 = (x + 1) / 2; w1 = wr[x];
+          return true;
+        }
+        k0 = (x + 1) / 2; w0 = wr[x];
+        return false;
+      };
+      int kx0, kx1 = 1, ky0, ky1 = 1;
+      T wx0, wx1 = T(0), wy0, wy1 = T(0);
+      const bool tx = axis(i, F.wlx, F.wrx, kx0, wx0, kx1, wx1);
+      const bool ty = axis(j, F.wly, F.wry, ky0, wy0, ky1, wy1);
+      T s2 = T(0);
+      auto term = [&](int kx, T wxv, int ky, T wyv) {
+        T v = Cc.z[Cc.at(kx, ky)];
+        if (TR) v /= Cc.hbx[kx] * Cc.hby[ky];
+        s2 += wxv * wyv * v;
+      };
+      term(kx0, wx0, ky0, wy0);
+      if (tx) term(kx1, wx1, ky0, wy0);
+      if (ty) {
+        term(kx0, wx0, ky1, wy1);
+        if (tx) term(kx1, wx1, ky1, wy1);
+      }
+      if (TR) s2 *= F.hbx[i] * F.hby[j];
+      return F.z[F.at(i, j)] + s2;
+    });
+    gs_rhs(F);
+    sweep(F, F.t);
   }
+
+  // ---- the finest fused level's iterate back to global memory (skewed)
+  {
+    const LdsLevel<T> V = lev(0);
+    const MgLevelG<T> G = lview(a.L[0]);
+    const int n = V.n;
+    const SkewT<T, TR> sk = level_skew<T, TR>(n);
+    for (int idx = tid; idx < n * n; idx += nt) {
+      const int i = idx % n + 1, j = idx / n + 1;
+      G.z[sk.at(i, j)] = V.z[idx];
+    }
+  }
+}
+
+// LDS bytes of the fused cycle from level n0 down (nl levels).
+template <typename T>
+inline size_t coarse_lds_bytes(int n0, int nl, bool nodal) {
+  size_t w = lds_image_words<T>(n0, nl, nodal);
+  for (int l = 0; l < nl; ++l) w += lds_work_words<T>(n0 >> l);
+  return w * sizeof(T);
 }
 
 // Corner stopping rule (Sec. 3.2): norm of the residual of the system the
