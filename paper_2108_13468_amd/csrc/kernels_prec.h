@@ -1091,10 +1091,12 @@ __host__ __device__ inline int lds_round(int w) {
   constexpr int P = 16 / (int)sizeof(T);
   return (w + P - 1) / P * P;
 }
-// constant words of one level: twelve tables, the inverse diagonal, nodal r
+// constant words of one level: twelve tables, the row couplings in sweep
+// order (2n + 8 entries), the inverse diagonal, nodal r
 template <typename T>
 __host__ __device__ inline int lds_const_words(int n, bool nodal) {
-  return 12 * lds_round<T>(n + 2) + lds_round<T>((n + 2) * n) + (nodal ? lds_round<T>(n * n) : 0);
+  return 12 * lds_round<T>(n + 2) + lds_round<T>(2 * n + 8) + lds_round<T>((n + 2) * n) +
+         (nodal ? lds_round<T>(n * n) : 0);
 }
 // work words of one level: iterate, right-hand side, residual
 template <typename T>
@@ -1114,6 +1116,7 @@ struct LdsLevel {
   T *z, *b, *t, *ic;  // node (1, 1); rows j = 0 and j = n + 1 are padding
   T *r;               // nodal r (no padding), or nullptr: constant rc
   T *W, *E, *S, *N, *Dx, *Dy, *hbx, *hby, *wlx, *wrx, *wly, *wry;
+  T *Y;               // Y[t]: upstream coupling of the sweep's row t (0 for t >= n)
   T rc;
   BLP_DEV int at(int i, int j) const { return (j - 1) * n + (i - 1); }
   BLP_DEV T rr(int i, int j) const { return r ? r[at(i, j)] : rc; }
@@ -1136,6 +1139,7 @@ BLP_DEV LdsLevel<T> lds_level(T *cbase, T *wbase, int n0, int l, bool nodal, T r
   T **tab[12] = {&v.W, &v.E, &v.S, &v.N, &v.Dx, &v.Dy, &v.hbx, &v.hby, &v.wlx, &v.wrx, &v.wly, &v.wry};
 #pragma unroll
   for (int k = 0; k < 12; ++k) { *tab[k] = p; p += a1; }
+  v.Y = p; p += lds_round<T>(2 * n + 8);
   v.ic = p + n; p += ap;
   v.r = nodal ? p : nullptr;
   T *q = wbase + wo;
@@ -1161,6 +1165,9 @@ __global__ void k_coarse_image(const CoarseArgs<T> *A) {
 #pragma unroll
     for (int k = 0; k < 12; ++k)
       for (int x = threadIdx.x; x < n + 2; x += blockDim.x) dst[k][x] = src[k][x];
+    // sweep row t at j = 1 + t (transposed, coupling N_{j-1}) or n - t (N_j)
+    for (int x = threadIdx.x; x < 2 * n + 8; x += blockDim.x)
+      V.Y[x] = x < n ? (TR ? G.g.N[x] : G.g.N[n - x]) : T(0);
     const SkewT<T, TR> sk = level_skew<T, TR>(n);
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
       const int i = idx % n + 1, j = idx / n + 1;
@@ -1190,11 +1197,13 @@ BLP_DEV double lds_apply(const LdsLevel<T> &L, int i, int j) {
 
 // Downstream sweep on an LDS level by one wave (lane = column, as the
 // skewed sweep): z = solution of the triangular system with right-hand side
-// rhs (the level's b or t).  Row t of a lane's column (t = 0 first) is clamped
-// to the padding rows -1 and n outside 0 .. n - 1, where rhs and the inverse
-// diagonal are zero: those steps compute z = 0, the upstream value of the
-// first row, and store it into the iterate's padding.  Lane 0 has no
-// upstream column.
+// rhs (the level's b or t).  Row t of a lane's column (t = 0 first) sits at
+// word o0 + t dq; outside rows 0 .. n - 1 the word is clamped to the padding
+// rows (t = -1 or n), where rhs and the inverse diagonal are zero: those
+// steps compute z = 0, the upstream value of the first row, and store it
+// into the iterate's padding.  The row coupling of lane l at step s (row
+// s - l) is the one lane l - 1 held at step s - 1, passed on by a DPP shift;
+// lane 0 takes row s's from the table.  Lane 0 has no upstream column.
 template <typename T, bool TR>
 BLP_DEV void lds_sweep(const LdsLevel<T> &L, const T *rhs, int lane) {
   constexpr int K = 8;
@@ -1203,32 +1212,83 @@ BLP_DEV void lds_sweep(const LdsLevel<T> &L, const T *rhs, int lane) {
   const int c = col ? lane : 0;
   const int i = TR ? 1 + c : n - c;
   const T cu = col ? (TR ? L.E[i - 1] : L.E[i]) : T(0);
-  // row t sits at j = 1 + t (transposed) or n - t: word o0 + t dq
+  // row t at j = 1 + t (transposed) or n - t
   const int o0 = TR ? i - 1 : (n - 1) * n + i - 1, dq = TR ? n : -n;
+  const int oa = o0 - dq, ob = o0 + n * dq;  // rows -1 and n
+  const int olo = min(oa, ob), ohi = max(oa, ob);
   const int lofs = col ? lane : 4 * n;  // lanes without a column stay in the padding
-  T z = T(0);
+  typedef typename Vec16<T>::type V16;
+  constexpr int P = 16 / (int)sizeof(T);
+  static_assert(K % P == 0, "whole 16-byte table reads");
+  T z = T(0), yc = T(0);
   for (int s0 = 0; s0 < 2 * n - 1; s0 += K) {
-    T bv[K], iv[K], yv[K];
+    const int os = o0 + (s0 - lofs) * dq;  // row of step s0 (unclamped)
+    T bv[K], iv[K], y0[K];
     int o[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int t = min(max(s0 + k - lofs, -1), n);
-      o[k] = o0 + t * dq;
+      o[k] = min(max(os + k * dq, olo), ohi);
       bv[k] = rhs[o[k]];
       iv[k] = L.ic[o[k]];
-      const int ty = min(max(t, 0), n - 1);
-      yv[k] = TR ? L.N[ty] : L.N[n - ty];  // N_{j-1} with j = 1 + t, or N_j with j = n - t
+    }
+    // lane 0's row couplings (rows s0 .. s0 + K - 1; wave-uniform address)
+    const V16 *yv = reinterpret_cast<const V16 *>(L.Y + s0);
+#pragma unroll
+    for (int q = 0; q < K / P; ++q) {
+      const V16 v = yv[q];
+#pragma unroll
+      for (int e = 0; e < P; ++e) y0[q * P + e] = v[e];
     }
     T res[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+      yc = dpp_mov<0x138>(y0[k], yc);         // lane l-1's previous coupling; lane 0: table
       const T zin = dpp_mov<0x138>(T(0), z);  // lane l-1's value; lane 0: none
-      z = (bv[k] - yv[k] * z - cu * zin) * iv[k];
+      z = (bv[k] - yc * z - cu * zin) * iv[k];
       res[k] = z;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) L.z[o[k]] = res[k];
   }
+}
+
+// Four Gauss-Seidel sweeps on an NC x NC coarsest level (as coarsest_body),
+// the iterate, right-hand side, inverse diagonal and couplings in registers.
+template <typename T, bool TR, int NC>
+BLP_DEV void lds_coarsest_regs(const LdsLevel<T> &V, bool zero) {
+  T z[NC * NC], b[NC * NC], ic[NC * NC], W[NC + 2], E[NC + 2], S[NC + 2], N[NC + 2];
+#pragma unroll
+  for (int q = 0; q < NC * NC; ++q) {
+    z[q] = zero ? T(0) : V.z[q];
+    b[q] = V.b[q];
+    ic[q] = V.ic[q];
+  }
+#pragma unroll
+  for (int k = 0; k < NC + 2; ++k) {
+    W[k] = V.W[k];
+    E[k] = V.E[k];
+    S[k] = V.S[k];
+    N[k] = V.N[k];
+  }
+#pragma unroll
+  for (int sw = 0; sw < 4; ++sw)
+#pragma unroll
+    for (int jj = 0; jj < NC; ++jj)
+#pragma unroll
+      for (int ii = 0; ii < NC; ++ii) {
+        const int i = TR ? ii + 1 : NC - ii, j = TR ? jj + 1 : NC - jj;
+        const int q = (j - 1) * NC + (i - 1);
+        const T zw = i > 1 ? z[q - 1] : T(0);
+        const T ze = i < NC ? z[q + 1] : T(0);
+        const T zs = j > 1 ? z[q - NC] : T(0);
+        const T zn = j < NC ? z[q + NC] : T(0);
+        T off;
+        if (!TR) off = W[i] * zw + E[i] * ze + S[j] * zs + N[j] * zn;
+        else off = E[i - 1] * zw + W[i + 1] * ze + N[j - 1] * zs + S[j + 1] * zn;
+        z[q] = (b[q] - off) * ic[q];
+      }
+#pragma unroll
+  for (int q = 0; q < NC * NC; ++q) V.z[q] = z[q];
 }
 
 template <typename T>
@@ -1245,7 +1305,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
   constexpr int P = 16 / (int)sizeof(T);
   T *cbase = reinterpret_cast<T *>(blp_lds);
   const CoarseArgs<T> &a = A[blockIdx.x];
-  if (a.ctrl->gate) return;
+  const int gate = a.ctrl->gate;  // tested after the loads below are issued
   const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
   const int n0 = a.L[0].g.nx;
   const bool nodal = a.L[0].g.r != nullptr;
@@ -1254,20 +1314,6 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
   T *wbase = cbase + cw;
   auto lev = [&](int l) { return lds_level<T>(cbase, wbase, n0, l, nodal, rc); };
 
-  // ---- constant image into LDS (eight 16-byte loads in flight per thread)
-  {
-    const BLP_GLOBAL V16 *src = gptr(reinterpret_cast<const V16 *>(a.image));
-    V16 *dst = reinterpret_cast<V16 *>(cbase);
-    const int nv = cw / P;
-    for (int v0 = tid; v0 < nv; v0 += 8 * nt) {
-      V16 tmp[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) tmp[u] = src[min(v0 + u * nt, nv - 1)];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (v0 + u * nt < nv) dst[v0 + u * nt] = tmp[u];
-    }
-  }
   // ---- zero padding rows of every level's right-hand side and residual
   for (int l = 0; l < nl; ++l) {
     const LdsLevel<T> Vl = lev(l);
@@ -1278,38 +1324,47 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
       arr[(r2 < 2 ? -n : n * n) + i] = T(0);
     }
   }
-  // ---- finest level's right-hand side (and iterate): skewed -> natural
+  // ---- constant image into LDS, and the finest level's right-hand side
+  // (and iterate) from the skewed work vectors: per round eight 16-byte
+  // image loads and eight node loads per thread are in flight together
   {
+    const BLP_GLOBAL V16 *src = gptr(reinterpret_cast<const V16 *>(a.image));
+    V16 *dst = reinterpret_cast<V16 *>(cbase);
+    const int nv = cw / P;
     const LdsLevel<T> V0 = lev(0);
     const MgLevelG<T> G = lview(a.L[0]);
     const int n = V0.n, nn = n * n;
     const SkewT<T, TR> sk = level_skew<T, TR>(n);
-    for (int b0 = tid; b0 < nn; b0 += 8 * nt) {
+    for (int r0 = tid; r0 < nv || r0 < nn; r0 += 8 * nt) {
+      V16 tmp[8];
       T vb[8], vz[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int idx = min(b0 + u * nt, nn - 1);
+        tmp[u] = src[min(r0 + u * nt, nv - 1)];
+        const int idx = min(r0 + u * nt, nn - 1);
         const size_t q = sk.at(idx % n + 1, idx / n + 1);
         vb[u] = G.b[q];
         vz[u] = zero_init ? T(0) : G.z[q];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (b0 + u * nt < nn) {
-          V0.b[b0 + u * nt] = vb[u];
-          V0.z[b0 + u * nt] = vz[u];
+      for (int u = 0; u < 8; ++u) {
+        if (r0 + u * nt < nv) dst[r0 + u * nt] = tmp[u];
+        if (r0 + u * nt < nn) {
+          V0.b[r0 + u * nt] = vb[u];
+          V0.z[r0 + u * nt] = vz[u];
         }
+      }
     }
   }
+  if (gate) return;  // the system's cycle is switched off (same in every thread)
   __syncthreads();
 
   // block-wide loop over the nodes of level V: out[node] = f(i, j)
+  // (lane = column i - 1, wave-strided rows: the levels have at most 64 columns)
   auto nodes = [&](const LdsLevel<T> &V, T *out, auto &&f) __attribute__((always_inline)) {
-    const int n = V.n, nn = n * n;
-    for (int idx = tid; idx < nn; idx += nt) {
-      const int i = idx % n + 1, j = idx / n + 1;
-      out[idx] = f(i, j);
-    }
+    const int n = V.n;
+    if (lane < n)
+      for (int j = (tid >> 6) + 1; j <= n; j += nt >> 6) out[(j - 1) * n + lane] = f(lane + 1, j);
     __syncthreads();
   };
   auto sweep = [&](const LdsLevel<T> &V, const T *rhs) __attribute__((always_inline)) {
@@ -1355,11 +1410,17 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
       return s2;
     });
   }
-  // coarsest level: four Gauss-Seidel sweeps by one thread (as coarsest_body)
+  // coarsest level: four Gauss-Seidel sweeps by one thread (as coarsest_body);
+  // in registers when it has at most 4 x 4 nodes
   if (tid == 0) {
     const LdsLevel<T> V = lev(nl - 1);
     const int n = V.n;
-    if (nl > 1 || zero_init)
+    const bool zc = nl > 1 || zero_init;
+    if (n == 2) lds_coarsest_regs<T, TR, 2>(V, zc);
+    else if (n == 3) lds_coarsest_regs<T, TR, 3>(V, zc);
+    else if (n == 4) lds_coarsest_regs<T, TR, 4>(V, zc);
+    else {
+    if (zc)
       for (int idx = 0; idx < n * n; ++idx) V.z[idx] = T(0);
     for (int sw = 0; sw < 4; ++sw) {
       for (int jj = 0; jj < n; ++jj)
@@ -1376,6 +1437,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
           const int q = V.at(i, j);
           V.z[q] = (V.b[q] - off) * V.ic[q];
         }
+    }
     }
   }
   __syncthreads();
