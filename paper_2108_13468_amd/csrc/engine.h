@@ -196,6 +196,19 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   std::vector<std::vector<MgArgs<T>>> mg(nl, std::vector<MgArgs<T>>(S));
   std::vector<std::vector<SweepArgs<T>>> swb(nl, std::vector<SweepArgs<T>>(S)), swt = swb;
   const int h = P.h, n1 = P.n1, hp = P.hp;
+  // channels and launch counters of the split sweeps (interior, then one per
+  // level: a level's two sweeps never run at the same time)
+  std::vector<unsigned long long *> chan(nl + 1, nullptr);
+  std::vector<int *> epoch(nl + 1, nullptr);
+  for (int k = 0; k <= nl; ++k) {
+    BLP_TRY(P.mem.get(&chan[k], (size_t)S * kChanStride<T>, st, true));
+    BLP_TRY(P.mem.get(&epoch[k], (size_t)S * 2, st, true));
+  }
+  auto split = [&](SweepArgs<T> a, int k, int s) {
+    a.chan = chan[k] + (size_t)s * kChanStride<T>;
+    a.epoch = epoch[k] + 2 * s;
+    return a;
+  };
   for (int s = 0; s < S; ++s) {
     System &y = *sys[s];
     blp_problem *p = y.p;
@@ -208,7 +221,7 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
     const T *dh = scaled ? f.dh : nullptr;
     ioI[s] = SkewIO<T, TR>{g, SkewT<T, TR>{h + 1, n1, h + 1, n1}, v, io[s].ldv, dh, z, io[s].ldz,
                            w.bI, w.zI, P.nslotI, y.gate};
-    swI[s] = SweepArgs<T>{g, h + 1, n1, h + 1, n1, w.bI, f.icI[TR ? 1 : 0], w.zI, y.gate};
+    swI[s] = split(SweepArgs<T>{g, h + 1, n1, h + 1, n1, w.bI, f.icI[TR ? 1 : 0], w.zI, y.gate}, nl, s);
     ioL[s] = LineIO<T>{g, h, n1, hp, v, io[s].ldv, dh, z, io[s].ldz, {w.bL[0], w.bL[1]},
                        {w.zL[0], w.zL[1]}, y.gate};
     LineArgs<T> la;
@@ -234,8 +247,8 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
           l + 1 < nl ? L[l + 1].view(TR, w.z[l + 1], w.b[l + 1], w.t[l + 1]) : MgLevel<T>{};
       mg[l][s] = MgArgs<T>{lv, cv, y.ctrl, y.mg_partials};
       const T *ic = L[l].ic[TR ? 1 : 0];
-      swb[l][s] = SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.b[l], ic, w.z[l], &y.ctrl->gate};
-      swt[l][s] = SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.t[l], ic, w.z[l], &y.ctrl->gate};
+      swb[l][s] = split(SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.b[l], ic, w.z[l], &y.ctrl->gate}, l, s);
+      swt[l][s] = split(SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.t[l], ic, w.z[l], &y.ctrl->gate}, l, s);
     }
   }
   // the coarse levels run as one fused cycle per system
@@ -288,23 +301,55 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
 // Sweep: superstep K = 4 or 2 chunks of 16 bytes per lane, D supersteps of
 // loads in flight (D + 1 register buffers of 2K words); more than 8 waves
 // leave registers for D = 1 only.
-inline int sweep_variants(int ncols) { return (ncols + 63) / 64 <= 8 ? 4 : 2; }
+// Sweep variants: G workgroups per system (G = 2 splits the bands over two
+// compute units, one wave per SIMD, joined by a channel in memory), K steps
+// per superstep, D supersteps of loads in flight.
+inline int sweep_variants(int ncols) {
+  const int nb = (ncols + 63) / 64;
+  return nb == 1 ? 4 : (nb <= 8 ? 6 : 4);
+}
+
+template <typename T, bool TR, int K, int D, int G>
+void sweep_launch_k(const Ctx &c, int S, int nb, const SweepArgs<T> *A) {
+  k_sweep<T, TR, K, D, G><<<dim3(S * G), dim3(64 * ((nb + G - 1) / G)), 0, c.stream>>>(A);
+}
 
 template <typename T, bool TR>
 void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A, int var = 0) {
   const int nb = (ncols + 63) / 64;
   constexpr int P = kChunk<T>;
-  const dim3 grid(S), block(64 * nb);
-  if (nb <= 8) {
+  if (nb == 1) {
     switch (var) {
-      case 1: k_sweep<T, TR, 4 * P, 2><<<grid, block, 0, c.stream>>>(A); break;
-      case 2: k_sweep<T, TR, 2 * P, 4><<<grid, block, 0, c.stream>>>(A); break;
-      case 3: k_sweep<T, TR, 2 * P, 2><<<grid, block, 0, c.stream>>>(A); break;
-      default: k_sweep<T, TR, 4 * P, 4><<<grid, block, 0, c.stream>>>(A); break;
+      case 1: sweep_launch_k<T, TR, 4 * P, 2, 1>(c, S, nb, A); break;
+      case 2: sweep_launch_k<T, TR, 2 * P, 4, 1>(c, S, nb, A); break;
+      case 3: sweep_launch_k<T, TR, 2 * P, 2, 1>(c, S, nb, A); break;
+      default: sweep_launch_k<T, TR, 4 * P, 4, 1>(c, S, nb, A); break;
+    }
+  } else if (nb <= 4) {
+    switch (var) {
+      case 1: sweep_launch_k<T, TR, 4 * P, 2, 1>(c, S, nb, A); break;
+      case 2: sweep_launch_k<T, TR, 2 * P, 4, 1>(c, S, nb, A); break;
+      case 3: sweep_launch_k<T, TR, 2 * P, 2, 1>(c, S, nb, A); break;
+      case 4: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
+      case 5: sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A); break;
+      default: sweep_launch_k<T, TR, 4 * P, 4, 1>(c, S, nb, A); break;
+    }
+  } else if (nb <= 8) {
+    switch (var) {
+      case 1: sweep_launch_k<T, TR, 4 * P, 4, 1>(c, S, nb, A); break;
+      case 2: sweep_launch_k<T, TR, 4 * P, 2, 1>(c, S, nb, A); break;
+      case 3: sweep_launch_k<T, TR, 2 * P, 4, 1>(c, S, nb, A); break;
+      case 4: sweep_launch_k<T, TR, 2 * P, 2, 1>(c, S, nb, A); break;
+      case 5: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
+      default: sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A); break;
     }
   } else {
-    if (var == 1) k_sweep<T, TR, 2 * P, 1><<<grid, block, 0, c.stream>>>(A);
-    else k_sweep<T, TR, 4 * P, 1><<<grid, block, 0, c.stream>>>(A);
+    switch (var) {
+      case 1: sweep_launch_k<T, TR, 4 * P, 1, 1>(c, S, nb, A); break;
+      case 2: sweep_launch_k<T, TR, 2 * P, 1, 1>(c, S, nb, A); break;
+      case 3: sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A); break;
+      default: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
+    }
   }
 }
 

@@ -197,10 +197,22 @@ struct SweepArgs {
   const T *ic;    // skewed 1/C (zero in padding)
   T *z;           // skewed result
   const int *gate;
+  // split sweeps (several workgroups per system): per group boundary, the
+  // channel of the writer band's last-column values (kChanStride words) and
+  // the writer's and reader's launch counters (2 ints); zero-initialised
+  unsigned long long *chan;
+  int *epoch;
 };
 
 constexpr int kSweepMaxRows = 1024;  // also bounds the rows of the coupling table
 constexpr int kSweepMaxBands = 16;
+// channel words per group boundary: one tagged 32-bit piece per word, for
+// every writer step of a band (at most kSweepMaxRows + 63 + 2 x 16)
+constexpr int kChanSteps = kSweepMaxRows + 128;
+template <typename T>
+constexpr int kChanStride = kChanSteps * (int)(sizeof(T) / 4);
+// bounded wait for a channel word (each round is one memory round trip)
+constexpr int kChanSpin = 1 << 13;
 
 // Words per copy of the row-coupling table for rows rows (entries -64 ..
 // rows + 63 + K of the row index, rounded up to whole chunks).
@@ -227,23 +239,82 @@ struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); 
 template <>
 struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
 
-// The sweep of one workgroup (wave w = band w of nb), or, SOLO, of a single
-// wave on a rectangle of at most 64 columns inside a larger kernel (no
-// barriers and no ring: with one band there is no upstream band).  ring holds
-// (nb + 1) x 64 words and ycs kChunk<T> x yc_stride<T, K>(rows) words of LDS,
-// both 16-byte aligned and provided by the caller.
-template <typename T, bool TR, int K, int D, bool SOLO>
-BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nthreads) {
-  constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64;
+// Channel words: a 32-bit piece of a value with the writer's launch count
+// in the high half, stored and loaded as one 64-bit word (relaxed,
+// device scope), so that a word read either carries this launch's count and
+// its piece, or an older count.
+template <typename T>
+BLP_DEV void chan_put(unsigned long long *w, T v, unsigned int tag) {
+  if constexpr (sizeof(T) == 4) {
+    const unsigned long long x = ((unsigned long long)tag << 32) | __float_as_uint(v);
+    __hip_atomic_store(gptr(w), x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    __hip_atomic_store(gptr(w), ((unsigned long long)tag << 32) | (u & 0xffffffffull),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gptr(w + 1), ((unsigned long long)tag << 32) | (u >> 32),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+template <typename T>
+struct ChanWord {
+  unsigned long long w[sizeof(T) / 4];
+};
+template <typename T>
+BLP_DEV ChanWord<T> chan_get(const unsigned long long *w) {
+  ChanWord<T> c;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k)
+    c.w[k] = __hip_atomic_load(gptr(w + k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return c;
+}
+template <typename T>
+BLP_DEV bool chan_ok(const ChanWord<T> &c, unsigned int tag) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) ok = ok && (unsigned int)(c.w[k] >> 32) == tag;
+  return ok;
+}
+template <typename T>
+BLP_DEV T chan_value(const ChanWord<T> &c) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float((unsigned int)c.w[0]);
+  } else {
+    return __longlong_as_double((long long)((c.w[0] & 0xffffffffull) | (c.w[1] << 32)));
+  }
+}
+
+// The sweep of one workgroup: wave w is band band0 + w of the rectangle's
+// nbt bands (G = 1: all of them).  ring holds (waves + 1) x 64 words and ycs
+// kChunk<T> x yc_stride<T, K>(rows) words of LDS, both 16-byte aligned.
+//
+// Split sweeps (G > 1 workgroups per system, group gi taking bands gi x
+// waves ..): the first band of group gi > 0 gets its upstream column from
+// the last band of group gi - 1 through the channel instead of the LDS ring.
+// The writer stores the K values of a superstep (one per lane); the reader
+// requests them with its operand loads, D supersteps ahead, checks their
+// launch count when it needs them (waiting, a bounded number of rounds, for
+// any not yet written) and puts them into its ring row.  Only steps whose
+// row exists need a value; after kChanSpin unanswered rounds the value is
+// NaN, which the solver reports.  Groups run in block order (group 0 has the
+// lowest block numbers), so a reader's writer has always started.
+template <typename T, bool TR, int K, int D, int G>
+BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nthreads, int gi) {
+  constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64, NW = sizeof(T) / 4;
   static_assert(K % P == 0 && 64 % K == 0 && 2 * K + P <= 64 && CK <= kSkewGroup, "superstep length");
   static_assert(LAG % K == 0 && LAG / K >= D, "lag in whole supersteps, at least D");
   typedef typename Vec16<T>::type V;
   const Grid<T> &g = a.g;
   const SkewT<T, TR> sk{a.i0, a.i1, a.j0, a.j1};
   const int mc = sk.mc(), mr = sk.mr(), nck = sk.nck();
-  const int nb = SOLO ? 1 : __builtin_amdgcn_readfirstlane(nthreads >> 6);
+  const int nbt = (mc + 63) >> 6;                                  // bands of the rectangle
+  const int nw = __builtin_amdgcn_readfirstlane(nthreads >> 6);    // waves (bands) per group
+  const int band0 = gi * nw;
+  const int nbg = min(nw, nbt - band0);                            // bands of this group
   const int lane = tid & 63;
-  const int band = SOLO ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);         // wave-uniform
+  const int band = band0 + wv;
+  const bool has = wv < nbg;
   const int c = band * 64 + lane;
   const bool colok = c < mc;
   const int i = sk.icol(colok ? c : mc - 1);
@@ -277,29 +348,26 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
       }
     }
   }
-  if (!SOLO)
-    for (int q = tid; q < (nb + 1) * RING; q += nthreads) ring[q] = T(0);
-  if (SOLO) {
-    // one wave: its LDS accesses are processed in order
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_wave_barrier();
-  } else {
-    __syncthreads();
-  }
+  for (int q = tid; q < (nw + 1) * RING; q += nthreads) ring[q] = T(0);
+  __syncthreads();
 
-  // the last band holds mcl columns, so its last node is at local step
-  // mr + mcl - 2; earlier bands finish earlier
-  const int mcl = mc - (nb - 1) * 64;
-  const int nsup = __builtin_amdgcn_readfirstlane(((nb - 1) * LAG + mr + mcl - 1 + K - 1) / K);
+  // the rectangle's last band holds mcl columns, so its last node is at
+  // local step mr + mcl - 2; other bands end at mr + 62
+  const int mcl = mc - (nbt - 1) * 64;
+  auto last_step = [&](int bd) { return mr - 2 + (bd == nbt - 1 ? mcl : 64); };
+  const int nsup =
+      __builtin_amdgcn_readfirstlane(((nbg - 1) * LAG + last_step(band0 + nbg - 1) + 1 + K - 1) / K);
   // this band's storage: chunk ck of this lane is element ck * 64
-  const BLP_GLOBAL V *__restrict__ bb = gptr(reinterpret_cast<const V *>(a.b + sk.slot(band, 0, 0)) + lane);
-  const BLP_GLOBAL V *__restrict__ bi = gptr(reinterpret_cast<const V *>(a.ic + sk.slot(band, 0, 0)) + lane);
-  BLP_GLOBAL V *__restrict__ zz = gptr(reinterpret_cast<V *>(a.z + sk.slot(band, 0, 0)) + lane);
-  const V *ring_in = SOLO ? nullptr : reinterpret_cast<const V *>(ring + band * RING);
-  V *ring_out = SOLO ? nullptr : reinterpret_cast<V *>(ring + (band + 1) * RING);
-  // last local step of this band that holds a node (its last column's last
-  // row), and the last superstep start at or below it
-  const int lastl = __builtin_amdgcn_readfirstlane(mr - 2 + (band == nb - 1 ? mcl : 64));
+  const int bs = has ? band : band0;
+  const BLP_GLOBAL V *__restrict__ bb = gptr(reinterpret_cast<const V *>(a.b + sk.slot(bs, 0, 0)) + lane);
+  const BLP_GLOBAL V *__restrict__ bi = gptr(reinterpret_cast<const V *>(a.ic + sk.slot(bs, 0, 0)) + lane);
+  BLP_GLOBAL V *__restrict__ zz = gptr(reinterpret_cast<V *>(a.z + sk.slot(bs, 0, 0)) + lane);
+  T *ring_in_w = ring + wv * RING;
+  const V *ring_in = reinterpret_cast<const V *>(ring_in_w);
+  V *ring_out = reinterpret_cast<V *>(ring + (wv + 1) * RING);
+  // last local step of this band that holds a node, and the last superstep
+  // start at or below it
+  const int lastl = __builtin_amdgcn_readfirstlane(last_step(band));
   const int shi = __builtin_amdgcn_readfirstlane(lastl / K * K);
   // the coupling of this lane at local step s is that of row s - lane, word
   // s + 64 - lane of copy 0, i.e. word s + 64 - lane - q of copy q with
@@ -308,8 +376,25 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
   const V *yc_base = reinterpret_cast<const V *>(ycs + yq * ys + 64 - lane - yq);
   // group of K / P chunks that holds no node (loads past the band's end)
   const int sink = __builtin_amdgcn_readfirstlane(nck / CK - 1);
+  // channel roles (split sweeps): the first wave of groups gi > 0 reads the
+  // boundary gi - 1, the last band of groups gi < G - 1 writes boundary gi
+  const bool reader = G > 1 && gi > 0 && wv == 0;
+  const bool writer = G > 1 && gi < G - 1 && wv == nbg - 1 && band0 + nbg < nbt;
+  unsigned long long *chw = nullptr, *chr = nullptr;
+  unsigned int tagw = 0, tagr = 0;
+  if (G > 1) {
+    const BLP_GLOBAL int *ep = gptr(a.epoch);
+    if (writer) {
+      chw = a.chan + (size_t)gi * kChanStride<T>;
+      tagw = (unsigned int)ep[2 * gi] + 1u;
+    }
+    if (reader) {
+      chr = a.chan + (size_t)(gi - 1) * kChanStride<T>;
+      tagr = (unsigned int)ep[2 * (gi - 1) + 1] + 1u;
+    }
+  }
 
-  auto load = [&](int u, T (&Bb)[K], T (&Bi)[K]) {  // superstep u's operands
+  auto load = [&](int u, T (&Bb)[K], T (&Bi)[K], ChanWord<T> &Bc) {  // superstep u's operands
     const int ck = (u < sink ? u : sink) * CK;
     const BLP_GLOBAL V *pb = bb + ck * 64, *pi = bi + ck * 64;
 #pragma unroll
@@ -320,6 +405,11 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
         Bb[q * P + e] = vb[e];
         Bi[q * P + e] = vi[e];
       }
+    }
+    // writer steps u K + 63 + lane (lanes < K) for the reader's ring
+    if (G > 1 && reader) {
+      const int st = min(u * K + 63 + (lane < K ? lane : 0), kChanSteps - 1);
+      Bc = chan_get<T>(chr + (size_t)st * NW);
     }
   };
   auto store = [&](int u, const T (&R)[K]) {  // superstep u's results (u < 0: sink)
@@ -334,21 +424,35 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
   };
 
   T buf_b[D + 1][K], buf_i[D + 1][K], res[K];
+  ChanWord<T> buf_c[D + 1];
 #pragma unroll
   for (int k = 0; k < K; ++k) res[k] = T(0);
   T z = T(0);  // this lane's latest result (the next row's upstream value)
-  auto barrier = [&]() {
-    if (SOLO) {
-      asm volatile("" ::: "memory");
-    } else {
-      lds_barrier();
-    }
-  };
   // superstep ml of this band: local steps ml K .. ml K + K - 1
-  auto superstep = [&](int ml, T (&Cb)[K], T (&Ci)[K], T (&Nb)[K], T (&Ni)[K]) {
+  auto superstep = [&](int ml, T (&Cb)[K], T (&Ci)[K], ChanWord<T> &Cc, T (&Nb)[K], T (&Ni)[K],
+                       ChanWord<T> &Nc) {
     const int sl = ml * K;
     store(ml - 1, res);
-    load(ml + D, Nb, Ni);
+    load(ml + D, Nb, Ni, Nc);
+    if (G > 1 && reader) {
+      // the writer's steps sl + 63 .. sl + 63 + K - 1 into ring slots
+      // (sl - 1 ..) mod 64; a step whose row does not exist (sl + lane >= mr)
+      // needs no value
+      if (lane < K) {
+        T v = T(0);
+        if (sl + lane < mr) {
+          ChanWord<T> cw = Cc;
+          int spin = 0;
+          while (!chan_ok<T>(cw, tagr) && spin < kChanSpin) {
+            __builtin_amdgcn_s_sleep(1);
+            cw = chan_get<T>(chr + (size_t)(sl + 63 + lane) * NW);
+            ++spin;
+          }
+          v = chan_ok<T>(cw, tagr) ? chan_value<T>(cw) : __builtin_nan("");
+        }
+        ring_in_w[(sl + 63 + lane) & (RING - 1)] = v;
+      }
+    }
     // LDS operands of the superstep, read up front so that no LDS latency
     // sits on the step-to-step dependency chain.  The writer band stores
     // its local step s (lane 63) in ring slot s mod 64; lane 0 of this band,
@@ -363,10 +467,7 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
 #pragma unroll
       for (int e = 0; e < P; ++e) yc[q * P + e] = v[e];
     }
-    if (SOLO) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) zb0[k] = T(0);
-    } else {
+    {
       const int r0 = (sl & (RING - 1)) / P;
       const V pv = ring_in[(r0 + RING / P - 1) & (RING / P - 1)];
       zb0[0] = pv[P - 1];
@@ -387,7 +488,7 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
     // the slots written here (steps sl .. sl + K - 1) and the slots the
     // next band reads in the same superstep (steps sl - K - P .. sl - 1 of
     // this band, mod 64) are disjoint: 2K + P <= 64
-    if (!SOLO && lane == 63) {
+    if (lane == 63) {
       const int r0 = (sl & (RING - 1)) / P;
 #pragma unroll
       for (int q = 0; q < CK; ++q) {
@@ -397,24 +498,33 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
         ring_out[r0 + q] = v;
       }
     }
-    barrier();
+    if (G > 1 && writer && lane < K) {
+      // this wave's own ring writes above are complete before its reads
+      const T v = reinterpret_cast<const T *>(ring_out)[(sl + lane) & (RING - 1)];
+      chan_put<T>(chw + (size_t)(sl + lane) * NW, v, tagw);
+    }
+    lds_barrier();
   };
-  // Band w runs LAG / K supersteps behind band w - 1 and works only on its
-  // own supersteps [m0, m0 + nact) of the workgroup's nsup: before and after
-  // those it only takes part in the barriers (no memory traffic).  Its
-  // first D supersteps of operands are requested D barriers before it starts,
-  // and the step loop follows those loads directly, so that the compiler's
-  // wait counts keep the D supersteps of loads in flight.
-  const int m0 = band * (LAG / K);
-  const int nact = __builtin_amdgcn_readfirstlane((lastl + K) / K);
+  // Band w runs LAG / K supersteps behind band w - 1 of its group and works
+  // only on its own supersteps [m0, m0 + nact) of the group's nsup: before
+  // and after those it only takes part in the barriers (no memory traffic).
+  // Its first D supersteps of operands are requested D barriers before it
+  // starts, and the step loop follows those loads directly, so that the
+  // compiler's wait counts keep the D supersteps of loads in flight.
+  const int m0 = wv * (LAG / K);
+  const int nact = has ? __builtin_amdgcn_readfirstlane((lastl + K) / K) : 0;
+  if (!has) {
+    for (int m = 0; m < nsup; ++m) lds_barrier();
+    return;
+  }
   if (m0 > 0) {
-    for (int m = 0; m < m0 - D; ++m) barrier();
+    for (int m = 0; m < m0 - D; ++m) lds_barrier();
   }
 #pragma unroll
-  for (int u = 0; u < D; ++u) load(u, buf_b[u], buf_i[u]);
+  for (int u = 0; u < D; ++u) load(u, buf_b[u], buf_i[u], buf_c[u]);
   if (m0 > 0) {
 #pragma unroll
-    for (int u = 0; u < D; ++u) barrier();
+    for (int u = 0; u < D; ++u) lds_barrier();
   }
   // whole groups of D + 1 supersteps (buffer roles fixed by unrolling), then
   // the remaining supersteps outside the loop, so that no partially executed
@@ -423,24 +533,33 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
   for (; ml + D < nact; ml += D + 1) {
 #pragma unroll
     for (int u = 0; u <= D; ++u)
-      superstep(ml + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
+      superstep(ml + u, buf_b[u], buf_i[u], buf_c[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)],
+                buf_c[(u + D) % (D + 1)]);
   }
 #pragma unroll
   for (int u = 0; u < D; ++u) {
     if (ml + u < nact)
-      superstep(ml + u, buf_b[u], buf_i[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)]);
+      superstep(ml + u, buf_b[u], buf_i[u], buf_c[u], buf_b[(u + D) % (D + 1)], buf_i[(u + D) % (D + 1)],
+                buf_c[(u + D) % (D + 1)]);
   }
   store(nact - 1, res);
-  for (int m = m0 + nact; m < nsup; ++m) barrier();
+  if (G > 1 && lane == 0) {
+    if (writer) gptr(a.epoch)[2 * gi] = (int)tagw;
+    if (reader) gptr(a.epoch)[2 * (gi - 1) + 1] = (int)tagr;
+  }
+  for (int m = m0 + nact; m < nsup; ++m) lds_barrier();
 }
 
-template <typename T, bool TR, int K, int D>
+// G workgroups per system (blocks g x S + s: every group-0 block precedes
+// every group-1 block); the rectangle's bands are split evenly.
+template <typename T, bool TR, int K, int D, int G>
 __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T> *A) {
-  const SweepArgs<T> a = A[blockIdx.x];  // one workgroup per system
+  const int S = gridDim.x / G, gi = blockIdx.x / S;
+  const SweepArgs<T> a = A[blockIdx.x - gi * S];
   if (gated(a.gate)) return;
   __shared__ __align__(16) T ring[(kSweepMaxBands + 1) * 64];
   __shared__ __align__(16) T ycs[kChunk<T> * yc_stride<T, K>(kSweepMaxRows)];
-  sweep_body<T, TR, K, D, false>(a, ring, ycs, threadIdx.x, blockDim.x);
+  sweep_body<T, TR, K, D, G>(a, ring, ycs, threadIdx.x, blockDim.x, gi);
 }
 
 // Natural <-> skewed copies of a rectangle of the fine grid (batched over
