@@ -27,9 +27,46 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solve time to rel-res 1e-8, 1024^2 eps=1e-6 (FP64 vs mixed) + HBM GB/s %peak"
 HBM_PEAK_GBS = 8000.0
-# kernel template behind each timing class in the mixed solve at this size
-KERNEL_NAMES = {"sweep": "k_sweep<float, false, 16, 4>", "gs_rhs": "k_gs_rhs<float, false>",
-                "lines": "k_lines<float, false, 2, 4, 6>", "spmv": "k_stencil<float, ...>"}
+# kernels behind each timing class in the mixed solve at this size
+KERNEL_NAMES = {"sweep": "k_sweep<float, false, 16, *, *> (all sweeps: interior and corner "
+                         "levels 512/256/128)",
+                "gs_rhs": "k_gs_rhs / k_mg_prolong_gs<float, false>",
+                "lines": "k_lines<float, false, 8, 1, 4>", "spmv": "k_stencil<float, ...>"}
+# measured HBM traffic of the sweep launches (two rocprofv3 --pmc runs,
+# FETCH_SIZE then WRITE_SIZE, scaled by a plain copy of known size), valid
+# while the sweep source is the one it was measured on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_traffic.txt")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2108_13468_amd", "csrc", "kernels_prec.h")
+
+
+def measured_traffic():
+    """Bytes per sweep launch from the committed counter summary, or None when
+    it is missing or was taken on a different kernel source."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_probe(args):
+    """A plain device copy of known size (counter calibration for the
+    traffic figure): 256 MiB read, 256 MiB written, three times."""
+    import torch
+    x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": x.numel() * 4, "copy_probe_bytes_written": y.numel() * 4}))
 
 
 def headline(args):
@@ -108,7 +145,8 @@ def headline(args):
     avg_us = 1e3 * ms / max(nl, 1)
     achieved = (by / max(nl, 1)) / (avg_us * 1e-6) / 1e9 if nl else 0.0
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic() if dom == "sweep" else None,
                 "kernel": KERNEL_NAMES.get(dom, dom) + " (mixed solve)",
                 "avg_launch_us": round(avg_us, 3), "launches": nl,
                 "bytes_per_launch": round(by / max(nl, 1), 1)}
@@ -339,7 +377,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("headline", "batch", "multi_rhs"), default="headline")
+    ap.add_argument("--workload", choices=("headline", "batch", "multi_rhs", "copy_probe"),
+                    default="headline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -349,7 +388,8 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    {"headline": headline, "batch": batch, "multi_rhs": multi_rhs}[args.workload](args)
+    {"headline": headline, "batch": batch, "multi_rhs": multi_rhs,
+     "copy_probe": copy_probe}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -403,7 +403,7 @@ void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
     k_gather_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
   }
   {
-    KScope ks(c, KC_SWEEP, (double)S * m * m * 2 * sizeof(T));
+    KScope ks(c, KC_SWEEP, (double)S * m * m * 3 * sizeof(T));
     sweep_launch<T, TR>(c, S, m, P.swI, P.varI);
   }
   KScope ks(c, KC_LAYOUT, 0.0);
@@ -448,14 +448,14 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   const dim3 gl(blocks1d(P.lslot[l]), S), gc(blocks1d(P.lslot[l + 1]), S);
   const double cc = (double)S * P.ln[l + 1] * P.ln[l + 1];
   if (zero_init) {
-    KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
+    KScope ks(c, KC_SWEEP, nn * 3 * sizeof(T));
     sweep_launch<T, TR>(c, S, n, P.swb[l], P.varL[l]);
   } else {
     {
       KScope ks(c, KC_GSRHS, nn * 3 * sizeof(T));
       k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
     }
-    KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
+    KScope ks(c, KC_SWEEP, nn * 3 * sizeof(T));
     sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
   }
   {
@@ -468,14 +468,12 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   }
   vcycle_run<T, TR>(c, P, l + 1, true);
   {
-    KScope ks(c, KC_MG, (2 * nn + cc) * sizeof(T));
-    k_mg_prolong<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
+    // coarse-grid correction folded into the post-smoothing right-hand side
+    // (the corrected iterate is not stored: the sweep rewrites z from t)
+    KScope ks(c, KC_GSRHS, (3 * nn + cc) * sizeof(T));
+    k_mg_prolong_gs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
   }
-  {
-    KScope ks(c, KC_GSRHS, nn * 3 * sizeof(T));
-    k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
-  }
-  KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
+  KScope ks(c, KC_SWEEP, nn * 3 * sizeof(T));
   sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
 }
 

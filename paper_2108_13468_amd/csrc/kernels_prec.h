@@ -1097,37 +1097,44 @@ __global__ void k_mg_restrict(const MgArgs<T> *A) {
 // Coarse-grid correction: forward z_f += P z_c; transposed
 // z_f += S_f P S_c^{-1} z_c.
 template <typename T, bool TR>
-BLP_DEV void prolong_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skc,
-                          int i, int j, size_t q) {
-  int kx[2], ky[2];
-  T wx[2], wy[2];
-  int nxk = 0, nyk = 0;
-  if (i % 2 == 0) { kx[0] = i / 2; wx[0] = T(1); nxk = 1; }
-  else {
-    if ((i - 1) / 2 >= 1) { kx[nxk] = (i - 1) / 2; wx[nxk++] = F.wlx[i]; }
-    kx[nxk] = (i + 1) / 2; wx[nxk++] = F.wrx[i];
-  }
-  if (j % 2 == 0) { ky[0] = j / 2; wy[0] = T(1); nyk = 1; }
-  else {
-    if ((j - 1) / 2 >= 1) { ky[nyk] = (j - 1) / 2; wy[nyk++] = F.wly[j]; }
-    ky[nyk] = (j + 1) / 2; wy[nyk++] = F.wry[j];
-  }
-  T s = T(0);
-  for (int b2 = 0; b2 < nyk; ++b2)
-    for (int a2 = 0; a2 < nxk; ++a2) {
-      T v = Cc.z[skc.at(kx[a2], ky[b2])];
-      if (TR) v /= Cc.hbx[kx[a2]] * Cc.hby[ky[b2]];
-      s += wx[a2] * wy[b2] * v;
+BLP_DEV T prolong_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skc,
+                       int i, int j, size_t q) {
+  // up to two coarse neighbours per axis: (k0, w0) and, if two, (k1, w1)
+  auto axis = [](int x, const BLP_GLOBAL T *wl, const BLP_GLOBAL T *wr, int &k0, T &w0, int &k1, T &w1) {
+    if (x % 2 == 0) { k0 = x / 2; w0 = T(1); return false; }
+    if ((x - 1) / 2 >= 1) {
+      k0 = (x - 1) / 2; w0 = wl[x];
+      k1 = (x + 1) / 2; w1 = wr[x];
+      return true;
     }
+    k0 = (x + 1) / 2; w0 = wr[x];
+    return false;
+  };
+  int kx0, kx1 = 1, ky0, ky1 = 1;
+  T wx0, wx1 = T(0), wy0, wy1 = T(0);
+  const bool tx = axis(i, F.wlx, F.wrx, kx0, wx0, kx1, wx1);
+  const bool ty = axis(j, F.wly, F.wry, ky0, wy0, ky1, wy1);
+  T s = T(0);
+  auto term = [&](int kx, T wxv, int ky, T wyv) {
+    T v = Cc.z[skc.at(kx, ky)];
+    if (TR) v /= Cc.hbx[kx] * Cc.hby[ky];
+    s += wxv * wyv * v;
+  };
+  term(kx0, wx0, ky0, wy0);
+  if (tx) term(kx1, wx1, ky0, wy0);
+  if (ty) {
+    term(kx0, wx0, ky1, wy1);
+    if (tx) term(kx1, wx1, ky1, wy1);
+  }
   if (TR) s *= F.hbx[i] * F.hby[j];
-  F.z[q] += s;
+  return F.z[q] + s;
 }
 template <typename T, bool TR>
 BLP_DEV void prolong_slot(const MgLevelG<T> &F, const MgLevelG<T> &Cc, size_t q) {
   const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
   int i, j;
   if (!skf.decode(q, i, j)) return;
-  prolong_node<T, TR>(F, Cc, skc, i, j, q);
+  F.z[q] = prolong_node<T, TR>(F, Cc, skc, i, j, q);
 }
 template <typename T, bool TR>
 __global__ void k_mg_prolong(const MgArgs<T> *A) {
@@ -1135,6 +1142,37 @@ __global__ void k_mg_prolong(const MgArgs<T> *A) {
   if (a.ctrl->gate) return;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < a.L.nslot) prolong_slot<T, TR>(lview(a.L), lview(a.Cc), q);
+}
+
+// Coarse-grid correction and Gauss-Seidel right-hand side in one pass: the
+// right-hand side of gs_rhs_node for the corrected iterate z + P z_c (as
+// prolong_node, rounded to the storage type), which enters only through the
+// two downstream neighbours.  The corrected iterate is not stored: the
+// post-smoothing sweep that follows recomputes every node of z from this
+// right-hand side alone.
+template <typename T, bool TR>
+BLP_DEV T prolong_gs_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skf,
+                          const SkewT<T, TR> &skc, int i, int j, size_t q) {
+  const GridG<T> &g = F.g;
+  const int n = g.nx;
+  const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
+  double v = F.b[q];
+  if (id >= 1 && id <= n)
+    v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)prolong_node<T, TR>(F, Cc, skc, id, j, skf.at(id, j));
+  if (jd >= 1 && jd <= g.ny)
+    v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)prolong_node<T, TR>(F, Cc, skc, i, jd, skf.at(i, jd));
+  return T(v);
+}
+template <typename T, bool TR>
+__global__ void k_mg_prolong_gs(const MgArgs<T> *A) {
+  const MgArgs<T> a = A[blockIdx.y];
+  if (a.ctrl->gate) return;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.L.nslot) return;
+  const MgLevelG<T> F = lview(a.L), Cc = lview(a.Cc);
+  const SkewT<T, TR> skf = level_skew<T, TR>(F.g.nx), skc = level_skew<T, TR>(Cc.g.nx);
+  int i, j;
+  F.t[q] = skf.decode(q, i, j) ? prolong_gs_node<T, TR>(F, Cc, skf, skc, i, j, q) : T(0);
 }
 
 // Coarsest level: four downstream Gauss-Seidel sweeps (transposed: the
