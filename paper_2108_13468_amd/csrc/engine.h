@@ -201,12 +201,12 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   std::vector<unsigned long long *> chan(nl + 1, nullptr);
   std::vector<int *> epoch(nl + 1, nullptr);
   for (int k = 0; k <= nl; ++k) {
-    BLP_TRY(P.mem.get(&chan[k], (size_t)S * kChanStride<T>, st, true));
-    BLP_TRY(P.mem.get(&epoch[k], (size_t)S * 2, st, true));
+    BLP_TRY(P.mem.get(&chan[k], (size_t)S * (kSweepMaxGroups - 1) * kChanStride<T>, st, true));
+    BLP_TRY(P.mem.get(&epoch[k], (size_t)S * 2 * (kSweepMaxGroups - 1), st, true));
   }
   auto split = [&](SweepArgs<T> a, int k, int s) {
-    a.chan = chan[k] + (size_t)s * kChanStride<T>;
-    a.epoch = epoch[k] + 2 * s;
+    a.chan = chan[k] + (size_t)s * (kSweepMaxGroups - 1) * kChanStride<T>;
+    a.epoch = epoch[k] + 2 * (kSweepMaxGroups - 1) * s;
     return a;
   };
   for (int s = 0; s < S; ++s) {
@@ -301,12 +301,14 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
 // Sweep: superstep K = 4 or 2 chunks of 16 bytes per lane, D supersteps of
 // loads in flight (D + 1 register buffers of 2K words); more than 8 waves
 // leave registers for D = 1 only.
-// Sweep variants: G workgroups per system (G = 2 splits the bands over two
-// compute units, one wave per SIMD, joined by a channel in memory), K steps
-// per superstep, D supersteps of loads in flight.
+// Sweep variants: G workgroups per system (G = 2 or 4 splits the bands over
+// as many compute units, joined by channels in memory), K steps per
+// superstep, D supersteps of loads in flight.  Above four bands the default
+// takes two compute units in FP32 and four in FP64; the alternative split is
+// variant 1.
 inline int sweep_variants(int ncols) {
   const int nb = (ncols + 63) / 64;
-  return nb == 1 ? 4 : (nb <= 8 ? 6 : 4);
+  return nb == 1 ? 4 : (nb <= 4 ? 6 : (nb <= 8 ? 7 : 4));
 }
 
 template <typename T, bool TR, int K, int D, int G>
@@ -336,12 +338,18 @@ void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A, int var
     }
   } else if (nb <= 8) {
     switch (var) {
-      case 1: sweep_launch_k<T, TR, 4 * P, 4, 1>(c, S, nb, A); break;
-      case 2: sweep_launch_k<T, TR, 4 * P, 2, 1>(c, S, nb, A); break;
-      case 3: sweep_launch_k<T, TR, 2 * P, 4, 1>(c, S, nb, A); break;
-      case 4: sweep_launch_k<T, TR, 2 * P, 2, 1>(c, S, nb, A); break;
+      case 1: sweep_launch_k<T, TR, 4 * P, 2, 6 - (int)sizeof(T) / 2>(c, S, nb, A); break;
+      case 2: sweep_launch_k<T, TR, 4 * P, 4, 1>(c, S, nb, A); break;
+      case 3: sweep_launch_k<T, TR, 4 * P, 2, 1>(c, S, nb, A); break;
+      case 4: sweep_launch_k<T, TR, 2 * P, 4, 1>(c, S, nb, A); break;
       case 5: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
-      default: sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A); break;
+      case 6: sweep_launch_k<T, TR, 4 * P, 4, 4>(c, S, nb, A); break;
+      default:
+        // two loads in flight; FP32 on two compute units, FP64 (twice the
+        // bytes per node) on four
+        if (sizeof(T) == 8) sweep_launch_k<T, TR, 4 * P, 2, 4>(c, S, nb, A);
+        else sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A);
+        break;
     }
   } else {
     switch (var) {

@@ -206,6 +206,7 @@ struct SweepArgs {
 
 constexpr int kSweepMaxRows = 1024;  // also bounds the rows of the coupling table
 constexpr int kSweepMaxBands = 16;
+constexpr int kSweepMaxGroups = 4;  // workgroups per system of a split sweep
 // channel words per group boundary: one tagged 32-bit piece per word, for
 // every writer step of a band (at most kSweepMaxRows + 63 + 2 x 16)
 constexpr int kChanSteps = kSweepMaxRows + 128;
@@ -213,6 +214,11 @@ template <typename T>
 constexpr int kChanStride = kChanSteps * (int)(sizeof(T) / 4);
 // bounded wait for a channel word (each round is one memory round trip)
 constexpr int kChanSpin = 1 << 13;
+// ring slots per band (the upstream band may run up to about ten supersteps
+// ahead before it waits for its reader) and the bounded wait for a band's
+// progress counter in LDS
+constexpr int kRing = 128;
+constexpr int kProgSpin = 1 << 22;
 
 // Words per copy of the row-coupling table for rows rows (entries -64 ..
 // rows + 63 + K of the row index, rounded up to whole chunks).
@@ -285,8 +291,17 @@ BLP_DEV T chan_value(const ChanWord<T> &c) {
 }
 
 // The sweep of one workgroup: wave w is band band0 + w of the rectangle's
-// nbt bands (G = 1: all of them).  ring holds (waves + 1) x 64 words and ycs
-// kChunk<T> x yc_stride<T, K>(rows) words of LDS, both 16-byte aligned.
+// nbt bands (G = 1: all of them).  ring holds (waves + 1) x kRing words, ycs
+// kChunk<T> x yc_stride<T, K>(rows) words and prog one int per wave, all LDS,
+// ring and ycs 16-byte aligned.
+//
+// The bands of a workgroup synchronise pairwise, not in lockstep: after a
+// superstep a band publishes the number of supersteps it has completed in
+// prog; before reading its ring a band waits until its upstream band has
+// completed the superstep that holds the last step it needs, and before
+// overwriting ring slots a band waits until its downstream band no longer
+// needs them.  A wave's LDS operations are processed in order, so a count
+// read by another wave implies the ring writes issued before it.
 //
 // Split sweeps (G > 1 workgroups per system, group gi taking bands gi x
 // waves ..): the first band of group gi > 0 gets its upstream column from
@@ -299,10 +314,10 @@ BLP_DEV T chan_value(const ChanWord<T> &c) {
 // NaN, which the solver reports.  Groups run in block order (group 0 has the
 // lowest block numbers), so a reader's writer has always started.
 template <typename T, bool TR, int K, int D, int G>
-BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nthreads, int gi) {
-  constexpr int P = kChunk<T>, CK = K / P, LAG = 64 + K, RING = 64, NW = sizeof(T) / 4;
+BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int tid, int nthreads,
+                        int gi) {
+  constexpr int P = kChunk<T>, CK = K / P, RING = kRing, NW = sizeof(T) / 4;
   static_assert(K % P == 0 && 64 % K == 0 && 2 * K + P <= 64 && CK <= kSkewGroup, "superstep length");
-  static_assert(LAG % K == 0 && LAG / K >= D, "lag in whole supersteps, at least D");
   typedef typename Vec16<T>::type V;
   const Grid<T> &g = a.g;
   const SkewT<T, TR> sk{a.i0, a.i1, a.j0, a.j1};
@@ -349,14 +364,13 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
     }
   }
   for (int q = tid; q < (nw + 1) * RING; q += nthreads) ring[q] = T(0);
+  for (int q = tid; q < nw; q += nthreads) prog[q] = 0;
   __syncthreads();
 
   // the rectangle's last band holds mcl columns, so its last node is at
   // local step mr + mcl - 2; other bands end at mr + 62
   const int mcl = mc - (nbt - 1) * 64;
   auto last_step = [&](int bd) { return mr - 2 + (bd == nbt - 1 ? mcl : 64); };
-  const int nsup =
-      __builtin_amdgcn_readfirstlane(((nbg - 1) * LAG + last_step(band0 + nbg - 1) + 1 + K - 1) / K);
   // this band's storage: chunk ck of this lane is element ck * 64
   const int bs = has ? band : band0;
   const BLP_GLOBAL V *__restrict__ bb = gptr(reinterpret_cast<const V *>(a.b + sk.slot(bs, 0, 0)) + lane);
@@ -423,6 +437,12 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
     }
   };
 
+  // supersteps with work of this band and of its upstream band (a full band:
+  // last step rows + 62), and whether a downstream band of this workgroup
+  // reads this band's ring
+  const int nact = has ? __builtin_amdgcn_readfirstlane((lastl + K) / K) : 0;
+  const int nact_up = (mr + 62 + K) / K;
+  const bool down = wv + 1 < nbg;
   T buf_b[D + 1][K], buf_i[D + 1][K], res[K];
   ChanWord<T> buf_c[D + 1];
 #pragma unroll
@@ -453,12 +473,25 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
         ring_in_w[(sl + 63 + lane) & (RING - 1)] = v;
       }
     }
+    // the upstream band of this workgroup has written its steps up to
+    // sl + K + 62 (those of its superstep (sl + K + 62) / K); past its last
+    // active superstep the values only feed padding rows
+    if (wv > 0) {
+      const int need = min(ml + (K + 62) / K + 1, nact_up);
+      int spin = 0;
+      while (__hip_atomic_load(prog + wv - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need &&
+             spin < kProgSpin) {
+        __builtin_amdgcn_s_sleep(1);
+        ++spin;
+      }
+      asm volatile("" ::: "memory");
+    }
     // LDS operands of the superstep, read up front so that no LDS latency
     // sits on the step-to-step dependency chain.  The writer band stores
-    // its local step s (lane 63) in ring slot s mod 64; lane 0 of this band,
-    // at local step s, needs the writer's step s + 63, slot (s - 1) mod 64,
-    // written at least one superstep earlier.  The last superstep may pass
-    // the last row of every lane: any finite coupling will do there.
+    // its local step s (lane 63) in ring slot s mod kRing; lane 0 of this
+    // band, at local step s, needs the writer's step s + 63, slot (s - 1 +
+    // 64) mod kRing.  The last superstep may pass the last row of every
+    // lane: any finite coupling will do there.
     T yc[K], zb0[K];
     const V *yr = yc_base + (sl > shi ? shi : sl) / P;
 #pragma unroll
@@ -468,7 +501,7 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
       for (int e = 0; e < P; ++e) yc[q * P + e] = v[e];
     }
     {
-      const int r0 = (sl & (RING - 1)) / P;
+      const int r0 = ((sl + 64) & (RING - 1)) / P;
       const V pv = ring_in[(r0 + RING / P - 1) & (RING / P - 1)];
       zb0[0] = pv[P - 1];
 #pragma unroll
@@ -485,9 +518,21 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
       z = (Cb[k] - yc[k] * z - cu * zin) * Ci[k];
       res[k] = z;
     }
-    // the slots written here (steps sl .. sl + K - 1) and the slots the
-    // next band reads in the same superstep (steps sl - K - P .. sl - 1 of
-    // this band, mod 64) are disjoint: 2K + P <= 64
+    // the slots written here (steps sl .. sl + K - 1) last held steps
+    // sl - kRing ..; the downstream band reads this band's steps from
+    // c K + 64 - P on at its superstep c, so it must have completed every
+    // superstep before the first c with c K + 64 - P > sl + K - 1 - kRing
+    if (down) {
+      const int need = (sl + K - RING - 64 + P + K - 1) / K;
+      int spin = 0;
+      while (need > 0 &&
+             __hip_atomic_load(prog + wv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < need &&
+             spin < kProgSpin) {
+        __builtin_amdgcn_s_sleep(1);
+        ++spin;
+      }
+      asm volatile("" ::: "memory");
+    }
     if (lane == 63) {
       const int r0 = (sl & (RING - 1)) / P;
 #pragma unroll
@@ -503,29 +548,16 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
       const T v = reinterpret_cast<const T *>(ring_out)[(sl + lane) & (RING - 1)];
       chan_put<T>(chw + (size_t)(sl + lane) * NW, v, tagw);
     }
-    lds_barrier();
+    asm volatile("" ::: "memory");
+    if (lane == 0) __hip_atomic_store(prog + wv, ml + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  // Band w runs LAG / K supersteps behind band w - 1 of its group and works
-  // only on its own supersteps [m0, m0 + nact) of the group's nsup: before
-  // and after those it only takes part in the barriers (no memory traffic).
-  // Its first D supersteps of operands are requested D barriers before it
-  // starts, and the step loop follows those loads directly, so that the
-  // compiler's wait counts keep the D supersteps of loads in flight.
-  const int m0 = wv * (LAG / K);
-  const int nact = has ? __builtin_amdgcn_readfirstlane((lastl + K) / K) : 0;
-  if (!has) {
-    for (int m = 0; m < nsup; ++m) lds_barrier();
-    return;
-  }
-  if (m0 > 0) {
-    for (int m = 0; m < m0 - D; ++m) lds_barrier();
-  }
+  // A band works on its supersteps 0 .. nact - 1 (local steps up to its last
+  // node's); its first D supersteps of operands are requested at once, and
+  // the step loop follows those loads directly, so that the compiler's wait
+  // counts keep D supersteps of loads in flight.
+  if (!has) return;
 #pragma unroll
   for (int u = 0; u < D; ++u) load(u, buf_b[u], buf_i[u], buf_c[u]);
-  if (m0 > 0) {
-#pragma unroll
-    for (int u = 0; u < D; ++u) lds_barrier();
-  }
   // whole groups of D + 1 supersteps (buffer roles fixed by unrolling), then
   // the remaining supersteps outside the loop, so that no partially executed
   // group reaches the loop back edge
@@ -547,7 +579,6 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int tid, int nth
     if (writer) gptr(a.epoch)[2 * gi] = (int)tagw;
     if (reader) gptr(a.epoch)[2 * (gi - 1) + 1] = (int)tagr;
   }
-  for (int m = m0 + nact; m < nsup; ++m) lds_barrier();
 }
 
 // G workgroups per system (blocks g x S + s: every group-0 block precedes
@@ -557,9 +588,10 @@ __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T>
   const int S = gridDim.x / G, gi = blockIdx.x / S;
   const SweepArgs<T> a = A[blockIdx.x - gi * S];
   if (gated(a.gate)) return;
-  __shared__ __align__(16) T ring[(kSweepMaxBands + 1) * 64];
+  __shared__ __align__(16) T ring[(kSweepMaxBands + 1) * kRing];
   __shared__ __align__(16) T ycs[kChunk<T> * yc_stride<T, K>(kSweepMaxRows)];
-  sweep_body<T, TR, K, D, G>(a, ring, ycs, threadIdx.x, blockDim.x, gi);
+  __shared__ int prog[kSweepMaxBands];
+  sweep_body<T, TR, K, D, G>(a, ring, ycs, prog, threadIdx.x, blockDim.x, gi);
 }
 
 // Natural <-> skewed copies of a rectangle of the fine grid (batched over
