@@ -159,12 +159,13 @@ inline size_t skew_size(int mc, int mr) {
 // Couplings to values outside the rectangle are already folded into rhs
 // (k_gather_skew), so the sweep sees zero boundary values.
 //
-// rhs, 1/C and z are in the skewed layout of the rectangle.  One workgroup;
-// wave w owns band w, lane l one column.  The upstream-column value comes
-// from lane l-1 by a DPP shift (lane 0: from the previous band, through an
-// LDS ring), the upstream-row value is the lane's own previous result.  Band
-// w runs LAG = 64 + K steps behind band w-1; an LDS-only barrier every K
-// steps (a superstep) orders the ring traffic.
+// rhs, 1/C and z are in the skewed layout of the rectangle.  One workgroup
+// (or G of them, see sweep_body); wave w owns band w, lane l one column.  The
+// upstream-column value comes from lane l-1 by a DPP shift (lane 0: from the
+// previous band, through an LDS ring), the upstream-row value is the lane's
+// own previous result.  Steps are processed K at a time (a superstep); band
+// w needs band w-1 to be 64 + K steps ahead, which per-band progress
+// counters in LDS ensure.
 //
 // Idle steps need no masking: padding slots hold rhs = 1/C = 0, so a lane
 // whose row is not yet reached computes exactly 0 (the ring starts at zero),
