@@ -68,11 +68,19 @@ struct System {
   KrylovStatus *st = nullptr;    // device, in the batch's array
   int *gate = nullptr;           // device, in the batch's array
   double *mg_partials = nullptr;
-  // Krylov workspace
+  // Krylov workspace of the current solve (one per precision, kept, so that
+  // alternating precisions neither reallocates nor invalidates plans)
   int ws_m = 0, ws_prec = -1;
   void *V = nullptr, *Z = nullptr;
   double *w = nullptr, *ks = nullptr, *partials = nullptr;
-  Alloc mem, kmem;
+  struct KrylovWS {
+    int m = 0;
+    void *V = nullptr, *Z = nullptr;
+    double *w = nullptr, *ks = nullptr, *partials = nullptr;
+    Alloc mem;
+  } kws[2];  // [0] FP64, [1] mixed
+  Alloc mem;
+  long long krylov_bytes() const { return kws[0].mem.bytes + kws[1].mem.bytes; }
 };
 
 template <typename T>
@@ -107,23 +115,34 @@ int alloc_work(System &s, hipStream_t st, SysWork<T> &w, const FineDev<T> &f,
 
 // Krylov workspace of a system for restart length m and precision prec.
 int ensure_krylov(System &s, hipStream_t st, int m, int prec) {
-  if (s.ws_m >= m && s.ws_prec == prec) return BLP_OK;
-  HIP_TRY(hipStreamSynchronize(st));
-  s.kmem.release();
-  const size_t n = s.p->n;
-  const size_t es = prec == BLP_MIXED ? sizeof(float) : sizeof(double);
-  char *V = nullptr, *Z = nullptr;
-  BLP_TRY(s.kmem.get(&V, (size_t)(m + 1) * n * es));
-  BLP_TRY(s.kmem.get(&Z, (size_t)m * n * es));
-  s.V = V;
-  s.Z = Z;
-  BLP_TRY(s.kmem.get(&s.w, n));
-  BLP_TRY(s.kmem.get(&s.ks, (size_t)(m + 1) * m + 2 * m + 3 * (m + 1) + m, st, true));
-  const size_t nblk = (n + KCHUNK - 1) / KCHUNK;
-  // stencil partials: one per block at the smallest strip height tried (8 rows)
-  const size_t nstencil = (size_t)((s.p->n1 + 255) / 256) * ((s.p->n1 + 7) / 8);
-  BLP_TRY(s.kmem.get(&s.partials, std::max(nblk * (size_t)(m + 2), std::max(nstencil, (size_t)256))));
-  s.ws_m = m;
+  System::KrylovWS &k = s.kws[prec == BLP_MIXED ? 1 : 0];
+  if (k.m < m) {
+    // grows only: plans built on the old buffers notice the new V (see
+    // get_solve_plan) and are rebuilt
+    HIP_TRY(hipStreamSynchronize(st));
+    k.mem.release();
+    k.m = 0;
+    const size_t n = s.p->n;
+    const size_t es = prec == BLP_MIXED ? sizeof(float) : sizeof(double);
+    char *V = nullptr, *Z = nullptr;
+    BLP_TRY(k.mem.get(&V, (size_t)(m + 1) * n * es));
+    BLP_TRY(k.mem.get(&Z, (size_t)m * n * es));
+    k.V = V;
+    k.Z = Z;
+    BLP_TRY(k.mem.get(&k.w, n));
+    BLP_TRY(k.mem.get(&k.ks, (size_t)(m + 1) * m + 2 * m + 3 * (m + 1) + m, st, true));
+    const size_t nblk = (n + KCHUNK - 1) / KCHUNK;
+    // stencil partials: one per block at the smallest strip height tried (8 rows)
+    const size_t nstencil = (size_t)((s.p->n1 + 255) / 256) * ((s.p->n1 + 7) / 8);
+    BLP_TRY(k.mem.get(&k.partials, std::max(nblk * (size_t)(m + 2), std::max(nstencil, (size_t)256))));
+    k.m = m;
+  }
+  s.V = k.V;
+  s.Z = k.Z;
+  s.w = k.w;
+  s.ks = k.ks;
+  s.partials = k.partials;
+  s.ws_m = k.m;
   s.ws_prec = prec;
   return BLP_OK;
 }
@@ -584,8 +603,15 @@ struct SolvePlan {
   int rows = kRows;  // stencil strip height (autotuner)
   bool tuned = false;
   Alloc mem;
-  std::vector<const double *> F;    // right-hand sides the plan was built for
+  std::vector<const double *> F;    // right-hand sides the plan is bound to
   std::vector<double *> U;
+  std::vector<const void *> V;      // Krylov bases the plan was built on
+  // host copies of the records that hold F and U (rebound in place when a
+  // solve passes other vectors; their device arrays keep their addresses,
+  // so captured graphs stay valid)
+  std::vector<SpmvArgs<double>> resid_h;
+  std::vector<NormArgs> norm_h;
+  std::vector<KArgs<TV>> kr_h;
   // captured step (graphs mode): part 1 of the preconditioner; the rest of
   // the step (corner copy-back, remaining regions, SpMV, Arnoldi)
   hipGraphExec_t g1 = nullptr, g2 = nullptr;
@@ -683,7 +709,7 @@ int batch_create(hipStream_t stream, blp_problem *const *probs, int S, std::uniq
 
 long long batch_bytes(const Batch &B) {
   long long b = B.mem.bytes;
-  for (const auto &y : B.sys) b += y->mem.bytes + y->kmem.bytes;
+  for (const auto &y : B.sys) b += y->mem.bytes + y->krylov_bytes();
   return b;
 }
 
@@ -701,6 +727,7 @@ int build_solve_plan(Batch &B, const std::vector<int> &cls, int m, const double 
   std::vector<KArgs<TV>> kr(S);
   P.F.clear();
   P.U.clear();
+  P.V.clear();
   for (int k = 0; k < S; ++k) {
     System &y = *B.sys[cls[k]];
     blp_problem *p = y.p;
@@ -714,13 +741,39 @@ int build_solve_plan(Batch &B, const std::vector<int> &cls, int m, const double 
     kr[k] = KArgs<TV>{(TV *)y.V, (TV *)y.Z, n, y.w, y.partials, y.ks, y.st, U[cls[k]], y.gate};
     P.F.push_back(F[cls[k]]);
     P.U.push_back(U[cls[k]]);
+    P.V.push_back(y.V);
   }
   BLP_TRY((build_prec_plan<TV, TR>(st, sys, io, SCALE, P.prec)));
   BLP_TRY(P.mem.put(&P.spmv, sp.data(), S, st));
   BLP_TRY(P.mem.put(&P.resid, rs.data(), S, st));
   BLP_TRY(P.mem.put(&P.norm, nm.data(), S, st));
   BLP_TRY(P.mem.put(&P.kr, kr.data(), S, st));
+  P.resid_h = rs;
+  P.norm_h = nm;
+  P.kr_h = kr;
   HIP_TRY(hipStreamSynchronize(st));
+  return BLP_OK;
+}
+
+// Point an existing plan at other right-hand sides and iterates: only the
+// residual, norm and Krylov records hold them.
+template <typename TV, bool TR, bool SCALE>
+int rebind_solve_plan(Batch &B, const std::vector<int> &cls, const double *const *F,
+                      double *const *U, SolvePlan<TV, TR, SCALE> &P) {
+  const int S = (int)cls.size();
+  for (int k = 0; k < S; ++k) {
+    P.resid_h[k].x = U[cls[k]];
+    P.resid_h[k].F = F[cls[k]];
+    P.norm_h[k].F = F[cls[k]];
+    P.kr_h[k].u = U[cls[k]];
+    P.F[k] = F[cls[k]];
+    P.U[k] = U[cls[k]];
+  }
+  HIP_TRY(hipMemcpyAsync(P.resid, P.resid_h.data(), S * sizeof(SpmvArgs<double>), hipMemcpyHostToDevice,
+                         B.stream));
+  HIP_TRY(hipMemcpyAsync(P.norm, P.norm_h.data(), S * sizeof(NormArgs), hipMemcpyHostToDevice, B.stream));
+  HIP_TRY(hipMemcpyAsync(P.kr, P.kr_h.data(), S * sizeof(KArgs<TV>), hipMemcpyHostToDevice, B.stream));
+  HIP_TRY(hipStreamSynchronize(B.stream));  // the host copies may change at the next rebind
   return BLP_OK;
 }
 
@@ -795,14 +848,18 @@ int get_solve_plan(Batch &B, int c, int m, const double *const *F, double *const
   auto it = B.plans.find(key);
   if (it != B.plans.end()) {
     auto *h = static_cast<PlanHolder<TV, TR, SCALE> *>(it->second.get());
-    bool same = true;
-    for (size_t k = 0; k < B.classes[c].size(); ++k)
-      same = same && h->plan.F[k] == F[B.classes[c][k]] && h->plan.U[k] == U[B.classes[c][k]];
-    if (same) {
+    bool basis = true, same = true;
+    for (size_t k = 0; k < B.classes[c].size(); ++k) {
+      const int s = B.classes[c][k];
+      basis = basis && h->plan.V[k] == B.sys[s]->V;
+      same = same && h->plan.F[k] == F[s] && h->plan.U[k] == U[s];
+    }
+    if (basis) {
+      if (!same) BLP_TRY((rebind_solve_plan<TV, TR, SCALE>(B, B.classes[c], F, U, h->plan)));
       *out = &h->plan;
       return BLP_OK;
     }
-    B.plans.erase(it);
+    B.plans.erase(it);  // built on a basis that has since been reallocated
   }
   std::unique_ptr<PlanHolder<TV, TR, SCALE>> h(new (std::nothrow) PlanHolder<TV, TR, SCALE>());
   if (!h) return BLP_E_NOMEM;

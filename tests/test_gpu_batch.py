@@ -108,3 +108,25 @@ def test_mixed_batch_against_oracle():
         say("  system %d N=%d eps=%.1e it=%d err %.2e" % (s, inst.N, inst.eps,
                                                          info[s]["iterations"], err))
         assert err <= 1e-6
+
+
+def test_alternating_precisions_reuse_plans():
+    """Solves that alternate FP64 and mixed precision on one problem, with a
+    fresh result vector each time, reuse their plans (rebound to the new
+    vectors) and the per-precision Krylov workspaces: every repeat reproduces
+    the first solve of its precision bit for bit, with the same iterations."""
+    inst = inputs.plain(256, 1e-5, seed=7)
+    say("alternating precisions N=%d" % inst.N)
+    (p,), (F,) = _problems([inst])
+    first = {}
+    for rnd in range(3):
+        for prec in ("fp64", "mixed"):
+            U, info = p.solve(F, tol=1e-8, scaled=True, precision=prec)
+            it = info[0]["iterations"]
+            assert info[0]["converged"]
+            if rnd == 0:
+                first[prec] = (U.clone(), it)
+            else:
+                U0, it0 = first[prec]
+                assert it == it0
+                assert bool((U == U0).all()), (prec, rnd, _rel(U, U0))
