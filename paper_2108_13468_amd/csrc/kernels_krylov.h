@@ -24,6 +24,38 @@ struct KOffsets {
 
 constexpr int KCHUNK = 4096;  // elements per block in the basis kernels
 constexpr int KPT = KCHUNK / 256;
+constexpr int KMAXD = 62;     // dot products per pass: j + 2 <= restart + 1 <= 61
+
+// Block partials of the nd dot products V_v . w (v < nv) and, if with_norm,
+// ||w||^2 as dot nv: each wave reduces every product by shuffles and leaves
+// its partial in shared memory, then one barrier, then thread v sums the
+// waves' partials of product v and publishes it (partials[bid * nd + v]).
+template <typename TV>
+BLP_DEV void block_dots(const BLP_GLOBAL TV *V, size_t n, size_t base, const double (&wl)[KPT], int nv,
+                        bool with_norm, double (*sd)[4], double *partials, size_t bid) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) {
+      const size_t q = base + (size_t)e * 256;
+      if (q < n) acc += (double)V[(size_t)v * n + q] * wl[e];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sd[v][wv] = acc;
+  }
+  if (with_norm) {
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) acc += wl[e] * wl[e];
+    acc = wave_sum(acc);
+    if (lane == 0) sd[nv][wv] = acc;
+  }
+  __syncthreads();
+  const int nd = nv + (with_norm ? 1 : 0);
+  for (int v = threadIdx.x; v < nd; v += blockDim.x)
+    publish(&partials[bid * nd + v], ((sd[v][0] + sd[v][1]) + sd[v][2]) + sd[v][3]);
+}
 
 // One system's Krylov state (batched: blockIdx.y selects the record).  The
 // step index j is read from device memory (jp), so one launch sequence
@@ -43,7 +75,7 @@ struct KArgs {
 // h1[i] = V_i . w (i = 0..j) and wn0 = ||w||.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_arnoldi_dot(const KArgs<TV> *A, const int *jp, KOffsets ko) {
-  __shared__ double sh[16];
+  __shared__ double sd[KMAXD][4];
   __shared__ bool last;
   const KArgs<TV> a = A[blockIdx.y];
   if (gated(a.gate)) return;
@@ -59,27 +91,19 @@ __global__ __launch_bounds__(256) void k_arnoldi_dot(const KArgs<TV> *A, const i
     wl[e] = q < n ? wv[q] : 0.0;
   }
   const int nd = j + 2;  // j+1 dots and ||w||^2
-  for (int v = 0; v <= j; ++v) {
-    double acc = 0.0;
-#pragma unroll
-    for (int e = 0; e < KPT; ++e) {
-      const size_t q = base + (size_t)e * 256;
-      if (q < n) acc += (double)V[(size_t)v * n + q] * wl[e];
-    }
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) publish(&a.partials[(size_t)blockIdx.x * nd + v], acc);
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int e = 0; e < KPT; ++e) acc += wl[e] * wl[e];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) publish(&a.partials[(size_t)blockIdx.x * nd + j + 1], acc);
+  block_dots<TV>(V, n, base, wl, j + 1, true, sd, a.partials, blockIdx.x);
   if (!arrive_last(&a.st->counter, &last, gridDim.x)) return;
-  for (int v = threadIdx.x; v < nd; v += blockDim.x) {
+  // last block: wave w sums the block partials of products w, w + 4, ...
+  // (lanes stride the blocks, then a fixed shuffle tree)
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int v = wid; v < nd; v += nw) {
     double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[(size_t)b * nd + v]);
-    if (v <= j) ko.h1(a.ks)[v] = s;
-    else a.st->wn0 = sqrt(s);
+    for (int b = lane; b < (int)gridDim.x; b += 64) s += collect(&a.partials[(size_t)b * nd + v]);
+    s = wave_sum(s);
+    if (lane == 0) {
+      if (v <= j) ko.h1(a.ks)[v] = s;
+      else a.st->wn0 = sqrt(s);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) reset_counter(&a.st->counter);
@@ -91,6 +115,7 @@ template <typename TV, bool NORM>
 __global__ __launch_bounds__(256) void k_arnoldi_update(const KArgs<TV> *A, const int *jp,
                                                         KOffsets ko) {
   __shared__ double sh[16];
+  __shared__ double sd[KMAXD][4];
   __shared__ bool last;
   __shared__ double hs[64];
   const KArgs<TV> a = A[blockIdx.y];
@@ -126,16 +151,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const KArgs<TV> *A, cons
   }
   const int nd = NORM ? 1 : j + 1;
   if (!NORM) {
-    for (int v = 0; v <= j; ++v) {
-      double acc = 0.0;
-#pragma unroll
-      for (int e = 0; e < KPT; ++e) {
-        const size_t q = base + (size_t)e * 256;
-        if (q < n) acc += (double)V[(size_t)v * n + q] * wl[e];
-      }
-      acc = block_sum(acc, sh);
-      if (threadIdx.x == 0) publish(&a.partials[(size_t)blockIdx.x * nd + v], acc);
-    }
+    block_dots<TV>(V, n, base, wl, j + 1, false, sd, a.partials, blockIdx.x);
   } else {
     double acc = 0.0;
 #pragma unroll
@@ -145,10 +161,12 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const KArgs<TV> *A, cons
   }
   if (!arrive_last(&st->counter, &last, gridDim.x)) return;
   if (!NORM) {
-    for (int v = threadIdx.x; v <= j; v += blockDim.x) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int v = wid; v <= j; v += nw) {
       double s = 0.0;
-      for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[(size_t)b * nd + v]);
-      ko.h2(ks)[v] = s;
+      for (int b = lane; b < (int)gridDim.x; b += 64) s += collect(&a.partials[(size_t)b * nd + v]);
+      s = wave_sum(s);
+      if (lane == 0) ko.h2(ks)[v] = s;
     }
     __syncthreads();
     if (threadIdx.x == 0) reset_counter(&st->counter);
