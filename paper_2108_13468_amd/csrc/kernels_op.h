@@ -71,9 +71,11 @@ __global__ __launch_bounds__(256) void k_stencil(const SpmvArgs<TX> *A, const in
   const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   if (threadIdx.x == 0) publish(&a.partials[bid], acc);
   if (!arrive_last(&a.st->counter, &last, nblk)) return;
+  // last block: block-wide fixed-order sum of the partials
+  double s = 0.0;
+  for (int b = threadIdx.x; b < (int)nblk; b += blockDim.x) s += collect(&a.partials[b]);
+  s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < (int)nblk; ++b) s += collect(&a.partials[b]);
     a.st->beta = sqrt(s);
     reset_counter(&a.st->counter);
   }
@@ -110,9 +112,10 @@ __global__ __launch_bounds__(256) void k_norm(const NormArgs *A) {
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
   if (!arrive_last(&a.st->counter, &last, gridDim.x)) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s += collect(&a.partials[b]);
+  s = block_sum(s, sh);
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += collect(&a.partials[b]);
     a.st->beta = sqrt(s);
     reset_counter(&a.st->counter);
   }
