@@ -1,0 +1,77 @@
+"""GPU solves in the paper's own setting (Sec. 3.3): the two-exponential-layer
+manufactured solution (c = (2, 3), r = 1, sigma = 5/2, lower bounds (2, 3)
+of c), FGMRES on the unscaled system stopped at ||R||_2 <= 10 ln N / N.
+
+Pins from the paper: the iteration counts of Table 7 (the numbers in
+parentheses), five corner V-cycles per apply (the 1e3 reduction of Sec. 3.2)
+and, at N <= 256, the max-norm errors of Table 6 (within 2%: the paper's
+errors carry its own loose stopping rule, as these solves do).  Parity: the
+GPU iterate meets the stopping rule under the oracle's operator and agrees
+with the oracle's FGMRES under the same rule (relative difference at most
+1e-8 when both stop at the same iteration; at a row whose residual sits at
+the threshold the two may stop one iteration apart, and the GPU iterate must
+then be as accurate as the oracle's)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_13468_amd import inputs
+from tests.mms import exponential_mms
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def read_golden(name):
+    rows = []
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append([float(t) for t in line.split()])
+    return {(e, int(n)): v for e, n, v in rows}
+
+
+@pytest.mark.parametrize("N", [128, 256, 512, 1024])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_paper_mode_table7(N, eps):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2108_13468_amd import blp
+    say("paper mode N=%d eps=%g" % (N, eps))
+    ref7 = read_golden("table7_exponential_iterations.txt")
+    ref6 = read_golden("table6_exponential_mms_errors.txt")
+    inst = inputs.mms_exponential(N, eps)
+    gp = blp.from_instance(inst).precondition()
+    op = O.Problem(N, eps, c1=inst.c1_at, c2=inst.c2_at, r=inst.r_const, sigma=inst.sigma,
+                   clow_x=inst.clow[0], clow_y=inst.clow[1])
+    u_exact, f = exponential_mms(eps, op.x, op.y)
+    tol = 10 * np.log(N) / N
+    U, info = gp.solve(torch.as_tensor(f, device="cuda"), tol=tol, absolute=True, scaled=False,
+                       precision="fp64")
+    info = info[0]
+    assert info["converged"], info
+    assert info["iterations"] == int(ref7[(eps, N)])
+    assert info["mg_cycles_min"] == 5 and info["mg_cycles_max"] == 5
+    Ug = U.cpu().numpy()
+    if N <= 256:
+        assert np.abs(Ug - u_exact).max() == pytest.approx(ref6[(eps, N)], rel=0.02)
+    # the GPU iterate meets the stopping rule (true residual, oracle operator)
+    assert np.linalg.norm(f - op.A(Ug)) <= tol
+    uo, st, io, _ = op.fgmres(f, tol=tol, absolute=True)
+    assert st == 0
+    if io.iterations == info["iterations"]:
+        assert np.abs(Ug - uo).max() <= 1e-8 * np.abs(uo).max()
+    else:
+        # a row whose residual sits at the threshold: rounding decides the
+        # last test, so two correct implementations may stop one iteration
+        # apart; the GPU iterate must then be as accurate as the oracle's
+        assert abs(io.iterations - info["iterations"]) == 1
+        assert np.abs(Ug - u_exact).max() <= 1.01 * np.abs(uo - u_exact).max()
