@@ -6,7 +6,7 @@
  * with no blocking, fusion or reordering; it is meant to be checked by eye
  * against the paper.  Compiled with -O2 -ffp-contract=off.
  *
- * Readings taken where the paper is silent (also listed in the design doc):
+ * Readings taken where the paper is silent:
  *  - unknowns are the interior nodes 1 <= i, j <= N-1 (Sec. 3 stencil);
  *  - the layer side of each axis is i <= N/2 (transition node included in
  *    the layer, Sec. 3.1 region definition);

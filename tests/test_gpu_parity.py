@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
 same seeded inputs.
 
-Tolerances (derived in the design doc):
+Tolerances (each derived from the rounding of the arithmetic involved):
   * operator applies: ||y_gpu - y_orc||_inf <= 1e-14 || |A| |x| ||_inf
     (different but equivalent association of the FP64 stencil sums);
   * preconditioner applies with a fixed cycle count (a fixed linear map):
