@@ -80,6 +80,13 @@ BLP_DEV BLP_GLOBAL T *gptr(T *p) {
   return (BLP_GLOBAL T *)p;
 }
 
+// Ordering point for the compiler only: no memory access is moved across
+// it, and nothing waits for loads in flight.  Kernels that test a gate
+// issue the gate's load and their data loads before this point and test the
+// gate after it, so that those loads travel together instead of the data
+// loads waiting for the gate.
+#define BLP_ISSUED() asm volatile("" ::: "memory")
+
 // "Last block" pattern: every block publishes its partial, then the last
 // block to arrive reads all partials.  Partials are stored and read through
 // to the device coherence point (relaxed agent-scope atomic accesses), and a
@@ -121,6 +128,10 @@ BLP_DEV void reset_counter(unsigned int *counter) {
 BLP_DEV long long step_of(const int *jp) { return jp ? (long long)*jp : 0; }
 // Per-system gate: nonzero means the system takes no part in the launch.
 BLP_DEV bool gated(const int *g) { return g && *g; }
+// The same two reads without a branch (a null pointer reads this zero word),
+// so that they travel with the loads that follow them.
+__device__ const int blp_zero_word = 0;
+BLP_DEV int read_or_zero(const int *p) { return *gptr(p ? p : &blp_zero_word); }
 
 
 

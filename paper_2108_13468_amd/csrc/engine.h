@@ -440,7 +440,7 @@ void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
 template <typename T, bool TR>
 void lines_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   const int S = P.S, L = P.n1 - P.h;
-  const dim3 gl((P.hp + 255) / 256, L, 2 * S);
+  const dim3 gl((P.hp + kLineTP - 1) / kLineTP, (L + kLineTQ - 1) / kLineTQ, 2 * S);
   {
     KScope ks(c, KC_LAYOUT, 0.0);
     k_gather_lines<T, TR><<<gl, 256, 0, c.stream>>>(P.ioL, jp);
@@ -511,7 +511,8 @@ template <typename T, bool TR>
 void mg_norm_run(const Ctx &c, const PrecPlan<T, TR> &P, int mode) {
   const int nblk = std::min(kMgNormBlocks, (int)blocks1d(P.lslot[0]));
   KScope ks(c, KC_MG, (double)P.S * P.ln[0] * P.ln[0] * 2 * sizeof(T));
-  k_mg_norm<T, TR><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.mg[0], mode);
+  if (mode == 1) k_mg_norm<T, TR, 1><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.mg[0]);
+  else k_mg_norm<T, TR, 0><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.mg[0]);
 }
 
 // The corner right-hand side and the first cycles: fixed mode runs all its

@@ -8,6 +8,7 @@
 // Givens rotations and the residual estimate are updated in FP64 by one
 // thread of that last block.
 #pragma once
+#include <type_traits>
 #include "common.h"
 
 // Krylov state layout (FP64, device): H[(m+1) x m] row-major, cs[m], sn[m],
@@ -26,6 +27,30 @@ constexpr int KCHUNK = 4096;  // elements per block in the basis kernels
 constexpr int KPT = KCHUNK / 256;
 constexpr int KMAXD = 62;     // dot products per pass: j + 2 <= restart + 1 <= 61
 
+// Basis vectors whose loads are issued together: one block per CU leaves a
+// single wave per SIMD, so the loads of several vectors must be in flight at
+// once to cover the memory latency.
+constexpr int KVU = 4;
+
+// Element q of a length-n vector, zero past n.  The load itself is
+// unconditional (at n - 1 past the end): a load under a condition is waited
+// for before the branch joins, which would serialise a thread's loads.
+template <typename TV>
+BLP_DEV TV load_elem(const BLP_GLOBAL TV *x, size_t n, size_t q) {
+  const TV v = x[q < n ? q : n - 1];
+  return q < n ? v : TV(0);
+}
+
+// Elements base + e * 256 (e < KPT) of basis vectors v0 .. v0 + NU - 1,
+// zero past n.
+template <typename TV, int NU>
+BLP_DEV void load_basis(const BLP_GLOBAL TV *V, size_t n, size_t base, int v0, TV (&x)[NU][KPT]) {
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+#pragma unroll
+    for (int e = 0; e < KPT; ++e) x[u][e] = load_elem(V + (size_t)(v0 + u) * n, n, base + (size_t)e * 256);
+}
+
 // Block partials of the nd dot products V_v . w (v < nv) and, if with_norm,
 // ||w||^2 as dot nv: each wave reduces every product by shuffles and leaves
 // its partial in shared memory, then one barrier, then thread v sums the
@@ -34,16 +59,23 @@ template <typename TV>
 BLP_DEV void block_dots(const BLP_GLOBAL TV *V, size_t n, size_t base, const double (&wl)[KPT], int nv,
                         bool with_norm, double (*sd)[4], double *partials, size_t bid) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int v = 0; v < nv; ++v) {
-    double acc = 0.0;
+  // elements past n hold zero in both factors and add +0 to each sum
+  auto dots = [&](int v0, auto nu) __attribute__((always_inline)) {
+    constexpr int NU = decltype(nu)::value;
+    TV x[NU][KPT];
+    load_basis<TV, NU>(V, n, base, v0, x);
 #pragma unroll
-    for (int e = 0; e < KPT; ++e) {
-      const size_t q = base + (size_t)e * 256;
-      if (q < n) acc += (double)V[(size_t)v * n + q] * wl[e];
+    for (int u = 0; u < NU; ++u) {
+      double acc = 0.0;
+#pragma unroll
+      for (int e = 0; e < KPT; ++e) acc += (double)x[u][e] * wl[e];
+      acc = wave_sum(acc);
+      if (lane == 0) sd[v0 + u][wv] = acc;
     }
-    acc = wave_sum(acc);
-    if (lane == 0) sd[v][wv] = acc;
-  }
+  };
+  int v = 0;
+  for (; v + KVU <= nv; v += KVU) dots(v, std::integral_constant<int, KVU>{});
+  for (; v < nv; ++v) dots(v, std::integral_constant<int, 1>{});
   if (with_norm) {
     double acc = 0.0;
 #pragma unroll
@@ -78,18 +110,16 @@ __global__ __launch_bounds__(256) void k_arnoldi_dot(const KArgs<TV> *A, const i
   __shared__ double sd[KMAXD][4];
   __shared__ bool last;
   const KArgs<TV> a = A[blockIdx.y];
-  if (gated(a.gate)) return;
-  const int j = (int)step_of(jp);
+  const int gate = read_or_zero(a.gate), j = read_or_zero(jp);
   const size_t n = a.n;
   const BLP_GLOBAL TV *V = gptr(a.V);
   const BLP_GLOBAL double *wv = gptr(a.w);
   const size_t base = (size_t)blockIdx.x * KCHUNK + threadIdx.x;
   double wl[KPT];
 #pragma unroll
-  for (int e = 0; e < KPT; ++e) {
-    const size_t q = base + (size_t)e * 256;
-    wl[e] = q < n ? wv[q] : 0.0;
-  }
+  for (int e = 0; e < KPT; ++e) wl[e] = load_elem(wv, n, base + (size_t)e * 256);
+  BLP_ISSUED();
+  if (gate) return;
   const int nd = j + 2;  // j+1 dots and ||w||^2
   block_dots<TV>(V, n, base, wl, j + 1, true, sd, a.partials, blockIdx.x);
   if (!arrive_last(&a.st->counter, &last, gridDim.x)) return;
@@ -119,31 +149,36 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const KArgs<TV> *A, cons
   __shared__ bool last;
   __shared__ double hs[64];
   const KArgs<TV> a = A[blockIdx.y];
-  if (gated(a.gate)) return;
-  const int j = (int)step_of(jp);
+  const int gate = read_or_zero(a.gate), j = read_or_zero(jp);
   const size_t n = a.n;
   const BLP_GLOBAL TV *V = gptr(a.V);
   BLP_GLOBAL double *w = gptr(a.w);
   double *ks = a.ks;
   KrylovStatus *st = a.st;
-  const double *hin = NORM ? ko.h2(ks) : ko.h1(ks);
-  for (int v = threadIdx.x; v <= j; v += blockDim.x) hs[v] = hin[v];
-  __syncthreads();
   const size_t base = (size_t)blockIdx.x * KCHUNK + threadIdx.x;
   double wl[KPT];
 #pragma unroll
-  for (int e = 0; e < KPT; ++e) {
-    const size_t q = base + (size_t)e * 256;
-    wl[e] = q < n ? w[q] : 0.0;
-  }
-  for (int v = 0; v <= j; ++v) {
-    const double hv = hs[v];
+  for (int e = 0; e < KPT; ++e) wl[e] = load_elem<double>(w, n, base + (size_t)e * 256);
+  const BLP_GLOBAL double *hin = gptr(NORM ? ko.h2(ks) : ko.h1(ks));
+  for (int v = threadIdx.x; v <= j; v += blockDim.x) hs[v] = hin[v];
+  BLP_ISSUED();
+  if (gate) return;
+  __syncthreads();
+  // past n both wl and the basis elements are zero (and w is not stored)
+  auto update = [&](int v0, auto nu) __attribute__((always_inline)) {
+    constexpr int NU = decltype(nu)::value;
+    TV x[NU][KPT];
+    load_basis<TV, NU>(V, n, base, v0, x);
 #pragma unroll
-    for (int e = 0; e < KPT; ++e) {
-      const size_t q = base + (size_t)e * 256;
-      if (q < n) wl[e] -= (double)V[(size_t)v * n + q] * hv;
+    for (int u = 0; u < NU; ++u) {
+      const double hv = hs[v0 + u];
+#pragma unroll
+      for (int e = 0; e < KPT; ++e) wl[e] -= (double)x[u][e] * hv;
     }
-  }
+  };
+  int v = 0;
+  for (; v + KVU <= j + 1; v += KVU) update(v, std::integral_constant<int, KVU>{});
+  for (; v <= j; ++v) update(v, std::integral_constant<int, 1>{});
 #pragma unroll
   for (int e = 0; e < KPT; ++e) {
     const size_t q = base + (size_t)e * 256;

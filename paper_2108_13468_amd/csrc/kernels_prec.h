@@ -865,6 +865,14 @@ __global__ __launch_bounds__(64 * W) void k_lines(const LineArgs<T> *A) {
 // dh and folds in the couplings to already-solved regions (see above), read
 // from z + j ldz; padding nodes p in [h, hp) get zero.  The scatter writes
 // the edge regions of z + j ldz.
+//
+// A block moves a tile of kLineTQ lines by kLineTP nodes.  In the X region
+// (r = 1) a line is a mesh row, contiguous in both layouts, and the tile is
+// copied directly.  In the Y region (r = 0) a line is a mesh column: the
+// tile passes through LDS so that the natural side is accessed along rows
+// (consecutive lines) and the line-major side along lines (consecutive
+// nodes).
+constexpr int kLineTQ = 32, kLineTP = 64, kLineThreads = 256;
 template <typename T>
 struct LineIO {
   Grid<T> g;
@@ -878,46 +886,90 @@ struct LineIO {
   const T *zL[2];  // line results [Y, X]
   const int *gate;
 };
+// Gathered value of node p of line q in region r (p < h).
 template <typename T, bool TR>
-__global__ void k_gather_lines(const LineIO<T> *A, const int *jp) {
-  const LineIO<T> a = A[blockIdx.z >> 1];
-  if (gated(a.gate)) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y, r = blockIdx.z & 1;
-  const int h = a.h, n1 = a.n1, hp = a.hp;
-  if (p >= hp) return;
-  T *out = a.bL[r];
-  const size_t o = (size_t)q * hp + p;
-  if (p >= h) {
-    out[o] = T(0);
-    return;
-  }
-  const Grid<T> &g = a.g;
-  const T *v = a.v + step_of(jp) * a.ldv;
-  const T *z = a.z + step_of(jp) * a.ldz;
+BLP_DEV T line_gather_node(const LineIO<T> &a, const BLP_GLOBAL T *v, const BLP_GLOBAL T *dh,
+                           const BLP_GLOBAL T *z, int r, int q, int p) {
+  const int h = a.h, n1 = a.n1;
   const int line = TR ? h + 1 + q : n1 - q;
   const int i = r == 0 ? line : p + 1, j = r == 0 ? p + 1 : line;
   const size_t k = vidx(i, j, n1);
   T val = v[k];
-  if (a.dh) val *= a.dh[k];
+  if (dh) val *= dh[k];
   if (!TR) {
-    if (p == h - 1) val -= r == 0 ? g.N[h] * z[vidx(i, h + 1, n1)] : g.E[h] * z[vidx(h + 1, j, n1)];
+    if (p == h - 1) val -= r == 0 ? a.g.N[h] * z[vidx(i, h + 1, n1)] : a.g.E[h] * z[vidx(h + 1, j, n1)];
   } else if (q == 0) {
-    val -= r == 0 ? g.E[h] * z[vidx(h, j, n1)] : g.N[h] * z[vidx(i, h, n1)];
+    val -= r == 0 ? a.g.E[h] * z[vidx(h, j, n1)] : a.g.N[h] * z[vidx(i, h, n1)];
   }
-  out[o] = val;
+  return val;
 }
 template <typename T, bool TR>
-__global__ void k_scatter_lines(const LineIO<T> *A, const int *jp) {
-  const LineIO<T> a = A[blockIdx.z >> 1];
+__global__ __launch_bounds__(kLineThreads) void k_gather_lines(const LineIO<T> *A, const int *jp) {
+  __shared__ T tile[kLineTP][kLineTQ + 1];
+  const LineIO<T> &a = A[blockIdx.z >> 1];
   if (gated(a.gate)) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y, r = blockIdx.z & 1;
-  const int h = a.h, n1 = a.n1;
-  if (p >= h) return;
-  const int line = TR ? h + 1 + q : n1 - q;
-  const int i = r == 0 ? line : p + 1, j = r == 0 ? p + 1 : line;
-  (a.z + step_of(jp) * a.ldz)[vidx(i, j, n1)] = a.zL[r][(size_t)q * a.hp + p];
+  const int r = blockIdx.z & 1, h = a.h, hp = a.hp, L = a.n1 - h;
+  const int p0 = blockIdx.x * kLineTP, q0 = blockIdx.y * kLineTQ, tid = threadIdx.x;
+  const BLP_GLOBAL T *v = gptr(a.v + step_of(jp) * a.ldv);
+  const BLP_GLOBAL T *z = gptr(a.z + step_of(jp) * a.ldz);
+  const BLP_GLOBAL T *dh = gptr(a.dh);
+  BLP_GLOBAL T *out = gptr(a.bL[r]);
+  constexpr int NE = kLineTQ * kLineTP / kLineThreads;
+  if (r == 1) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int p = p0 + tid % kLineTP, q = q0 + tid / kLineTP + e * (kLineThreads / kLineTP);
+      if (q < L && p < hp) out[(size_t)q * hp + p] = p < h ? line_gather_node<T, TR>(a, v, dh, z, 1, q, p) : T(0);
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int ql = tid % kLineTQ, pl = tid / kLineTQ + e * (kLineThreads / kLineTQ);
+    const int q = q0 + ql, p = p0 + pl;
+    tile[pl][ql] = (q < L && p < h) ? line_gather_node<T, TR>(a, v, dh, z, 0, q, p) : T(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int pl = tid % kLineTP, ql = tid / kLineTP + e * (kLineThreads / kLineTP);
+    const int q = q0 + ql, p = p0 + pl;
+    if (q < L && p < hp) out[(size_t)q * hp + p] = tile[pl][ql];
+  }
+}
+template <typename T, bool TR>
+__global__ __launch_bounds__(kLineThreads) void k_scatter_lines(const LineIO<T> *A, const int *jp) {
+  __shared__ T tile[kLineTP][kLineTQ + 1];
+  const LineIO<T> &a = A[blockIdx.z >> 1];
+  if (gated(a.gate)) return;
+  const int r = blockIdx.z & 1, h = a.h, hp = a.hp, n1 = a.n1, L = n1 - h;
+  const int p0 = blockIdx.x * kLineTP, q0 = blockIdx.y * kLineTQ, tid = threadIdx.x;
+  BLP_GLOBAL T *z = gptr(a.z + step_of(jp) * a.ldz);
+  const BLP_GLOBAL T *zl = gptr(a.zL[r]);
+  constexpr int NE = kLineTQ * kLineTP / kLineThreads;
+  if (r == 1) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int p = p0 + tid % kLineTP, q = q0 + tid / kLineTP + e * (kLineThreads / kLineTP);
+      const int line = TR ? h + 1 + q : n1 - q;
+      if (q < L && p < h) z[vidx(p + 1, line, n1)] = zl[(size_t)q * hp + p];
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int pl = tid % kLineTP, ql = tid / kLineTP + e * (kLineThreads / kLineTP);
+    const int q = q0 + ql, p = p0 + pl;
+    if (q < L && p < h) tile[pl][ql] = zl[(size_t)q * hp + p];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int ql = tid % kLineTQ, pl = tid / kLineTQ + e * (kLineThreads / kLineTQ);
+    const int q = q0 + ql, p = p0 + pl;
+    const int line = TR ? h + 1 + q : n1 - q;
+    if (q < L && p < h) z[vidx(line, p + 1, n1)] = tile[pl][ql];
+  }
 }
 
 // Thomas factorisation of every line (setup), row stride hp; the padding
@@ -1011,16 +1063,19 @@ BLP_DEV SkewT<T, TR> level_skew(int n) { return SkewT<T, TR>{1, n, 1, n}; }
 
 // (A z)_ij (forward) or (A^T z)_ij (transposed) on a level, z skewed, in
 // FP64 arithmetic whatever the storage precision (residuals of the FP32
-// cycle would otherwise lose the digits that cancel in b - A z).
+// cycle would otherwise lose the digits that cancel in b - A z).  A
+// neighbour outside the level is read at the node itself and counts as
+// zero: every load is unconditional, so all of them are in flight together
+// (a load under a condition is waited for before the branch joins).
 template <typename T, bool TR>
 BLP_DEV double level_apply(const GridG<T> &g, const SkewT<T, TR> &sk, const BLP_GLOBAL T *z, int i,
                            int j) {
   const int n = g.nx;
+  const bool hw = i > 1, he = i < n, hs = j > 1, hn = j < g.ny;
   const double zc = z[sk.at(i, j)];
-  const double zw = i > 1 ? (double)z[sk.at(i - 1, j)] : 0.0;
-  const double ze = i < n ? (double)z[sk.at(i + 1, j)] : 0.0;
-  const double zs = j > 1 ? (double)z[sk.at(i, j - 1)] : 0.0;
-  const double zn = j < g.ny ? (double)z[sk.at(i, j + 1)] : 0.0;
+  const double lw = z[sk.at(hw ? i - 1 : i, j)], le = z[sk.at(he ? i + 1 : i, j)];
+  const double ls = z[sk.at(i, hs ? j - 1 : j)], ln = z[sk.at(i, hn ? j + 1 : j)];
+  const double zw = hw ? lw : 0.0, ze = he ? le : 0.0, zs = hs ? ls : 0.0, zn = hn ? ln : 0.0;
   const double C = (double)g.Dx[i] + (double)g.Dy[j] + (double)g.rr(i, j);
   if (!TR)
     return C * zc + (double)g.W[i] * zw + (double)g.E[i] * ze + (double)g.S[j] * zs +
@@ -1034,178 +1089,182 @@ BLP_DEV double level_apply(const GridG<T> &g, const SkewT<T, TR> &sk, const BLP_
 // forward b - W_i z_{i-1,j} - S_j z_{i,j-1}, transposed
 // b - W_{i+1} z_{i+1,j} - S_{j+1} z_{i,j+1}; the sweep then solves the
 // triangular system with this right-hand side, which is one Gauss-Seidel
-// sweep.  FP64 arithmetic (the terms largely cancel); padding slots get 0.
+// sweep.  FP64 arithmetic (the terms largely cancel).  Loads as in
+// level_apply.
 template <typename T, bool TR>
-BLP_DEV void gs_rhs_node(const MgLevelG<T> &L, const SkewT<T, TR> &sk, int i, int j, size_t q) {
+BLP_DEV double gs_rhs_value(const MgLevelG<T> &L, const SkewT<T, TR> &sk, int i, int j, size_t q) {
   const GridG<T> &g = L.g;
   const int n = g.nx;
   const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
+  const bool hx = id >= 1 && id <= n, hy = jd >= 1 && jd <= g.ny;
+  const double zx = L.z[sk.at(hx ? id : i, j)], zy = L.z[sk.at(i, hy ? jd : j)];
+  const double cx = TR ? g.W[i + 1] : g.W[i], cy = TR ? g.S[j + 1] : g.S[j];
+  // an absent neighbour enters with weight zero (v - 0 z = v exactly); a
+  // select between v and v - c z would be compiled into a branch holding
+  // the loads
   double v = L.b[q];
-  if (id >= 1 && id <= n) v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)L.z[sk.at(id, j)];
-  if (jd >= 1 && jd <= g.ny) v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)L.z[sk.at(i, jd)];
-  L.t[q] = T(v);
+  v -= (hx ? cx : 0.0) * zx;
+  v -= (hy ? cy : 0.0) * zy;
+  return v;
 }
-template <typename T, bool TR>
-BLP_DEV void gs_rhs_slot(const MgLevelG<T> &L, size_t q) {
-  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
-  int i, j;
-  if (!sk.decode(q, i, j)) {
-    L.t[q] = T(0);
-    return;
-  }
-  gs_rhs_node<T, TR>(L, sk, i, j, q);
-}
+
+// The level kernels below take one skewed slot per thread; a padding slot
+// evaluates node (1, 1), whose reads are in range, and discards the value.
+// The system's gate is read together with the data and tested before the
+// stores.
 template <typename T, bool TR>
 __global__ void k_gs_rhs(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
+  const int gate = gptr(a.ctrl)->gate;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < a.L.nslot) gs_rhs_slot<T, TR>(lview(a.L), q);
+  if (q >= a.L.nslot) return;
+  const MgLevelG<T> L = lview(a.L);
+  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
+  int i = 1, j = 1;
+  const bool node = sk.decode(q, i, j);
+  if (!node) i = j = 1;
+  const double v = gs_rhs_value<T, TR>(L, sk, i, j, q);
+  BLP_ISSUED();
+  if (gate) return;
+  L.t[q] = node ? T(v) : T(0);
 }
 
 // t = b - A z (forward) or b - A^T z (transposed) on a level.
 template <typename T, bool TR>
-BLP_DEV void resid_node(const MgLevelG<T> &L, const SkewT<T, TR> &sk, int i, int j, size_t q) {
-  L.t[q] = T((double)L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j));
-}
-template <typename T, bool TR>
-BLP_DEV void resid_slot(const MgLevelG<T> &L, size_t q) {
-  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
-  int i, j;
-  if (!sk.decode(q, i, j)) return;
-  resid_node<T, TR>(L, sk, i, j, q);
-}
-template <typename T, bool TR>
 __global__ void k_mg_resid(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
+  const int gate = gptr(a.ctrl)->gate;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < a.L.nslot) resid_slot<T, TR>(lview(a.L), q);
-}
-
-// One-dimensional transfer weight from fine node i to coarse node k
-// (i in {2k-1, 2k, 2k+1}).
-template <typename T>
-BLP_DEV T w1d(const BLP_GLOBAL T *wl, const BLP_GLOBAL T *wr, int i, int k) {
-  if (i == 2 * k) return T(1);
-  if (i == 2 * k - 1) return wr[i];
-  return wl[i];  // i == 2k+1
+  if (q >= a.L.nslot) return;
+  const MgLevelG<T> L = lview(a.L);
+  const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
+  int i = 1, j = 1;
+  const bool node = sk.decode(q, i, j);
+  if (!node) i = j = 1;
+  const double r = (double)L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j);
+  BLP_ISSUED();
+  if (gate || !node) return;
+  L.t[q] = T(r);
 }
 
 // Coarse right-hand side: forward b_c = S_c^{-1} P^T S_f t_f (FE rescaling,
-// Sec. 3.2), transposed b_c = P^T t_f.  Gathers the 3x3 fine neighbourhood.
+// Sec. 3.2), transposed b_c = P^T t_f.  Gathers the 3x3 fine neighbourhood
+// 2k-1 .. 2k+1 by 2m-1 .. 2m+1; a fine node past the level's edge is read
+// at 2k (2m), which always exists, and left out of the sum.
 template <typename T, bool TR>
-BLP_DEV void restrict_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skf,
-                           int k, int m, size_t q) {
+BLP_DEV T restrict_value(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skf, int k,
+                         int m) {
   const int nf = F.g.nx;
   T s = T(0);
-  for (int jj = 2 * m - 1; jj <= 2 * m + 1; ++jj) {
-    if (jj < 1 || jj > nf) continue;
-    const T wy = w1d(F.wly, F.wry, jj, m);
-    for (int ii = 2 * k - 1; ii <= 2 * k + 1; ++ii) {
-      if (ii < 1 || ii > nf) continue;
-      T v = F.t[skf.at(ii, jj)] * w1d(F.wlx, F.wrx, ii, k) * wy;
-      if (!TR) v *= F.hbx[ii] * F.hby[jj];
-      s += v;
+#pragma unroll
+  for (int dj = -1; dj <= 1; ++dj) {
+    const int jj = 2 * m + dj;
+    const bool iny = jj >= 1 && jj <= nf;
+    const int jc = iny ? jj : 2 * m;
+    const T wy = dj == 0 ? T(1) : (dj < 0 ? F.wry[jc] : F.wly[jc]);
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+      const int ii = 2 * k + di;
+      const bool inx = ii >= 1 && ii <= nf;
+      const int ic = inx ? ii : 2 * k;
+      const T wx = di == 0 ? T(1) : (di < 0 ? F.wrx[ic] : F.wlx[ic]);
+      T v = F.t[skf.at(ic, jc)] * wx * wy;
+      if (!TR) v *= F.hbx[ic] * F.hby[jc];
+      s = (inx && iny) ? s + v : s;
     }
   }
   if (!TR) s /= Cc.hbx[k] * Cc.hby[m];
-  Cc.b[q] = s;
-}
-template <typename T, bool TR>
-BLP_DEV void restrict_slot(const MgLevelG<T> &F, const MgLevelG<T> &Cc, size_t q) {
-  const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
-  int k, m;
-  if (!skc.decode(q, k, m)) return;
-  restrict_node<T, TR>(F, Cc, skf, k, m, q);
+  return s;
 }
 template <typename T, bool TR>
 __global__ void k_mg_restrict(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
+  const int gate = gptr(a.ctrl)->gate;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < a.Cc.nslot) restrict_slot<T, TR>(lview(a.L), lview(a.Cc), q);
+  if (q >= a.Cc.nslot) return;
+  const MgLevelG<T> F = lview(a.L), Cc = lview(a.Cc);
+  const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
+  int k = 1, m = 1;
+  const bool node = skc.decode(q, k, m);
+  if (!node) k = m = 1;
+  const T v = restrict_value<T, TR>(F, Cc, skf, k, m);
+  BLP_ISSUED();
+  if (gate || !node) return;
+  Cc.b[q] = v;
 }
 
-// Coarse-grid correction: forward z_f += P z_c; transposed
-// z_f += S_f P S_c^{-1} z_c.
+// Coarse-grid correction at fine node (i, j): forward z_f + P z_c;
+// transposed z_f + S_f P S_c^{-1} z_c.  Per axis a fine node has one coarse
+// neighbour (even index, weight 1, or the first node) or two (odd index,
+// weights wl and wr); an absent second neighbour is read at coarse node 1
+// and left out.
 template <typename T, bool TR>
-BLP_DEV T prolong_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skc,
-                       int i, int j, size_t q) {
-  // up to two coarse neighbours per axis: (k0, w0) and, if two, (k1, w1)
+BLP_DEV T prolong_value(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skc, int i,
+                        int j, size_t q) {
   auto axis = [](int x, const BLP_GLOBAL T *wl, const BLP_GLOBAL T *wr, int &k0, T &w0, int &k1, T &w1) {
-    if (x % 2 == 0) { k0 = x / 2; w0 = T(1); return false; }
-    if ((x - 1) / 2 >= 1) {
-      k0 = (x - 1) / 2; w0 = wl[x];
-      k1 = (x + 1) / 2; w1 = wr[x];
-      return true;
-    }
-    k0 = (x + 1) / 2; w0 = wr[x];
-    return false;
+    const T l = wl[x], r = wr[x];
+    const bool even = x % 2 == 0, two = !even && (x - 1) / 2 >= 1;
+    k0 = even ? x / 2 : (two ? (x - 1) / 2 : (x + 1) / 2);
+    w0 = even ? T(1) : (two ? l : r);
+    k1 = two ? (x + 1) / 2 : 1;
+    w1 = two ? r : T(0);
+    return two;
   };
-  int kx0, kx1 = 1, ky0, ky1 = 1;
-  T wx0, wx1 = T(0), wy0, wy1 = T(0);
+  int kx0, kx1, ky0, ky1;
+  T wx0, wx1, wy0, wy1;
   const bool tx = axis(i, F.wlx, F.wrx, kx0, wx0, kx1, wx1);
   const bool ty = axis(j, F.wly, F.wry, ky0, wy0, ky1, wy1);
   T s = T(0);
-  auto term = [&](int kx, T wxv, int ky, T wyv) {
+  auto term = [&](int kx, T wxv, int ky, T wyv, bool on) {
     T v = Cc.z[skc.at(kx, ky)];
     if (TR) v /= Cc.hbx[kx] * Cc.hby[ky];
-    s += wxv * wyv * v;
+    s += (on ? wxv * wyv : T(0)) * v;  // weight zero: s unchanged
   };
-  term(kx0, wx0, ky0, wy0);
-  if (tx) term(kx1, wx1, ky0, wy0);
-  if (ty) {
-    term(kx0, wx0, ky1, wy1);
-    if (tx) term(kx1, wx1, ky1, wy1);
-  }
+  term(kx0, wx0, ky0, wy0, true);
+  term(kx1, wx1, ky0, wy0, tx);
+  term(kx0, wx0, ky1, wy1, ty);
+  term(kx1, wx1, ky1, wy1, tx && ty);
   if (TR) s *= F.hbx[i] * F.hby[j];
   return F.z[q] + s;
 }
-template <typename T, bool TR>
-BLP_DEV void prolong_slot(const MgLevelG<T> &F, const MgLevelG<T> &Cc, size_t q) {
-  const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
-  int i, j;
-  if (!skf.decode(q, i, j)) return;
-  F.z[q] = prolong_node<T, TR>(F, Cc, skc, i, j, q);
-}
-template <typename T, bool TR>
-__global__ void k_mg_prolong(const MgArgs<T> *A) {
-  const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < a.L.nslot) prolong_slot<T, TR>(lview(a.L), lview(a.Cc), q);
-}
 
 // Coarse-grid correction and Gauss-Seidel right-hand side in one pass: the
-// right-hand side of gs_rhs_node for the corrected iterate z + P z_c (as
-// prolong_node, rounded to the storage type), which enters only through the
-// two downstream neighbours.  The corrected iterate is not stored: the
+// right-hand side of gs_rhs_value for the corrected iterate z + P z_c (as
+// prolong_value, rounded to the storage type), which enters only through
+// the two downstream neighbours.  The corrected iterate is not stored: the
 // post-smoothing sweep that follows recomputes every node of z from this
 // right-hand side alone.
 template <typename T, bool TR>
-BLP_DEV T prolong_gs_node(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skf,
-                          const SkewT<T, TR> &skc, int i, int j, size_t q) {
+BLP_DEV T prolong_gs_value(const MgLevelG<T> &F, const MgLevelG<T> &Cc, const SkewT<T, TR> &skf,
+                           const SkewT<T, TR> &skc, int i, int j, size_t q) {
   const GridG<T> &g = F.g;
   const int n = g.nx;
   const int id = TR ? i + 1 : i - 1, jd = TR ? j + 1 : j - 1;
+  const bool hx = id >= 1 && id <= n, hy = jd >= 1 && jd <= g.ny;
+  const int ic = hx ? id : i, jc = hy ? jd : j;
+  const double cx = TR ? g.W[i + 1] : g.W[i], cy = TR ? g.S[j + 1] : g.S[j];
+  const double px = prolong_value<T, TR>(F, Cc, skc, ic, j, skf.at(ic, j));
+  const double py = prolong_value<T, TR>(F, Cc, skc, i, jc, skf.at(i, jc));
   double v = F.b[q];
-  if (id >= 1 && id <= n)
-    v -= (double)(TR ? g.W[i + 1] : g.W[i]) * (double)prolong_node<T, TR>(F, Cc, skc, id, j, skf.at(id, j));
-  if (jd >= 1 && jd <= g.ny)
-    v -= (double)(TR ? g.S[j + 1] : g.S[j]) * (double)prolong_node<T, TR>(F, Cc, skc, i, jd, skf.at(i, jd));
+  v -= (hx ? cx : 0.0) * px;  // weight zero: v unchanged
+  v -= (hy ? cy : 0.0) * py;
   return T(v);
 }
 template <typename T, bool TR>
 __global__ void k_mg_prolong_gs(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
-  if (a.ctrl->gate) return;
+  const int gate = gptr(a.ctrl)->gate;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= a.L.nslot) return;
   const MgLevelG<T> F = lview(a.L), Cc = lview(a.Cc);
   const SkewT<T, TR> skf = level_skew<T, TR>(F.g.nx), skc = level_skew<T, TR>(Cc.g.nx);
-  int i, j;
-  F.t[q] = skf.decode(q, i, j) ? prolong_gs_node<T, TR>(F, Cc, skf, skc, i, j, q) : T(0);
+  int i = 1, j = 1;
+  const bool node = skf.decode(q, i, j);
+  if (!node) i = j = 1;
+  const T v = prolong_gs_value<T, TR>(F, Cc, skf, skc, i, j, q);
+  BLP_ISSUED();
+  if (gate) return;
+  F.t[q] = node ? v : T(0);
 }
 
 // Coarsest level: four downstream Gauss-Seidel sweeps (transposed: the
@@ -1582,7 +1641,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
       sweep(F, F.b);
     }
     nodes(F, F.t, [&](int i, int j) { return T((double)F.b[F.at(i, j)] - lds_apply<T, TR>(F, i, j)); });
-    // coarse right-hand side (as restrict_node)
+    // coarse right-hand side (as restrict_value)
     const int nf = F.n;
     nodes(Cc, Cc.b, [&](int k, int m) {
       T s2 = T(0);
@@ -1633,7 +1692,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_mg_coarse(const CoarseArgs<T
   __syncthreads();
   for (int l = nl - 2; l >= 0; --l) {
     const LdsLevel<T> F = lev(l), Cc = lev(l + 1);
-    // coarse-grid correction (as prolong_node)
+    // coarse-grid correction (as prolong_value)
     nodes(F, F.z, [&](int i, int j) {
       // up to two coarse neighbours per axis: (k0, w0) and, if two, (k1, w1)
       auto axis = [](int x, const T *wl, const T *wr, int &k0, T &w0, int &k1, T &w1) {
@@ -1694,26 +1753,42 @@ inline size_t coarse_lds_bytes(int n0, int nl, bool nodal) {
 // cycle works on -- forward ||S (b - A z)||, transposed ||b - A^T z|| -- with
 // mode 0 measuring ||S b|| (resp. ||b||) before the first cycle.  The last
 // block of each system compares against rtol and sets its gate.
-template <typename T, bool TR>
-__global__ __launch_bounds__(256) void k_mg_norm(const MgArgs<T> *A, int mode) {
+template <typename T, bool TR, int mode>
+__global__ __launch_bounds__(256) void k_mg_norm(const MgArgs<T> *A) {
   __shared__ double sh[16];
   __shared__ bool last;
   const MgArgs<T> a = A[blockIdx.y];
   MgCtrl *ctrl = a.ctrl;
-  if (ctrl->gate) return;  // uniform across the system's blocks
+  const int gate = gptr(ctrl)->gate;  // uniform across the system's blocks
   const MgLevelG<T> L = lview(a.L);
   const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
   const size_t nslot = a.L.nslot;
+  // grid-stride loop, NU slots per round with their loads issued together;
+  // padding slots and slots past the end evaluate node (1, 1) and add
+  // nothing, so each thread sums its slots in increasing q
+  constexpr int NU = 4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
   double acc = 0.0;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nslot;
-       q += (size_t)gridDim.x * blockDim.x) {
-    int i, j;
-    if (!sk.decode(q, i, j)) continue;
-    double v = (double)L.b[q];
-    if (mode == 1) v -= level_apply<T, TR>(L.g, sk, L.z, i, j);
-    if (!TR) v *= (double)L.hbx[i] * (double)L.hby[j];
-    acc += v * v;
+  for (size_t q0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < nslot; q0 += NU * stride) {
+    double vs[NU];
+    bool on[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const size_t q = q0 + u * stride, qc = q < nslot ? q : nslot - 1;
+      int i = 1, j = 1;
+      const bool node = sk.decode(qc, i, j);
+      if (!node) i = j = 1;
+      on[u] = node & (q < nslot);
+      double v = (double)L.b[qc];
+      if (mode == 1) v -= level_apply<T, TR>(L.g, sk, L.z, i, j);
+      if (!TR) v *= (double)L.hbx[i] * (double)L.hby[j];
+      vs[u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < NU; ++u) acc = on[u] ? acc + vs[u] * vs[u] : acc;
   }
+  BLP_ISSUED();
+  if (gate) return;
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
   if (!arrive_last(&ctrl->counter, &last, gridDim.x)) return;
