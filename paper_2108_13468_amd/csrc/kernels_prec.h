@@ -316,7 +316,7 @@ BLP_DEV T chan_value(const ChanWord<T> &c) {
 // lowest block numbers), so a reader's writer has always started.
 template <typename T, bool TR, int K, int D, int G>
 BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int tid, int nthreads,
-                        int gi) {
+                        int gi, int gate) {
   constexpr int P = kChunk<T>, CK = K / P, RING = kRing, NW = sizeof(T) / 4;
   static_assert(K % P == 0 && 64 % K == 0 && 2 * K + P <= 64 && CK <= kSkewGroup, "superstep length");
   typedef typename Vec16<T>::type V;
@@ -337,22 +337,25 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int t
   // upstream x coupling, read through a global (not generic) pointer before
   // the barrier below: a generic load still in flight at the first use inside
   // the step loop would make every iteration wait for all loads in flight
+  // (every load of this prologue is unconditional, at an in-range index:
+  // a load under a condition is waited for before the branch joins)
   const BLP_GLOBAL T *gE = gptr(g.E), *gN = gptr(g.N);
-  const T cu = colok ? (TR ? gE[i - 1] : gE[i]) : T(0);
+  const T cuv = TR ? gE[i - 1] : gE[i];
+  const T cu = colok ? cuv : T(0);
   // row-coupling table: copy q (q < P) holds at word w the upstream y
-  // coupling of row w + q - 64 (zero outside rows 0 .. mr - 1).  One load
-  // per row, four in flight per thread, each value stored into every copy.
+  // coupling of row w + q - 64 (zero outside rows 0 .. mr - 1; those read
+  // row 0).  One load per row, four in flight per thread, each value stored
+  // into every copy.
   const int ys = yc_stride<T, K>(mr);
   for (int x0 = tid; x0 < ys + P - 1; x0 += 4 * nthreads) {
     T v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int t = x0 + u * nthreads - 64;
-      v[u] = T(0);
-      if (t >= 0 && t < mr) {
-        const int j = sk.jrow(t);
-        v[u] = TR ? gN[j - 1] : gN[j];
-      }
+      const bool in = t >= 0 && t < mr;
+      const int j = sk.jrow(in ? t : 0);
+      const T val = TR ? gN[j - 1] : gN[j];
+      v[u] = in ? val : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -366,6 +369,9 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int t
   }
   for (int q = tid; q < (nw + 1) * RING; q += nthreads) ring[q] = T(0);
   for (int q = tid; q < nw; q += nthreads) prog[q] = 0;
+  // the gate (the same in every thread) was read with the loads above
+  BLP_ISSUED();
+  if (gate) return;
   __syncthreads();
 
   // the rectangle's last band holds mcl columns, so its last node is at
@@ -398,14 +404,16 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int t
   unsigned long long *chw = nullptr, *chr = nullptr;
   unsigned int tagw = 0, tagr = 0;
   if (G > 1) {
+    // both counters are read in every wave (at boundaries that exist)
     const BLP_GLOBAL int *ep = gptr(a.epoch);
+    const int ew = ep[2 * min(gi, G - 2)], er = ep[2 * max(gi - 1, 0) + 1];
     if (writer) {
       chw = a.chan + (size_t)gi * kChanStride<T>;
-      tagw = (unsigned int)ep[2 * gi] + 1u;
+      tagw = (unsigned int)ew + 1u;
     }
     if (reader) {
       chr = a.chan + (size_t)(gi - 1) * kChanStride<T>;
-      tagr = (unsigned int)ep[2 * (gi - 1) + 1] + 1u;
+      tagr = (unsigned int)er + 1u;
     }
   }
 
@@ -588,11 +596,11 @@ template <typename T, bool TR, int K, int D, int G>
 __global__ __launch_bounds__(D > 1 ? 512 : 1024) void k_sweep(const SweepArgs<T> *A) {
   const int S = gridDim.x / G, gi = blockIdx.x / S;
   const SweepArgs<T> a = A[blockIdx.x - gi * S];
-  if (gated(a.gate)) return;
+  const int gate = read_or_zero(a.gate);  // tested once the first loads are issued
   __shared__ __align__(16) T ring[(kSweepMaxBands + 1) * kRing];
   __shared__ __align__(16) T ycs[kChunk<T> * yc_stride<T, K>(kSweepMaxRows)];
   __shared__ int prog[kSweepMaxBands];
-  sweep_body<T, TR, K, D, G>(a, ring, ycs, prog, threadIdx.x, blockDim.x, gi);
+  sweep_body<T, TR, K, D, G>(a, ring, ycs, prog, threadIdx.x, blockDim.x, gi, gate);
 }
 
 // Natural <-> skewed copies of a rectangle of the fine grid (batched over
