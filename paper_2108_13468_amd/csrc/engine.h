@@ -424,17 +424,17 @@ void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A, int var = 0
 template <typename T, bool TR>
 void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   const int S = P.S, m = P.n1 - P.h;
-  const dim3 gg(blocks1d(P.nslotI), S);
+  const dim3 gg((skew_steps<T>(m) + kSkewTS - 1) / kSkewTS, (m + 63) / 64, S);
   {
     KScope ks(c, KC_LAYOUT, 0.0);
-    k_gather_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
+    k_gather_skew<T, TR><<<gg, kSkewThreads, 0, c.stream>>>(P.ioI, jp);
   }
   {
     KScope ks(c, KC_SWEEP, (double)S * m * m * 3 * sizeof(T));
     sweep_launch<T, TR>(c, S, m, P.swI, P.varI);
   }
   KScope ks(c, KC_LAYOUT, 0.0);
-  k_scatter_skew<T, TR><<<gg, 256, 0, c.stream>>>(P.ioI, jp);
+  k_scatter_skew<T, TR><<<gg, kSkewThreads, 0, c.stream>>>(P.ioI, jp);
 }
 
 template <typename T, bool TR>

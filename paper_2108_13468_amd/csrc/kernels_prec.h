@@ -626,40 +626,136 @@ struct SkewIO {
   size_t nslot;
   const int *gate;
 };
-template <typename T, bool TR>
-__global__ void k_gather_skew(const SkewIO<T, TR> *A, const int *jp) {
-  const SkewIO<T, TR> a = A[blockIdx.y];
-  if (gated(a.gate)) return;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.nslot) return;
-  const Grid<T> &g = a.g;
-  const int ld = g.nx;
-  const T *v = a.v + step_of(jp) * a.ldv;
-  const T *zb = a.z + step_of(jp) * a.ldz;
-  int i, j;
-  T val = T(0);
-  if (a.sk.decode(q, i, j)) {
-    const size_t o = vidx(i, j, ld);
-    val = v[o];
-    if (a.dh) val *= a.dh[o];
-    if (!TR) {
-      if (i == a.sk.i1 && i < g.nx) val -= g.E[i] * zb[vidx(i + 1, j, ld)];
-      if (j == a.sk.j1 && j < g.ny) val -= g.N[j] * zb[vidx(i, j + 1, ld)];
-    } else {
-      if (i == a.sk.i0 && i > 1) val -= g.E[i - 1] * zb[vidx(i - 1, j, ld)];
-      if (j == a.sk.j0 && j > 1) val -= g.N[j - 1] * zb[vidx(i, j - 1, ld)];
-    }
-  }
-  a.bbuf[q] = val;
+// A block moves the slots of kSkewTS steps of one band (blockIdx.x: step
+// tile, blockIdx.y: band, blockIdx.z: system), which are contiguous in the
+// skewed layout.  Their nodes (c, s - lane) lie on mesh rows s0 - 63 ..
+// s0 + kSkewTS - 1; "virtual row" r pairs row s0 - 64 + r (lanes l >= 64 - r)
+// with row s0 + r (lanes l < 64 - r), so that every lane has a node and each
+// half is a contiguous piece of a mesh row; lane l of virtual row r holds step
+// s0 + (r + l) mod 64.  The tile passes through LDS between the two layouts.
+constexpr int kSkewTS = 64, kSkewThreads = 256, kSkewUnroll = 8;
+template <typename T>
+inline int skew_steps(int mr) {  // steps (slots per lane) of a band
+  constexpr int P = kChunk<T>;
+  return ((mr + 62) / (kSkewGroup * P) + 2) * kSkewGroup * P;
 }
 template <typename T, bool TR>
-__global__ void k_scatter_skew(const SkewIO<T, TR> *A, const int *jp) {
-  const SkewIO<T, TR> a = A[blockIdx.y];
-  if (gated(a.gate)) return;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.nslot) return;
-  int i, j;
-  if (a.sk.decode(q, i, j)) (a.z + step_of(jp) * a.ldz)[vidx(i, j, a.g.nx)] = a.zbuf[q];
+__global__ __launch_bounds__(kSkewThreads) void k_gather_skew(const SkewIO<T, TR> *A, const int *jp) {
+  __shared__ T tile[kSkewTS][65];
+  constexpr int P = kChunk<T>, NW = kSkewThreads / 64, RW = kSkewTS / NW;
+  const SkewIO<T, TR> a = A[blockIdx.z];  // a copy: read before the barrier
+  const int gate = read_or_zero(a.gate);
+  const SkewT<T, TR> sk = a.sk;
+  const int mc = sk.mc(), mr = sk.mr(), ns = sk.nck() * P;
+  const int band = blockIdx.y, s0 = blockIdx.x * kSkewTS;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const Grid<T> &g = a.g;
+  const int ld = g.nx;
+  const BLP_GLOBAL T *v = gptr(a.v + step_of(jp) * a.ldv);
+  const BLP_GLOBAL T *zb = gptr(a.z + step_of(jp) * a.ldz);
+  // scaling factors (absent: read v again and leave the value as it is)
+  const bool scaled = a.dh != nullptr;
+  const BLP_GLOBAL T *dh = gptr(scaled ? a.dh : a.v + step_of(jp) * a.ldv);
+  const int c = band * 64 + lane;
+  const int i = sk.icol(c < mc ? c : mc - 1);
+  // wave w takes virtual rows w, w + NW, ..; kSkewUnroll of them per round,
+  // loads first (node reads at clamped in-range positions)
+  const BLP_GLOBAL T *gE = gptr(g.E), *gN = gptr(g.N);
+#pragma unroll
+  for (int r0 = 0; r0 < RW; r0 += kSkewUnroll) {
+    T xs[kSkewUnroll], ys[kSkewUnroll];
+#pragma unroll
+    for (int u = 0; u < kSkewUnroll; ++u) {
+      const int r = w + (r0 + u) * NW;
+      const int t = lane >= 64 - r ? s0 - 64 + r : s0 + r;
+      const size_t o = vidx(i, sk.jrow(t < 0 ? 0 : (t < mr ? t : mr - 1)), ld);
+      xs[u] = v[o];
+      ys[u] = dh[o];
+    }
+    // the loads above are issued before any value is selected (a select
+    // could otherwise become a branch that holds them)
+    BLP_ISSUED();
+#pragma unroll
+    for (int u = 0; u < kSkewUnroll; ++u) {
+      const int r = w + (r0 + u) * NW;
+      const int t = lane >= 64 - r ? s0 - 64 + r : s0 + r;
+      const bool in = c < mc && t >= 0 && t < mr;
+      T val = in ? (scaled ? xs[u] * ys[u] : xs[u]) : T(0);
+      // couplings to the solved values past the rectangle's upstream sides
+      // (edge nodes only)
+      if (in) {
+        const int j = sk.jrow(t);
+        if (!TR) {
+          if (i == sk.i1 && i < g.nx) val -= gE[i] * zb[vidx(i + 1, j, ld)];
+          if (j == sk.j1 && j < g.ny) val -= gN[j] * zb[vidx(i, j + 1, ld)];
+        } else {
+          if (i == sk.i0 && i > 1) val -= gE[i - 1] * zb[vidx(i - 1, j, ld)];
+          if (j == sk.j0 && j > 1) val -= gN[j - 1] * zb[vidx(i, j - 1, ld)];
+        }
+      }
+      tile[(r + lane) & 63][lane] = val;
+    }
+  }
+  BLP_ISSUED();
+  if (gate) return;
+  __syncthreads();
+  // the tile's slots: o = (chunk * 64 + lane) * P + e holds step s0 + chunk P + e
+  BLP_GLOBAL T *out = gptr(a.bbuf + sk.slot(band, s0, 0));
+  const int no = min(kSkewTS, ns - s0) * 64;
+  for (int o = tid; o < no; o += kSkewThreads) out[o] = tile[(o / (64 * P)) * P + o % P][(o / P) & 63];
+}
+template <typename T, bool TR>
+__global__ __launch_bounds__(kSkewThreads) void k_scatter_skew(const SkewIO<T, TR> *A, const int *jp) {
+  __shared__ T tile[kSkewTS][65];
+  constexpr int P = kChunk<T>, NW = kSkewThreads / 64, RW = kSkewTS / NW;
+  const SkewIO<T, TR> a = A[blockIdx.z];  // a copy: read before the barrier
+  const int gate = read_or_zero(a.gate);
+  const SkewT<T, TR> sk = a.sk;
+  const int mc = sk.mc(), mr = sk.mr(), ns = sk.nck() * P;
+  const int band = blockIdx.y, s0 = blockIdx.x * kSkewTS;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const BLP_GLOBAL T *in = gptr(a.zbuf + sk.slot(band, s0, 0));
+  const int no = min(kSkewTS, ns - s0) * 64;
+  constexpr int NO = kSkewTS * 64 / kSkewThreads;
+  T x[NO];
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const int o = tid + k * kSkewThreads;
+    x[k] = in[o < no ? o : no - 1];
+  }
+  BLP_ISSUED();
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    const int o = tid + k * kSkewThreads;
+    if (o < no) tile[(o / (64 * P)) * P + o % P][(o / P) & 63] = x[k];
+  }
+  if (gate) return;
+  __syncthreads();
+  BLP_GLOBAL T *z = gptr(a.z + step_of(jp) * a.ldz);
+  BLP_GLOBAL T *zs = gptr(const_cast<T *>(a.zbuf) + sk.slot(band, s0, 0));
+  const int ld = a.g.nx;
+  const int c = band * 64 + lane;
+  const int i = sk.icol(c < mc ? c : mc - 1);
+  // every lane stores (all addresses first, so that no store waits for the
+  // one before it to release its address registers): a node goes to z; a
+  // padding slot is written back unchanged to its own place in the skewed
+  // buffer, and a lane whose step lies past the band's last slot (s >= ns,
+  // no slot: last tile of a band) writes the tile's first slot back
+  // unchanged.  Each block owns its tile's slots and has read them above.
+  T val[RW];
+  BLP_GLOBAL T *dst[RW];
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    const int r = w + k * NW, sl = (r + lane) & 63;
+    const int t = lane >= 64 - r ? s0 - 64 + r : s0 + r;
+    const bool node = c < mc && t >= 0 && t < mr;  // implies s0 + sl < ns
+    const bool slot = s0 + sl < ns;
+    val[k] = slot ? tile[sl][lane] : tile[0][0];
+    dst[k] = node ? z + vidx(i, sk.jrow(node ? t : 0), ld)
+                  : zs + (slot ? ((sl / P) * 64 + lane) * P + sl % P : 0);
+  }
+#pragma unroll
+  for (int k = 0; k < RW; ++k) *dst[k] = val[k];
 }
 
 // 1/C_ij in the skewed layout of a rectangle (setup).
