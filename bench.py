@@ -281,6 +281,10 @@ def batch(args):
                                   for N in (128, 256, 512, 1024)}},
            "converged": sum(d["converged"] for d in info),
            "iterations": {"min": min(it), "max": max(it), "mean": round(float(np.mean(it)), 2)},
+           # the instances with the most iterations set the batch's sequential chain
+           "hardest": [{"N": insts[k].N, "eps": float("%.3g" % insts[k].eps), "iterations": it[k],
+                        "corner_cycles": [info[k]["mg_cycles_min"], info[k]["mg_cycles_max"]]}
+                       for k in sorted(range(len(it)), key=lambda k: -it[k])[:3]],
            "setup_s": round(setup_s, 3), "footprint_bytes": b.footprint(),
            "roofline": roofline_of(kt), "kernels_per_solve": kernels_of(kt, 1),
            "tuning": b.describe()}

@@ -1129,7 +1129,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       }
       BLP_TRY(join(B));
       BLP_TRY(read_all(B));
-      bool any = false;
+      bool any = false, left = false;
       for (int s = 0; s < S; ++s) {
         if (!incyc[s]) continue;
         ++it[s];
@@ -1139,11 +1139,15 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
         if (hist && hist[s] && !std::is_same<TV, float>::value) hist[s][it[s]] = est;
         if (!std::isfinite(est)) return BLP_E_NUMERIC;
         const bool happy = B.st_h[s].happy != 0;
-        if (est <= cyc_target[s] || happy || j + 1 >= m || it[s] >= o->maxit) incyc[s] = 0;
+        if (est <= cyc_target[s] || happy || j + 1 >= m || it[s] >= o->maxit) {
+          incyc[s] = 0;
+          left = true;
+        }
         any = any || incyc[s];
       }
       if (!any) break;
-      BLP_TRY(set_gates(incyc));
+      // the device gates still equal incyc unless a system left the cycle
+      if (left) BLP_TRY(set_gates(incyc));
       BLP_TRY(fork(B));
       for (int k = 0; k < NC; ++k) {
         if (!live(k, incyc)) continue;
