@@ -150,6 +150,32 @@ def headline(args):
                 "kernel": KERNEL_NAMES.get(dom, dom) + " (mixed solve)",
                 "avg_launch_us": round(avg_us, 3), "launches": nl,
                 "bytes_per_launch": round(by / max(nl, 1), 1)}
+    # Second bound of the single-right-hand-side sweeps: their dependency
+    # chain.  A sweep of an n x n rectangle is 2n - 1 anti-diagonals, each a
+    # dependent step.  Per preconditioner apply of the mixed solve: the
+    # interior (m = N - 1 - N/2) once, and the corner levels above the
+    # LDS-resident cycle (N/2, N/4, .. while above 64 nodes and even) twice
+    # per corner cycle.
+    latency = None
+    if dom == "sweep":
+        applies = i32["iterations"]
+        cycles = 0.5 * (i32["mg_cycles_min"] + i32["mg_cycles_max"])
+        m = args.N - 1 - args.N // 2
+        lv, n = [], args.N // 2
+        while n > 64 and n % 2 == 0:
+            lv.append(n)
+            n //= 2
+        per_apply = [(2 * m - 1, 1.0)] + [(2 * q - 1, 2.0 * cycles) for q in lv]
+        launches = applies * sum(c for _, c in per_apply)
+        steps = applies * sum(st * c for st, c in per_apply)
+        per_launch = steps / launches
+        latency = {"kernel": roofline["kernel"],
+                   "chain": "2n - 1 dependent anti-diagonal steps per n x n sweep",
+                   "launches_modelled": round(launches, 1),
+                   "launches_measured": round(nl / args.steps, 1),  # per solve
+                   "dependent_steps_per_launch": round(per_launch, 1),
+                   "ns_per_step": round(1e3 * avg_us / per_launch, 2),
+                   "cycles_per_step_at_2.4GHz": round(2.4 * 1e3 * avg_us / per_launch, 1)}
     kernels = {prec: {k: {"ms": round(v[0] / args.steps, 3),
                           "launches": v[1] // args.steps,
                           "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else 0.0,
@@ -184,6 +210,7 @@ def headline(args):
         "rel_res": {"fp64": i64["res"] / i64["norm_F"], "mixed": i32["res"] / i32["norm_F"]},
         "footprint_bytes": gp.footprint(),
         "roofline": roofline,
+        "latency": latency,
         "kernels_per_step": kernels,
         "paper_context": {"seconds": 0.921, "iterations": 5,
                           "hardware": "one core of a 2.4 GHz Xeon, serial C",
