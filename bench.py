@@ -413,9 +413,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the solver's multi-GPU path is not part of this "
-              "build (instances and right-hand sides shard without communication); run with "
-              "--gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (instances and "
+              "right-hand sides shard without communication); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
