@@ -46,23 +46,52 @@ __global__ __launch_bounds__(256) void k_stencil(const SpmvArgs<TX> *A, const in
     const double cw = TR ? gE[i - 1] : gW[i];
     const double ce = TR ? gW[i + 1] : gE[i];
     const double dx = gptr(g.Dx)[i];
-    double xs = j0 > 1 ? (double)x[vidx(i, j0 - 1, n)] : 0.0;
+    // Neighbours outside the grid are read at the node itself and weighted
+    // by zero, and the nodal r (when absent: a table entry, unused) through
+    // a pointer chosen once: every load of a row is unconditional, so the
+    // rows' loads overlap instead of each waiting at a branch.  For finite
+    // x the weights change nothing; a non-finite x at the node already makes
+    // its own term non-finite.
+    const int iw = i > 1 ? i - 1 : i, ie = i < n ? i + 1 : i;
+    const double mw = i > 1 ? 1.0 : 0.0, me = i < n ? 1.0 : 0.0;
+    const bool nodal = gr != nullptr;
+    const BLP_GLOBAL double *rp = nodal ? gr : gDy;
+    const double mr = nodal ? 1.0 : 0.0, rc = nodal ? 0.0 : g.rc;
+    double xs = (j0 > 1 ? 1.0 : 0.0) * (double)x[vidx(i, j0 > 1 ? j0 - 1 : j0, n)];
     double xc = (double)x[vidx(i, j0, n)];
-    for (int j = j0; j <= j1; ++j) {
-      const double xn = j < g.ny ? (double)x[vidx(i, j + 1, n)] : 0.0;
-      const double xw = i > 1 ? (double)x[vidx(i - 1, j, n)] : 0.0;
-      const double xe = i < n ? (double)x[vidx(i + 1, j, n)] : 0.0;
-      const double cs = TR ? gN[j - 1] : gS[j];
-      const double cn = TR ? gS[j + 1] : gN[j];
-      const size_t q = vidx(i, j, n);
-      const double C = dx + gDy[j] + (gr ? gr[q] : g.rc);
-      double v = C * xc + cw * xw + ce * xe + cs * xs + cn * xn;
-      if (RESID) v = Fv[q] - v;
-      if (SCALE) v /= sqrt(C);
-      y[q] = v;
-      if (RESID) acc += v * v;
-      xs = xc;
-      xc = xn;
+    // rows in groups of four: the group's loads first (rows past j1 read
+    // row j1 and are not stored), then its arithmetic and stores
+    constexpr int RG = 4;
+    for (int jb = j0; jb <= j1; jb += RG) {
+      double xn[RG], xw[RG], xe[RG], cs[RG], cn[RG], dy[RG], rl[RG];
+      size_t qv[RG];
+#pragma unroll
+      for (int u = 0; u < RG; ++u) {
+        const int j = jb + u <= j1 ? jb + u : j1;
+        qv[u] = vidx(i, j, n);
+        xn[u] = (j < g.ny ? 1.0 : 0.0) * (double)x[vidx(i, j < g.ny ? j + 1 : j, n)];
+        xw[u] = mw * (double)x[vidx(iw, j, n)];
+        xe[u] = me * (double)x[vidx(ie, j, n)];
+        cs[u] = TR ? gN[j - 1] : gS[j];
+        cn[u] = TR ? gS[j + 1] : gN[j];
+        dy[u] = gDy[j];
+        rl[u] = rp[nodal ? qv[u] : (size_t)j];
+      }
+      double fv[RG];
+#pragma unroll
+      for (int u = 0; u < RG; ++u) fv[u] = RESID ? Fv[qv[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < RG; ++u) {
+        if (jb + u > j1) break;
+        const double C = dx + dy[u] + (mr * rl[u] + rc);  // r_ij or the constant r
+        double v = C * xc + cw * xw[u] + ce * xe[u] + cs[u] * xs + cn[u] * xn[u];
+        if (RESID) v = fv[u] - v;
+        if (SCALE) v /= sqrt(C);
+        y[qv[u]] = v;
+        if (RESID) acc += v * v;
+        xs = xc;
+        xc = xn[u];
+      }
     }
   }
   if (!RESID) return;
