@@ -8,15 +8,19 @@ apart.  The JSON line carries the per-kernel roofline of the dominant kernel
 (HIP events recorded by the library on its stream over the timed steps) and
 the CPU oracle timed on this host.
 
-Two further workloads print their own line when asked for (--workload):
-  batch      64 uneven instances solved together (mixed, 1e-8): solves/s;
-  multi_rhs  N = 2048, eps = 1e-6, 16 right-hand sides: mixed solves and the
-             adjoint solves of their gradients.
+The default run also measures, in the same JSON line:
+  batch       64 uneven instances solved together (mixed, 1e-8): solves/s;
+  multi_rhs   N = 2048, eps = 1e-6, 16 right-hand sides: mixed solves and the
+              adjoint solves of their gradients;
+  copy        the attainable HBM bandwidth of a plain 1 GiB device copy;
+each with its own roofline entry and CPU-oracle baseline.  --workload runs
+one of them alone (its own JSON line).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E] [--no-cpu]
-                       [--workload headline|batch|multi_rhs]
+                       [--workload all|headline|batch|multi_rhs|copy_probe]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,12 +41,14 @@ KERNEL_NAMES = {"sweep": "k_sweep<float, false, 16, *, *> (all sweeps: interior 
 # while the sweep source is the one it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_traffic.txt")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_2108_13468_amd", "csrc", "kernels_prec.h")
+# worker pool of the CPU baselines: the host's cores available to this
+# process, at most 16 (one GPU's share of a shared host)
+POOL_MAX = 16
 
 
 def measured_traffic():
     """Bytes per sweep launch from the committed counter summary, or None when
     it is missing or was taken on a different kernel source."""
-    import hashlib
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
@@ -57,6 +63,24 @@ def measured_traffic():
         return None
 
 
+def host_info():
+    """Cores this process may use (the pool size of the CPU baselines) and
+    the CPU model."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": avail, "pool": min(POOL_MAX, avail), "cpu_model": model}
+
+
 def copy_probe(args):
     """A plain device copy of known size (counter calibration for the
     traffic figure): 256 MiB read, 256 MiB written, three times."""
@@ -66,7 +90,74 @@ def copy_probe(args):
     for _ in range(3):
         y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes_read": x.numel() * 4, "copy_probe_bytes_written": y.numel() * 4}))
+    return {"copy_probe_bytes_read": x.numel() * 4, "copy_probe_bytes_written": y.numel() * 4}
+
+
+def copy_bandwidth():
+    """Attainable HBM bandwidth: a 1 GiB device-to-device copy (read plus
+    write bytes over the event time, median of 10)."""
+    import numpy as np
+    import torch
+    n = 1 << 28  # 1 GiB of float32
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    ts = []
+    for _ in range(10):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    gbs = 2.0 * n * 4 / (ms * 1e-3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_copied": n * 4, "ms": round(ms, 3), "GBps": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def roofline_of(kt, names=None, prefer=None, traffic=None):
+    """Roofline entry of the dominant kernel class (or `prefer`) of a timing
+    dictionary {class: (ms, launches, algorithmic bytes)}: algorithmic bytes
+    per launch over the average launch duration."""
+    dom = prefer or max(kt, key=lambda k: kt[k][0])
+    ms, nl, by = kt[dom]
+    avg_us = 1e3 * ms / max(nl, 1)
+    bpl = by / max(nl, 1)
+    achieved = bpl / (avg_us * 1e-6) / 1e9 if nl else 0.0
+    out = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+           "kernel": (names or {}).get(dom, dom), "avg_launch_us": round(avg_us, 3),
+           "launches": nl, "bytes_per_launch": round(bpl, 1)}
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / bpl, 3)
+    return out
+
+
+def kernels_of(kt, steps):
+    return {k: {"ms": round(v[0] / steps, 3), "launches": v[1] // steps,
+                "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else 0.0,
+                "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 2) if v[0] > 0 else 0.0}
+            for k, v in kt.items()}
+
+
+def pool_map(fn, items, cores):
+    """fn over items with `cores` threads (the oracle's C calls release the
+    interpreter lock); returns (results, wall seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=max(1, min(cores, len(items)))) as ex:
+        res = list(ex.map(fn, items))
+    return res, time.perf_counter() - t0
+
+
+def unscaled_rel_res(gp, F, U):
+    """||F - A U||_2 / ||F||_2 with the library's FP64 operator."""
+    import torch
+    r = F - gp.apply("A", U)
+    return float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(F))
 
 
 def headline(args):
@@ -88,13 +179,9 @@ def headline(args):
     F = gp.sine_rhs(inst.a)
     opts = dict(tol=1e-8, scaled=True, restart=50, maxit=2000)
 
-    def step():
-        U64, i64 = gp.solve(F, precision="fp64", **opts)
-        U32, i32 = gp.solve(F, precision="mixed", **opts)
-        return U64, i64[0], U32, i32[0]
-
     for _ in range(args.warmup):
-        step()
+        gp.solve(F, precision="fp64", **opts)
+        gp.solve(F, precision="mixed", **opts)
     torch.cuda.synchronize()
 
     # Timed steps: one event pair around each solve, nothing between kernels.
@@ -139,17 +226,12 @@ def headline(args):
     fp64_ms = float(np.median(t_fp64))
     mixed_ms = float(np.median(t_mixed))
     # dominant kernel of the mixed solve (the headline value)
-    km = acc["mixed"]
+    km = {k: tuple(v) for k, v in acc["mixed"].items()}
     dom = max(km, key=lambda k: km[k][0])
-    ms, nl, by = km[dom]
-    avg_us = 1e3 * ms / max(nl, 1)
-    achieved = (by / max(nl, 1)) / (avg_us * 1e-6) / 1e9 if nl else 0.0
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": measured_traffic() if dom == "sweep" else None,
-                "kernel": KERNEL_NAMES.get(dom, dom) + " (mixed solve)",
-                "avg_launch_us": round(avg_us, 3), "launches": nl,
-                "bytes_per_launch": round(by / max(nl, 1), 1)}
+    roofline = roofline_of(km, KERNEL_NAMES, traffic=measured_traffic() if dom == "sweep" else None)
+    roofline["kernel"] += " (mixed solve)"
+    avg_us = roofline["avg_launch_us"]
+    nl = km[dom][1]
     # Second bound of the single-right-hand-side sweeps: their dependency
     # chain.  A sweep of an n x n rectangle is 2n - 1 anti-diagonals, each a
     # dependent step.  Per preconditioner apply of the mixed solve: the
@@ -176,11 +258,7 @@ def headline(args):
                    "dependent_steps_per_launch": round(per_launch, 1),
                    "ns_per_step": round(1e3 * avg_us / per_launch, 2),
                    "cycles_per_step_at_2.4GHz": round(2.4 * 1e3 * avg_us / per_launch, 1)}
-    kernels = {prec: {k: {"ms": round(v[0] / args.steps, 3),
-                          "launches": v[1] // args.steps,
-                          "avg_us": round(1e3 * v[0] / v[1], 3) if v[1] else 0.0,
-                          "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 2) if v[0] > 0 else 0.0}
-                      for k, v in acc[prec].items()}
+    kernels = {prec: kernels_of({k: tuple(v) for k, v in acc[prec].items()}, args.steps)
                for prec in acc}
 
     out = {
@@ -207,7 +285,11 @@ def headline(args):
         "iterations": {"fp64": i64["iterations"], "mixed": i32["iterations"],
                        "mixed_restarts": i32["restarts"],
                        "corner_cycles": [i64["mg_cycles_min"], i64["mg_cycles_max"]]},
+        # the stopping test is on the Jacobi-scaled system; the plain
+        # residual of the same iterates is reported beside it
         "rel_res": {"fp64": i64["res"] / i64["norm_F"], "mixed": i32["res"] / i32["norm_F"]},
+        "rel_res_unscaled": {"fp64": unscaled_rel_res(gp, F, U64),
+                             "mixed": unscaled_rel_res(gp, F, U32)},
         "footprint_bytes": gp.footprint(),
         "roofline": roofline,
         "latency": latency,
@@ -227,45 +309,18 @@ def headline(args):
         cpu_ms = 1e3 * (time.perf_counter() - t0)
         ut, _, _, _ = op.fgmres(Fo, tol=1e-10, scaled=True, maxit=2000)
         scale = np.abs(ut).max()
+        hi = host_info()
         out["cpu_baseline"] = {"value": round(cpu_ms, 1), "unit": "ms", "cores": 1,
                                "kind": "oracle",
                                "sample": "one FP64 solve of the same problem to the same "
                                          "tolerance (plain C oracle, single thread, %d "
-                                         "iterations)" % info_o.iterations}
+                                         "iterations)" % info_o.iterations,
+                               "cpu_model": hi["cpu_model"], "nproc": hi["nproc"]}
         out["err_vs_oracle"] = {
             "fp64": float(np.abs(U64.cpu().numpy() - ut).max() / scale),
             "mixed": float(np.abs(U32.cpu().numpy() - ut).max() / scale),
             "reference": "oracle FGMRES to scaled relative residual 1e-10, max-norm relative"}
-    print(json.dumps(out), flush=True)
-
-
-def roofline_of(kt, names=None, prefer=None):
-    """Roofline entry of the dominant kernel class (or `prefer`) of a timing
-    dictionary {class: (ms, launches, algorithmic bytes)}."""
-    dom = prefer or max(kt, key=lambda k: kt[k][0])
-    ms, nl, by = kt[dom]
-    avg_us = 1e3 * ms / max(nl, 1)
-    achieved = (by / max(nl, 1)) / (avg_us * 1e-6) / 1e9 if nl else 0.0
-    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": (names or {}).get(dom, dom), "avg_launch_us": round(avg_us, 3),
-            "launches": nl, "bytes_per_launch": round(by / max(nl, 1), 1)}
-
-
-def kernels_of(kt, steps):
-    return {k: {"ms": round(v[0] / steps, 3), "launches": v[1] // steps,
-                "GBps": round(v[2] / (v[0] * 1e-3) / 1e9, 2) if v[0] > 0 else 0.0}
-            for k, v in kt.items()}
-
-
-def oracle_pool(jobs):
-    """Run oracle solves (callables) one per host core; returns (wall s, cores)."""
-    from concurrent.futures import ThreadPoolExecutor
-    cores = min(len(jobs), os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(lambda f: f(), jobs))
-    return time.perf_counter() - t0, cores
+    return out
 
 
 def batch(args):
@@ -282,23 +337,24 @@ def batch(args):
     setup_s = time.perf_counter() - t0
     b = blp.Batch(ps, graphs=True, autotune=True)
     opts = dict(tol=1e-8, precision="mixed", maxit=2000)
-    for _ in range(args.warmup):
+    steps, warmup = args.side_steps, args.side_warmup
+    for _ in range(warmup):
         b.solve(F, **opts)
     a, c = ev(), ev()
     a.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         U, info = b.solve(F, **opts)
     c.record()
     torch.cuda.synchronize()
-    ms = a.elapsed_time(c) / args.steps
+    ms = a.elapsed_time(c) / steps
     b.timing(True)
     b.solve(F, **opts)
     kt = b.timing(False)
     it = [d["iterations"] for d in info]
     out = {"metric": "batched solves/s, 64 uneven instances (N in {128..1024}, eps in [1e-8,1e-2]), "
                      "mixed, rel-res 1e-8",
-           "value": round(64e3 / ms, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "value": round(64e3 / ms, 3), "unit": "solves/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "64 instances drawn by the uneven-batch recipe (seed 2): N "
                                   "uniform in {128,256,512,1024}, log10 eps uniform in [-8,-2], "
@@ -317,23 +373,40 @@ def batch(args):
            "tuning": b.describe()}
     if not args.no_cpu:
         from oracle import oracle as O
-        # bounded sample: the first eight instances with N <= 256 (a full
-        # N = 1024 oracle solve can take tens of seconds)
-        sample = [i for i in insts if i.N <= 256][:8]
+        hi = host_info()
 
-        def job(i):
-            def run():
-                op = O.Problem(i.N, i.eps, c1=i.c1_at, c2=i.c2_at, r=i.r_const)
-                op.fgmres(O.sine_series(i.N, op.x, op.y, i.a), tol=1e-8, scaled=True, maxit=2000)
-            return run
-        wall, cores = oracle_pool([job(i) for i in sample])
-        out["cpu_baseline"] = {"value": round(len(sample) / wall, 3), "unit": "solves/s",
-                               "cores": cores, "kind": "oracle",
-                               "sample": "the first %d instances with N <= 256 (N %s), one FP64 "
-                                         "oracle solve per core; the GPU batch also holds the "
-                                         "N = 512 and 1024 instances" % (len(sample),
-                                                                         [i.N for i in sample])}
-    print(json.dumps(out), flush=True)
+        def solve(k):
+            i = insts[k]
+            t = time.perf_counter()
+            op = O.Problem(i.N, i.eps, c1=i.c1_at, c2=i.c2_at, r=i.r_const)
+            _, st, io, _ = op.fgmres(O.sine_series(i.N, op.x, op.y, i.a), tol=1e-8, scaled=True,
+                                     maxit=2000)
+            return time.perf_counter() - t, io.iterations
+
+        # every N <= 256 instance is solved (measured); N = 512 and 1024 are
+        # extrapolated from the first two instances of each class: their
+        # seconds per iteration times each instance's iteration count (the
+        # GPU run's, the same algorithm)
+        small = [k for k, i in enumerate(insts) if i.N <= 256]
+        sample = {N: [k for k, i in enumerate(insts) if i.N == N][:2] for N in (512, 1024)}
+        res, wall_small = pool_map(solve, small + sample[512] + sample[1024], hi["pool"])
+        t_of = dict(zip(small + sample[512] + sample[1024], res))
+        per_it = {N: sum(t_of[k][0] for k in ks) / max(1, sum(t_of[k][1] for k in ks))
+                  for N, ks in sample.items()}
+        est = [t_of[k][0] if k in small else it[k] * per_it[insts[k].N] for k in range(64)]
+        cpu_s = sum(est)
+        wall = max(max(est), cpu_s / hi["pool"])
+        out["cpu_baseline"] = {
+            "value": round(64 / wall, 3), "unit": "solves/s", "cores": hi["pool"],
+            "kind": "oracle",
+            "sample": "all 40 instances with N <= 256 solved by the FP64 oracle (one solve per "
+                      "core, %.1f s wall); the 24 with N = 512 and 1024 extrapolated from the "
+                      "first two of each class (%.3f and %.3f s per iteration) times their "
+                      "iteration counts; value = 64 / max(longest solve, total CPU seconds / "
+                      "cores) = 64 / %.1f s" % (wall_small, per_it[512], per_it[1024], wall),
+            "cpu_seconds_total": round(cpu_s, 1), "cpu_model": hi["cpu_model"],
+            "nproc": hi["nproc"]}
+    return out
 
 
 def multi_rhs(args):
@@ -357,47 +430,67 @@ def multi_rhs(args):
         G = [u.clone() for u in U]  # dJ/du of J = 0.5 ||u||^2 per right-hand side
         L, i2 = b.solve_adjoint(G, **opts)
         return i1, i2
-    for _ in range(args.warmup):
+    steps, warmup = args.side_steps, args.side_warmup
+    for _ in range(warmup):
         step()
     a, c = ev(), ev()
     a.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         i1, i2 = step()
     c.record()
     torch.cuda.synchronize()
-    ms = a.elapsed_time(c) / args.steps
+    ms = a.elapsed_time(c) / steps
     b.timing(True)
     step()
     kt = b.timing(False)
+    by_kernel = {k: roofline_of(kt, prefer=k) for k in ("spmv", "sweep", "lines", "mg_other",
+                                                          "krylov")}
     out = {"metric": "16 right-hand sides at N=2048, eps=1e-6: mixed solves + adjoint gradients",
-           "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False,
+           "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "N=2048 (4.19M unknowns), eps=1e-6, c=(1+x^2,1+y), r=1, 16 "
                                   "seeded 3x3 sine right-hand sides; 16 FGMRES(50) mixed solves "
                                   "to 1e-8 and 16 adjoint solves, one batch (graphs, autotuned)"},
            "iterations": {"forward": [d["iterations"] for d in i1],
                           "adjoint": [d["iterations"] for d in i2]},
+           "corner_cycles": {"forward": [min(d["mg_cycles_min"] for d in i1),
+                                         max(d["mg_cycles_max"] for d in i1)],
+                             "adjoint": [min(d["mg_cycles_min"] for d in i2),
+                                         max(d["mg_cycles_max"] for d in i2)]},
            "setup_s": round(setup_s, 3),
            "footprint_bytes": {"batch": b.footprint(), "problem": p.footprint()},
-           "roofline": {"spmv": roofline_of(kt, prefer="spmv"),
-                        "sweep": roofline_of(kt, prefer="sweep"),
-                        "lines": roofline_of(kt, prefer="lines"),
-                        "dominant": roofline_of(kt)},
+           "roofline": roofline_of(kt),
+           "roofline_by_kernel": by_kernel,
            "kernels_per_step": kernels_of(kt, 1), "tuning": b.describe()}
     if not args.no_cpu:
         from oracle import oracle as O
+        hi = host_info()
         op = O.Problem(inst.N, inst.eps, c1=inst.c1_at, c2=inst.c2_at, r=inst.r_const)
-        Fo = O.sine_series(inst.N, op.x, op.y, A[0])
-        t1 = time.perf_counter()
-        _, _, info_o, _ = op.fgmres(Fo, tol=1e-8, scaled=True, maxit=2000)
-        cpu_s = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": round(1e3 * cpu_s * 2 * len(F), 1), "unit": "ms",
-                               "cores": 1, "kind": "oracle",
-                               "sample": "one FP64 oracle solve of the first right-hand side "
-                                         "(%d iterations, %.1f s), scaled to 16 forward and 16 "
-                                         "adjoint solves" % (info_o.iterations, cpu_s)}
-    print(json.dumps(out), flush=True)
+        Fo = [O.sine_series(inst.N, op.x, op.y, A[k]) for k in range(A.shape[0])]
+
+        def fwd(k):
+            t = time.perf_counter()
+            _, _, io, _ = op.fgmres(Fo[k], tol=1e-8, scaled=True, maxit=2000)
+            return time.perf_counter() - t, io.iterations
+
+        # the 16 forward solves, one per core (measured); the adjoint solves
+        # extrapolated from two iterations of the first one
+        res, wall_f = pool_map(fwd, list(range(len(Fo))), hi["pool"])
+        t = time.perf_counter()
+        _, _, ia, _ = op.fgmres(Fo[0], tol=1e-8, scaled=True, maxit=2, transpose=True)
+        per_it_adj = (time.perf_counter() - t) / max(1, ia.iterations)
+        adj = [d["iterations"] * per_it_adj for d in i2]
+        wall_a = max(max(adj), sum(adj) / hi["pool"])
+        out["cpu_baseline"] = {
+            "value": round(1e3 * (wall_f + wall_a), 1), "unit": "ms", "cores": hi["pool"],
+            "kind": "oracle",
+            "sample": "the 16 forward FP64 oracle solves, one per core (measured, %.1f s wall); "
+                      "the 16 adjoint solves extrapolated from two iterations of the first "
+                      "(%.2f s per iteration) times the adjoint iteration counts, spread over "
+                      "the cores (%.1f s)" % (wall_f, per_it_adj, wall_a),
+            "cpu_model": hi["cpu_model"], "nproc": hi["nproc"]}
+    return out
 
 
 def main():
@@ -405,11 +498,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--side-steps", type=int, default=3,
+                    help="timed solves of the batch and multi-RHS workloads")
+    ap.add_argument("--side-warmup", type=int, default=1)
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("headline", "batch", "multi_rhs", "copy_probe"),
-                    default="headline")
+    ap.add_argument("--workload", choices=("all", "headline", "batch", "multi_rhs", "copy_probe"),
+                    default="all")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -419,8 +515,18 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    {"headline": headline, "batch": batch, "multi_rhs": multi_rhs,
-     "copy_probe": copy_probe}[args.workload](args)
+    if args.workload == "all":
+        out = headline(args)
+        print("headline done", file=sys.stderr, flush=True)
+        out["batch"] = batch(args)
+        print("batch done", file=sys.stderr, flush=True)
+        out["multi_rhs"] = multi_rhs(args)
+        print("multi_rhs done", file=sys.stderr, flush=True)
+        out["copy_bandwidth"] = copy_bandwidth()
+    else:
+        out = {"headline": headline, "batch": batch, "multi_rhs": multi_rhs,
+               "copy_probe": copy_probe}[args.workload](args)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

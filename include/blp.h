@@ -102,6 +102,8 @@ int blp_nodes(const blp_problem *p, double *x, double *y);
  *             = 0: stationary iteration until the corner residual of the
  *             rescaled system has dropped by mg_rtol (paper: 1e-3), at most
  *             mg_maxcyc cycles.
+ * Calling it again on a preconditioned problem only replaces the options;
+ * every later solve (single or batched) uses the new ones.
  * Errors: BLP_E_INVAL, BLP_E_NOMEM, BLP_E_HIP. */
 typedef struct {
   int mg_fixed;
@@ -177,20 +179,27 @@ int blp_solve_adjoint(blp_problem *p, int nrhs, const double *G, double *Lambda,
  * target, so each system follows exactly the iteration of its single solve.
  * opts (may be NULL): graphs = 1 replays the launches of one Krylov step from
  * HIP graphs captured on first use; autotune = 1 times the candidate kernel
- * variants of each mesh size once and keeps the fastest.
- * Errors: BLP_E_INVAL (S < 1, NULL problem), BLP_E_STATE (a problem not
- * preconditioned), BLP_E_NOMEM, BLP_E_HIP. */
+ * variants of each mesh size once and keeps the fastest.  sweep_variant
+ * (a test hook; 0 = default or the autotuner's choice): v > 0 runs every
+ * triangular sweep of the batch in scheduling variant (v - 1) modulo the
+ * number of variants its width has; all variants compute bit-identical
+ * results.
+ * Errors: BLP_E_INVAL (S < 1, NULL problem, sweep_variant < 0), BLP_E_STATE
+ * (a problem not preconditioned), BLP_E_NOMEM, BLP_E_HIP. */
 typedef struct blp_batch blp_batch;
 typedef struct {
   int graphs;
   int autotune;
+  int sweep_variant;
 } blp_batch_opts;
 int blp_batch_create(blp_problem *const *probs, int S, void *hip_stream,
                      const blp_batch_opts *opts, blp_batch **out);
 
 /* F[s], U[s]: device vectors of system s ((N_s-1)^2 doubles; F and U host
  * arrays of S pointers).  info: host, S entries (may be NULL).  Same solve
- * options and errors as blp_solve (BLP_W_NOCONV if any system hit maxit). */
+ * options and errors as blp_solve (BLP_W_NOCONV if any system hit maxit);
+ * also BLP_E_INVAL when the problems of the batch were preconditioned with
+ * different blp_prec_opts (the corner cycle schedule is shared). */
 int blp_batch_solve(blp_batch *b, const double *const *F, double *const *U,
                     const blp_solve_opts *opts, blp_solve_info *info);
 /* Adjoint systems A_s^T L_s = G_s, as blp_solve_adjoint. */

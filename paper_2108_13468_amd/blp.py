@@ -50,7 +50,7 @@ class SolveOpts(C.Structure):
 
 
 class BatchOpts(C.Structure):
-    _fields_ = [("graphs", C.c_int), ("autotune", C.c_int)]
+    _fields_ = [("graphs", C.c_int), ("autotune", C.c_int), ("sweep_variant", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -64,7 +64,11 @@ class SolveInfo(C.Structure):
 
 
 class BlpError(RuntimeError):
-    pass
+    """A negative status of the library; .code holds it."""
+
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 _lib = None
@@ -119,7 +123,7 @@ def lib():
 
 def _check(rc, what):
     if rc < 0:
-        raise BlpError("%s failed: %s (%d)" % (what, lib().blp_strerror(rc).decode(), rc))
+        raise BlpError("%s failed: %s (%d)" % (what, lib().blp_strerror(rc).decode(), rc), rc)
     return rc
 
 
@@ -299,7 +303,7 @@ class Batch:
     several times, once per right-hand side).  Runs on torch's current
     stream at creation."""
 
-    def __init__(self, problems, graphs=False, autotune=False):
+    def __init__(self, problems, graphs=False, autotune=False, sweep_variant=0):
         import torch
         self.torch = torch
         self.problems = list(problems)  # kept alive while the batch exists
@@ -308,7 +312,8 @@ class Batch:
         stream = torch.cuda.current_stream()
         h = C.c_void_p()
         _check(lib().blp_batch_create(arr, S, C.c_void_p(stream.cuda_stream),
-                                      C.byref(BatchOpts(int(graphs), int(autotune))), C.byref(h)),
+                                      C.byref(BatchOpts(int(graphs), int(autotune),
+                                                        int(sweep_variant))), C.byref(h)),
                "blp_batch_create")
         self._h = h
         self.S = S

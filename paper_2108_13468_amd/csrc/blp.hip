@@ -682,6 +682,11 @@ int blp_batch_create(blp_problem *const *probs, int S, void *stream, const blp_b
   if (o) {
     b->B->graphs = o->graphs != 0;
     b->B->autotune = o->autotune != 0;
+    if (o->sweep_variant < 0) {
+      delete b;
+      return BLP_E_INVAL;
+    }
+    b->B->sweep_variant = o->sweep_variant;
   }
   if (b->B->graphs) {
     // graphs are captured on a stream of the batch's own (capture is not

@@ -430,7 +430,7 @@ void interior_run(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
     k_gather_skew<T, TR><<<gg, kSkewThreads, 0, c.stream>>>(P.ioI, jp);
   }
   {
-    KScope ks(c, KC_SWEEP, (double)S * m * m * 3 * sizeof(T));
+    KScope ks(c, KC_SWEEP, (double)S * m * m * 2 * sizeof(T));
     sweep_launch<T, TR>(c, S, m, P.swI, P.varI);
   }
   KScope ks(c, KC_LAYOUT, 0.0);
@@ -475,14 +475,14 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   const dim3 gl(blocks1d(P.lslot[l]), S), gc(blocks1d(P.lslot[l + 1]), S);
   const double cc = (double)S * P.ln[l + 1] * P.ln[l + 1];
   if (zero_init) {
-    KScope ks(c, KC_SWEEP, nn * 3 * sizeof(T));
+    KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
     sweep_launch<T, TR>(c, S, n, P.swb[l], P.varL[l]);
   } else {
     {
       KScope ks(c, KC_GSRHS, nn * 3 * sizeof(T));
       k_gs_rhs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
     }
-    KScope ks(c, KC_SWEEP, nn * 3 * sizeof(T));
+    KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
     sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
   }
   {
@@ -500,7 +500,7 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
     KScope ks(c, KC_GSRHS, (3 * nn + cc) * sizeof(T));
     k_mg_prolong_gs<T, TR><<<gl, 256, 0, c.stream>>>(P.mg[l]);
   }
-  KScope ks(c, KC_SWEEP, nn * 3 * sizeof(T));
+  KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
   sweep_launch<T, TR>(c, S, n, P.swt[l], P.varL[l]);
 }
 
@@ -607,6 +607,9 @@ struct SolvePlan {
   std::vector<const double *> F;    // right-hand sides the plan is bound to
   std::vector<double *> U;
   std::vector<const void *> V;      // Krylov bases the plan was built on
+  // preconditioner options the plan was built with (its corner records hold
+  // the stopping rule, its captured graphs the cycle schedule)
+  blp_prec_opts po{0, 0.0, 0};
   // host copies of the records that hold F and U (rebound in place when a
   // solve passes other vectors; their device arrays keep their addresses,
   // so captured graphs stay valid)
@@ -642,6 +645,7 @@ struct Batch {
   Timer *timer = nullptr;  // the problem's timer (own batches) or own_timer
   Timer own_timer;
   int graphs = 0, autotune = 0;  // blp_batch_opts
+  int sweep_variant = 0;          // blp_batch_opts test hook (0: default)
   hipStream_t user = nullptr;     // caller's stream when the batch runs on its own
   bool own_stream = false;
   // one stream per mesh class when there are several (default priority)
@@ -729,6 +733,7 @@ int build_solve_plan(Batch &B, const std::vector<int> &cls, int m, const double 
   P.F.clear();
   P.U.clear();
   P.V.clear();
+  P.po = B.sys[cls[0]]->p->popts;
   for (int k = 0; k < S; ++k) {
     System &y = *B.sys[cls[k]];
     blp_problem *p = y.p;
@@ -855,17 +860,29 @@ int get_solve_plan(Batch &B, int c, int m, const double *const *F, double *const
       basis = basis && h->plan.V[k] == B.sys[s]->V;
       same = same && h->plan.F[k] == F[s] && h->plan.U[k] == U[s];
     }
-    if (basis) {
+    // a problem preconditioned again with other options needs a new plan
+    const blp_prec_opts &q = B.sys[B.classes[c][0]]->p->popts;
+    const bool opts = q.mg_fixed == h->plan.po.mg_fixed && q.mg_rtol == h->plan.po.mg_rtol &&
+                      q.mg_maxcyc == h->plan.po.mg_maxcyc;
+    if (basis && opts) {
       if (!same) BLP_TRY((rebind_solve_plan<TV, TR, SCALE>(B, B.classes[c], F, U, h->plan)));
       *out = &h->plan;
       return BLP_OK;
     }
-    B.plans.erase(it);  // built on a basis that has since been reallocated
+    B.plans.erase(it);  // built on a basis since reallocated, or with other options
   }
   std::unique_ptr<PlanHolder<TV, TR, SCALE>> h(new (std::nothrow) PlanHolder<TV, TR, SCALE>());
   if (!h) return BLP_E_NOMEM;
   BLP_TRY((build_solve_plan<TV, TR, SCALE>(B, B.classes[c], m, F, U, h->plan)));
   if (B.autotune) BLP_TRY((tune_plan<TV, TR, SCALE>(B, c, h->plan)));
+  if (B.sweep_variant > 0) {
+    // every sweep of the plan takes the requested variant (modulo the
+    // number its width has)
+    PrecPlan<TV, TR> &Q = h->plan.prec;
+    const int v = B.sweep_variant - 1;
+    Q.varI = v % sweep_variants(Q.n1 - Q.h);
+    for (size_t l = 0; l < Q.ln.size(); ++l) Q.varL[l] = v % sweep_variants(Q.ln[l]);
+  }
   *out = &h->plan;
   B.plans[key] = std::move(h);
   return BLP_OK;
@@ -1213,8 +1230,14 @@ int batch_solve(Batch &B, bool tr, const double *const *F, double *const *U, con
                 blp_solve_info *info, double *const *hist) {
   if (!o || !(o->tol > 0) || o->restart < 1 || o->restart > 60 || o->maxit < 1) return BLP_E_INVAL;
   if (o->precision != BLP_FP64 && o->precision != BLP_MIXED) return BLP_E_INVAL;
-  for (size_t s = 0; s < B.sys.size(); ++s)
+  // one corner stopping rule for the whole batch (its schedule is shared)
+  const blp_prec_opts &q0 = B.sys[0]->p->popts;
+  for (size_t s = 0; s < B.sys.size(); ++s) {
     if (!F[s] || !U[s]) return BLP_E_INVAL;
+    const blp_prec_opts &q = B.sys[s]->p->popts;
+    if (q.mg_fixed != q0.mg_fixed || q.mg_rtol != q0.mg_rtol || q.mg_maxcyc != q0.mg_maxcyc)
+      return BLP_E_INVAL;
+  }
   // a batch on its own stream starts after the caller's pending work (the
   // right-hand sides) and has finished when this returns
   if (B.own_stream) HIP_TRY(hipStreamSynchronize(B.user));

@@ -302,7 +302,10 @@ BLP_DEV T chan_value(const ChanWord<T> &c) {
 // completed the superstep that holds the last step it needs, and before
 // overwriting ring slots a band waits until its downstream band no longer
 // needs them.  A wave's LDS operations are processed in order, so a count
-// read by another wave implies the ring writes issued before it.
+// read by another wave implies the ring writes issued before it.  Both
+// waits are bounded (kProgSpin rounds); a wait that runs out turns the
+// band's values from there on into NaN, which the solver reports as a
+// non-finite residual rather than returning a wrong result.
 //
 // Split sweeps (G > 1 workgroups per system, group gi taking bands gi x
 // waves ..): the first band of group gi > 0 gets its upstream column from
@@ -494,6 +497,9 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int t
         ++spin;
       }
       asm volatile("" ::: "memory");
+      // an expired wait would read stale ring values: poison this band's
+      // chain instead, so that the solver reports a non-finite residual
+      if (spin >= kProgSpin) z = __builtin_nan("");
     }
     // LDS operands of the superstep, read up front so that no LDS latency
     // sits on the step-to-step dependency chain.  The writer band stores
@@ -541,6 +547,13 @@ BLP_DEV void sweep_body(const SweepArgs<T> &a, T *ring, T *ycs, int *prog, int t
         ++spin;
       }
       asm volatile("" ::: "memory");
+      // an expired wait would overwrite ring slots the downstream band still
+      // reads: publish NaN there (and carry it on) instead
+      if (spin >= kProgSpin) {
+        z = __builtin_nan("");
+#pragma unroll
+        for (int k = 0; k < K; ++k) res[k] = z;
+      }
     }
     if (lane == 63) {
       const int r0 = (sl & (RING - 1)) / P;

@@ -130,3 +130,58 @@ def test_alternating_precisions_reuse_plans():
                 U0, it0 = first[prec]
                 assert it == it0
                 assert bool((U == U0).all()), (prec, rnd, _rel(U, U0))
+
+
+def test_full_batch_recipe_against_references():
+    """The 64-instance uneven batch exactly as the benchmark runs it (graphs,
+    autotuner, mixed precision, scaled relative residual 1e-8), compared with
+    references for the instances that set its difficulty: the two with the
+    most iterations (N = 1024 at eps near 5e-4, N = 512 at eps near 2e-3),
+    the smallest eps of each mesh size (down to 1.2e-8), and the largest eps
+    at N = 128 and 256.  References: for eps >= 1e-4, where restarted FGMRES
+    needs hundreds of iterations, the direct solve of the oracle's matrix;
+    below, the oracle's FGMRES to a scaled relative residual of 1e-9 (a few
+    iterations; the FP64 floor of both there lies near 1e-10).  Bound: the
+    mixed target, 1e-6 max-norm relative error; every instance of the batch
+    must converge."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2108_13468_amd import blp
+    from tests.reference import direct, max_rel
+    insts = inputs.batch_cases(64)
+    picks = [13, 47, 10, 61, 15, 16, 41, 58]
+    say("full batch recipe: references for instances %s (N %s, eps %s)" % (
+        picks, [insts[k].N for k in picks], ["%.1e" % insts[k].eps for k in picks]))
+
+    def ref(k):
+        i = insts[k]
+        op = O.Problem(i.N, i.eps, c1=i.c1_at, c2=i.c2_at, r=i.r_const)
+        F = O.sine_series(i.N, op.x, op.y, i.a)
+        if i.eps >= 1e-4:
+            return direct(op, F)
+        u, st, io, _ = op.fgmres(F, tol=1e-9, scaled=True, maxit=500)
+        assert st == 0
+        return u, io.true_res / io.norm_F
+
+    slow = [k for k in picks if insts[k].eps >= 1e-4 and insts[k].N >= 512]
+    with ThreadPoolExecutor(2) as ex:
+        # the large direct solves one at a time, the rest beside them
+        futs_slow = ex.submit(lambda: {k: ref(k) for k in slow})
+        futs_fast = ex.submit(lambda: {k: ref(k) for k in picks if k not in slow})
+        ps, F = _problems(insts)
+        b = blp.Batch(ps, graphs=True, autotune=True)
+        U, info = b.solve(F, tol=1e-8, precision="mixed", maxit=2000)
+        torch.cuda.synchronize()
+        refs = dict(futs_slow.result())
+        refs.update(futs_fast.result())
+    assert all(d["converged"] == 1 for d in info), [k for k, d in enumerate(info)
+                                                     if not d["converged"]]
+    it = [d["iterations"] for d in info]
+    say("  iterations: max %d, mean %.1f" % (max(it), float(np.mean(it))))
+    for k in picks:
+        u_t, res = refs[k]
+        assert res <= 1e-9, (k, res)
+        err = max_rel(U[k].cpu().numpy(), u_t)
+        say("  instance %d N=%d eps=%.2e: %d iterations, error %.2e (reference residual %.1e)" % (
+            k, insts[k].N, insts[k].eps, it[k], err, res))
+        assert err <= 1e-6, k

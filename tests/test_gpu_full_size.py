@@ -1,21 +1,33 @@
 """GPU solves at the full workload sizes, in the launch configurations the
-benchmark times.
+benchmark times, compared element by element with references computed on
+the CPU from the oracle's operator.
 
-* N = 1024, eps = 1e-6 (the headline problem): single FP64 and mixed solves
-  against the oracle's solution at relative residual 1e-10: max-norm
-  relative error at most 1e-8 (FP64) and 1e-6 (mixed);
-* N = 2048, eps = 1e-6 (the multi-right-hand-side workload): a graphed,
-  autotuned batch of two forward and two adjoint mixed solves.  The oracle
-  cannot solve at this size within a test, so each result is checked by a
-  property that holds at any size: the true residual of the scaled system,
-  computed with the oracle's operator, meets the tolerance."""
+* N = 1024, c = (1+x^2, 1+y), r = 1, seeded 3x3 sine f, eps in {1e-2, 1e-4,
+  1e-6}: single FP64 and mixed solves to a scaled relative residual of
+  1e-8.  Reference: the oracle's FGMRES to 1e-10 (eps = 1e-4, 1e-6); at
+  eps = 1e-2, where restarted FGMRES needs about a thousand iterations, the
+  direct solve of the oracle's matrix.  Bound: max-norm relative error at
+  most 1e-6 for the mixed solve; the FP64 claim (error at most 1e-8) is
+  checked on an FP64 solve to 1e-10, since a relative residual of 1e-8 does
+  not bound the relative error by 1e-8 (at eps = 1e-2 it is 1.1e-8).  Each
+  case prints iterations, solve times and errors of both precisions at 1e-8.
+* N = 2048, eps = 1e-6, 16 right-hand sides: one graphed, autotuned batch of
+  the 16 forward mixed solves and one of the adjoint solves, as the
+  benchmark runs them.  The first right-hand side is compared with the
+  oracle's FGMRES solutions, forward and adjoint (the adjoint data is the
+  oracle's forward solution), at a scaled relative residual of 1e-9: at this
+  size the oracle's FP64 restarted FGMRES stalls between 1e-9 and 1e-10.
+  Every result is also checked by its scaled residual under the oracle's
+  operator."""
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2108_13468_amd import inputs
+from tests.reference import direct, max_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -30,52 +42,106 @@ def _oracle(inst):
                      sigma=inst.sigma, clow_x=inst.clow[0], clow_y=inst.clow[1])
 
 
-def test_headline_problem_against_oracle():
+def _timed_solve(gp, F, **kw):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    gp.solve(F, **kw)  # warm (plans)
+    a.record()
+    U, info = gp.solve(F, **kw)
+    b.record()
+    torch.cuda.synchronize()
+    return U, info[0], a.elapsed_time(b)
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-4, 1e-2])
+def test_headline_problem_against_reference(eps):
     import torch
     assert torch.cuda.is_available()
     from paper_2108_13468_amd import blp
-    inst = inputs.headline_case(1e-6)
+    inst = inputs.headline_case(eps)
     say("headline problem N=%d eps=%g" % (inst.N, inst.eps))
-    gp = blp.from_instance(inst).precondition()
     op = _oracle(inst)
     F = O.sine_series(inst.N, op.x, op.y, inst.a)
-    u_t, st, _, _ = op.fgmres(F, tol=1e-10, scaled=True)
-    assert st == 0
-    Fd = torch.as_tensor(F, device="cuda")
-    for prec, bound in (("fp64", 1e-8), ("mixed", 1e-6)):
-        U, info = gp.solve(Fd, tol=1e-8, scaled=True, precision=prec)
-        assert info[0]["converged"], info
-        err = np.abs(U.cpu().numpy() - u_t).max() / np.abs(u_t).max()
-        say("  %s: %d iterations, error %.2e" % (prec, info[0]["iterations"], err))
-        assert err <= bound
+    with ThreadPoolExecutor(1) as ex:
+        if eps >= 1e-2:
+            fut = ex.submit(direct, op, F)
+        else:
+            fut = ex.submit(lambda: (op.fgmres(F, tol=1e-10, scaled=True, maxit=2000), None))
+        gp = blp.from_instance(inst).precondition()
+        Fd = torch.as_tensor(F, device="cuda")
+        got = {}
+        for prec in ("fp64", "mixed"):
+            got[prec] = _timed_solve(gp, Fd, tol=1e-8, scaled=True, precision=prec, maxit=3000)
+        U10, i10 = gp.solve(Fd, tol=1e-10, scaled=True, precision="fp64", maxit=4000)
+        ref = fut.result()
+    if eps >= 1e-2:
+        u_t, res = ref
+        say("  reference: direct solve, scaled residual %.1e" % res)
+        assert res <= 1e-11
+    else:
+        (u_t, st, io, _), _ = ref
+        say("  reference: oracle FGMRES, %d iterations" % io.iterations)
+        assert st == 0
+    errs = {}
+    for prec in ("fp64", "mixed"):
+        U, info, ms = got[prec]
+        assert info["converged"], info
+        errs[prec] = max_rel(U.cpu().numpy(), u_t)
+        say("  %s: %d iterations (%d restarts), %.2f ms, error %.2e" % (
+            prec, info["iterations"], info["restarts"], ms, errs[prec]))
+    assert errs["mixed"] <= 1e-6
+    assert i10[0]["converged"], i10
+    e10 = max_rel(U10.cpu().numpy(), u_t)
+    say("  fp64 to 1e-10: %d iterations, error %.2e" % (i10[0]["iterations"], e10))
+    assert e10 <= 1e-8
+    say("  mixed %s FP64 at eps=%g (%.2f vs %.2f ms)" % (
+        "beats" if got["mixed"][2] < got["fp64"][2] else "does not beat", eps, got["mixed"][2],
+        got["fp64"][2]))
 
 
-def test_multi_rhs_workload_residuals():
+def test_multi_rhs_workload_against_oracle():
     import torch
     assert torch.cuda.is_available()
     from paper_2108_13468_amd import blp
     inst, A = inputs.multi_rhs_case()
-    say("multi-RHS workload N=%d eps=%g, 2 of %d right-hand sides" % (inst.N, inst.eps, len(A)))
-    p = blp.from_instance(inst).precondition()
+    nr = len(A)
+    say("multi-RHS workload N=%d eps=%g, %d right-hand sides" % (inst.N, inst.eps, nr))
     op = _oracle(inst)
+    Fs = [O.sine_series(inst.N, op.x, op.y, A[k]) for k in range(nr)]
+    picked = (0,)
+
+    def forward_then_adjoint(k):
+        u, st, _, _ = op.fgmres(Fs[k], tol=1e-9, scaled=True, maxit=100)
+        lam, st2, _, _ = op.fgmres(u, tol=1e-9, scaled=True, maxit=100, transpose=True)
+        return u, lam, st, st2
+
+    with ThreadPoolExecutor(len(picked)) as ex:
+        futs = [ex.submit(forward_then_adjoint, k) for k in picked]
+        p = blp.from_instance(inst).precondition()
+        b = blp.Batch([p] * nr, graphs=True, autotune=True)
+        Fd = [torch.as_tensor(F, device="cuda") for F in Fs]
+        U, info = b.solve(Fd, tol=1e-8, precision="mixed")
+        refs = [f.result() for f in futs]
+    # adjoint data: the oracle's forward solutions of the picked systems,
+    # the forward solutions' own values elsewhere (dJ/du of 0.5 ||u||^2)
+    G = [u.clone() for u in U]
+    for k, r in zip(picked, refs):
+        G[k] = torch.as_tensor(r[0], device="cuda")
+    L, infa = b.solve_adjoint(G, tol=1e-8, precision="mixed")
     d = np.sqrt(op.csr().diagonal())
-    Fs = [O.sine_series(inst.N, op.x, op.y, A[k]) for k in range(2)]
-    b = blp.Batch([p, p], graphs=True, autotune=True)
-    tol = 1e-8
-    # one scaled-residual check per result: ||D^-1/2 (F - A u)|| <= tol ||D^-1/2 F||
-    # (plus a margin for the FP64 evaluation order of the two residuals)
-    U, info = b.solve([torch.as_tensor(F, device="cuda") for F in Fs], tol=tol, precision="mixed")
-    for k in range(2):
-        assert info[k]["converged"], info[k]
+    for k in range(nr):
+        assert info[k]["converged"] and infa[k]["converged"], (k, info[k], infa[k])
         u = U[k].cpu().numpy()
         rel = np.linalg.norm((Fs[k] - op.A(u)) / d) / np.linalg.norm(Fs[k] / d)
-        say("  forward %d: %d iterations, scaled residual %.2e" % (k, info[k]["iterations"], rel))
-        assert rel <= tol * (1 + 1e-3)
-    L, info = b.solve_adjoint([torch.as_tensor(F, device="cuda") for F in Fs], tol=tol,
-                              precision="mixed")
-    for k in range(2):
-        assert info[k]["converged"], info[k]
+        g = G[k].cpu().numpy()
         lam = L[k].cpu().numpy()
-        rel = np.linalg.norm((Fs[k] - op.AT(lam)) / d) / np.linalg.norm(Fs[k] / d)
-        say("  adjoint %d: %d iterations, scaled residual %.2e" % (k, info[k]["iterations"], rel))
-        assert rel <= tol * (1 + 1e-3)
+        rela = np.linalg.norm((g - op.AT(lam)) / d) / np.linalg.norm(g / d)
+        # (a margin for the FP64 evaluation order of the two residuals)
+        assert rel <= 1e-8 * (1 + 1e-3) and rela <= 1e-8 * (1 + 1e-3), (k, rel, rela)
+    for k, (u_t, lam_t, st, st2) in zip(picked, refs):
+        assert st == 0 and st2 == 0
+        eu = max_rel(U[k].cpu().numpy(), u_t)
+        el = max_rel(L[k].cpu().numpy(), lam_t)
+        say("  rhs %d: forward %d iterations, error %.2e; adjoint %d iterations, error %.2e" % (
+            k, info[k]["iterations"], eu, infa[k]["iterations"], el))
+        assert eu <= 1e-6 and el <= 1e-6

@@ -8,9 +8,11 @@ and, at N <= 256, the max-norm errors of Table 6 (within 2%: the paper's
 errors carry its own loose stopping rule, as these solves do).  Parity: the
 GPU iterate meets the stopping rule under the oracle's operator and agrees
 with the oracle's FGMRES under the same rule (relative difference at most
-1e-8 when both stop at the same iteration; at a row whose residual sits at
-the threshold the two may stop one iteration apart, and the GPU iterate must
-then be as accurate as the oracle's)."""
+1e-8 when both stop at the same iteration; at a row whose true residual sits
+at the threshold the two may stop one iteration apart: then the later run's
+residual at the earlier stopping iteration must lie within 25% above the
+threshold, and the two iterates after that many iterations must agree to
+1e-8)."""
 import os
 import sys
 
@@ -70,8 +72,29 @@ def test_paper_mode_table7(N, eps):
     if io.iterations == info["iterations"]:
         assert np.abs(Ug - uo).max() <= 1e-8 * np.abs(uo).max()
     else:
-        # a row whose residual sits at the threshold: rounding decides the
-        # last test, so two correct implementations may stop one iteration
-        # apart; the GPU iterate must then be as accurate as the oracle's
-        assert abs(io.iterations - info["iterations"]) == 1
-        assert np.abs(Ug - u_exact).max() <= 1.01 * np.abs(uo - u_exact).max()
+        # a row whose true residual sits at the threshold: rounding decides
+        # the last test, so two correct implementations may stop one
+        # iteration apart.  Accepted only when (a) the run that stopped
+        # later had, at the other's stopping iteration, a true residual just
+        # above the threshold (within 25%: one iteration reduces it about
+        # twenty-fold here), and (b) the two iterates after the same number
+        # of iterations agree as closely as in the rows where both stop
+        # together.
+        k = min(io.iterations, info["iterations"])
+        assert max(io.iterations, info["iterations"]) == k + 1
+        if info["iterations"] == k:
+            uk, _, _, _ = op.fgmres(f, tol=tol, absolute=True, maxit=k)
+            late = np.linalg.norm(f - op.A(uk)) / tol
+            Ugk = Ug
+        else:
+            uk = uo
+            Uk, _ = gp.solve(torch.as_tensor(f, device="cuda"), tol=tol, absolute=True,
+                             scaled=False, precision="fp64", maxit=k)
+            Ugk = Uk.cpu().numpy()
+            late = np.linalg.norm(f - op.A(Ugk)) / tol
+        diff = np.abs(Ugk - uk).max() / np.abs(uk).max()
+        say("  stopped one apart (gpu %d, oracle %d): residual of the later run after %d "
+            "iterations = %.4f x threshold, iterates after %d differ by %.2e" % (
+                info["iterations"], io.iterations, k, late, k, diff))
+        assert 1.0 < late <= 1.25
+        assert diff <= 1e-8

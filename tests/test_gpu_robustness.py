@@ -1,0 +1,163 @@
+"""GPU tests of the library's failure paths and scheduling invariants, all
+through the C ABI:
+
+* forced failures: maxit = 1 returns BLP_W_NOCONV with the solve record
+  filled in; a NaN in the right-hand side gives BLP_E_NUMERIC; a
+  preconditioned solve or an M^{-1} apply before blp_precondition gives
+  BLP_E_STATE; an unknown operator code gives BLP_E_INVAL;
+* the corner cycle cap (Sec. 3.2 stopping rule with mg_maxcyc = 1) shows in
+  the reported cycle counts;
+* blp_precondition called again with another stopping rule after a solve:
+  the next solve follows the new rule exactly as a freshly preconditioned
+  problem does; a batch whose problems have different rules is refused;
+* every scheduling variant of the triangular sweeps (one, two or four
+  workgroups per system, superstep length, loads in flight), forced on the
+  interior sweep and every corner level, gives results bit for bit equal to
+  the default schedule, forward and transposed, FP64 and FP32."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2108_13468_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+BLP_W_NOCONV, BLP_E_INVAL, BLP_E_STATE, BLP_E_NUMERIC = 1, -1, -4, -5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _problem(N=128, eps=1e-5, seed=41, **pk):
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2108_13468_amd import blp
+    inst = inputs.plain(N, eps, seed=seed)
+    p = blp.from_instance(inst)
+    return p, inst
+
+
+def test_maxit_reports_noconv_with_info():
+    p, inst = _problem()
+    p.precondition()
+    F = p.sine_rhs(inst.a)
+    for prec in ("fp64", "mixed"):
+        say("maxit=1, %s" % prec)
+        U, info = p.solve(F, tol=1e-12, maxit=1, precision=prec)
+        d = info[0]
+        assert d["status"] == BLP_W_NOCONV
+        assert d["iterations"] == 1 and d["converged"] == 0
+        assert np.isfinite(d["res"]) and 0 < d["res"] < d["norm_F"]
+        assert d["mg_cycles_min"] >= 1
+        assert np.isfinite(U.cpu().numpy()).all()
+
+
+def test_nan_rhs_is_numeric_error():
+    from paper_2108_13468_amd import blp
+    p, inst = _problem()
+    p.precondition()
+    F = p.sine_rhs(inst.a)
+    F[17] = float("nan")
+    for prec in ("fp64", "mixed"):
+        say("NaN right-hand side, %s" % prec)
+        with pytest.raises(blp.BlpError) as e:
+            p.solve(F, tol=1e-8, precision=prec)
+        assert e.value.code == BLP_E_NUMERIC
+
+
+def test_calls_out_of_order_and_bad_op():
+    import torch
+    from paper_2108_13468_amd import blp
+    p, inst = _problem()
+    F = p.sine_rhs(inst.a)
+    say("solve and M^-1 before blp_precondition")
+    with pytest.raises(blp.BlpError) as e:
+        p.solve(F, tol=1e-8)
+    assert e.value.code == BLP_E_STATE
+    with pytest.raises(blp.BlpError) as e:
+        p.apply("MINV", F)
+    assert e.value.code == BLP_E_STATE
+    # an unpreconditioned solve is allowed before set-up (plain GMRES
+    # stagnates on this operator: it only has to run and report)
+    U, info = p.solve(F, tol=1e-6, precond=False, maxit=100)
+    assert info[0]["status"] in (0, BLP_W_NOCONV) and info[0]["iterations"] > 0
+    assert np.isfinite(info[0]["res"]) and info[0]["res"] < info[0]["norm_F"]
+    y = torch.empty_like(F)
+    rc = blp.lib().blp_apply(p._h, 99, blp.C.c_void_p(F.data_ptr()), blp.C.c_void_p(y.data_ptr()),
+                             None)
+    assert rc == BLP_E_INVAL
+
+
+def test_cycle_cap_and_reprecondition():
+    """Sec. 3.2: the corner solve is a stationary iteration stopped at a
+    residual reduction (1e-3) or at the cap.  Changing the rule after a solve
+    must take effect in the next solve, for single and batched solves."""
+    from paper_2108_13468_amd import blp
+    p, inst = _problem(N=256, eps=1e-6)
+    p.precondition()
+    F = p.sine_rhs(inst.a)
+    _, i0 = p.solve(F, tol=1e-8)
+    say("default rule: cycles %d..%d" % (i0[0]["mg_cycles_min"], i0[0]["mg_cycles_max"]))
+    assert i0[0]["mg_cycles_min"] >= 2
+    for prec in ("fp64", "mixed"):
+        for rtol, cap in ((1e-3, 1), (1e-1, 20), (1e-6, 20), (1e-3, 20)):
+            p.precondition(mg_rtol=rtol, mg_maxcyc=cap)
+            U, i1 = p.solve(F, tol=1e-8, precision=prec)
+            q, _ = _problem(N=256, eps=1e-6)
+            q.precondition(mg_rtol=rtol, mg_maxcyc=cap)
+            V, i2 = q.solve(F, tol=1e-8, precision=prec)
+            a, b = i1[0], i2[0]
+            say("%s rtol=%g cap=%d: cycles %d..%d (fresh %d..%d), iterations %d (%d)" % (
+                prec, rtol, cap, a["mg_cycles_min"], a["mg_cycles_max"], b["mg_cycles_min"],
+                b["mg_cycles_max"], a["iterations"], b["iterations"]))
+            assert (a["mg_cycles_min"], a["mg_cycles_max"], a["mg_cycles_total"], a["iterations"]) == \
+                   (b["mg_cycles_min"], b["mg_cycles_max"], b["mg_cycles_total"], b["iterations"])
+            assert a["mg_cycles_max"] <= cap
+            if cap == 1:
+                assert a["mg_cycles_min"] == a["mg_cycles_max"] == 1
+            assert np.array_equal(U.cpu().numpy(), V.cpu().numpy())
+    # a fixed cycle count after an adaptive solve (the batch plan and its
+    # graphs are rebuilt)
+    p.precondition(mg_fixed=2)
+    b = blp.Batch([p], graphs=True)
+    _, i3 = b.solve([F], tol=1e-8)
+    assert i3[0]["mg_cycles_min"] == i3[0]["mg_cycles_max"] == 2
+    p.precondition(mg_fixed=3)
+    _, i4 = b.solve([F], tol=1e-8)
+    assert i4[0]["mg_cycles_min"] == i4[0]["mg_cycles_max"] == 3
+    # problems with different rules cannot share a batch
+    q, _ = _problem(N=256, eps=1e-6)
+    q.precondition(mg_rtol=1e-2)
+    with pytest.raises(blp.BlpError) as e:
+        blp.Batch([p, q]).solve([F, F], tol=1e-8)
+    assert e.value.code == BLP_E_INVAL
+
+
+@pytest.mark.parametrize("N", [128, 520, 1024])
+def test_sweep_variants_bitwise(N):
+    """N = 128: one-band interior; N = 520: five-band interior and corner
+    levels of 260 and 130 nodes; N = 1024: eight bands, levels 512/256/128."""
+    import torch
+    from paper_2108_13468_amd import blp
+    p, inst = _problem(N=N, eps=1e-6, seed=42)
+    p.precondition()
+    F = p.sine_rhs(inst.a)
+    for prec in ("fp64", "mixed"):
+        ref = None
+        for v in range(0, 8):
+            b = blp.Batch([p], sweep_variant=v)
+            U, info = b.solve([F], tol=1e-8, precision=prec)
+            L, ia = b.solve_adjoint([F], tol=1e-8, precision=prec)
+            assert info[0]["converged"] and ia[0]["converged"]
+            got = (U[0].clone(), L[0].clone(), info[0]["iterations"], ia[0]["iterations"])
+            if ref is None:
+                ref = got
+                say("N=%d %s: %d / %d iterations" % (N, prec, got[2], got[3]))
+                continue
+            assert got[2:] == ref[2:], (v, prec)
+            assert torch.equal(got[0], ref[0]), ("forward", v, prec)
+            assert torch.equal(got[1], ref[1]), ("adjoint", v, prec)
+            b.close()
