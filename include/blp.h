@@ -238,11 +238,21 @@ int blp_apply(blp_problem *p, int op, const double *x, double *y, int *cycles);
  *                   (adjoint of blp_sine_rhs); w: device, g: host K*L.
  * blp_bilinear_project: G[q*m+p] = sum_ij w_ij phi_p(x_i) phi_q(y_j)
  *                   w: device (N-1)^2, G: host m*m.
- * blp_mul: out_ij = a_ij * b_ij (device vectors), used for dJ/dr = -lambda u. */
+ * blp_mul: out_ij = a_ij * b_ij (device vectors).
+ * blp_reaction_gradient: the gradient of a misfit with respect to the
+ *                   bilinear reaction controls, through the discrete adjoint:
+ *                   A depends on r through its diagonal only, so
+ *                   dJ/dR[q*m+p] = -sum_s sum_ij Lambda_s,ij U_s,ij phi_p(x_i) phi_q(y_j)
+ *                   over the nrhs stacked pairs (Lambda_s, U_s) (device,
+ *                   nrhs x (N-1)^2 each: adjoint solutions and solutions);
+ *                   G: host m*m.  The sum over right-hand sides and the sign
+ *                   are taken on the device. */
 int blp_sine_rhs(blp_problem *p, int K, int L, const double *a, double *F);
 int blp_sine_project(blp_problem *p, int K, int L, const double *w, double *g);
 int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G);
 int blp_mul(blp_problem *p, const double *a, const double *b, double *out);
+int blp_reaction_gradient(blp_problem *p, int m, int nrhs, const double *Lambda, const double *U,
+                          double *G);
 
 /* Per-kernel-class timing with HIP events on the handle's stream.
  * enable = 1: discard earlier records and start recording an event pair

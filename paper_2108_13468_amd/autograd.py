@@ -7,7 +7,7 @@ on the interior nodes.  For a scalar J(U) the backward pass uses the discrete
 adjoint:
   A^T lambda = dJ/dU          (blp_solve_adjoint: FGMRES with M^T),
   dJ/da_kl = sum_ij lambda_ij sin(k pi x_i) sin(l pi y_j)   (blp_sine_project),
-  dJ/dR_pq = -sum_ij lambda_ij u_ij phi_p(x_i) phi_q(y_j)   (blp_mul, blp_bilinear_project),
+  dJ/dR_pq = -sum_ij lambda_ij u_ij phi_p(x_i) phi_q(y_j)   (blp_reaction_gradient),
 since F is linear in a and A depends on r only through its diagonal, with r
 the bilinear interpolant of R on control nodes {0, 1/(m-1), ..., 1} in each
 axis.  The mesh depends on eps, N and the convection bounds only, so neither
@@ -93,10 +93,8 @@ class SolveFunction(torch.autograd.Function):
         ga = np.stack([p.sine_project(lam[s], K, L) for s in range(nrhs)])
         gR = None
         if ctx.needs_input_grad[1]:
-            mR = ctx.R_shape
-            gR = np.zeros(mR)
-            for s in range(nrhs):
-                gR -= p.bilinear_project(p.mul(lam[s], U[s]), mR[0])
+            # summed over the right-hand sides, sign included, on the device
+            gR = p.reaction_gradient(lam, U, ctx.R_shape[0])
         ga_t = torch.from_numpy(ga.reshape(ctx.a_shape)).to(*ctx.a_meta)
         gR_t = None if gR is None else torch.from_numpy(gR).to(*ctx.R_meta)
         return ga_t, gR_t, None

@@ -22,7 +22,7 @@ OPS = {"A": 0, "AT": 1, "MINV": 2, "MINVT": 3, "MINV32": 4}
 # Symbols declared in include/blp.h (checked by the CPU tests).
 EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_solve",
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
-           "blp_bilinear_project", "blp_mul", "blp_timing", "blp_footprint", "blp_destroy",
+           "blp_bilinear_project", "blp_mul", "blp_reaction_gradient", "blp_timing", "blp_footprint", "blp_destroy",
            "blp_strerror", "blp_batch_create", "blp_batch_solve", "blp_batch_solve_adjoint",
            "blp_batch_footprint", "blp_batch_describe", "blp_batch_timing", "blp_batch_destroy")
 NCLASS = 7
@@ -101,6 +101,7 @@ def lib():
         L.blp_sine_project.argtypes = [vp, C.c_int, C.c_int, vp, _dp]
         L.blp_bilinear_project.argtypes = [vp, C.c_int, vp, _dp]
         L.blp_mul.argtypes = [vp, vp, vp, vp]
+        L.blp_reaction_gradient.argtypes = [vp, C.c_int, C.c_int, vp, vp, _dp]
         L.blp_timing.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_longlong), _dp]
         L.blp_footprint.restype = C.c_longlong
         L.blp_footprint.argtypes = [vp]
@@ -257,6 +258,19 @@ class Problem:
         G = np.zeros(m * m)
         _check(lib().blp_bilinear_project(self._h, m, C.c_void_p(self._vec(w).data_ptr()),
                                           G.ctypes.data_as(_dp)), "blp_bilinear_project")
+        return G.reshape(m, m)
+
+    def reaction_gradient(self, lam, U, m):
+        """dJ/dR (m x m) from the adjoint solutions lam and solutions U
+        (nrhs stacked vectors each): -sum over right-hand sides and nodes of
+        lam u phi_p(x) phi_q(y)."""
+        lam, U = self._vec(lam.reshape(-1)), self._vec(U.reshape(-1))
+        if lam.numel() != U.numel():
+            raise ValueError("lam and U must hold the same number of vectors")
+        G = np.zeros(m * m)
+        _check(lib().blp_reaction_gradient(self._h, m, lam.numel() // self.n,
+                                           C.c_void_p(lam.data_ptr()), C.c_void_p(U.data_ptr()),
+                                           G.ctypes.data_as(_dp)), "blp_reaction_gradient")
         return G.reshape(m, m)
 
     def mul(self, a, b):

@@ -792,7 +792,8 @@ int blp_sine_rhs(blp_problem *p, int K, int L, const double *a, double *F) {
   return rc;
 }
 
-static int project(blp_problem *p, int K, int L, int kind, const double *w, double *g) {
+static int project(blp_problem *p, int K, int L, int kind, int nrhs, double scale, const double *w,
+                   const double *v, double *g) {
   const int N = p->N, n1 = p->n1;
   double *xd, *yd, *tx, *ty, *t, *gd;
   std::vector<void *> tmp;
@@ -813,7 +814,7 @@ static int project(blp_problem *p, int K, int L, int kind, const double *w, doub
   } else {
     k_axis_table<<<dim3(blocks1d(N + 1), K), 256, 0, p->stream>>>(xd, N, K, kind, tx);
     k_axis_table<<<dim3(blocks1d(N + 1), L), 256, 0, p->stream>>>(yd, N, L, kind, ty);
-    k_project_rows<<<n1, 256, 0, p->stream>>>(N, K, w, tx, t);
+    k_project_rows<<<n1, 256, 0, p->stream>>>(N, K, nrhs, scale, w, v, tx, t);
     k_project_cols<<<dim3(K, L), 256, 0, p->stream>>>(N, K, t, ty, gd);
     if (hipMemcpyAsync(g, gd, (size_t)K * L * sizeof(double), hipMemcpyDeviceToHost, p->stream) ||
         hipGetLastError() != hipSuccess || hipStreamSynchronize(p->stream) != hipSuccess)
@@ -825,12 +826,18 @@ static int project(blp_problem *p, int K, int L, int kind, const double *w, doub
 
 int blp_sine_project(blp_problem *p, int K, int L, const double *w, double *g) {
   if (!p || K < 1 || L < 1 || !w || !g) return BLP_E_INVAL;
-  return project(p, K, L, 0, w, g);
+  return project(p, K, L, 0, 1, 1.0, w, nullptr, g);
 }
 
 int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G) {
   if (!p || m < 2 || !w || !G) return BLP_E_INVAL;
-  return project(p, m, m, 1, w, G);
+  return project(p, m, m, 1, 1, 1.0, w, nullptr, G);
+}
+
+int blp_reaction_gradient(blp_problem *p, int m, int nrhs, const double *Lambda, const double *U,
+                          double *G) {
+  if (!p || m < 2 || nrhs < 1 || !Lambda || !U || !G) return BLP_E_INVAL;
+  return project(p, m, m, 1, nrhs, -1.0, Lambda, U, G);
 }
 
 int blp_mul(blp_problem *p, const double *a, const double *b, double *out) {

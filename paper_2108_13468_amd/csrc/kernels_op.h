@@ -200,18 +200,25 @@ __global__ void k_synth(int N, int K, int L, const double *a, const double *tx,
 }
 
 // Projection onto separable functions, stage 1: per row j and function k,
-// t[k][j] = sum_i w_ij tx[k][i].  One block per row.
-__global__ __launch_bounds__(256) void k_project_rows(int N, int K, const double *w,
+// t[k][j] = scale sum_{s < nrhs} sum_i w_s,ij (v_s,ij) tx[k][i], with the
+// nrhs vectors of w (and of v, when given: the weight is then the product
+// w v) stacked at stride (N-1)^2.  One block per row.
+__global__ __launch_bounds__(256) void k_project_rows(int N, int K, int nrhs, double scale,
+                                                      const double *w, const double *v,
                                                       const double *tx, double *t) {
   __shared__ double sh[16];
   const int n1 = N - 1;
+  const size_t n = (size_t)n1 * n1;
   const int j = blockIdx.x + 1;
   for (int k = 0; k < K; ++k) {
     double acc = 0.0;
-    for (int i = threadIdx.x + 1; i <= n1; i += blockDim.x)
-      acc += w[vidx(i, j, n1)] * tx[(size_t)k * (N + 1) + i];
+    for (int s = 0; s < nrhs; ++s)
+      for (int i = threadIdx.x + 1; i <= n1; i += blockDim.x) {
+        const size_t q = s * n + vidx(i, j, n1);
+        acc += (v ? w[q] * v[q] : w[q]) * tx[(size_t)k * (N + 1) + i];
+      }
     acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) t[(size_t)k * n1 + (j - 1)] = acc;
+    if (threadIdx.x == 0) t[(size_t)k * n1 + (j - 1)] = scale * acc;
   }
 }
 

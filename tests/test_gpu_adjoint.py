@@ -126,3 +126,23 @@ def test_autograd_several_right_hand_sides():
         assert np.abs(ga[s] - ga1).max() <= 1e-9 * np.abs(ga1).max()
         gR_sum += gR1
     assert np.abs(gR - gR_sum).max() <= 1e-9 * np.abs(gR_sum).max()
+
+
+@pytest.mark.parametrize("m", [4, 5])
+def test_reaction_gradient_entry_point(m):
+    """blp_reaction_gradient: -sum over three stacked (lambda, u) pairs of the
+    bilinear projection of lambda u (Sec. 3's reaction term enters A only on
+    the diagonal), against the oracle's projection of each product."""
+    import torch
+    from paper_2108_13468_amd import blp
+    N, eps = 96, 1e-4
+    inst = inputs.plain(N, eps, seed=23)
+    p = blp.from_instance(inst)
+    x, y = p.nodes()
+    rng = np.random.default_rng(24)
+    lam = rng.standard_normal((3, (N - 1) ** 2))
+    u = rng.standard_normal((3, (N - 1) ** 2))
+    G = p.reaction_gradient(torch.as_tensor(lam, device="cuda"), torch.as_tensor(u, device="cuda"), m)
+    ref = -sum(O.bilinear_project(N, x, y, lam[s] * u[s], m) for s in range(3))
+    say("reaction gradient m=%d: max |G - ref| = %.2e" % (m, np.abs(G - ref).max()))
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
