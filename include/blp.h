@@ -42,6 +42,7 @@ extern "C" {
 #define BLP_E_HIP (-3)     /* a HIP runtime call or kernel launch failed    */
 #define BLP_E_STATE (-4)   /* call out of order (e.g. solve before setup)   */
 #define BLP_E_NUMERIC (-5) /* NaN or Inf met in a residual norm             */
+#define BLP_E_SCRATCH (-6) /* request larger than a fixed scratch buffer    */
 
 typedef struct blp_problem blp_problem;
 
@@ -253,6 +254,20 @@ int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G);
 int blp_mul(blp_problem *p, const double *a, const double *b, double *out);
 int blp_reaction_gradient(blp_problem *p, int m, int nrhs, const double *Lambda, const double *U,
                           double *G);
+
+/* blp_sine_project without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving or optimisation
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * stream as blp_sine_project.  Its tables and partial sums live in a fixed
+ * 4 MiB scratch array that the library holds on every GPU it runs on until
+ * the process ends: K(N+1) + L(N+1) + K(N-1) + K L doubles, each part
+ * rounded up to 256 bytes, must fit (K, L <= 64 always fit at N <= 2048).
+ * The caller's current device must be the one the problem was assembled
+ * on.  Calls on one GPU share its scratch array: calls that overlap in time
+ * on one GPU (from several host threads, or on several streams) race.
+ * Errors: BLP_E_INVAL, BLP_E_SCRATCH (tables larger than the scratch array),
+ * BLP_E_STATE (another device current), BLP_E_HIP. */
+int blp_sine_project_noalloc(blp_problem *p, int K, int L, const double *w, double *g);
 
 /* Per-kernel-class timing with HIP events on the handle's stream.
  * enable = 1: discard earlier records and start recording an event pair

@@ -22,7 +22,7 @@ OPS = {"A": 0, "AT": 1, "MINV": 2, "MINVT": 3, "MINV32": 4}
 # Symbols declared in include/blp.h (checked by the CPU tests).
 EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_solve",
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
-           "blp_bilinear_project", "blp_mul", "blp_reaction_gradient", "blp_timing", "blp_footprint", "blp_destroy",
+           "blp_bilinear_project", "blp_mul", "blp_reaction_gradient", "blp_sine_project_noalloc", "blp_timing", "blp_footprint", "blp_destroy",
            "blp_strerror", "blp_batch_create", "blp_batch_solve", "blp_batch_solve_adjoint",
            "blp_batch_footprint", "blp_batch_describe", "blp_batch_timing", "blp_batch_destroy")
 NCLASS = 7
@@ -99,6 +99,7 @@ def lib():
         L.blp_apply.argtypes = [vp, C.c_int, vp, vp, C.POINTER(C.c_int)]
         L.blp_sine_rhs.argtypes = [vp, C.c_int, C.c_int, _dp, vp]
         L.blp_sine_project.argtypes = [vp, C.c_int, C.c_int, vp, _dp]
+        L.blp_sine_project_noalloc.argtypes = [vp, C.c_int, C.c_int, vp, _dp]
         L.blp_bilinear_project.argtypes = [vp, C.c_int, vp, _dp]
         L.blp_mul.argtypes = [vp, vp, vp, vp]
         L.blp_reaction_gradient.argtypes = [vp, C.c_int, C.c_int, vp, vp, _dp]
@@ -252,6 +253,14 @@ class Problem:
         g = np.zeros(K * L)
         _check(lib().blp_sine_project(self._h, K, L, C.c_void_p(self._vec(w).data_ptr()),
                                       g.ctypes.data_as(_dp)), "blp_sine_project")
+        return g.reshape(L, K)
+
+    def sine_project_noalloc(self, w, K, L):
+        """As sine_project, through the allocation-free entry point (fixed
+        scratch array; raises BlpError with code -6 when it does not fit)."""
+        g = np.zeros(K * L)
+        _check(lib().blp_sine_project_noalloc(self._h, K, L, C.c_void_p(self._vec(w).data_ptr()),
+                                              g.ctypes.data_as(_dp)), "blp_sine_project_noalloc")
         return g.reshape(L, K)
 
     def bilinear_project(self, w, m):

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <chrono>
@@ -151,6 +152,8 @@ struct blp_problem {
   double eps;
   hipStream_t stream;
   std::vector<double> xn, yn, wx, wy, c1, c2;  // nodes, widths (1..N), coefficients (0..N)
+  int device = -1;                  // current device at assemble
+  double *xd = nullptr, *yd = nullptr;  // nodes on the device (N + 1 each)
   AxisTab fx, fy;
   bool r_nodal = false;
   double rc = 0.0;
@@ -577,6 +580,10 @@ int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2, co
   p->n = (size_t)(N - 1) * (N - 1);
   p->eps = eps;
   p->stream = (hipStream_t)stream;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return BLP_E_HIP;
+  }
   axis_mesh(N, shishkin_tau(N, eps, sigma, clx), p->xn, p->wx);
   axis_mesh(N, shishkin_tau(N, eps, sigma, cly), p->yn, p->wy);
   p->c1.assign(N + 1, 0.0);
@@ -592,7 +599,8 @@ int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2, co
     blp_destroy(p);
     return code;
   };
-  if ((rc = p->upload(&p->f64.W, p->fx.W)) || (rc = p->upload(&p->f64.E, p->fx.E)) ||
+  if ((rc = p->upload(&p->xd, p->xn)) || (rc = p->upload(&p->yd, p->yn)) ||
+      (rc = p->upload(&p->f64.W, p->fx.W)) || (rc = p->upload(&p->f64.E, p->fx.E)) ||
       (rc = p->upload(&p->f64.Dx, p->fx.D)) || (rc = p->upload(&p->f64.S, p->fy.W)) ||
       (rc = p->upload(&p->f64.N, p->fy.E)) || (rc = p->upload(&p->f64.Dy, p->fy.D)) ||
       (rc = p->upload(&p->f32.W, p->fx.W)) || (rc = p->upload(&p->f32.E, p->fx.E)) ||
@@ -792,6 +800,37 @@ int blp_sine_rhs(blp_problem *p, int K, int L, const double *a, double *F) {
   return rc;
 }
 
+// Scratch of the allocation-free projection (blp_sine_project_noalloc): a
+// fixed array that every GPU the library runs on holds once, at its own
+// address, until the process ends.  Host code never uses this name as an
+// address: the device address is looked up per device (scratch_ptr) and
+// passed to the kernels.  Calls that overlap on one GPU share it and race.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// This GPU's scratch address, looked up once per device with that device
+// current (the caller's current device, which must be the problem's).
+int scratch_ptr(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return BLP_E_STATE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return BLP_E_HIP;
+    g_scratch_ptr[dev] = static_cast<double *>(q);
+  }
+  *out = g_scratch_ptr[dev];
+  return BLP_OK;
+}
+
+// doubles rounded up to whole 256-byte blocks
+size_t scratch_words(size_t words) { return (words + 31) / 32 * 32; }
+}  // namespace
+
 static int project(blp_problem *p, int K, int L, int kind, int nrhs, double scale, const double *w,
                    const double *v, double *g) {
   const int N = p->N, n1 = p->n1;
@@ -832,6 +871,30 @@ int blp_sine_project(blp_problem *p, int K, int L, const double *w, double *g) {
 int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G) {
   if (!p || m < 2 || !w || !G) return BLP_E_INVAL;
   return project(p, m, m, 1, 1, 1.0, w, nullptr, G);
+}
+
+int blp_sine_project_noalloc(blp_problem *p, int K, int L, const double *w, double *g) {
+  if (!p || K < 1 || L < 1 || !w || !g) return BLP_E_INVAL;
+  const int N = p->N, n1 = p->n1;
+  // tables of the two axes, row partials and the K x L result
+  const size_t ntx = scratch_words((size_t)K * (N + 1)), nty = scratch_words((size_t)L * (N + 1));
+  const size_t nt = scratch_words((size_t)K * n1), ng = scratch_words((size_t)K * L);
+  if ((ntx + nty + nt + ng) * sizeof(double) > kScratchBytes) return BLP_E_SCRATCH;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return BLP_E_STATE;
+  double *base = nullptr;
+  BLP_TRY(scratch_ptr(dev, &base));
+  // every word read below is written first in the same call: nothing to clear
+  double *tx = base, *ty = tx + ntx, *t = ty + nty, *gd = t + nt;
+  k_axis_table<<<dim3(blocks1d(N + 1), K), 256, 0, p->stream>>>(p->xd, N, K, 0, tx);
+  k_axis_table<<<dim3(blocks1d(N + 1), L), 256, 0, p->stream>>>(p->yd, N, L, 0, ty);
+  k_project_rows<<<n1, 256, 0, p->stream>>>(N, K, 1, 1.0, w, nullptr, tx, t);
+  k_project_cols<<<dim3(K, L), 256, 0, p->stream>>>(N, K, t, ty, gd);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(g, gd, (size_t)K * L * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return BLP_OK;
 }
 
 int blp_reaction_gradient(blp_problem *p, int m, int nrhs, const double *Lambda, const double *U,
@@ -879,6 +942,7 @@ const char *blp_strerror(int code) {
     case BLP_E_HIP: return "HIP runtime error";
     case BLP_E_STATE: return "call out of order";
     case BLP_E_NUMERIC: return "NaN or Inf in a residual";
+    case BLP_E_SCRATCH: return "request exceeds the fixed scratch buffer of the allocation-free call";
     default: return "unknown error";
   }
 }
