@@ -66,26 +66,52 @@ typedef struct {
   const double *v;
 } blp_field;
 
-/* Shishkin mesh parameters (eq. tau exponential): sigma and the lower bounds
- * clow_x <= c1, clow_y <= c2.  The workloads use sigma = 2, clow = 1; the
- * paper's Sec. 3.3 tests use sigma = 5/2. */
+/* Mesh parameters.  The paper's mesh (Sec. 3 eq. tau exponential) is the
+ * tensor Shishkin mesh: per axis, tau = min(1/2, sigma eps ln(N) / clow) and
+ * N/2 equal cells on each side of it; clow_x <= c1 and clow_y <= c2 are the
+ * lower bounds of the convection.  The workloads use sigma = 2, clow = 1; the
+ * paper's Sec. 3.3 tests use sigma = 5/2.  Sec. 3 admits any fitted tensor
+ * mesh with a transition point between the layer and the interior, and
+ * Sec. 2.2 (remark on the general Shishkin mesh) lets the layer hold a
+ * fraction q of the cells:
+ *   kind         BLP_MESH_SHISHKIN: equal layer cells,
+ *                tau = min(q, sigma eps ln(N) / clow);
+ *                BLP_MESH_BAKHVALOV_SHISHKIN: tau = sigma eps ln(N) / clow
+ *                and graded layer cells that make exp(-clow x / (sigma eps))
+ *                fall in equal steps from 1 at x = 0 to 1/N at tau,
+ *                x_i = -(sigma eps / clow) ln(1 - (1 - 1/N) i / (qN))
+ *                (a uniform mesh when sigma eps ln(N) / clow >= q)
+ *   layer_cells  qN, the cells on [0, tau] per axis (2 <= qN <= N-2;
+ *                0 = N/2); the layer side of each axis (regions of Sec. 3.1)
+ *                is then i <= qN, and the corner multigrid coarsens it by
+ *                halving while the node count is even.
+ * The interior cells are equal in every case. */
+#define BLP_MESH_SHISHKIN 0
+#define BLP_MESH_BAKHVALOV_SHISHKIN 1
 typedef struct {
   double sigma;
   double clow_x, clow_y;
+  int kind;
+  int layer_cells;
 } blp_mesh_opts;
 
-/* One mesh axis: nodes[0..N] (host, N+1 doubles).  Returns tau through
- * *tau (may be NULL).  Pure host computation in FP64.  Errors: BLP_E_INVAL
- * for odd N, N < 4, eps outside (0,1] or non-positive sigma/clow. */
-int blp_mesh(int N, double eps, double sigma, double clow, double *nodes,
+/* Mesh nodes of both axes: x[0..N], y[0..N] (host, N+1 doubles each), and
+ * through tau (host, 2 doubles, may be NULL) the transition points tau_x,
+ * tau_y.  opts may be NULL (the paper's Shishkin mesh, sigma = 2,
+ * clow = 1).  Pure host computation in FP64.  Errors: BLP_E_INVAL for odd
+ * N, N < 4, eps outside (0,1], non-positive sigma or clow, an unknown kind
+ * or layer_cells outside its range. */
+int blp_mesh(int N, double eps, const blp_mesh_opts *opts, double *x, double *y,
              double *tau);
 
 /* Build the discrete operator on the device (Sec. 3, 2D stencil) and the
  * per-axis stencil tables; uploads r (BLP_BILINEAR controls are expanded to
  * nodal values by a kernel).  stream: a hipStream_t (NULL = default stream)
- * that every later call on this handle uses.  Errors: BLP_E_INVAL (odd N,
- * N < 4 or N > 2048, eps outside (0,1], c1 <= 0, c2 < 0, r < 0, NaN, bad field kind),
- * BLP_E_NOMEM, BLP_E_HIP. */
+ * that every later call on this handle uses.  mesh may be NULL (see
+ * blp_mesh_opts).  Errors: BLP_E_INVAL (odd N, N < 4 or N > 2048, eps
+ * outside (0,1], c1 <= 0, c2 < 0, r < 0, NaN, bad field kind, bad mesh
+ * options, or regions larger than the kernels hold: more than 1024 layer
+ * cells or more than 1024 interior nodes per axis), BLP_E_NOMEM, BLP_E_HIP. */
 int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2,
                  const blp_field *r, const blp_mesh_opts *mesh, void *stream,
                  blp_problem **out);

@@ -8,8 +8,8 @@
  *
  * Readings taken where the paper is silent:
  *  - unknowns are the interior nodes 1 <= i, j <= N-1 (Sec. 3 stencil);
- *  - the layer side of each axis is i <= N/2 (transition node included in
- *    the layer, Sec. 3.1 region definition);
+ *  - the layer side of each axis is i <= h, h = N/2 for the paper's meshes
+ *    (transition node included in the layer, Sec. 3.1 region definition);
  *  - corner multigrid level l+1 keeps the even-numbered nodes of level l, so
  *    the transition node is always kept; the node beyond the transition node
  *    (first interior-mesh node) is a fixed zero "exterior" node at the same
@@ -30,18 +30,49 @@
 
 double orc_mesh_axis(int N, double eps, double sigma, double clow,
                      double *nodes, double *widths) {
-  double tau = sigma * eps * log((double)N) / clow;
-  if (tau > 0.5) tau = 0.5;
-  double hl = 2.0 * tau / N;          /* N/2 cells on [0, tau]  */
-  double hi = 2.0 * (1.0 - tau) / N;  /* N/2 cells on [tau, 1]  */
-  for (int k = 0; k <= N; ++k) {
-    if (k <= N / 2)
-      nodes[k] = k * hl;
-    else
-      nodes[k] = tau + (k - N / 2) * hi;
-  }
+  return orc_mesh_axis_ex(N, eps, sigma, clow, 0, N / 2, nodes, widths);
+}
+
+/* Layer-adapted meshes with nl cells in the layer [0, tau] and N - nl equal
+ * cells on [tau, 1] (Sec. 2.2's remark on Linss's general Shishkin mesh, with
+ * q = nl / N; Sec. 3 allows any fitted tensor mesh with a transition point).
+ *  kind 0 (Shishkin): tau = min(q, sigma eps ln(N) / clow), equal layer cells.
+ *  kind 1 (Bakhvalov-Shishkin): tau = sigma eps ln(N) / clow; the layer nodes
+ *    equidistribute the layer function: exp(-clow x_i / (sigma eps)) falls
+ *    linearly in i from 1 at i = 0 to 1/N at i = nl, i.e.
+ *    x_i = -(sigma eps / clow) ln(1 - (1 - 1/N) i / nl).
+ *    When sigma eps ln(N) / clow >= q the mesh is uniform (as the Shishkin
+ *    mesh is then).
+ * Widths come from closed forms, never from differences of nodes. */
+double orc_mesh_axis_ex(int N, double eps, double sigma, double clow, int kind, int nl,
+                        double *nodes, double *widths) {
+  double q = (double)nl / N;
+  double tl = sigma * eps * log((double)N) / clow;
+  double tau = tl < q ? tl : q;
+  int graded = kind == 1 && tl < q;
+  double hl = tau / nl;             /* Shishkin layer cells */
+  double hi = (1.0 - tau) / (N - nl); /* interior cells       */
+  double s = sigma * eps / clow, a = (1.0 - 1.0 / N) / nl;
   widths[0] = 0.0;
-  for (int k = 1; k <= N; ++k) widths[k] = (k <= N / 2) ? hl : hi;
+  nodes[0] = 0.0;
+  for (int k = 1; k <= N; ++k) {
+    if (k < nl) {
+      if (graded) {
+        /* x_k = -s ln(1 - a k);  h_k = s ln((1 - a (k-1)) / (1 - a k)) */
+        nodes[k] = -s * log1p(-a * k);
+        widths[k] = s * log1p(a / (1.0 - a * k));
+      } else {
+        nodes[k] = k * hl;
+        widths[k] = hl;
+      }
+    } else if (k == nl) {
+      nodes[k] = tau;
+      widths[k] = graded ? s * log1p(a / (1.0 - a * k)) : hl;
+    } else {
+      nodes[k] = tau + (k - nl) * hi;
+      widths[k] = hi;
+    }
+  }
   return tau;
 }
 
@@ -129,7 +160,7 @@ static double nrm2(int n, const double *a) { return sqrt(dot(n, a, a)); }
 /* ------------------------------------------------------------------------ */
 
 struct orc_problem {
-  int N, n1, h; /* n1 = N-1 unknowns per axis, h = N/2 */
+  int N, n1, h; /* n1 = N-1 unknowns per axis, h = layer cells (N/2 by default) */
   double *xn, *yn;
   grid fine;
   int L;       /* corner multigrid levels; lev[0] is the corner block A_CC */
@@ -161,17 +192,23 @@ static void grid_free(grid *g) {
 orc_problem *orc_create(int N, double eps, double sigma, double clow_x,
                         double clow_y, const double *c1x, const double *c2y,
                         const double *r_int) {
-  if (N < 4 || N % 2) return NULL;
+  return orc_create_ex(N, eps, sigma, clow_x, clow_y, 0, N / 2, c1x, c2y, r_int);
+}
+
+orc_problem *orc_create_ex(int N, double eps, double sigma, double clow_x,
+                           double clow_y, int kind, int nl, const double *c1x,
+                           const double *c2y, const double *r_int) {
+  if (N < 4 || N % 2 || nl < 2 || nl > N - 2 || kind < 0 || kind > 1) return NULL;
   orc_problem *p = calloc(1, sizeof(*p));
   p->N = N;
   p->n1 = N - 1;
-  p->h = N / 2;
+  p->h = nl; /* last node of the layer side of each axis */
   p->xn = calloc(N + 1, sizeof(double));
   p->yn = calloc(N + 1, sizeof(double));
   double *wx = calloc(N + 2, sizeof(double));
   double *wy = calloc(N + 2, sizeof(double));
-  orc_mesh_axis(N, eps, sigma, clow_x, p->xn, wx);
-  orc_mesh_axis(N, eps, sigma, clow_y, p->yn, wy);
+  orc_mesh_axis_ex(N, eps, sigma, clow_x, kind, nl, p->xn, wx);
+  orc_mesh_axis_ex(N, eps, sigma, clow_y, kind, nl, p->yn, wy);
 
   p->fine = grid_alloc(p->n1, p->n1, eps);
   for (int k = 1; k <= N; ++k) {

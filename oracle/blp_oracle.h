@@ -29,6 +29,14 @@ extern "C" {
 double orc_mesh_axis(int N, double eps, double sigma, double clow,
                      double *nodes, double *widths);
 
+/* General layer-adapted axis: nl cells on the layer [0, tau], N - nl equal
+ * cells on [tau, 1].  kind 0: Shishkin, tau = min(nl/N, sigma eps ln N /
+ * clow), equal layer cells; kind 1: Bakhvalov-Shishkin, graded layer cells
+ * equidistributing exp(-clow x / (sigma eps)) (uniform mesh when
+ * sigma eps ln N / clow >= nl/N).  Returns tau. */
+double orc_mesh_axis_ex(int N, double eps, double sigma, double clow, int kind, int nl,
+                        double *nodes, double *widths);
+
 /* Opaque problem: the full grid operator plus its corner multigrid levels. */
 typedef struct orc_problem orc_problem;
 
@@ -37,6 +45,12 @@ typedef struct orc_problem orc_problem;
 orc_problem *orc_create(int N, double eps, double sigma, double clow_x,
                         double clow_y, const double *c1x, const double *c2y,
                         const double *r_int);
+/* The same on the general mesh of orc_mesh_axis_ex (kind, nl on both axes);
+ * the layer side of each axis is then i <= nl.  NULL for nl outside
+ * [2, N-2] or an unknown kind. */
+orc_problem *orc_create_ex(int N, double eps, double sigma, double clow_x,
+                           double clow_y, int kind, int nl, const double *c1x,
+                           const double *c2y, const double *r_int);
 void orc_destroy(orc_problem *p);
 
 int orc_n(const orc_problem *p);             /* (N-1)^2 */

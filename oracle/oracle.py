@@ -49,6 +49,12 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                  _dp, _dp, _dp]
+        L.orc_mesh_axis_ex.restype = C.c_double
+        L.orc_mesh_axis_ex.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
+                                       C.c_int, _dp, _dp]
+        L.orc_create_ex.restype = C.c_void_p
+        L.orc_create_ex.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_destroy.argtypes = [C.c_void_p]
         for f in ("orc_n", "orc_num_levels"):
             getattr(L, f).restype = C.c_int
@@ -91,10 +97,18 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def mesh_axis(N, eps, sigma=2.0, clow=1.0):
+MESH_KINDS = {"shishkin": 0, "bakhvalov-shishkin": 1}
+
+
+def mesh_axis(N, eps, sigma=2.0, clow=1.0, kind="shishkin", layer_cells=None):
+    """One axis of the layer-adapted mesh: (tau, nodes[0..N], widths[0..N]).
+    kind 'shishkin' or 'bakhvalov-shishkin'; layer_cells = cells on [0, tau]
+    (default N/2)."""
     nodes = np.zeros(N + 1)
     widths = np.zeros(N + 2)
-    tau = lib().orc_mesh_axis(N, eps, sigma, clow, _p(nodes), _p(widths))
+    nl = N // 2 if layer_cells is None else int(layer_cells)
+    tau = lib().orc_mesh_axis_ex(N, eps, sigma, clow, MESH_KINDS[kind], nl, _p(nodes),
+                                 _p(widths))
     return tau, nodes, widths[: N + 1]
 
 
@@ -103,10 +117,11 @@ class Problem:
     boundary-layer preconditioner and FGMRES of the paper (FP64, CPU)."""
 
     def __init__(self, N, eps, c1=None, c2=None, r=None, sigma=2.0, clow_x=1.0,
-                 clow_y=1.0):
+                 clow_y=1.0, mesh_kind="shishkin", layer_cells=None):
         self.N, self.eps, self.n1 = N, eps, N - 1
-        tx, self.x, self.hx = mesh_axis(N, eps, sigma, clow_x)
-        ty, self.y, self.hy = mesh_axis(N, eps, sigma, clow_y)
+        nl = N // 2 if layer_cells is None else int(layer_cells)
+        tx, self.x, self.hx = mesh_axis(N, eps, sigma, clow_x, mesh_kind, nl)
+        ty, self.y, self.hy = mesh_axis(N, eps, sigma, clow_y, mesh_kind, nl)
         self.tau_x, self.tau_y = tx, ty
         c1x = _f64(c1(self.x) if callable(c1) else (np.ones(N + 1) if c1 is None else c1))
         c2y = _f64(c2(self.y) if callable(c2) else (np.ones(N + 1) if c2 is None else c2))
@@ -117,11 +132,12 @@ class Problem:
         else:
             rr = _f64(r).ravel()
         self.c1x, self.c2y, self.r = c1x, c2y, rr
-        self._h = lib().orc_create(N, eps, sigma, clow_x, clow_y, _p(c1x), _p(c2y), _p(rr))
+        self._h = lib().orc_create_ex(N, eps, sigma, clow_x, clow_y, MESH_KINDS[mesh_kind], nl,
+                                      _p(c1x), _p(c2y), _p(rr))
         if not self._h:
-            raise ValueError("orc_create rejected N=%r" % N)
+            raise ValueError("orc_create_ex rejected N=%r, layer cells %r" % (N, nl))
         self.n = self.n1 * self.n1
-        self.h = N // 2
+        self.h = nl
 
     def __del__(self):
         h = getattr(self, "_h", None)

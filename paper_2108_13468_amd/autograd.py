@@ -29,8 +29,7 @@ class Solver:
     def __init__(self, N, eps, c1, c2, sigma=2.0, clow=(1.0, 1.0), tol=1e-12, scaled=True,
                  precision="fp64", restart=50, maxit=2000, mg_fixed=0):
         self.N, self.eps, self.sigma, self.clow = N, eps, sigma, tuple(clow)
-        _, x = blp.mesh(N, eps, sigma, self.clow[0])
-        _, y = blp.mesh(N, eps, sigma, self.clow[1])
+        _, x, y = blp.mesh(N, eps, sigma, self.clow)
         self.c1 = np.asarray(c1(x) if callable(c1) else c1, dtype=np.float64)
         self.c2 = np.asarray(c2(y) if callable(c2) else c2, dtype=np.float64)
         self.opts = dict(tol=tol, scaled=scaled, precision=precision, restart=restart, maxit=maxit)

@@ -36,7 +36,15 @@ class Field(C.Structure):
 
 
 class MeshOpts(C.Structure):
-    _fields_ = [("sigma", C.c_double), ("clow_x", C.c_double), ("clow_y", C.c_double)]
+    _fields_ = [("sigma", C.c_double), ("clow_x", C.c_double), ("clow_y", C.c_double),
+                ("kind", C.c_int), ("layer_cells", C.c_int)]
+
+
+MESH_KINDS = {"shishkin": 0, "bakhvalov-shishkin": 1}
+
+
+def _mesh_opts(sigma, clow, kind, layer_cells):
+    return MeshOpts(sigma, clow[0], clow[1], MESH_KINDS[kind], int(layer_cells or 0))
 
 
 class PrecOpts(C.Structure):
@@ -88,7 +96,7 @@ def lib():
                            "(or python paper_2108_13468_amd/build.py)")
         L = C.CDLL(LIBPATH)
         vp = C.c_void_p
-        L.blp_mesh.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp]
+        L.blp_mesh.argtypes = [C.c_int, C.c_double, C.POINTER(MeshOpts), _dp, _dp, _dp]
         L.blp_assemble.argtypes = [C.c_int, C.c_double, C.POINTER(Field), C.POINTER(Field),
                                    C.POINTER(Field), C.POINTER(MeshOpts), vp, C.POINTER(vp)]
         L.blp_nodes.argtypes = [vp, _dp, _dp]
@@ -133,11 +141,13 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def mesh(N, eps, sigma=2.0, clow=1.0):
-    nodes = np.zeros(N + 1)
-    tau = C.c_double()
-    _check(lib().blp_mesh(N, eps, sigma, clow, nodes.ctypes.data_as(_dp), C.byref(tau)), "blp_mesh")
-    return tau.value, nodes
+def mesh(N, eps, sigma=2.0, clow=(1.0, 1.0), kind="shishkin", layer_cells=None):
+    """Mesh nodes of both axes: ((tau_x, tau_y), x[0..N], y[0..N])."""
+    x, y, tau = np.zeros(N + 1), np.zeros(N + 1), np.zeros(2)
+    o = _mesh_opts(sigma, clow, kind, layer_cells)
+    _check(lib().blp_mesh(N, eps, C.byref(o), x.ctypes.data_as(_dp), y.ctypes.data_as(_dp),
+                          tau.ctypes.data_as(_dp)), "blp_mesh")
+    return (float(tau[0]), float(tau[1])), x, y
 
 
 def _field(spec, N, keep):
@@ -157,7 +167,8 @@ def _field(spec, N, keep):
 class Problem:
     """An assembled operator on the device (one handle of the C library)."""
 
-    def __init__(self, N, eps, c1, c2, r, sigma=2.0, clow=(1.0, 1.0), stream=None):
+    def __init__(self, N, eps, c1, c2, r, sigma=2.0, clow=(1.0, 1.0), stream=None,
+                 mesh_kind="shishkin", layer_cells=None):
         import torch
         self.torch = torch
         self.N, self.eps, self.n = N, eps, (N - 1) ** 2
@@ -167,7 +178,7 @@ class Problem:
         self.stream = stream
         keep = []
         f1, f2, fr = _field(c1, N, keep), _field(c2, N, keep), _field(r, N, keep)
-        mo = MeshOpts(sigma, clow[0], clow[1])
+        mo = _mesh_opts(sigma, clow, mesh_kind, layer_cells)
         h = C.c_void_p()
         _check(lib().blp_assemble(N, eps, C.byref(f1), C.byref(f2), C.byref(fr), C.byref(mo),
                                   C.c_void_p(stream.cuda_stream), C.byref(h)), "blp_assemble")
@@ -308,8 +319,7 @@ class Problem:
 def from_instance(inst, nodal_r=None):
     """Assemble a problem from an inputs.Instance (coefficients sampled at the
     mesh nodes, which blp_mesh returns)."""
-    _, x = mesh(inst.N, inst.eps, inst.sigma, inst.clow[0])
-    _, y = mesh(inst.N, inst.eps, inst.sigma, inst.clow[1])
+    _, x, y = mesh(inst.N, inst.eps, inst.sigma, inst.clow, inst.mesh_kind, inst.layer_cells)
     if inst.r_ctrl is not None:
         r = ("bilinear", inst.r_ctrl)
     elif nodal_r is not None:
@@ -317,7 +327,8 @@ def from_instance(inst, nodal_r=None):
     else:
         r = float(inst.r_const)
     return Problem(inst.N, inst.eps, ("axis", inst.c1_at(x)), ("axis", inst.c2_at(y)), r,
-                   sigma=inst.sigma, clow=inst.clow)
+                   sigma=inst.sigma, clow=inst.clow, mesh_kind=inst.mesh_kind,
+                   layer_cells=inst.layer_cells)
 
 
 class Batch:

@@ -263,18 +263,48 @@ bool finite_all(const double *v, size_t n) {
   return true;
 }
 
-double shishkin_tau(int N, double eps, double sigma, double clow) {
-  return std::min(0.5, sigma * eps * std::log((double)N) / clow);
-}
-
-// Widths of one axis: 2 tau / N on the N/2 layer cells, 2 (1 - tau) / N on the
-// others, taken from the closed form (never as differences of coordinates).
-void axis_mesh(int N, double tau, std::vector<double> &nodes, std::vector<double> &w) {
+// One axis of a layer-adapted mesh: nl cells on the layer [0, tau], N - nl
+// equal cells on [tau, 1] (Sec. 2.2's general Shishkin construction, q =
+// nl / N; Sec. 3 admits any fitted tensor mesh with a transition point).
+// BLP_MESH_SHISHKIN: tau = min(q, sigma eps ln N / clow), equal layer cells.
+// BLP_MESH_BAKHVALOV_SHISHKIN: tau = sigma eps ln N / clow, and the layer
+// nodes make exp(-clow x / (sigma eps)) fall in equal steps from 1 to 1/N:
+// x_i = -(sigma eps / clow) ln(1 - (1 - 1/N) i / nl); uniform mesh when that
+// tau reaches q.  Widths are taken from the closed forms (never as
+// differences of coordinates): w[k] = x_k - x_{k-1}, w[0] = w[N+1] = 0.
+// Returns tau.
+double axis_mesh(int N, double eps, double sigma, double clow, int kind, int nl,
+                 std::vector<double> &nodes, std::vector<double> &w) {
   nodes.assign(N + 1, 0.0);
   w.assign(N + 2, 0.0);
-  const double hl = 2.0 * tau / N, hi = 2.0 * (1.0 - tau) / N;
-  for (int k = 0; k <= N; ++k) nodes[k] = k <= N / 2 ? k * hl : tau + (k - N / 2) * hi;
-  for (int k = 1; k <= N; ++k) w[k] = k <= N / 2 ? hl : hi;
+  const double q = (double)nl / N, layer = sigma * eps * std::log((double)N) / clow;
+  const double tau = std::min(q, layer);
+  const bool graded = kind == BLP_MESH_BAKHVALOV_SHISHKIN && layer < q;
+  const double hl = tau / nl, hi = (1.0 - tau) / (N - nl);
+  const double s = sigma * eps / clow, a = (1.0 - 1.0 / N) / nl;
+  for (int k = 1; k <= nl; ++k) {
+    w[k] = graded ? s * std::log1p(a / (1.0 - a * k)) : hl;
+    nodes[k] = k == nl ? tau : (graded ? -s * std::log1p(-a * k) : k * hl);
+  }
+  for (int k = nl + 1; k <= N; ++k) {
+    w[k] = hi;
+    nodes[k] = tau + (k - nl) * hi;
+  }
+  return tau;
+}
+
+// Mesh options with defaults filled in (NULL: the paper's Shishkin mesh,
+// sigma = 2, clow = 1, N/2 layer cells); BLP_E_INVAL when outside the
+// constructions above.
+int mesh_options(int N, const blp_mesh_opts *o, blp_mesh_opts *out) {
+  blp_mesh_opts m{2.0, 1.0, 1.0, BLP_MESH_SHISHKIN, 0};
+  if (o) m = *o;
+  if (m.layer_cells == 0) m.layer_cells = N / 2;
+  if (!(m.sigma > 0) || !(m.clow_x > 0) || !(m.clow_y > 0)) return BLP_E_INVAL;
+  if (m.kind != BLP_MESH_SHISHKIN && m.kind != BLP_MESH_BAKHVALOV_SHISHKIN) return BLP_E_INVAL;
+  if (m.layer_cells < 2 || m.layer_cells > N - 2) return BLP_E_INVAL;
+  *out = m;
+  return BLP_OK;
 }
 
 // ------------------------------------------------------------------------ //
@@ -548,14 +578,19 @@ int check_field(const blp_field *f, int N, bool allow_nodal, double lo, bool str
 
 extern "C" {
 
-int blp_mesh(int N, double eps, double sigma, double clow, double *nodes, double *tau) {
-  if (N < 4 || N % 2 || !(eps > 0 && eps <= 1) || !(sigma > 0) || !(clow > 0) || !nodes)
-    return BLP_E_INVAL;
-  const double t = shishkin_tau(N, eps, sigma, clow);
-  std::vector<double> x, w;
-  axis_mesh(N, t, x, w);
-  std::memcpy(nodes, x.data(), sizeof(double) * (N + 1));
-  if (tau) *tau = t;
+int blp_mesh(int N, double eps, const blp_mesh_opts *o, double *x, double *y, double *tau) {
+  if (N < 4 || N % 2 || !(eps > 0 && eps <= 1) || !x || !y) return BLP_E_INVAL;
+  blp_mesh_opts m;
+  BLP_TRY(mesh_options(N, o, &m));
+  std::vector<double> nodes, w;
+  const double tx = axis_mesh(N, eps, m.sigma, m.clow_x, m.kind, m.layer_cells, nodes, w);
+  std::memcpy(x, nodes.data(), sizeof(double) * (N + 1));
+  const double ty = axis_mesh(N, eps, m.sigma, m.clow_y, m.kind, m.layer_cells, nodes, w);
+  std::memcpy(y, nodes.data(), sizeof(double) * (N + 1));
+  if (tau) {
+    tau[0] = tx;
+    tau[1] = ty;
+  }
   return BLP_OK;
 }
 
@@ -568,15 +603,17 @@ int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2, co
   BLP_TRY(check_field(c1, N, false, 0.0, true));
   BLP_TRY(check_field(c2, N, false, 0.0, false));
   BLP_TRY(check_field(r, N, true, 0.0, false));
-  const double sigma = mesh ? mesh->sigma : 2.0;
-  const double clx = mesh ? mesh->clow_x : 1.0, cly = mesh ? mesh->clow_y : 1.0;
-  if (!(sigma > 0) || !(clx > 0) || !(cly > 0)) return BLP_E_INVAL;
+  blp_mesh_opts m;
+  BLP_TRY(mesh_options(N, mesh, &m));
+  // region sizes the kernels hold: edge lines of at most 1024 nodes, an
+  // interior sweep of at most 16 bands of 64 columns
+  if (m.layer_cells > 1024 || N - 1 - m.layer_cells > 1024) return BLP_E_INVAL;
 
   blp_problem *p = new (std::nothrow) blp_problem();
   if (!p) return BLP_E_NOMEM;
   p->N = N;
   p->n1 = N - 1;
-  p->h = N / 2;
+  p->h = m.layer_cells;
   p->n = (size_t)(N - 1) * (N - 1);
   p->eps = eps;
   p->stream = (hipStream_t)stream;
@@ -584,8 +621,8 @@ int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2, co
     delete p;
     return BLP_E_HIP;
   }
-  axis_mesh(N, shishkin_tau(N, eps, sigma, clx), p->xn, p->wx);
-  axis_mesh(N, shishkin_tau(N, eps, sigma, cly), p->yn, p->wy);
+  axis_mesh(N, eps, m.sigma, m.clow_x, m.kind, m.layer_cells, p->xn, p->wx);
+  axis_mesh(N, eps, m.sigma, m.clow_y, m.kind, m.layer_cells, p->yn, p->wy);
   p->c1.assign(N + 1, 0.0);
   p->c2.assign(N + 1, 0.0);
   for (int k = 0; k <= N; ++k) {

@@ -31,6 +31,8 @@ class Instance:
     a: np.ndarray = field(default_factory=lambda: np.zeros((3, 3)))  # [l-1, k-1]
     sigma: float = 2.0
     clow: Tuple[float, float] = (1.0, 1.0)
+    mesh_kind: str = "shishkin"          # or "bakhvalov-shishkin"
+    layer_cells: Optional[int] = None    # cells on [0, tau] per axis (None: N/2)
 
     def c1_at(self, x):
         c = self.c1

@@ -33,10 +33,30 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("N,eps,sigma,clow", [(64, 1e-2, 2.0, 1.0), (1024, 1e-6, 2.0, 1.0),
                                               (256, 1e-4, 2.5, 3.0), (8, 1.0, 2.0, 1.0)])
 def test_mesh_matches_oracle(N, eps, sigma, clow):
-    tau, x = blp.mesh(N, eps, sigma, clow)
+    (tau, _), x, _ = blp.mesh(N, eps, sigma, (clow, 1.0))
     tau_o, x_o, _ = O.mesh_axis(N, eps, sigma, clow)
     assert tau == tau_o
     np.testing.assert_array_equal(x, x_o)
+
+
+@pytest.mark.parametrize("kind", ["shishkin", "bakhvalov-shishkin"])
+@pytest.mark.parametrize("N,eps,nl", [(64, 1e-4, None), (1024, 1e-6, 256), (512, 1e-5, 384),
+                                      (128, 0.5, None), (256, 1e-8, 64)])
+def test_general_mesh_matches_oracle(kind, N, eps, nl):
+    (tx, ty), x, y = blp.mesh(N, eps, 2.5, (2.0, 3.0), kind, nl)
+    tx_o, x_o, _ = O.mesh_axis(N, eps, 2.5, 2.0, kind, nl)
+    ty_o, y_o, _ = O.mesh_axis(N, eps, 2.5, 3.0, kind, nl)
+    assert (tx, ty) == (tx_o, ty_o)
+    # the two sides evaluate the same closed forms; allow one rounding
+    np.testing.assert_allclose(x, x_o, rtol=4e-16, atol=0)
+    np.testing.assert_allclose(y, y_o, rtol=4e-16, atol=0)
+
+
+@pytest.mark.parametrize("kind,nl", [("shishkin", 64), ("shishkin", 1), ("shishkin", 63),
+                                     ("bakhvalov-shishkin", 0 - 2), ("nonsense", None)])
+def test_mesh_rejects_bad_layer_options(kind, nl):
+    with pytest.raises((blp.BlpError, KeyError)):
+        blp.mesh(64, 1e-4, 2.0, (1.0, 1.0), kind, nl)
 
 
 @pytest.mark.parametrize("N,eps", [(63, 1e-2), (2, 1e-2), (64, 0.0), (64, 1.5), (64, float("nan"))])
@@ -67,5 +87,5 @@ def test_assemble_validation(args):
 
 
 def test_strerror_names_codes():
-    for code in (0, 1, -1, -2, -3, -4, -5):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert blp.lib().blp_strerror(code)
