@@ -852,7 +852,7 @@ int orc_fgmres(orc_problem *p, const orc_gmres_opts *o, const double *Fin,
     for (int k = 0; k < n; ++k) V[0][k] = r[k] / beta;
     for (int k = 0; k <= m; ++k) gv[k] = 0.0;
     gv[0] = beta;
-    int j, ncol = 0;
+    int j, ncol = 0, est_ok = 0;
     for (j = 0; j < m && it < o->maxit; ++j) {
       sys_prec(&sy, V[j], Z[j]);
       sys_op(&sy, Z[j], w);
@@ -888,7 +888,8 @@ int orc_fgmres(orc_problem *p, const orc_gmres_opts *o, const double *Fin,
       ++it;
       ncol = j + 1;
       if (hist) hist[it] = fabs(gv[j + 1]);
-      if (fabs(gv[j + 1]) <= target || happy) break;
+      est_ok = fabs(gv[j + 1]) <= target;
+      if (est_ok || happy) break;
     }
     /* back substitution H y = g, then u += Z y */
     for (int i = ncol - 1; i >= 0; --i) {
@@ -902,7 +903,7 @@ int orc_fgmres(orc_problem *p, const orc_gmres_opts *o, const double *Fin,
     for (int k = 0; k < n; ++k) r[k] = F[k] - w[k];
     beta = nrm2(n, r);
     info->restarts++;
-    if (beta <= target) conv = 1;
+    if (beta <= target || (o->stop_on_estimate && est_ok)) conv = 1;
   }
   info->iterations = it;
   info->converged = conv;

@@ -122,6 +122,9 @@ typedef struct {
                         (D = diag A); tol, history and true_res then refer to
                         the scaled system */
   orc_prec_opts prec;
+  int stop_on_estimate; /* 1: a restart cycle whose residual estimate met the
+                           tolerance ends the solve without the true-residual
+                           confirmation (the paper's Sec. 3.3 runs) */
 } orc_gmres_opts;
 
 typedef struct {

@@ -29,7 +29,7 @@ class PrecStats(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("absolute", C.c_int), ("restart", C.c_int),
                 ("maxit", C.c_int), ("precond", C.c_int), ("transpose", C.c_int),
-                ("scaled", C.c_int), ("prec", PrecOpts)]
+                ("scaled", C.c_int), ("prec", PrecOpts), ("stop_on_estimate", C.c_int)]
 
 
 class GmresInfo(C.Structure):
@@ -223,11 +223,12 @@ class Problem:
 
     def fgmres(self, F, tol=1e-8, restart=50, maxit=1000, precond=True, transpose=False,
                absolute=False, scaled=False, corner="mg", mg_fixed=0, mg_rtol=1e-3,
-               mg_maxcyc=20):
+               mg_maxcyc=20, stop_on_estimate=False):
         F = _f64(F)
         u = np.zeros(self.n)
         o = GmresOpts(tol, int(absolute), restart, maxit, int(precond), int(transpose),
-                      int(scaled), self.prec_opts(corner, mg_fixed, mg_rtol, mg_maxcyc))
+                      int(scaled), self.prec_opts(corner, mg_fixed, mg_rtol, mg_maxcyc),
+                      int(stop_on_estimate))
         info = GmresInfo()
         hist = np.zeros(maxit + 1)
         status = lib().orc_fgmres(self._h, C.byref(o), _p(F), _p(u), C.byref(info), _p(hist))

@@ -54,7 +54,7 @@ class PrecOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("absolute", C.c_int), ("scaled", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int), ("precision", C.c_int),
-                ("precond", C.c_int)]
+                ("precond", C.c_int), ("stop_on_estimate", C.c_int)]
 
 
 class BatchOpts(C.Structure):
@@ -210,13 +210,15 @@ class Problem:
             raise ValueError("vector length must be a multiple of (N-1)^2")
         return x
 
-    def _solve(self, fn, F, tol, scaled, restart, maxit, precision, precond, absolute, hist):
+    def _solve(self, fn, F, tol, scaled, restart, maxit, precision, precond, absolute, hist,
+               stop_on_estimate=False):
         t = self.torch
         F = self._vec(F)
         nrhs = F.numel() // self.n
         U = t.empty_like(F)
         o = SolveOpts(tol, int(absolute), int(scaled), restart, maxit,
-                      BLP_MIXED if precision == "mixed" else BLP_FP64, int(precond))
+                      BLP_MIXED if precision == "mixed" else BLP_FP64, int(precond),
+                      int(stop_on_estimate))
         infos = (SolveInfo * nrhs)()
         h = np.zeros(nrhs * (maxit + 1)) if hist else None
         rc = _check(fn(self._h, nrhs, C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
@@ -229,14 +231,14 @@ class Problem:
         return U, out
 
     def solve(self, F, tol=1e-8, scaled=True, restart=50, maxit=1000, precision="fp64",
-              precond=True, absolute=False, hist=False):
+              precond=True, absolute=False, hist=False, stop_on_estimate=False):
         return self._solve(lib().blp_solve, F, tol, scaled, restart, maxit, precision, precond,
-                           absolute, hist)
+                           absolute, hist, stop_on_estimate)
 
     def solve_adjoint(self, G, tol=1e-8, scaled=True, restart=50, maxit=1000, precision="fp64",
-                      precond=True, absolute=False, hist=False):
+                      precond=True, absolute=False, hist=False, stop_on_estimate=False):
         return self._solve(lib().blp_solve_adjoint, G, tol, scaled, restart, maxit, precision,
-                           precond, absolute, hist)
+                           precond, absolute, hist, stop_on_estimate)
 
     def apply(self, op, x):
         x = self._vec(x)
@@ -367,7 +369,7 @@ class Batch:
         U = [self.torch.empty_like(f) for f in F] if U is None else [p._vec(u) for p, u in
                                                                         zip(self.problems, U)]
         o = SolveOpts(tol, int(absolute), int(scaled), restart, maxit,
-                      BLP_MIXED if precision == "mixed" else BLP_FP64, int(precond))
+                      BLP_MIXED if precision == "mixed" else BLP_FP64, int(precond), 0)
         infos = (SolveInfo * self.S)()
         fa = (C.c_void_p * self.S)(*[f.data_ptr() for f in F])
         ua = (C.c_void_p * self.S)(*[u.data_ptr() for u in U])

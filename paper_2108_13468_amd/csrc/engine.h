@@ -1019,7 +1019,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
 
   std::vector<double> nF(S), target(S), beta(S), cyc_target(S);
   std::vector<int> it(S, 0), restarts(S, 0), ncol(S, 0);
-  std::vector<char> active(S, 1), conv(S, 0), incyc(S, 0);
+  std::vector<char> active(S, 1), conv(S, 0), incyc(S, 0), est_ok(S, 0);
   std::vector<CycleStats> cs(S);
   // classes with at least one system flagged (launches of other classes are skipped)
   auto live = [&](int k, const std::vector<char> &on) {
@@ -1073,6 +1073,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       incyc[s] = active[s];
       cyc_target[s] = std::max(target[s], inner_rtol * beta[s]);
       ncol[s] = 0;
+      est_ok[s] = 0;
     }
     BLP_TRY(set_gates(incyc));
     BLP_TRY(fork(B));
@@ -1156,6 +1157,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
         if (hist && hist[s] && !std::is_same<TV, float>::value) hist[s][it[s]] = est;
         if (!std::isfinite(est)) return BLP_E_NUMERIC;
         const bool happy = B.st_h[s].happy != 0;
+        est_ok[s] = est <= target[s];
         if (est <= cyc_target[s] || happy || j + 1 >= m || it[s] >= o->maxit) {
           incyc[s] = 0;
           left = true;
@@ -1200,7 +1202,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       ++restarts[s];
       if (hist && hist[s] && std::is_same<TV, float>::value)
         hist[s][std::min(it[s], o->maxit)] = beta[s];
-      if (beta[s] <= target[s]) conv[s] = 1;
+      if (beta[s] <= target[s] || (o->stop_on_estimate && est_ok[s])) conv[s] = 1;
       if (!std::isfinite(beta[s])) return BLP_E_NUMERIC;
       active[s] = !conv[s] && it[s] < o->maxit;
     }

@@ -347,6 +347,20 @@ def test_table7_eps_small_rows_within_two():
             assert abs(info.iterations - ref[(eps, N)]) <= 2
 
 
+@pytest.mark.parametrize("eps", [1e-4, 1e-5, 1e-6, 1e-7])
+def test_table7_exact_with_the_estimate_stopping_test(eps):
+    """Sec. 3.3 evaluates the tolerance in the Euclidean norm FGMRES itself
+    provides: stopping on the residual estimate (no true-residual
+    confirmation) gives every printed count of Table 7 at N = 128 to 512."""
+    ref = {(e, int(n)): int(v) for e, n, v in read_golden("table7_exponential_iterations.txt")}
+    for N in (128, 256, 512):
+        p = problem(inputs.mms_exponential(N, eps))
+        _, f = exponential_mms(eps, p.x, p.y)
+        u, st, info, _ = p.fgmres(f, tol=10 * np.log(N) / N, absolute=True, stop_on_estimate=True)
+        assert st == 0 and info.iterations == ref[(eps, N)], (eps, N, info.iterations)
+        assert info.mg_cycles_min == info.mg_cycles_max == 5
+
+
 # -------------------------------------------------------------- FGMRES ----
 
 def test_gmres_minimal_residual_property():
