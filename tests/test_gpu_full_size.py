@@ -16,7 +16,9 @@ the CPU from the oracle's operator.
   benchmark runs them.  The first right-hand side is compared with the
   oracle's FGMRES solutions, forward and adjoint (the adjoint data is the
   oracle's forward solution), at a scaled relative residual of 1e-9: at this
-  size the oracle's FP64 restarted FGMRES stalls between 1e-9 and 1e-10.
+  size the oracle's FP64 restarted FGMRES stalls between 1e-9 and 1e-10; so
+  is its gradient with respect to the sine coefficients (the benchmark's
+  allocation-free projection).
   Every result is also checked by its scaled residual under the oracle's
   operator."""
 import sys
@@ -145,3 +147,9 @@ def test_multi_rhs_workload_against_oracle():
         say("  rhs %d: forward %d iterations, error %.2e; adjoint %d iterations, error %.2e" % (
             k, info[k]["iterations"], eu, infa[k]["iterations"], el))
         assert eu <= 1e-6 and el <= 1e-6
+        # the misfit gradient with respect to the 3 x 3 sine coefficients
+        ga = p.sine_project_noalloc(L[k], 3, 3)
+        go = O.sine_project(inst.N, op.x, op.y, lam_t, 3, 3)
+        eg = np.abs(ga - go).max() / np.abs(go).max()
+        say("  rhs %d: dJ/da error %.2e" % (k, eg))
+        assert eg <= 1e-6
