@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <tuple>
 #include <chrono>
@@ -142,8 +143,13 @@ struct Timer {
 
 }  // namespace
 
+// A batch runs one part per mesh size.  Each part is a lockstep batch of
+// that size's systems with its own FGMRES loop, stream and host thread, so
+// that a part whose systems need many iterations is never held back by the
+// steps of another.
 struct blp_batch {
-  std::unique_ptr<Batch> B;
+  std::vector<std::unique_ptr<Batch>> parts;
+  std::vector<std::vector<int>> index;  // part -> the caller's system indices
 };
 
 struct blp_problem {
@@ -716,68 +722,141 @@ int blp_batch_create(blp_problem *const *probs, int S, void *stream, const blp_b
     if (!probs[s]) return BLP_E_INVAL;
     if (!probs[s]->prec_ready) return BLP_E_STATE;
   }
-  blp_batch *b = new (std::nothrow) blp_batch();
+  if (o && o->sweep_variant < 0) return BLP_E_INVAL;
+  std::unique_ptr<blp_batch> b(new (std::nothrow) blp_batch());
   if (!b) return BLP_E_NOMEM;
-  const int rc = batch_create((hipStream_t)stream, probs, S, b->B);
-  if (rc < 0) {
-    delete b;
-    return rc;
-  }
-  b->B->timer = &b->B->own_timer;
-  if (o) {
-    b->B->graphs = o->graphs != 0;
-    b->B->autotune = o->autotune != 0;
-    if (o->sweep_variant < 0) {
-      delete b;
-      return BLP_E_INVAL;
+  // one part per mesh size, largest first
+  std::map<int, std::vector<int>> byN;
+  for (int s = 0; s < S; ++s) byN[probs[s]->N].push_back(s);
+  const bool graphs = o && o->graphs != 0;
+  for (auto it = byN.rbegin(); it != byN.rend(); ++it) {
+    std::vector<blp_problem *> pp;
+    for (int s : it->second) pp.push_back(probs[s]);
+    std::unique_ptr<Batch> B;
+    BLP_TRY(batch_create((hipStream_t)stream, pp.data(), (int)pp.size(), B));
+    B->timer = &B->own_timer;
+    if (o) {
+      B->graphs = o->graphs != 0;
+      B->autotune = o->autotune != 0;
+      B->sweep_variant = o->sweep_variant;
     }
-    b->B->sweep_variant = o->sweep_variant;
-  }
-  if (b->B->graphs) {
-    // graphs are captured on a stream of the batch's own (capture is not
-    // possible on the legacy default stream); default priority
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      delete b;
-      return BLP_E_HIP;
+    if (graphs || byN.size() > 1) {
+      // a stream of the part's own: graphs cannot be captured on the legacy
+      // default stream, and parts run concurrently; default priority
+      hipStream_t st = nullptr;
+      HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      B->user = B->stream;
+      B->stream = st;
+      B->own_stream = true;
     }
-    b->B->user = b->B->stream;
-    b->B->stream = st;
-    b->B->own_stream = true;
+    b->parts.push_back(std::move(B));
+    b->index.push_back(it->second);
   }
-  *out = b;
+  *out = b.release();
   return BLP_OK;
+}
+
+// Solve every part, each on its own host thread; results and records go
+// back to the caller's system order.  The most severe status wins (an
+// error over BLP_W_NOCONV over BLP_OK).
+static int parts_solve(blp_batch *b, bool tr, const double *const *F, double *const *U,
+                       const blp_solve_opts *o, blp_solve_info *info) {
+  const size_t P = b->parts.size();
+  std::vector<int> rc(P, BLP_OK);
+  std::vector<std::vector<blp_solve_info>> inf(P);
+  auto run = [&](size_t k) {
+    const std::vector<int> &ix = b->index[k];
+    std::vector<const double *> f(ix.size());
+    std::vector<double *> u(ix.size());
+    for (size_t q = 0; q < ix.size(); ++q) {
+      f[q] = F[ix[q]];
+      u[q] = U[ix[q]];
+    }
+    inf[k].assign(ix.size(), blp_solve_info{});
+    rc[k] = batch_solve(*b->parts[k], tr, f.data(), u.data(), o, inf[k].data(), nullptr);
+  };
+  if (P == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    try {
+      for (size_t k = 1; k < P; ++k) th.emplace_back(run, k);
+    } catch (...) {
+      for (auto &t : th) t.join();
+      return BLP_E_NOMEM;
+    }
+    run(0);
+    for (auto &t : th) t.join();
+  }
+  int out = BLP_OK;
+  for (size_t k = 0; k < P; ++k) {
+    if (rc[k] < 0 && (out >= 0 || rc[k] < out)) out = rc[k];
+    if (rc[k] == BLP_W_NOCONV && out == BLP_OK) out = BLP_W_NOCONV;
+    if (info)
+      for (size_t q = 0; q < b->index[k].size(); ++q) info[b->index[k][q]] = inf[k][q];
+  }
+  return out;
 }
 
 int blp_batch_solve(blp_batch *b, const double *const *F, double *const *U,
                     const blp_solve_opts *o, blp_solve_info *info) {
   if (!b || !F || !U) return BLP_E_INVAL;
-  return batch_solve(*b->B, false, F, U, o, info, nullptr);
+  return parts_solve(b, false, F, U, o, info);
 }
 
 int blp_batch_solve_adjoint(blp_batch *b, const double *const *G, double *const *L,
                             const blp_solve_opts *o, blp_solve_info *info) {
   if (!b || !G || !L) return BLP_E_INVAL;
-  return batch_solve(*b->B, true, G, L, o, info, nullptr);
+  return parts_solve(b, true, G, L, o, info);
 }
 
-long long blp_batch_footprint(const blp_batch *b) { return b ? batch_bytes(*b->B) : 0; }
+long long blp_batch_footprint(const blp_batch *b) {
+  long long n = 0;
+  if (b)
+    for (const auto &B : b->parts) n += batch_bytes(*B);
+  return n;
+}
 
 int blp_batch_timing(blp_batch *b, int enable, double *ms, long long *launches, double *bytes) {
   if (!b) return BLP_E_INVAL;
-  Batch &B = *b->B;
-  HIP_TRY(hipStreamSynchronize(B.stream));
-  for (hipStream_t q : B.cstream) HIP_TRY(hipStreamSynchronize(q));
+  for (auto &B : b->parts) {
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    for (hipStream_t q : B->cstream) HIP_TRY(hipStreamSynchronize(q));
+  }
   if (enable) {
-    B.own_timer.start();
+    for (auto &B : b->parts) B->own_timer.start();
     return BLP_OK;
   }
-  return B.own_timer.stop(ms, launches, bytes, BLP_NCLASS);
+  // per-class sums over the parts (their launches overlap in time)
+  double tms[BLP_NCLASS] = {}, tby[BLP_NCLASS] = {};
+  long long tl[BLP_NCLASS] = {};
+  for (auto &B : b->parts) {
+    double m[BLP_NCLASS], y[BLP_NCLASS];
+    long long l[BLP_NCLASS];
+    BLP_TRY(B->own_timer.stop(m, l, y, BLP_NCLASS));
+    for (int k = 0; k < BLP_NCLASS; ++k) {
+      tms[k] += m[k];
+      tl[k] += l[k];
+      tby[k] += y[k];
+    }
+  }
+  for (int k = 0; k < BLP_NCLASS; ++k) {
+    if (ms) ms[k] = tms[k];
+    if (launches) launches[k] = tl[k];
+    if (bytes) bytes[k] = tby[k];
+  }
+  return BLP_OK;
 }
 
 int blp_batch_describe(const blp_batch *b, char *buf, int len) {
   if (!b || !buf || len < 1) return BLP_E_INVAL;
-  const std::string s = describe(*b->B);
+  std::string s;
+  for (size_t k = 0; k < b->parts.size(); ++k) {
+    char h[64];
+    snprintf(h, sizeof h, "part %zu (own FGMRES loop):\n", k);
+    s += h;
+    s += describe(*b->parts[k]);
+  }
   const int n = std::min((int)s.size(), len - 1);
   std::memcpy(buf, s.data(), n);
   buf[n] = 0;

@@ -185,6 +185,20 @@ struct PrecPlan {
   Alloc mem;
 };
 
+// The fused coarse cycle's dynamic LDS limit is an attribute of the kernel,
+// shared by every plan and host thread: it is only ever raised, under a lock.
+template <typename T, bool TR>
+int raise_coarse_lds(size_t bytes) {
+  static std::mutex mu;
+  static size_t set = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (bytes <= set) return BLP_OK;
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mg_coarse<T, TR>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  set = bytes;
+  return BLP_OK;
+}
+
 template <typename T, bool TR>
 int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std::vector<IOSpec> &io,
                     bool scaled, PrecPlan<T, TR> &P) {
@@ -281,8 +295,7 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
     bool nodal = false;
     for (int q = 0; q < S; ++q) nodal = nodal || mg[P.lc][q].L.g.r != nullptr;
     P.coarse_lds = coarse_lds_bytes<T>(P.ln[P.lc], nl - P.lc, nodal);
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mg_coarse<T, TR>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.coarse_lds));
+    BLP_TRY((raise_coarse_lds<T, TR>(P.coarse_lds)));
     // constant LDS images, one per system (zero padding rows)
     const size_t iw = (size_t)lds_image_words<T>(P.ln[P.lc], nl - P.lc, nodal);
     T *img = nullptr;
