@@ -157,6 +157,40 @@ void orc_bilinear(int N, const double *x, const double *y, int m,
 void orc_bilinear_project(int N, const double *x, const double *y, int m,
                           const double *w, double *G);
 
+/* ---- The one-dimensional method (Sec. 2) -------------------------------- */
+
+/* -eps u'' - c u' + r u = f on (0,1), u(0) = u(1) = 0, upwind stencil
+ * (eq. stencil_1d) on a mesh with widths w[1..N] (w[k] = x_k - x_{k-1}, from
+ * orc_mesh_axis_ex), c[0..N] and r[0..N] at the nodes; unknowns are nodes
+ * 1..N-1; the layer set L is nodes 1..nl (transition node included). */
+typedef struct orc1_problem orc1_problem;
+orc1_problem *orc1_create(int N, double eps, const double *w, const double *c,
+                          const double *r, int nl);
+void orc1_destroy(orc1_problem *p);
+int orc1_n(const orc1_problem *p);
+void orc1_stencil(const orc1_problem *p, int i, double *out3); /* W, C, E of row i */
+void orc1_apply_A(const orc1_problem *p, const double *v, double *y);
+/* U^E = A^{-1} f (Thomas, no pivoting) */
+void orc1_solve_A(const orc1_problem *p, const double *f, double *u);
+/* z = M^{-1} b with M of eq. block_M; the tridiagonal M itself (rows of n) */
+void orc1_prec_apply(const orc1_problem *p, const double *b, double *z);
+void orc1_prec_matrix(const orc1_problem *p, double *sub, double *diag, double *sup);
+
+typedef struct {
+  double K, g;  /* stop when ||F - A u_k||_inf <= K g (Sec. 2.4) */
+  int maxit;    /* no restart: at most maxit iterations */
+  int left;     /* 1: M on the left (M^{-1} A); 0: on the right (A M^{-1}) */
+} orc1_gmres_opts;
+typedef struct {
+  int iterations, converged;
+  double res_inf; /* ||F - A u||_inf at exit */
+} orc1_gmres_info;
+/* Unrestarted preconditioned GMRES from u = 0.  hist (may be NULL, maxit+1
+ * doubles): the inf-norm residual after each iteration.  Returns 0 when the
+ * test was met. */
+int orc1_gmres(const orc1_problem *p, const orc1_gmres_opts *o, const double *F, double *u,
+               orc1_gmres_info *info, double *hist);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,17 +7,19 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "blp_oracle.c")
+SRCS = [os.path.join(HERE, "blp_oracle.c"), os.path.join(HERE, "blp_oracle_1d.c")]
+HDR = os.path.join(HERE, "blp_oracle.h")
 LIB = os.path.join(HERE, "libblp_oracle.so")
 
 
 def build_oracle(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+    if not force and os.path.exists(LIB) and all(
+            os.path.getmtime(LIB) >= os.path.getmtime(f) for f in SRCS + [HDR]):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math",
            "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", tmp, SRC, "-lm"]
+           "-o", tmp] + SRCS + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

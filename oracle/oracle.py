@@ -39,6 +39,14 @@ class GmresInfo(C.Structure):
                 ("mg_cycles_max", C.c_int)]
 
 
+class Gmres1Opts(C.Structure):
+    _fields_ = [("K", C.c_double), ("g", C.c_double), ("maxit", C.c_int), ("left", C.c_int)]
+
+
+class Gmres1Info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("res_inf", C.c_double)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -85,6 +93,18 @@ def lib():
         L.orc_sine_project.argtypes = [C.c_int, _dp, _dp, C.c_int, C.c_int, _dp, _dp]
         L.orc_bilinear.argtypes = [C.c_int, _dp, _dp, C.c_int, _dp, _dp]
         L.orc_bilinear_project.argtypes = [C.c_int, _dp, _dp, C.c_int, _dp, _dp]
+        L.orc1_create.restype = C.c_void_p
+        L.orc1_create.argtypes = [C.c_int, C.c_double, _dp, _dp, _dp, C.c_int]
+        L.orc1_destroy.argtypes = [C.c_void_p]
+        L.orc1_n.restype = C.c_int
+        L.orc1_n.argtypes = [C.c_void_p]
+        L.orc1_stencil.argtypes = [C.c_void_p, C.c_int, _dp]
+        for f in ("orc1_apply_A", "orc1_solve_A", "orc1_prec_apply"):
+            getattr(L, f).argtypes = [C.c_void_p, _dp, _dp]
+        L.orc1_prec_matrix.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.orc1_gmres.restype = C.c_int
+        L.orc1_gmres.argtypes = [C.c_void_p, C.POINTER(Gmres1Opts), _dp, _dp,
+                                 C.POINTER(Gmres1Info), _dp]
         _lib = L
     return _lib
 
@@ -266,3 +286,75 @@ def bilinear_project(N, x, y, w, m):
     G = np.zeros(m * m)
     lib().orc_bilinear_project(N, _p(_f64(x)), _p(_f64(y)), m, _p(_f64(w)), _p(G))
     return G.reshape(m, m)
+
+
+class Problem1D:
+    """The one-dimensional method of Sec. 2 (FP64, CPU): upwind stencil on a
+    layer-adapted mesh, the block preconditioner M of eq. block_M and
+    unrestarted GMRES with the inf-norm residual test of Sec. 2.4.  c and r
+    are callables of x or arrays of the N+1 nodal values."""
+
+    def __init__(self, N, eps, c, r, sigma=2.0, clow=1.0, mesh_kind="shishkin",
+                 layer_cells=None):
+        self.N, self.eps, self.n = N, eps, N - 1
+        self.nl = N // 2 if layer_cells is None else int(layer_cells)
+        self.tau, self.x, w = mesh_axis(N, eps, sigma, clow, mesh_kind, self.nl)
+        self.w = np.zeros(N + 2)
+        self.w[: N + 1] = w
+        cv = _f64(c(self.x) if callable(c) else c)
+        rv = _f64(r(self.x) if callable(r) else (np.full(N + 1, float(r)) if np.isscalar(r) else r))
+        self.c, self.r = cv, rv
+        self._h = lib().orc1_create(N, eps, _p(self.w), _p(cv), _p(rv), self.nl)
+        if not self._h:
+            raise ValueError("orc1_create rejected N=%r, layer cells %r" % (N, self.nl))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        self._h = None
+        if h and _lib is not None:
+            _lib.orc1_destroy(h)
+
+    def stencil(self, i):
+        out = np.zeros(3)
+        lib().orc1_stencil(self._h, i, _p(out))
+        return out
+
+    def _op(self, name, v):
+        v = _f64(v)
+        y = np.zeros(self.n)
+        getattr(lib(), name)(self._h, _p(v), _p(y))
+        return y
+
+    def A(self, v):
+        return self._op("orc1_apply_A", v)
+
+    def solve(self, f):
+        return self._op("orc1_solve_A", f)
+
+    def M_inv(self, b):
+        return self._op("orc1_prec_apply", b)
+
+    def M_tridiag(self):
+        a, d, e = np.zeros(self.n), np.zeros(self.n), np.zeros(self.n)
+        lib().orc1_prec_matrix(self._h, _p(a), _p(d), _p(e))
+        return a, d, e
+
+    def dense(self):
+        A = np.zeros((self.n, self.n))
+        for k in range(self.n):
+            W, Cc, E = self.stencil(k + 1)
+            A[k, k] = Cc
+            if k > 0:
+                A[k, k - 1] = W
+            if k < self.n - 1:
+                A[k, k + 1] = E
+        return A
+
+    def gmres(self, F, K, g, maxit=200, left=True):
+        F = _f64(F)
+        u = np.zeros(self.n)
+        info = Gmres1Info()
+        hist = np.zeros(maxit + 1)
+        st = lib().orc1_gmres(self._h, C.byref(Gmres1Opts(K, g, maxit, int(left))), _p(F), _p(u),
+                              C.byref(info), _p(hist))
+        return u, st, info, hist[: info.iterations + 1]
