@@ -12,12 +12,13 @@ The default run also measures, in the same JSON line:
   batch       64 uneven instances solved together (mixed, 1e-8): solves/s;
   multi_rhs   N = 2048, eps = 1e-6, 16 right-hand sides: mixed solves and the
               adjoint solves of their gradients;
+  oned        the 1D method for 2048 problems in one launch: solves/s;
   copy        the attainable HBM bandwidth of a plain 1 GiB device copy;
 each with its own roofline entry and CPU-oracle baseline.  --workload runs
 one of them alone (its own JSON line).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eps E] [--no-cpu]
-                       [--workload all|headline|batch|multi_rhs|copy_probe]
+                       [--workload all|headline|batch|multi_rhs|oned|copy_probe]
 """
 import argparse
 import hashlib
@@ -500,6 +501,76 @@ def multi_rhs(args):
     return out
 
 
+def oned(args):
+    """The 1D method (Sec. 2) for 2048 independent problems in one launch:
+    the paper's test problem (c = 2 + sin 5x, r = 1, f = 4 exp(-x)) with N
+    uniform in {128, ..., 2048} and log10 eps uniform in [-8, -4], M on the
+    left, ||F - A u||_inf <= ||U^E||_inf ln(N)/N: solves/s."""
+    import numpy as np
+    import torch
+    from paper_2108_13468_amd import blp
+    rng = np.random.default_rng(5)
+    S = 2048
+    Ns = rng.choice([128, 256, 512, 1024, 2048], size=S)
+    epss = 10.0 ** rng.uniform(-8.0, -4.0, size=S)
+    probs, F = [], []
+    for N, eps in zip(Ns, epss):
+        _, x, _ = blp.mesh(int(N), float(eps), 2.0, (0.99, 0.99))
+        probs.append(dict(N=int(N), eps=float(eps), c=2.0 + np.sin(5.0 * x), r=np.ones(N + 1),
+                          clow=0.99))
+        F.append(torch.as_tensor(4.0 * np.exp(-x[1:-1]), device="cuda"))
+    steps, warmup = args.side_steps, args.side_warmup
+    for _ in range(warmup):
+        blp.solve_1d(probs, F, maxit=100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        U, info = blp.solve_1d(probs, F, maxit=100)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    it = np.array([d["iterations"] for d in info])
+    # algorithmic bytes of the basis traffic: per iteration j (0-based) the
+    # modified Gram-Schmidt reads j + 1 basis vectors twice and the update
+    # reads j + 1 more; the operator, M^{-1} and residual stream about 12
+    # vectors; 8 bytes per value, n = N - 1
+    nbytes = sum(8.0 * (N - 1) * sum(3 * (j + 1) + 12 for j in range(k)) for N, k in zip(Ns, it))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"metric": "1D method: batched solves/s, 2048 problems in one launch",
+           "value": round(S * 1e3 / ms, 1), "unit": "solves/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "2048 instances of -eps u'' - (2 + sin 5x) u' + u = 4 exp(-x) on "
+                                  "Shishkin meshes (Clow = 0.99): N uniform in {128..2048}, log10 "
+                                  "eps uniform in [-8, -4]; unrestarted GMRES with M of eq. block_M "
+                                  "on the left, one workgroup per problem, one launch per batch "
+                                  "(host set-up and copies included)"},
+           "converged": int(sum(d["converged"] for d in info)),
+           "iterations": {"min": int(it.min()), "max": int(it.max()), "mean": round(float(it.mean()), 2)},
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                        "kernel": "k_gmres1d (whole call)",
+                        "note": "one workgroup per problem: latency of block reductions and scans, "
+                                "not bandwidth, sets the pace"}}
+    if not args.no_cpu:
+        from oracle import oracle as O
+        hi = host_info()
+
+        def solve(k):
+            N, eps = int(Ns[k]), float(epss[k])
+            p = O.Problem1D(N, eps, lambda x: 2.0 + np.sin(5.0 * x), 1.0, clow=0.99)
+            Fo = 4.0 * np.exp(-p.x[1:-1])
+            K = np.abs(p.solve(Fo)).max()
+            p.gmres(Fo, K=K, g=np.log(N) / N, maxit=100)
+
+        _, wall = pool_map(solve, list(range(S)), hi["pool"])
+        out["cpu_baseline"] = {"value": round(S / wall, 1), "unit": "solves/s", "cores": hi["pool"],
+                               "kind": "oracle",
+                               "sample": "all 2048 problems, one FP64 oracle solve per core "
+                                         "(direct solve for K, then GMRES), %.2f s wall" % wall,
+                               "cpu_model": hi["cpu_model"], "nproc": hi["nproc"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -511,8 +582,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", choices=("all", "headline", "batch", "multi_rhs", "copy_probe"),
-                    default="all")
+    ap.add_argument("--workload", choices=("all", "headline", "batch", "multi_rhs", "oned",
+                                           "copy_probe"), default="all")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -529,9 +600,11 @@ def main():
         print("batch done", file=sys.stderr, flush=True)
         out["multi_rhs"] = multi_rhs(args)
         print("multi_rhs done", file=sys.stderr, flush=True)
+        out["oned"] = oned(args)
+        print("oned done", file=sys.stderr, flush=True)
         out["copy_bandwidth"] = copy_bandwidth()
     else:
-        out = {"headline": headline, "batch": batch, "multi_rhs": multi_rhs,
+        out = {"headline": headline, "batch": batch, "multi_rhs": multi_rhs, "oned": oned,
                "copy_probe": copy_probe}[args.workload](args)
     print(json.dumps(out), flush=True)
 

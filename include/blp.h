@@ -302,6 +302,46 @@ int blp_reaction_gradient(blp_problem *p, int m, int nrhs, const double *Lambda,
  * BLP_E_STATE (another device current), BLP_E_HIP. */
 int blp_sine_project_noalloc(blp_problem *p, int K, int L, const double *w, double *g);
 
+/* The one-dimensional method (Sec. 2) for a batch of S independent problems
+ *   -eps u'' - c u' + r u = f on (0,1), u(0) = u(1) = 0,
+ * upwind stencil (eq. stencil_1d) on the layer-adapted mesh of
+ * blp_mesh_opts (one axis: sigma, clow, kind, layer_cells), preconditioner
+ * M of eq. block_M (A with the sub-diagonal of the interior block A_II
+ * dropped, the coupling A_IL kept), unrestarted GMRES from u = 0 stopped
+ * when ||F - A u||_inf <= K g(N) (Sec. 2.4).  One launch solves the whole
+ * batch: one workgroup runs one problem's GMRES to the end on the device.
+ *   probs[s]   N (even, 4..4096), eps in (0,1], mesh parameters, and host
+ *              arrays c[0..N] (> 0) and r[0..N] (>= 0) at the nodes
+ *   F[s], U[s] device, N-1 doubles each (nodes 1..N-1); host arrays of S
+ *              pointers
+ *   opts       maxit (1..128), left (1: M^{-1} A as the paper's MATLAB
+ *              gmres; 0: A M^{-1}), K (<= 0: K = ||U^E||_inf from a direct
+ *              tridiagonal solve on the device, as the paper suggests), g
+ *              (<= 0: g(N) = ln(N)/N)
+ *   info       host, S entries (may be NULL)
+ * Device work memory is allocated and freed by the call.  Errors:
+ * BLP_E_INVAL, BLP_E_NOMEM, BLP_E_HIP, BLP_E_NUMERIC; BLP_W_NOCONV if any
+ * problem reached maxit. */
+typedef struct {
+  int N;
+  double eps;
+  double sigma, clow;
+  int kind, layer_cells;
+  const double *c, *r;
+} blp1d_problem;
+typedef struct {
+  int maxit;
+  int left;
+  double K, g;
+} blp1d_opts;
+typedef struct {
+  int iterations, converged;
+  double res_inf; /* ||F - A u||_inf at exit */
+  double K;       /* the K used */
+} blp1d_info;
+int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, double *const *U,
+                const blp1d_opts *opts, void *stream, blp1d_info *info);
+
 /* Per-kernel-class timing with HIP events on the handle's stream.
  * enable = 1: discard earlier records and start recording an event pair
  * around every launch of the classes below; enable = 0: synchronise, stop

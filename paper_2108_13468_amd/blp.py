@@ -22,7 +22,8 @@ OPS = {"A": 0, "AT": 1, "MINV": 2, "MINVT": 3, "MINV32": 4}
 # Symbols declared in include/blp.h (checked by the CPU tests).
 EXPORTS = ("blp_mesh", "blp_assemble", "blp_nodes", "blp_precondition", "blp_solve",
            "blp_solve_adjoint", "blp_apply", "blp_sine_rhs", "blp_sine_project",
-           "blp_bilinear_project", "blp_mul", "blp_reaction_gradient", "blp_sine_project_noalloc", "blp_timing", "blp_footprint", "blp_destroy",
+           "blp_bilinear_project", "blp_mul", "blp_reaction_gradient", "blp_sine_project_noalloc",
+           "blp1d_solve", "blp_timing", "blp_footprint", "blp_destroy",
            "blp_strerror", "blp_batch_create", "blp_batch_solve", "blp_batch_solve_adjoint",
            "blp_batch_footprint", "blp_batch_describe", "blp_batch_timing", "blp_batch_destroy")
 NCLASS = 7
@@ -59,6 +60,20 @@ class SolveOpts(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("graphs", C.c_int), ("autotune", C.c_int), ("sweep_variant", C.c_int)]
+
+
+class Problem1D(C.Structure):
+    _fields_ = [("N", C.c_int), ("eps", C.c_double), ("sigma", C.c_double), ("clow", C.c_double),
+                ("kind", C.c_int), ("layer_cells", C.c_int), ("c", _dp), ("r", _dp)]
+
+
+class Opts1D(C.Structure):
+    _fields_ = [("maxit", C.c_int), ("left", C.c_int), ("K", C.c_double), ("g", C.c_double)]
+
+
+class Info1D(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("res_inf", C.c_double),
+                ("K", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -127,6 +142,8 @@ def lib():
         L.blp_batch_footprint.restype = C.c_longlong
         L.blp_batch_footprint.argtypes = [vp]
         L.blp_batch_destroy.argtypes = [vp]
+        L.blp1d_solve.argtypes = [C.c_int, C.POINTER(Problem1D), C.POINTER(vp), C.POINTER(vp),
+                                  C.POINTER(Opts1D), vp, C.POINTER(Info1D)]
         _lib = L
     return _lib
 
@@ -408,3 +425,37 @@ class Batch:
         buf = C.create_string_buffer(8192)
         _check(lib().blp_batch_describe(self._h, buf, len(buf)), "blp_batch_describe")
         return buf.value.decode()
+
+
+def solve_1d(problems, F, maxit=100, left=True, K=0.0, g=0.0, U=None):
+    """The 1D method (Sec. 2) for a batch in one launch (blp1d_solve).
+    problems: list of dicts with N, eps, c, r (arrays of N+1 nodal values)
+    and optionally sigma (2), clow (1), kind ('shishkin'), layer_cells (N/2);
+    F: list of float64 device tensors of N-1 values.  Returns (U, infos)."""
+    import torch
+    S = len(problems)
+    if len(F) != S:
+        raise ValueError("one right-hand side per problem")
+    keep = []
+    arr = (Problem1D * S)()
+    for k, q in enumerate(problems):
+        cv, rv = _f64(q["c"]), _f64(q["r"])
+        keep += [cv, rv]
+        arr[k] = Problem1D(q["N"], q["eps"], q.get("sigma", 2.0), q.get("clow", 1.0),
+                           MESH_KINDS[q.get("kind", "shishkin")], int(q.get("layer_cells") or 0),
+                           cv.ctypes.data_as(_dp), rv.ctypes.data_as(_dp))
+    for f, q in zip(F, problems):
+        if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64
+                and f.is_contiguous() and f.numel() == q["N"] - 1):
+            raise TypeError("F must hold contiguous float64 device vectors of N-1 values")
+    U = [torch.empty_like(f) for f in F] if U is None else U
+    fa = (C.c_void_p * S)(*[f.data_ptr() for f in F])
+    ua = (C.c_void_p * S)(*[u.data_ptr() for u in U])
+    infos = (Info1D * S)()
+    stream = torch.cuda.current_stream().cuda_stream
+    rc = _check(lib().blp1d_solve(S, arr, fa, ua, C.byref(Opts1D(maxit, int(left), K, g)),
+                                  C.c_void_p(stream), infos), "blp1d_solve")
+    out = [{k: getattr(i, k) for k, _ in Info1D._fields_} for i in infos]
+    for d in out:
+        d["status"] = rc
+    return U, out

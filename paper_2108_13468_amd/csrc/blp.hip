@@ -27,6 +27,7 @@
 #include "kernels_krylov.h"
 #include "kernels_op.h"
 #include "kernels_prec.h"
+#include "kernels_1d.h"
 
 namespace {
 
@@ -987,6 +988,115 @@ int blp_sine_project(blp_problem *p, int K, int L, const double *w, double *g) {
 int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G) {
   if (!p || m < 2 || !w || !G) return BLP_E_INVAL;
   return project(p, m, m, 1, 1, 1.0, w, nullptr, G);
+}
+
+int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, double *const *U,
+                const blp1d_opts *o, void *stream, blp1d_info *info) {
+  if (S < 1 || !probs || !F || !U || !o) return BLP_E_INVAL;
+  if (o->maxit < 1 || o->maxit > k1dMaxIt) return BLP_E_INVAL;
+  const hipStream_t st = (hipStream_t)stream;
+  const int m = o->maxit;
+  // per problem: nodal c and r (copied in), and device work space (stencil
+  // rows, factorisations, vectors, basis, Hessenberg, record), built by the
+  // kernel itself
+  std::vector<OneDArgs> args(S);
+  std::vector<size_t> off(S + 1, 0), woff(S + 1, 0);
+  std::vector<blp_mesh_opts> mo(S);
+  for (int s = 0; s < S; ++s) {
+    const blp1d_problem &q = probs[s];
+    if (q.N < 4 || q.N % 2 || q.N > 4096 || !(q.eps > 0 && q.eps <= 1) || !q.c || !q.r ||
+        !F[s] || !U[s])
+      return BLP_E_INVAL;
+    const blp_mesh_opts in{q.sigma, q.clow, q.clow, q.kind, q.layer_cells};
+    BLP_TRY(mesh_options(q.N, &in, &mo[s]));
+    for (int k = 0; k <= q.N; ++k)
+      if (!(q.c[k] > 0) || !(q.r[k] >= 0)) return BLP_E_INVAL;
+    const size_t n = (size_t)q.N - 1;
+    off[s + 1] = off[s] + 2 * ((size_t)q.N + 1);
+    woff[s + 1] = woff[s] + 9 * n + (size_t)(m + 1) * n + (size_t)(m + 1) * m + 4;
+  }
+  std::vector<double> host(off[S]);
+  for (int s = 0; s < S; ++s) {
+    const int N = probs[s].N;
+    std::memcpy(host.data() + off[s], probs[s].c, (N + 1) * sizeof(double));
+    std::memcpy(host.data() + off[s] + N + 1, probs[s].r, (N + 1) * sizeof(double));
+  }
+  double *dev = nullptr, *work = nullptr;
+  OneDArgs *dargs = nullptr;
+  int rc = BLP_OK;
+  if (hipMalloc((void **)&dev, off[S] * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&work, woff[S] * sizeof(double)) != hipSuccess ||
+      hipMalloc((void **)&dargs, S * sizeof(OneDArgs)) != hipSuccess) {
+    (void)hipFree(dev);
+    (void)hipFree(work);
+    return BLP_E_NOMEM;
+  }
+  for (int s = 0; s < S; ++s) {
+    const blp1d_problem &q = probs[s];
+    const blp_mesh_opts &mm = mo[s];
+    const int N = q.N, n = N - 1, nl = mm.layer_cells;
+    // the constants of the closed-form widths (the same construction as
+    // blp_mesh's, evaluated per cell in the kernel)
+    const double qf = (double)nl / N, layer = mm.sigma * q.eps * std::log((double)N) / mm.clow_x;
+    const double tau = std::min(qf, layer);
+    OneDArgs &a = args[s];
+    double *wk = work + woff[s];
+    a.n = n;
+    a.nl = nl;
+    a.eps = q.eps;
+    a.hl = tau / nl;
+    a.hi = (1.0 - tau) / (N - nl);
+    a.s = mm.sigma * q.eps / mm.clow_x;
+    a.a = (1.0 - 1.0 / N) / nl;
+    a.graded = mm.kind == BLP_MESH_BAKHVALOV_SHISHKIN && layer < qf;
+    a.c = dev + off[s];
+    a.r = dev + off[s] + N + 1;
+    a.W = wk;
+    a.C = wk + n;
+    a.E = wk + 2 * n;
+    a.a_inv = wk + 3 * n;
+    a.a_cp = wk + 4 * n;
+    a.m_inv = wk + 5 * n;
+    a.m_cp = wk + 6 * n;
+    a.t = wk + 7 * n;
+    a.w = wk + 8 * n;
+    a.V = wk + 9 * n;
+    a.H = a.V + (size_t)(m + 1) * n;
+    a.info = a.H + (size_t)(m + 1) * m;
+    a.F = F[s];
+    a.U = U[s];
+    a.K = o->K;
+    a.g = o->g > 0 ? o->g : std::log((double)N) / N;
+    a.maxit = m;
+    a.left = o->left != 0;
+  }
+  std::vector<double> out(4 * (size_t)S);
+  if (hipMemcpyAsync(dev, host.data(), off[S] * sizeof(double), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(dargs, args.data(), S * sizeof(OneDArgs), hipMemcpyHostToDevice, st)) {
+    rc = BLP_E_HIP;
+  } else {
+    k_gmres1d<<<S, k1dThreads, 0, st>>>(dargs);
+    if (hipGetLastError() != hipSuccess) rc = BLP_E_HIP;
+    for (int s = 0; s < S && rc == BLP_OK; ++s)
+      if (hipMemcpyAsync(&out[4 * s], args[s].info, 4 * sizeof(double), hipMemcpyDeviceToHost, st))
+        rc = BLP_E_HIP;
+    if (rc == BLP_OK && hipStreamSynchronize(st) != hipSuccess) rc = BLP_E_HIP;
+  }
+  (void)hipFree(dargs);
+  (void)hipFree(work);
+  (void)hipFree(dev);
+  if (rc != BLP_OK) return rc;
+  for (int s = 0; s < S; ++s) {
+    if (info) {
+      info[s].iterations = (int)out[4 * s];
+      info[s].converged = out[4 * s + 1] != 0.0;
+      info[s].res_inf = out[4 * s + 2];
+      info[s].K = out[4 * s + 3];
+    }
+    if (!std::isfinite(out[4 * s + 2])) rc = BLP_E_NUMERIC;
+    else if (out[4 * s + 1] == 0.0 && rc == BLP_OK) rc = BLP_W_NOCONV;
+  }
+  return rc;
 }
 
 int blp_sine_project_noalloc(blp_problem *p, int K, int L, const double *w, double *g) {

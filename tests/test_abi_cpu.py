@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "blp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(blp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(blp[0-9a-z]*_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_binding_exports():
