@@ -46,13 +46,23 @@ double orc_mesh_axis(int N, double eps, double sigma, double clow,
  * Widths come from closed forms, never from differences of nodes. */
 double orc_mesh_axis_ex(int N, double eps, double sigma, double clow, int kind, int nl,
                         double *nodes, double *widths) {
+  return orc_mesh_axis_layer(N, eps, sigma, clow, kind, nl, 0, nodes, widths);
+}
+
+/* The same for either layer type of the axis (Sec. 3, eq. tau parabolic and
+ * eq. tau exponential): an exponential layer has the width scale eps / clow,
+ * a parabolic one sqrt(eps) (clow unused); tau = sigma (scale) ln N, capped
+ * at q as above, and the graded kind uses the same scale. */
+double orc_mesh_axis_layer(int N, double eps, double sigma, double clow, int kind, int nl,
+                           int parabolic, double *nodes, double *widths) {
   double q = (double)nl / N;
-  double tl = sigma * eps * log((double)N) / clow;
+  double tl = parabolic ? sigma * sqrt(eps) * log((double)N)
+                        : sigma * eps * log((double)N) / clow;
   double tau = tl < q ? tl : q;
   int graded = kind == 1 && tl < q;
   double hl = tau / nl;             /* Shishkin layer cells */
   double hi = (1.0 - tau) / (N - nl); /* interior cells       */
-  double s = sigma * eps / clow, a = (1.0 - 1.0 / N) / nl;
+  double s = parabolic ? sigma * sqrt(eps) : sigma * eps / clow, a = (1.0 - 1.0 / N) / nl;
   widths[0] = 0.0;
   nodes[0] = 0.0;
   for (int k = 1; k <= N; ++k) {
@@ -165,6 +175,9 @@ struct orc_problem {
   grid fine;
   int L;       /* corner multigrid levels; lev[0] is the corner block A_CC */
   grid *lev;
+  int ylayer;  /* 0: exponential layer at y = 0; 1: parabolic layer (c2 = 0) */
+  int PL;      /* semicoarsening levels of the parabolic corner multigrid */
+  struct plevel *pl;
   double *band[2]; /* banded LU of A_CC (0) and A_CC^T (1), built lazily */
 };
 
@@ -198,7 +211,17 @@ orc_problem *orc_create(int N, double eps, double sigma, double clow_x,
 orc_problem *orc_create_ex(int N, double eps, double sigma, double clow_x,
                            double clow_y, int kind, int nl, const double *c1x,
                            const double *c2y, const double *r_int) {
-  if (N < 4 || N % 2 || nl < 2 || nl > N - 2 || kind < 0 || kind > 1) return NULL;
+  return orc_create_px(N, eps, sigma, clow_x, clow_y, kind, nl, 0, c1x, c2y, r_int);
+}
+
+static void par_build(orc_problem *p);
+
+orc_problem *orc_create_px(int N, double eps, double sigma, double clow_x,
+                           double clow_y, int kind, int nl, int ylayer,
+                           const double *c1x, const double *c2y, const double *r_int) {
+  if (N < 4 || N % 2 || nl < 2 || nl > N - 2 || kind < 0 || kind > 1 || ylayer < 0 ||
+      ylayer > 1)
+    return NULL;
   orc_problem *p = calloc(1, sizeof(*p));
   p->N = N;
   p->n1 = N - 1;
@@ -208,7 +231,8 @@ orc_problem *orc_create_ex(int N, double eps, double sigma, double clow_x,
   double *wx = calloc(N + 2, sizeof(double));
   double *wy = calloc(N + 2, sizeof(double));
   orc_mesh_axis_ex(N, eps, sigma, clow_x, kind, nl, p->xn, wx);
-  orc_mesh_axis_ex(N, eps, sigma, clow_y, kind, nl, p->yn, wy);
+  orc_mesh_axis_layer(N, eps, sigma, clow_y, kind, nl, ylayer, p->yn, wy);
+  p->ylayer = ylayer;
 
   p->fine = grid_alloc(p->n1, p->n1, eps);
   for (int k = 1; k <= N; ++k) {
@@ -257,8 +281,11 @@ orc_problem *orc_create_ex(int N, double eps, double sigma, double clow_x,
       for (int i = 1; i <= c->nx; ++i)
         c->r[gidx(c, i, j)] = f->r[gidx(f, 2 * i, 2 * j)];
   }
+  if (ylayer) par_build(p);
   return p;
 }
+
+static void par_free(orc_problem *p);
 
 void orc_destroy(orc_problem *p) {
   if (!p) return;
@@ -267,6 +294,7 @@ void orc_destroy(orc_problem *p) {
   grid_free(&p->fine);
   for (int l = 0; l < p->L; ++l) grid_free(&p->lev[l]);
   free(p->lev);
+  par_free(p);
   free(p->band[0]);
   free(p->band[1]);
   free(p);
@@ -707,6 +735,297 @@ void orc_level_gs(const orc_problem *p, int l, const double *b, double *z) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Corner multigrid, one parabolic and one exponential layer (Sec. 3.2).    */
+/*                                                                          */
+/* The corner block is an anisotropic operator there (West-East couplings   */
+/* of order 1/eps times the North-South ones), so the cycle coarsens by two */
+/* in x only.  On the finest level each row of A_CC is multiplied by        */
+/* hbar_i kbar_j (finite-element-like scaling); coarse operators are the    */
+/* Galerkin products P^T A P, 9-point stencils.  Interpolation to an odd    */
+/* fine node is operator induced: its row, collapsed North-South to three   */
+/* points, is solved for the node's value given the two even neighbours     */
+/* (which are coarse nodes); even nodes are injected; restriction is P^T.   */
+/* Smoothing: pointwise Gauss-Seidel in the downstream order (top-right to  */
+/* bottom-left); the coarsest level gets four sweeps.                       */
+/* ------------------------------------------------------------------------ */
+
+/* A level of the semicoarsening hierarchy: nx x ny unknowns, node (i, j) at
+ * (j-1) nx + (i-1); a[9 k + 3 (dj+1) + (di+1)] = coefficient of node
+ * (i+di, j+dj) in row k (zero for nodes outside the level); wl, wr = the
+ * interpolation weights of odd node i toward the coarse nodes (i-1)/2 and
+ * (i+1)/2 (fine nodes i-1 and i+1). */
+struct plevel {
+  int nx, ny;
+  double *a;
+  double *wl, *wr;
+};
+
+static int pidx(const struct plevel *v, int i, int j) { return (j - 1) * v->nx + (i - 1); }
+
+static double pget(const struct plevel *v, const double *z, int i, int j) {
+  if (i < 1 || i > v->nx || j < 1 || j > v->ny) return 0.0;
+  return z[pidx(v, i, j)];
+}
+
+static double *pcoef(const struct plevel *v, int i, int j, int di, int dj) {
+  return &v->a[9 * pidx(v, i, j) + 3 * (dj + 1) + (di + 1)];
+}
+
+/* Coarse nodes that fine node i (x index) interpolates from, with weights:
+ * even i: i/2 with weight 1; odd i: (i-1)/2 (dropped when it is the
+ * boundary node 0) with wl and (i+1)/2 with wr. */
+static int pcols(const struct plevel *f, int i, int j, int I[2], double w[2]) {
+  if (i % 2 == 0) {
+    I[0] = i / 2;
+    w[0] = 1.0;
+    return 1;
+  }
+  int n = 0;
+  if ((i - 1) / 2 >= 1) {
+    I[n] = (i - 1) / 2;
+    w[n++] = f->wl[pidx(f, i, j)];
+  }
+  I[n] = (i + 1) / 2;
+  w[n++] = f->wr[pidx(f, i, j)];
+  return n;
+}
+
+static struct plevel plevel_alloc(int nx, int ny) {
+  struct plevel v;
+  v.nx = nx;
+  v.ny = ny;
+  v.a = calloc((size_t)9 * nx * ny, sizeof(double));
+  v.wl = calloc((size_t)nx * ny, sizeof(double));
+  v.wr = calloc((size_t)nx * ny, sizeof(double));
+  return v;
+}
+
+/* Interpolation weights of level f (toward the next coarser level) from its
+ * own stencil: for odd i the row collapsed North-South,
+ *   (sum_dj a_{-1,dj}) z_{i-1} + (sum_dj a_{0,dj}) z_i + (sum_dj a_{+1,dj}) z_{i+1} = 0,
+ * solved for z_i. */
+static void par_weights(struct plevel *f) {
+  for (int j = 1; j <= f->ny; ++j)
+    for (int i = 1; i <= f->nx; i += 2) {
+      double w = 0.0, c = 0.0, e = 0.0;
+      for (int dj = -1; dj <= 1; ++dj) {
+        w += *pcoef(f, i, j, -1, dj);
+        c += *pcoef(f, i, j, 0, dj);
+        e += *pcoef(f, i, j, 1, dj);
+      }
+      f->wl[pidx(f, i, j)] = -w / c;
+      f->wr[pidx(f, i, j)] = -e / c;
+    }
+}
+
+/* Galerkin coarse operator A_c = P^T A_f P, by scattering each product
+ * P_{p,(I,j)} A_{p,q} P_{q,(I',j')}: fine row p = (i, j) restricts to the
+ * coarse nodes of pcols(i, j) (same j), its neighbour q = (i+di, j+dj)
+ * interpolates from those of pcols(i+di, j+dj), and I' - I lies in -1..1. */
+static void par_galerkin(const struct plevel *f, struct plevel *c) {
+  for (int j = 1; j <= f->ny; ++j)
+    for (int i = 1; i <= f->nx; ++i) {
+      int I[2], n = 0;
+      double rho[2];
+      n = pcols(f, i, j, I, rho);
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          int qi = i + di, qj = j + dj;
+          if (qi < 1 || qi > f->nx || qj < 1 || qj > f->ny) continue;
+          double a = *pcoef(f, i, j, di, dj);
+          int Iq[2];
+          double pi[2];
+          int nq = pcols(f, qi, qj, Iq, pi);
+          for (int s = 0; s < n; ++s)
+            for (int t = 0; t < nq; ++t) {
+              int d = Iq[t] - I[s];
+              if (d < -1 || d > 1) abort(); /* cannot happen: |qi - i| <= 1 */
+              *pcoef(c, I[s], j, d, dj) += rho[s] * a * pi[t];
+            }
+        }
+    }
+}
+
+/* FE rescaling factor of fine corner node (i, j): hbar_i kbar_j. */
+static double par_scale(const orc_problem *p, int i, int j) {
+  const grid *g = &p->fine;
+  return 0.5 * (g->hx[i] + g->hx[i + 1]) * 0.5 * (g->hy[j] + g->hy[j + 1]);
+}
+
+static void par_build(orc_problem *p) {
+  int h = p->h;
+  int L = 1;
+  for (int m = h; m % 2 == 0 && m > 2; m /= 2) ++L;
+  p->PL = L;
+  p->pl = calloc(L, sizeof(struct plevel));
+  /* level 0: the rows of A_CC (couplings into X, Y or I left out), each
+   * multiplied by hbar_i kbar_j */
+  p->pl[0] = plevel_alloc(h, h);
+  struct plevel *f = &p->pl[0];
+  for (int j = 1; j <= h; ++j)
+    for (int i = 1; i <= h; ++i) {
+      stencil5 s = gstencil(&p->fine, i, j);
+      double sc = par_scale(p, i, j);
+      *pcoef(f, i, j, 0, 0) = sc * s.C;
+      if (i > 1) *pcoef(f, i, j, -1, 0) = sc * s.W;
+      if (i < h) *pcoef(f, i, j, 1, 0) = sc * s.E;
+      if (j > 1) *pcoef(f, i, j, 0, -1) = sc * s.S;
+      if (j < h) *pcoef(f, i, j, 0, 1) = sc * s.Nn;
+    }
+  for (int l = 0; l + 1 < L; ++l) {
+    par_weights(&p->pl[l]);
+    p->pl[l + 1] = plevel_alloc(p->pl[l].nx / 2, h);
+    par_galerkin(&p->pl[l], &p->pl[l + 1]);
+  }
+}
+
+static void par_free(orc_problem *p) {
+  for (int l = 0; l < p->PL; ++l) {
+    free(p->pl[l].a);
+    free(p->pl[l].wl);
+    free(p->pl[l].wr);
+  }
+  free(p->pl);
+  p->pl = NULL;
+  p->PL = 0;
+}
+
+static void par_apply(const struct plevel *v, const double *z, double *y) {
+  for (int j = 1; j <= v->ny; ++j)
+    for (int i = 1; i <= v->nx; ++i) {
+      double s = 0.0;
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) s += *pcoef(v, i, j, di, dj) * pget(v, z, i + di, j + dj);
+      y[pidx(v, i, j)] = s;
+    }
+}
+
+/* One downstream Gauss-Seidel sweep in place: rows from top to bottom, each
+ * from right to left, every node solved for with its neighbours' latest
+ * values. */
+static void par_gs(const struct plevel *v, const double *b, double *z) {
+  for (int j = v->ny; j >= 1; --j)
+    for (int i = v->nx; i >= 1; --i) {
+      double acc = b[pidx(v, i, j)];
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di)
+          if (di || dj) acc -= *pcoef(v, i, j, di, dj) * pget(v, z, i + di, j + dj);
+      z[pidx(v, i, j)] = acc / *pcoef(v, i, j, 0, 0);
+    }
+}
+
+/* bc = P^T rf. */
+static void par_restrict(const struct plevel *f, const struct plevel *c, const double *rf,
+                         double *bc) {
+  for (int k = 0; k < c->nx * c->ny; ++k) bc[k] = 0.0;
+  for (int j = 1; j <= f->ny; ++j)
+    for (int i = 1; i <= f->nx; ++i) {
+      int I[2];
+      double w[2];
+      int n = pcols(f, i, j, I, w);
+      for (int s = 0; s < n; ++s) bc[pidx(c, I[s], j)] += w[s] * rf[pidx(f, i, j)];
+    }
+}
+
+/* zf += P zc. */
+static void par_prolong_add(const struct plevel *f, const struct plevel *c, const double *zc,
+                            double *zf) {
+  for (int j = 1; j <= f->ny; ++j)
+    for (int i = 1; i <= f->nx; ++i) {
+      int I[2];
+      double w[2];
+      int n = pcols(f, i, j, I, w);
+      double s = 0.0;
+      for (int t = 0; t < n; ++t) s += w[t] * zc[pidx(c, I[t], j)];
+      zf[pidx(f, i, j)] += s;
+    }
+}
+
+static void par_vcycle(const orc_problem *p, int l, const double *b, double *z) {
+  const struct plevel *v = &p->pl[l];
+  int n = v->nx * v->ny;
+  if (l == p->PL - 1) {
+    for (int s = 0; s < 4; ++s) par_gs(v, b, z);
+    return;
+  }
+  const struct plevel *c = &p->pl[l + 1];
+  int nc = c->nx * c->ny;
+  double *r = malloc(sizeof(double) * n);
+  double *bc = malloc(sizeof(double) * nc);
+  double *zc = calloc(nc, sizeof(double));
+  par_gs(v, b, z);
+  par_apply(v, z, r);
+  for (int k = 0; k < n; ++k) r[k] = b[k] - r[k];
+  par_restrict(v, c, r, bc);
+  par_vcycle(p, l + 1, bc, zc);
+  par_prolong_add(v, c, zc, z);
+  par_gs(v, b, z);
+  free(r);
+  free(bc);
+  free(zc);
+}
+
+/* Corner solve of the parabolic case: V(1,1) cycles on the rescaled system
+ * S A_CC z = S b from z = 0 until ||S b - S A_CC z||_2 <= rtol ||S b||_2
+ * (Sec. 3.2: a reduction by 1e2), or a fixed number of cycles. */
+static int par_corner_mg(orc_problem *p, int fixed_cycles, double rtol, int maxcyc,
+                         const double *b, double *z) {
+  const struct plevel *v = &p->pl[0];
+  int n = v->nx * v->ny;
+  double *bs = malloc(sizeof(double) * n), *r = malloc(sizeof(double) * n);
+  for (int j = 1; j <= v->ny; ++j)
+    for (int i = 1; i <= v->nx; ++i) bs[pidx(v, i, j)] = par_scale(p, i, j) * b[pidx(v, i, j)];
+  for (int k = 0; k < n; ++k) z[k] = 0.0;
+  int cyc = 0;
+  if (fixed_cycles > 0) {
+    for (; cyc < fixed_cycles; ++cyc) par_vcycle(p, 0, bs, z);
+  } else {
+    double nb = nrm2(n, bs);
+    while (nb > 0.0 && cyc < maxcyc) {
+      par_vcycle(p, 0, bs, z);
+      ++cyc;
+      par_apply(v, z, r);
+      for (int k = 0; k < n; ++k) r[k] = bs[k] - r[k];
+      if (nrm2(n, r) <= rtol * nb) break;
+    }
+  }
+  free(bs);
+  free(r);
+  return cyc;
+}
+
+int orc_par_num_levels(const orc_problem *p) { return p->PL; }
+int orc_par_level_nx(const orc_problem *p, int l) { return p->pl[l].nx; }
+void orc_par_level_stencil(const orc_problem *p, int l, double *a9) {
+  memcpy(a9, p->pl[l].a, sizeof(double) * 9 * p->pl[l].nx * p->pl[l].ny);
+}
+void orc_par_level_weights(const orc_problem *p, int l, double *wl, double *wr) {
+  size_t n = (size_t)p->pl[l].nx * p->pl[l].ny;
+  memcpy(wl, p->pl[l].wl, sizeof(double) * n);
+  memcpy(wr, p->pl[l].wr, sizeof(double) * n);
+}
+void orc_par_level_apply(const orc_problem *p, int l, const double *x, double *y) {
+  par_apply(&p->pl[l], x, y);
+}
+void orc_par_level_gs(const orc_problem *p, int l, const double *b, double *z) {
+  par_gs(&p->pl[l], b, z);
+}
+void orc_par_level_restrict(const orc_problem *p, int l, const double *rf, double *bc) {
+  par_restrict(&p->pl[l], &p->pl[l + 1], rf, bc);
+}
+void orc_par_level_interp(const orc_problem *p, int l, const double *zc, double *zf) {
+  const struct plevel *f = &p->pl[l];
+  for (int k = 0; k < f->nx * f->ny; ++k) zf[k] = 0.0;
+  par_prolong_add(f, &p->pl[l + 1], zc, zf);
+}
+int orc_par_corner_mg(orc_problem *p, int fixed_cycles, double rtol, int maxcyc,
+                      const double *b, double *z) {
+  if (!p->ylayer) return -1;
+  return par_corner_mg(p, fixed_cycles, rtol, maxcyc, b, z);
+}
+int orc_y_layer(const orc_problem *p) { return p->ylayer; }
+
+/* ------------------------------------------------------------------------ */
 /* Full preconditioner apply                                                 */
 /* ------------------------------------------------------------------------ */
 
@@ -723,13 +1042,23 @@ static void stats_add(orc_prec_stats *st, int cycles) {
   st->mg_cycles_total += cycles;
 }
 
+/* The corner solve of M: exact (the idealised M-hat) or the multigrid of the
+ * problem's layer type.  The parabolic cycle has no transposed form here:
+ * asked for one, it returns NaN so that the misuse cannot pass unnoticed. */
 static void corner_solve(orc_problem *p, const orc_prec_opts *o, int transpose,
                          const double *bC, double *zC, orc_prec_stats *st) {
   int cyc = 0;
-  if (o->corner == 0)
+  if (o->corner == 0) {
     orc_corner_exact(p, transpose, bC, zC);
-  else
+  } else if (p->ylayer) {
+    if (transpose) {
+      for (int k = 0; k < p->h * p->h; ++k) zC[k] = NAN;
+    } else {
+      cyc = par_corner_mg(p, o->mg_fixed, o->mg_rtol, o->mg_maxcyc, bC, zC);
+    }
+  } else {
     cyc = orc_corner_mg(p, transpose, o->mg_fixed, o->mg_rtol, o->mg_maxcyc, bC, zC);
+  }
   stats_add(st, cyc);
 }
 

@@ -6,8 +6,9 @@
  * Perturbed Convection Diffusion" (arXiv 2108.13468): the upwind 5-point
  * discretisation on a tensor Shishkin mesh (Sec. 3, eqs. tau exponential and
  * the 2D stencil), the block upper-triangular boundary-layer preconditioner
- * (Sec. 3.1, eq. 2D blocks), the corner multigrid for two exponential layers
- * (Sec. 3.2) and FGMRES (Sec. 3.3).
+ * (Sec. 3.1, eq. 2D blocks), the corner multigrids for two exponential
+ * layers and for one parabolic and one exponential layer (Sec. 3.2) and
+ * FGMRES (Sec. 3.3).
  *
  * Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
  * load this library.  It shares no code, header or table with the HIP path.
@@ -36,6 +37,11 @@ double orc_mesh_axis(int N, double eps, double sigma, double clow,
  * sigma eps ln N / clow >= nl/N).  Returns tau. */
 double orc_mesh_axis_ex(int N, double eps, double sigma, double clow, int kind, int nl,
                         double *nodes, double *widths);
+/* The same with the axis's layer type: parabolic = 0 as above; parabolic = 1
+ * (Sec. 3, eq. tau parabolic) uses sqrt(eps) in place of eps / clow:
+ * tau = min(nl/N, sigma sqrt(eps) ln N). */
+double orc_mesh_axis_layer(int N, double eps, double sigma, double clow, int kind, int nl,
+                           int parabolic, double *nodes, double *widths);
 
 /* Opaque problem: the full grid operator plus its corner multigrid levels. */
 typedef struct orc_problem orc_problem;
@@ -51,7 +57,14 @@ orc_problem *orc_create(int N, double eps, double sigma, double clow_x,
 orc_problem *orc_create_ex(int N, double eps, double sigma, double clow_x,
                            double clow_y, int kind, int nl, const double *c1x,
                            const double *c2y, const double *r_int);
+/* The same with the layer type at y = 0: ylayer 0 exponential, 1 parabolic
+ * (the case c2 = 0 of Sec. 3: y-axis mesh of eq. tau parabolic, corner
+ * multigrid with x-semicoarsening, see orc_par_corner_mg). */
+orc_problem *orc_create_px(int N, double eps, double sigma, double clow_x,
+                           double clow_y, int kind, int nl, int ylayer,
+                           const double *c1x, const double *c2y, const double *r_int);
 void orc_destroy(orc_problem *p);
+int orc_y_layer(const orc_problem *p);
 
 int orc_n(const orc_problem *p);             /* (N-1)^2 */
 int orc_num_levels(const orc_problem *p);    /* corner multigrid levels */
@@ -108,6 +121,27 @@ void orc_level_apply(const orc_problem *p, int l, const double *x, double *y);
 void orc_level_restrict(const orc_problem *p, int l, const double *rf, double *bc);
 void orc_level_interp(const orc_problem *p, int l, const double *zc, double *zf);
 void orc_level_gs(const orc_problem *p, int l, const double *b, double *z);
+
+/* Parabolic-case corner multigrid (Sec. 3.2): V(1,1) cycles with
+ * x-semicoarsening, Galerkin 9-point coarse operators on the rescaled
+ * corner block S A_CC (S = diag(hbar_i kbar_j)), operator-induced
+ * interpolation, downstream Gauss-Seidel; stops when the rescaled residual
+ * has fallen by rtol (or after fixed_cycles > 0 cycles).  Returns the
+ * cycles used, -1 for a problem without the parabolic layer.  Level l has
+ * (h >> l) x h nodes; the per-level accessors below are for pins:
+ * a9[9 k + 3 (dj+1) + (di+1)] couples node k = (j-1) nx + (i-1) to
+ * (i+di, j+dj); wl, wr are the weights of odd fine nodes toward coarse
+ * nodes (i-1)/2 and (i+1)/2. */
+int orc_par_corner_mg(orc_problem *p, int fixed_cycles, double rtol, int maxcyc,
+                      const double *b, double *z);
+int orc_par_num_levels(const orc_problem *p);
+int orc_par_level_nx(const orc_problem *p, int l);
+void orc_par_level_stencil(const orc_problem *p, int l, double *a9);
+void orc_par_level_weights(const orc_problem *p, int l, double *wl, double *wr);
+void orc_par_level_apply(const orc_problem *p, int l, const double *x, double *y);
+void orc_par_level_gs(const orc_problem *p, int l, const double *b, double *z);
+void orc_par_level_restrict(const orc_problem *p, int l, const double *rf, double *bc);
+void orc_par_level_interp(const orc_problem *p, int l, const double *zc, double *zf);
 
 /* FGMRES (Saad's flexible GMRES with modified Gram-Schmidt), right
  * preconditioned, x0 = 0. */

@@ -63,7 +63,25 @@ def lib():
         L.orc_create_ex.restype = C.c_void_p
         L.orc_create_ex.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_int, C.c_int, _dp, _dp, _dp]
+        L.orc_mesh_axis_layer.restype = C.c_double
+        L.orc_mesh_axis_layer.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int,
+                                          C.c_int, C.c_int, _dp, _dp]
+        L.orc_create_px.restype = C.c_void_p
+        L.orc_create_px.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
         L.orc_destroy.argtypes = [C.c_void_p]
+        for f in ("orc_y_layer", "orc_par_num_levels"):
+            getattr(L, f).restype = C.c_int
+            getattr(L, f).argtypes = [C.c_void_p]
+        L.orc_par_level_nx.restype = C.c_int
+        L.orc_par_level_nx.argtypes = [C.c_void_p, C.c_int]
+        L.orc_par_level_stencil.argtypes = [C.c_void_p, C.c_int, _dp]
+        L.orc_par_level_weights.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        for f in ("orc_par_level_apply", "orc_par_level_gs", "orc_par_level_restrict",
+                  "orc_par_level_interp"):
+            getattr(L, f).argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_par_corner_mg.restype = C.c_int
+        L.orc_par_corner_mg.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_int, _dp, _dp]
         for f in ("orc_n", "orc_num_levels"):
             getattr(L, f).restype = C.c_int
             getattr(L, f).argtypes = [C.c_void_p]
@@ -118,17 +136,20 @@ def _f64(a):
 
 
 MESH_KINDS = {"shishkin": 0, "bakhvalov-shishkin": 1}
+LAYERS = {"exponential": 0, "parabolic": 1}
 
 
-def mesh_axis(N, eps, sigma=2.0, clow=1.0, kind="shishkin", layer_cells=None):
+def mesh_axis(N, eps, sigma=2.0, clow=1.0, kind="shishkin", layer_cells=None,
+              layer="exponential"):
     """One axis of the layer-adapted mesh: (tau, nodes[0..N], widths[0..N]).
     kind 'shishkin' or 'bakhvalov-shishkin'; layer_cells = cells on [0, tau]
-    (default N/2)."""
+    (default N/2); layer 'exponential' (width scale eps/clow) or 'parabolic'
+    (sqrt(eps))."""
     nodes = np.zeros(N + 1)
     widths = np.zeros(N + 2)
     nl = N // 2 if layer_cells is None else int(layer_cells)
-    tau = lib().orc_mesh_axis_ex(N, eps, sigma, clow, MESH_KINDS[kind], nl, _p(nodes),
-                                 _p(widths))
+    tau = lib().orc_mesh_axis_layer(N, eps, sigma, clow, MESH_KINDS[kind], nl, LAYERS[layer],
+                                    _p(nodes), _p(widths))
     return tau, nodes, widths[: N + 1]
 
 
@@ -137,11 +158,12 @@ class Problem:
     boundary-layer preconditioner and FGMRES of the paper (FP64, CPU)."""
 
     def __init__(self, N, eps, c1=None, c2=None, r=None, sigma=2.0, clow_x=1.0,
-                 clow_y=1.0, mesh_kind="shishkin", layer_cells=None):
+                 clow_y=1.0, mesh_kind="shishkin", layer_cells=None, y_layer="exponential"):
         self.N, self.eps, self.n1 = N, eps, N - 1
         nl = N // 2 if layer_cells is None else int(layer_cells)
+        self.y_layer = y_layer
         tx, self.x, self.hx = mesh_axis(N, eps, sigma, clow_x, mesh_kind, nl)
-        ty, self.y, self.hy = mesh_axis(N, eps, sigma, clow_y, mesh_kind, nl)
+        ty, self.y, self.hy = mesh_axis(N, eps, sigma, clow_y, mesh_kind, nl, layer=y_layer)
         self.tau_x, self.tau_y = tx, ty
         c1x = _f64(c1(self.x) if callable(c1) else (np.ones(N + 1) if c1 is None else c1))
         c2y = _f64(c2(self.y) if callable(c2) else (np.ones(N + 1) if c2 is None else c2))
@@ -152,10 +174,10 @@ class Problem:
         else:
             rr = _f64(r).ravel()
         self.c1x, self.c2y, self.r = c1x, c2y, rr
-        self._h = lib().orc_create_ex(N, eps, sigma, clow_x, clow_y, MESH_KINDS[mesh_kind], nl,
-                                      _p(c1x), _p(c2y), _p(rr))
+        self._h = lib().orc_create_px(N, eps, sigma, clow_x, clow_y, MESH_KINDS[mesh_kind], nl,
+                                      LAYERS[y_layer], _p(c1x), _p(c2y), _p(rr))
         if not self._h:
-            raise ValueError("orc_create_ex rejected N=%r, layer cells %r" % (N, nl))
+            raise ValueError("orc_create_px rejected N=%r, layer cells %r" % (N, nl))
         self.n = self.n1 * self.n1
         self.h = nl
 
@@ -214,10 +236,48 @@ class Problem:
         return z
 
     def corner_mg(self, bC, transpose=False, fixed=0, rtol=1e-3, maxcyc=20):
+        """The corner multigrid of the problem's layer type (the parabolic one
+        has no transposed form)."""
         bC = _f64(bC)
         z = np.zeros_like(bC)
-        cyc = lib().orc_corner_mg(self._h, int(transpose), fixed, rtol, maxcyc, _p(bC), _p(z))
+        if self.y_layer == "parabolic":
+            if transpose:
+                raise ValueError("the parabolic corner cycle has no transposed form")
+            cyc = lib().orc_par_corner_mg(self._h, fixed, rtol, maxcyc, _p(bC), _p(z))
+        else:
+            cyc = lib().orc_corner_mg(self._h, int(transpose), fixed, rtol, maxcyc, _p(bC),
+                                      _p(z))
         return z, cyc
+
+    # parabolic-case semicoarsening hierarchy (level l: nx_l x h nodes) -----
+    @property
+    def par_levels(self):
+        return [lib().orc_par_level_nx(self._h, l) for l in range(lib().orc_par_num_levels(self._h))]
+
+    def par_stencil(self, l):
+        """9-point stencils of level l, array [j-1, i-1, dj+1, di+1]."""
+        nx = self.par_levels[l]
+        a = np.zeros(9 * nx * self.h)
+        lib().orc_par_level_stencil(self._h, l, _p(a))
+        return a.reshape(self.h, nx, 3, 3)
+
+    def par_weights(self, l):
+        nx = self.par_levels[l]
+        wl, wr = np.zeros(nx * self.h), np.zeros(nx * self.h)
+        lib().orc_par_level_weights(self._h, l, _p(wl), _p(wr))
+        return wl.reshape(self.h, nx), wr.reshape(self.h, nx)
+
+    def par_op(self, name, l, v, z=None):
+        sizes = self.par_levels
+        v = _f64(v)
+        if name == "gs":
+            out = _f64(z).copy()
+        elif name == "restrict":
+            out = np.zeros(sizes[l + 1] * self.h)
+        else:
+            out = np.zeros(sizes[l] * self.h)
+        getattr(lib(), "orc_par_level_" + name)(self._h, l, _p(v), _p(out))
+        return out
 
     def corner_exact(self, bC, transpose=False):
         bC = _f64(bC)

@@ -33,6 +33,7 @@ class Instance:
     clow: Tuple[float, float] = (1.0, 1.0)
     mesh_kind: str = "shishkin"          # or "bakhvalov-shishkin"
     layer_cells: Optional[int] = None    # cells on [0, tau] per axis (None: N/2)
+    y_layer: str = "exponential"         # or "parabolic" (c2 = 0: layer width sqrt(eps))
 
     def c1_at(self, x):
         c = self.c1
@@ -117,3 +118,14 @@ def mms_exponential(N, eps):
     solution (see tests)."""
     return Instance(N=N, eps=eps, c1=(2.0, 0.0, 0.0), c2=(3.0, 0.0, 0.0),
                     r_const=1.0, sigma=2.5, clow=(2.0, 3.0))
+
+
+def mms_parabolic(N, eps):
+    """The paper's test with one parabolic and one exponential layer (Sec.
+    3.3): -eps Lap u - u_x + u = f, so c = (1, 0), r = 1; sigma = 5/2; the
+    x-layer mesh takes the lower bound Clow = 0.99 of c1 = 1 (the bound the
+    one-dimensional tables are reproduced with); the y-axis transition point
+    is sigma sqrt(eps) ln N.  f is supplied by the manufactured solution (see
+    tests)."""
+    return Instance(N=N, eps=eps, c1=(1.0, 0.0, 0.0), c2=(0.0, 0.0, 0.0), r_const=1.0,
+                    sigma=2.5, clow=(0.99, 1.0), y_layer="parabolic")
