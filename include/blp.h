@@ -85,14 +85,24 @@ typedef struct {
  *                0 = N/2); the layer side of each axis (regions of Sec. 3.1)
  *                is then i <= qN, and the corner multigrid coarsens it by
  *                halving while the node count is even.
+ *   y_layer      the layer at y = 0: BLP_LAYER_EXPONENTIAL (c2 > 0, as
+ *                above) or BLP_LAYER_PARABOLIC (Sec. 3, the case c2 = 0:
+ *                eq. tau parabolic, tau_y = min(q, sigma sqrt(eps) ln N),
+ *                clow_y unused; the graded kind grades with the scale
+ *                sigma sqrt(eps)).  A parabolic problem's corner block is
+ *                solved by the semicoarsening multigrid of Sec. 3.2 (see
+ *                blp_precondition).
  * The interior cells are equal in every case. */
 #define BLP_MESH_SHISHKIN 0
 #define BLP_MESH_BAKHVALOV_SHISHKIN 1
+#define BLP_LAYER_EXPONENTIAL 0
+#define BLP_LAYER_PARABOLIC 1
 typedef struct {
   double sigma;
   double clow_x, clow_y;
   int kind;
   int layer_cells;
+  int y_layer;
 } blp_mesh_opts;
 
 /* Mesh nodes of both axes: x[0..N], y[0..N] (host, N+1 doubles each), and
@@ -121,14 +131,25 @@ int blp_nodes(const blp_problem *p, double *x, double *y);
 
 /* Preconditioner setup (Sec. 3.1 and 3.2; setup phase described in
  * Sec. 3.3): Thomas factorisations of the X and Y edge-layer lines (no
- * pivoting, Lemma diag_dom), the corner multigrid hierarchy (full
- * coarsening, rediscretised levels, FE rescaling) and the FP32 copies used
- * by the mixed-precision mode.
+ * pivoting, Lemma diag_dom), the corner multigrid hierarchy and the FP32
+ * copies used by the mixed-precision mode.  The hierarchy follows the
+ * problem's layer at y = 0: two exponential layers, full coarsening with
+ * rediscretised levels and FE rescaling; a parabolic layer, coarsening by
+ * two in x only with Galerkin 9-point coarse operators of the
+ * hbar_i kbar_j-rescaled corner block, operator-induced interpolation (each
+ * odd column's row collapsed North-South) and its transpose as restriction,
+ * built on the device in FP64.  Both smooth with downstream Gauss-Seidel,
+ * one sweep before and after the coarse correction, four on the coarsest
+ * level.
  *   mg_fixed  > 0: every corner solve runs exactly this many V(1,1) cycles
  *             (makes M a fixed linear operator; needed for M^T identities)
  *             = 0: stationary iteration until the corner residual of the
- *             rescaled system has dropped by mg_rtol (paper: 1e-3), at most
- *             mg_maxcyc cycles.
+ *             rescaled system has dropped by mg_rtol (paper: 1e-3 for two
+ *             exponential layers, 1e-2 with a parabolic one; o = NULL takes
+ *             these), at most mg_maxcyc cycles.
+ * The parabolic cycle has no transposed form: for such a problem every
+ * transposed apply or solve (blp_prec_apply with transpose, the adjoint
+ * solves) returns BLP_E_INVAL.
  * Calling it again on a preconditioned problem only replaces the options;
  * every later solve (single or batched) uses the new ones.
  * Errors: BLP_E_INVAL, BLP_E_NOMEM, BLP_E_HIP. */

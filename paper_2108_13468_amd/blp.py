@@ -38,14 +38,16 @@ class Field(C.Structure):
 
 class MeshOpts(C.Structure):
     _fields_ = [("sigma", C.c_double), ("clow_x", C.c_double), ("clow_y", C.c_double),
-                ("kind", C.c_int), ("layer_cells", C.c_int)]
+                ("kind", C.c_int), ("layer_cells", C.c_int), ("y_layer", C.c_int)]
 
 
 MESH_KINDS = {"shishkin": 0, "bakhvalov-shishkin": 1}
+Y_LAYERS = {"exponential": 0, "parabolic": 1}
 
 
-def _mesh_opts(sigma, clow, kind, layer_cells):
-    return MeshOpts(sigma, clow[0], clow[1], MESH_KINDS[kind], int(layer_cells or 0))
+def _mesh_opts(sigma, clow, kind, layer_cells, y_layer="exponential"):
+    return MeshOpts(sigma, clow[0], clow[1], MESH_KINDS[kind], int(layer_cells or 0),
+                    Y_LAYERS[y_layer])
 
 
 class PrecOpts(C.Structure):
@@ -158,10 +160,12 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def mesh(N, eps, sigma=2.0, clow=(1.0, 1.0), kind="shishkin", layer_cells=None):
-    """Mesh nodes of both axes: ((tau_x, tau_y), x[0..N], y[0..N])."""
+def mesh(N, eps, sigma=2.0, clow=(1.0, 1.0), kind="shishkin", layer_cells=None,
+         y_layer="exponential"):
+    """Mesh nodes of both axes: ((tau_x, tau_y), x[0..N], y[0..N]); y_layer
+    'parabolic' takes the transition point sigma sqrt(eps) ln N on y."""
     x, y, tau = np.zeros(N + 1), np.zeros(N + 1), np.zeros(2)
-    o = _mesh_opts(sigma, clow, kind, layer_cells)
+    o = _mesh_opts(sigma, clow, kind, layer_cells, y_layer)
     _check(lib().blp_mesh(N, eps, C.byref(o), x.ctypes.data_as(_dp), y.ctypes.data_as(_dp),
                           tau.ctypes.data_as(_dp)), "blp_mesh")
     return (float(tau[0]), float(tau[1])), x, y
@@ -185,7 +189,7 @@ class Problem:
     """An assembled operator on the device (one handle of the C library)."""
 
     def __init__(self, N, eps, c1, c2, r, sigma=2.0, clow=(1.0, 1.0), stream=None,
-                 mesh_kind="shishkin", layer_cells=None):
+                 mesh_kind="shishkin", layer_cells=None, y_layer="exponential"):
         import torch
         self.torch = torch
         self.N, self.eps, self.n = N, eps, (N - 1) ** 2
@@ -195,7 +199,8 @@ class Problem:
         self.stream = stream
         keep = []
         f1, f2, fr = _field(c1, N, keep), _field(c2, N, keep), _field(r, N, keep)
-        mo = _mesh_opts(sigma, clow, mesh_kind, layer_cells)
+        mo = _mesh_opts(sigma, clow, mesh_kind, layer_cells, y_layer)
+        self.y_layer = y_layer
         h = C.c_void_p()
         _check(lib().blp_assemble(N, eps, C.byref(f1), C.byref(f2), C.byref(fr), C.byref(mo),
                                   C.c_void_p(stream.cuda_stream), C.byref(h)), "blp_assemble")
@@ -214,7 +219,11 @@ class Problem:
         _check(lib().blp_nodes(self._h, x.ctypes.data_as(_dp), y.ctypes.data_as(_dp)), "blp_nodes")
         return x, y
 
-    def precondition(self, mg_fixed=0, mg_rtol=1e-3, mg_maxcyc=20):
+    def precondition(self, mg_fixed=0, mg_rtol=None, mg_maxcyc=20):
+        """mg_rtol None: the paper's corner reduction, 1e-3 for two
+        exponential layers, 1e-2 with a parabolic layer (Sec. 3.2)."""
+        if mg_rtol is None:
+            mg_rtol = 1e-2 if self.y_layer == "parabolic" else 1e-3
         o = PrecOpts(mg_fixed, mg_rtol, mg_maxcyc)
         _check(lib().blp_precondition(self._h, C.byref(o)), "blp_precondition")
         return self
@@ -338,7 +347,8 @@ class Problem:
 def from_instance(inst, nodal_r=None):
     """Assemble a problem from an inputs.Instance (coefficients sampled at the
     mesh nodes, which blp_mesh returns)."""
-    _, x, y = mesh(inst.N, inst.eps, inst.sigma, inst.clow, inst.mesh_kind, inst.layer_cells)
+    _, x, y = mesh(inst.N, inst.eps, inst.sigma, inst.clow, inst.mesh_kind, inst.layer_cells,
+                   inst.y_layer)
     if inst.r_ctrl is not None:
         r = ("bilinear", inst.r_ctrl)
     elif nodal_r is not None:
@@ -347,7 +357,7 @@ def from_instance(inst, nodal_r=None):
         r = float(inst.r_const)
     return Problem(inst.N, inst.eps, ("axis", inst.c1_at(x)), ("axis", inst.c2_at(y)), r,
                    sigma=inst.sigma, clow=inst.clow, mesh_kind=inst.mesh_kind,
-                   layer_cells=inst.layer_cells)
+                   layer_cells=inst.layer_cells, y_layer=inst.y_layer)
 
 
 class Batch:

@@ -28,6 +28,7 @@
 #include "kernels_op.h"
 #include "kernels_prec.h"
 #include "kernels_1d.h"
+#include "kernels_par.h"
 
 namespace {
 
@@ -80,6 +81,16 @@ struct LevelDev {
   MgLevel<T> view(bool tr, T *z, T *b, T *t) const {
     return MgLevel<T>{grid(), ic[tr ? 1 : 0], hbx, hby, wlx, wrx, wly, wry, z, b, t, nslot};
   }
+};
+
+// A level of the parabolic-case corner hierarchy: nx columns, h rows.
+template <typename T>
+struct ParLevelDev {
+  int nx = 0;
+  T *a = nullptr;            // nine coupling planes (coarse levels only)
+  T *ic = nullptr;           // 1 / centre coupling
+  T *wl = nullptr, *wr = nullptr;  // weights toward the next level (not on the coarsest)
+  T *sx = nullptr, *sy = nullptr;  // level 0: rescaling factors hbar_i, kbar_j (0..h+1)
 };
 
 template <typename T>
@@ -170,6 +181,11 @@ struct blp_problem {
   blp_prec_opts popts{0, 1e-3, 20};
   std::vector<LevelDev<double>> l64;
   std::vector<LevelDev<float>> l32;
+  // layer at y = 0: BLP_LAYER_EXPONENTIAL (corner levels l64/l32 above) or
+  // BLP_LAYER_PARABOLIC (x-semicoarsening levels pl64/pl32)
+  int ylayer = BLP_LAYER_EXPONENTIAL;
+  std::vector<ParLevelDev<double>> pl64;
+  std::vector<ParLevelDev<float>> pl32;
   // solves run as a batch of systems over this problem (rebuilt when the
   // number of right-hand sides changes); FP32 staging of the test hook
   Batch *own = nullptr;
@@ -251,6 +267,12 @@ std::vector<LevelDev<double>> &levels<double>(blp_problem *p) { return p->l64; }
 template <>
 std::vector<LevelDev<float>> &levels<float>(blp_problem *p) { return p->l32; }
 template <typename T>
+std::vector<ParLevelDev<T>> &par_levels(blp_problem *p);
+template <>
+std::vector<ParLevelDev<double>> &par_levels<double>(blp_problem *p) { return p->pl64; }
+template <>
+std::vector<ParLevelDev<float>> &par_levels<float>(blp_problem *p) { return p->pl32; }
+template <typename T>
 Grid<T> fine_grid(blp_problem *p);
 template <>
 Grid<double> fine_grid<double>(blp_problem *p) { return p->grid64(); }
@@ -279,16 +301,20 @@ bool finite_all(const double *v, size_t n) {
 // x_i = -(sigma eps / clow) ln(1 - (1 - 1/N) i / nl); uniform mesh when that
 // tau reaches q.  Widths are taken from the closed forms (never as
 // differences of coordinates): w[k] = x_k - x_{k-1}, w[0] = w[N+1] = 0.
-// Returns tau.
+// A parabolic layer (eq. tau parabolic) takes the width scale sqrt(eps)
+// where an exponential one takes eps / clow.  Returns tau.
 double axis_mesh(int N, double eps, double sigma, double clow, int kind, int nl,
-                 std::vector<double> &nodes, std::vector<double> &w) {
+                 std::vector<double> &nodes, std::vector<double> &w, bool parabolic = false) {
   nodes.assign(N + 1, 0.0);
   w.assign(N + 2, 0.0);
-  const double q = (double)nl / N, layer = sigma * eps * std::log((double)N) / clow;
+  const double q = (double)nl / N;
+  const double layer = parabolic ? sigma * std::sqrt(eps) * std::log((double)N)
+                                 : sigma * eps * std::log((double)N) / clow;
   const double tau = std::min(q, layer);
   const bool graded = kind == BLP_MESH_BAKHVALOV_SHISHKIN && layer < q;
   const double hl = tau / nl, hi = (1.0 - tau) / (N - nl);
-  const double s = sigma * eps / clow, a = (1.0 - 1.0 / N) / nl;
+  const double s = parabolic ? sigma * std::sqrt(eps) : sigma * eps / clow,
+               a = (1.0 - 1.0 / N) / nl;
   for (int k = 1; k <= nl; ++k) {
     w[k] = graded ? s * std::log1p(a / (1.0 - a * k)) : hl;
     nodes[k] = k == nl ? tau : (graded ? -s * std::log1p(-a * k) : k * hl);
@@ -304,11 +330,12 @@ double axis_mesh(int N, double eps, double sigma, double clow, int kind, int nl,
 // sigma = 2, clow = 1, N/2 layer cells); BLP_E_INVAL when outside the
 // constructions above.
 int mesh_options(int N, const blp_mesh_opts *o, blp_mesh_opts *out) {
-  blp_mesh_opts m{2.0, 1.0, 1.0, BLP_MESH_SHISHKIN, 0};
+  blp_mesh_opts m{2.0, 1.0, 1.0, BLP_MESH_SHISHKIN, 0, BLP_LAYER_EXPONENTIAL};
   if (o) m = *o;
   if (m.layer_cells == 0) m.layer_cells = N / 2;
   if (!(m.sigma > 0) || !(m.clow_x > 0) || !(m.clow_y > 0)) return BLP_E_INVAL;
   if (m.kind != BLP_MESH_SHISHKIN && m.kind != BLP_MESH_BAKHVALOV_SHISHKIN) return BLP_E_INVAL;
+  if (m.y_layer != BLP_LAYER_EXPONENTIAL && m.y_layer != BLP_LAYER_PARABOLIC) return BLP_E_INVAL;
   if (m.layer_cells < 2 || m.layer_cells > N - 2) return BLP_E_INVAL;
   *out = m;
   return BLP_OK;
@@ -394,6 +421,9 @@ void level_diag(blp_problem *p, const LevelDev<double> &l64, LevelDev<T> &d) {
   k_diag_skew<T, true><<<blocks1d(d.nslot), 256, 0, p->stream>>>(l64.grid(), st, d.ic[1], d.nslot);
 }
 
+int build_exp_levels(blp_problem *p);
+int build_par_levels(blp_problem *p);
+
 int build_preconditioner(blp_problem *p) {
   const int h = p->h, n1 = p->n1;
   BLP_TRY(build_fine_prec(p, p->f64));
@@ -415,6 +445,21 @@ int build_preconditioner(blp_problem *p) {
                                                                     p->f32.fac[v][k], fl);
   }
   // ---- corner multigrid hierarchy (Sec. 3.2) ------------------------------
+  if (p->ylayer == BLP_LAYER_PARABOLIC) {
+    BLP_TRY(build_par_levels(p));
+  } else {
+    BLP_TRY(build_exp_levels(p));
+  }
+  BLP_TRY(p->alloc(&p->tmp32a, p->n));
+  BLP_TRY(p->alloc(&p->tmp32b, p->n));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return BLP_OK;
+}
+
+// Two exponential layers: full coarsening, rediscretised levels.
+int build_exp_levels(blp_problem *p) {
+  const int h = p->h, n1 = p->n1;
   std::vector<LevelHost> LH;
   {
     LevelHost l0;
@@ -466,10 +511,55 @@ int build_preconditioner(blp_problem *p) {
     level_diag<double>(p, p->l64[l], p->l64[l]);
     level_diag<float>(p, p->l64[l], p->l32[l]);
   }
-  BLP_TRY(p->alloc(&p->tmp32a, p->n));
-  BLP_TRY(p->alloc(&p->tmp32b, p->n));
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(p->stream));
+  return BLP_OK;
+}
+
+// One parabolic and one exponential layer: x-semicoarsening, Galerkin
+// levels (set up in FP64 on the device, then copied to FP32).  Coarsening
+// halves the columns while their count is even and above 2.
+int build_par_levels(blp_problem *p) {
+  const int h = p->h;
+  int L = 1;
+  for (int m = h; m % 2 == 0 && m > 2; m /= 2) ++L;
+  std::vector<ParLevelDev<double>> &D = p->pl64;
+  std::vector<ParLevelDev<float>> &F = p->pl32;
+  D.assign(L, ParLevelDev<double>{});
+  F.assign(L, ParLevelDev<float>{});
+  std::vector<double> sx(h + 2, 0.0), sy(h + 2, 0.0);
+  for (int k = 1; k <= h; ++k) {
+    sx[k] = 0.5 * (p->wx[k] + p->wx[k + 1]);
+    sy[k] = 0.5 * (p->wy[k] + p->wy[k + 1]);
+  }
+  BLP_TRY(p->upload(&D[0].sx, sx));
+  BLP_TRY(p->upload(&D[0].sy, sy));
+  BLP_TRY(p->upload(&F[0].sx, sx));
+  BLP_TRY(p->upload(&F[0].sy, sy));
+  auto to32 = [&](const double *src, float **dst, size_t n) {
+    BLP_TRY(p->alloc(dst, n));
+    k_convert<double, float><<<blocks1d(n), 256, 0, p->stream>>>(src, *dst, n);
+    return BLP_OK;
+  };
+  for (int l = 0; l < L; ++l) {
+    D[l].nx = F[l].nx = h >> l;
+    const int nx = D[l].nx;
+    const size_t n = (size_t)nx * h;
+    const ParSetupLevel f{p->grid64(), D[0].sx, D[0].sy, l ? D[l].a : nullptr, nx, h};
+    BLP_TRY(p->alloc(&D[l].ic, n));
+    k_par_invc<<<grid2d(nx, h), 256, 0, p->stream>>>(f, D[l].ic);
+    BLP_TRY(to32(D[l].ic, &F[l].ic, n));
+    if (l + 1 < L) {
+      BLP_TRY(zalloc(p, &D[l].wl, n));
+      BLP_TRY(zalloc(p, &D[l].wr, n));
+      k_par_weights<<<grid2d((nx + 1) / 2, h), 256, 0, p->stream>>>(f, D[l].wl, D[l].wr);
+      const int nxc = nx / 2;
+      BLP_TRY(p->alloc(&D[l + 1].a, (size_t)9 * nxc * h));
+      k_par_rap<<<grid2d(nxc, h), 256, 0, p->stream>>>(f, D[l].wl, D[l].wr, nxc, D[l + 1].a);
+      BLP_TRY(to32(D[l].wl, &F[l].wl, n));
+      BLP_TRY(to32(D[l].wr, &F[l].wr, n));
+      BLP_TRY(to32(D[l + 1].a, &F[l + 1].a, (size_t)9 * nxc * h));
+    }
+    HIP_TRY(hipGetLastError());
+  }
   return BLP_OK;
 }
 
@@ -592,7 +682,8 @@ int blp_mesh(int N, double eps, const blp_mesh_opts *o, double *x, double *y, do
   std::vector<double> nodes, w;
   const double tx = axis_mesh(N, eps, m.sigma, m.clow_x, m.kind, m.layer_cells, nodes, w);
   std::memcpy(x, nodes.data(), sizeof(double) * (N + 1));
-  const double ty = axis_mesh(N, eps, m.sigma, m.clow_y, m.kind, m.layer_cells, nodes, w);
+  const double ty = axis_mesh(N, eps, m.sigma, m.clow_y, m.kind, m.layer_cells, nodes, w,
+                              m.y_layer == BLP_LAYER_PARABOLIC);
   std::memcpy(y, nodes.data(), sizeof(double) * (N + 1));
   if (tau) {
     tau[0] = tx;
@@ -629,7 +720,9 @@ int blp_assemble(int N, double eps, const blp_field *c1, const blp_field *c2, co
     return BLP_E_HIP;
   }
   axis_mesh(N, eps, m.sigma, m.clow_x, m.kind, m.layer_cells, p->xn, p->wx);
-  axis_mesh(N, eps, m.sigma, m.clow_y, m.kind, m.layer_cells, p->yn, p->wy);
+  axis_mesh(N, eps, m.sigma, m.clow_y, m.kind, m.layer_cells, p->yn, p->wy,
+            m.y_layer == BLP_LAYER_PARABOLIC);
+  p->ylayer = m.y_layer;
   p->c1.assign(N + 1, 0.0);
   p->c2.assign(N + 1, 0.0);
   for (int k = 0; k <= N; ++k) {
@@ -694,7 +787,10 @@ int blp_nodes(const blp_problem *p, double *x, double *y) {
 
 int blp_precondition(blp_problem *p, const blp_prec_opts *o) {
   if (!p) return BLP_E_INVAL;
-  blp_prec_opts po = o ? *o : blp_prec_opts{0, 1e-3, 20};
+  // default corner stopping rule (Sec. 3.2): a residual reduction by 1e3
+  // for two exponential layers, by 1e2 with a parabolic layer
+  blp_prec_opts po = o ? *o
+                       : blp_prec_opts{0, p->ylayer == BLP_LAYER_PARABOLIC ? 1e-2 : 1e-3, 20};
   if (po.mg_fixed < 0 || (po.mg_fixed == 0 && (!(po.mg_rtol > 0 && po.mg_rtol < 1) || po.mg_maxcyc < 1)))
     return BLP_E_INVAL;
   p->popts = po;
@@ -726,9 +822,10 @@ int blp_batch_create(blp_problem *const *probs, int S, void *stream, const blp_b
   if (o && o->sweep_variant < 0) return BLP_E_INVAL;
   std::unique_ptr<blp_batch> b(new (std::nothrow) blp_batch());
   if (!b) return BLP_E_NOMEM;
-  // one part per mesh size, largest first
+  // one part per mesh size and corner kind (exponential / parabolic layer
+  // at y = 0), largest meshes first
   std::map<int, std::vector<int>> byN;
-  for (int s = 0; s < S; ++s) byN[probs[s]->N].push_back(s);
+  for (int s = 0; s < S; ++s) byN[2 * probs[s]->N + probs[s]->ylayer].push_back(s);
   const bool graphs = o && o->graphs != 0;
   for (auto it = byN.rbegin(); it != byN.rend(); ++it) {
     std::vector<blp_problem *> pp;
@@ -1007,7 +1104,7 @@ int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, doubl
     if (q.N < 4 || q.N % 2 || q.N > 4096 || !(q.eps > 0 && q.eps <= 1) || !q.c || !q.r ||
         !F[s] || !U[s])
       return BLP_E_INVAL;
-    const blp_mesh_opts in{q.sigma, q.clow, q.clow, q.kind, q.layer_cells};
+    const blp_mesh_opts in{q.sigma, q.clow, q.clow, q.kind, q.layer_cells, BLP_LAYER_EXPONENTIAL};
     BLP_TRY(mesh_options(q.N, &in, &mo[s]));
     for (int k = 0; k <= q.N; ++k)
       if (!(q.c[k] > 0) || !(q.r[k] >= 0)) return BLP_E_INVAL;

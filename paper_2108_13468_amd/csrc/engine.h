@@ -58,6 +58,7 @@ struct SysWork {
   T *bI = nullptr, *zI = nullptr;                    // interior region, skewed
   T *bL[2] = {nullptr, nullptr}, *zL[2] = {nullptr, nullptr};  // edge lines [Y, X]
   std::vector<T *> z, b, t;                          // corner levels, skewed
+  std::vector<T *> pz, pb, pt;                       // parabolic-case corner levels, natural
 };
 
 struct System {
@@ -109,6 +110,16 @@ int alloc_work(System &s, hipStream_t st, SysWork<T> &w, const FineDev<T> &f,
     BLP_TRY(s.mem.get(&w.z[l], L[l].nslot, st, true));
     BLP_TRY(s.mem.get(&w.b[l], L[l].nslot, st, true));
     BLP_TRY(s.mem.get(&w.t[l], L[l].nslot, st, true));
+  }
+  const std::vector<ParLevelDev<T>> &PL = par_levels<T>(p);
+  w.pz.assign(PL.size(), nullptr);
+  w.pb.assign(PL.size(), nullptr);
+  w.pt.assign(PL.size(), nullptr);
+  for (size_t l = 0; l < PL.size(); ++l) {
+    const size_t n = (size_t)PL[l].nx * h;
+    BLP_TRY(s.mem.get(&w.pz[l], n, st, true));
+    BLP_TRY(s.mem.get(&w.pb[l], n, st, true));
+    BLP_TRY(s.mem.get(&w.pt[l], n, st, true));
   }
   return BLP_OK;
 }
@@ -172,6 +183,10 @@ struct PrecPlan {
   LineIO<T> *ioL = nullptr;
   LineArgs<T> *lnA = nullptr;
   CornerIO<T> *cr = nullptr;
+  // parabolic-case corner (x-semicoarsening): level columns and records
+  bool par = false;
+  std::vector<int> pn;
+  std::vector<ParArgs<T> *> pa;
   std::vector<MgArgs<T> *> mg;
   std::vector<SweepArgs<T> *> swb, swt;  // per level: sweep from b, from t
   // kernel variants (autotuner; 0 = default)
@@ -212,6 +227,16 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   P.scaled = scaled;
   const std::vector<LevelDev<T>> &L0 = levels<T>(p0);
   const int nl = (int)L0.size();
+  P.par = p0->ylayer == BLP_LAYER_PARABOLIC;
+  // the parabolic corner cycle has no transposed form
+  if (P.par && TR) return BLP_E_INVAL;
+  for (System *y : sys)
+    if ((y->p->ylayer == BLP_LAYER_PARABOLIC) != P.par) return BLP_E_INVAL;
+  const std::vector<ParLevelDev<T>> &PL0 = par_levels<T>(p0);
+  const int npl = (int)PL0.size();
+  P.pn.resize(npl);
+  for (int l = 0; l < npl; ++l) P.pn[l] = PL0[l].nx;
+  std::vector<std::vector<ParArgs<T>>> pa(npl, std::vector<ParArgs<T>>(S));
   P.ln.resize(nl);
   P.lslot.resize(nl);
   for (int l = 0; l < nl; ++l) {
@@ -272,8 +297,27 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
     }
     la.gate = y.gate;
     lnA[s] = la;
-    cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.b[0], w.z[0], y.ctrl,
-                        p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate};
+    if (P.par) {
+      cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.pb[0], w.pz[0], y.ctrl,
+                          p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate, 1};
+      const std::vector<ParLevelDev<T>> &PL = par_levels<T>(p);
+      for (int l = 0; l < npl; ++l) {
+        const bool last = l + 1 == npl;
+        pa[l][s] = ParArgs<T>{PL[l].nx,  h,
+                              g,         PL[0].sx,
+                              PL[0].sy,  PL[l].a,
+                              PL[l].ic,  PL[l].wl,
+                              PL[l].wr,  w.pz[l],
+                              w.pb[l],   w.pt[l],
+                              last ? 0 : PL[l + 1].nx,
+                              last ? nullptr : w.pz[l + 1],
+                              last ? nullptr : w.pb[l + 1],
+                              y.ctrl,    y.mg_partials};
+      }
+    } else {
+      cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.b[0], w.z[0], y.ctrl,
+                          p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate, 0};
+    }
     for (int l = 0; l < nl; ++l) {
       const MgLevel<T> lv = L[l].view(TR, w.z[l], w.b[l], w.t[l]);
       const MgLevel<T> cv =
@@ -316,6 +360,8 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   BLP_TRY(P.mem.put(&P.ioL, ioL.data(), S, st));
   BLP_TRY(P.mem.put(&P.lnA, lnA.data(), S, st));
   BLP_TRY(P.mem.put(&P.cr, cr.data(), S, st));
+  P.pa.assign(npl, nullptr);
+  for (int l = 0; l < npl; ++l) BLP_TRY(P.mem.put(&P.pa[l], pa[l].data(), S, st));
   P.mg.assign(nl, nullptr);
   P.swb.assign(nl, nullptr);
   P.swt.assign(nl, nullptr);
@@ -520,6 +566,70 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
 // blocks of the corner residual-norm reduction (one partial each)
 constexpr int kMgNormBlocks = 256;
 
+// Parabolic case: one downstream Gauss-Seidel sweep of level l for every
+// system (one wave each; C columns per lane, the smallest chunk that covers
+// the level).
+template <typename T, bool L0>
+void par_gs_launch(const Ctx &c, int S, int nx, const ParArgs<T> *A, int zero_init) {
+  const int C = nx <= 64 ? 1 : nx <= 128 ? 2 : nx <= 256 ? 4 : nx <= 512 ? 8 : 16;
+  switch (C) {
+    case 1: k_par_gs<T, 1, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
+    case 2: k_par_gs<T, 2, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
+    case 4: k_par_gs<T, 4, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
+    case 8: k_par_gs<T, 8, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
+    default: k_par_gs<T, 16, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
+  }
+}
+
+template <typename T, bool TR>
+void par_gs_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, int zero_init) {
+  const int nx = P.pn[l];
+  // words per node: level 0 b, z in and out (+ nodal r); coarse levels also
+  // the nine couplings and 1/centre
+  KScope ks(c, KC_SWEEP, (double)P.S * nx * P.h * (l ? 12 : 3) * sizeof(T));
+  if (l == 0) par_gs_launch<T, true>(c, P.S, nx, P.pa[l], zero_init);
+  else par_gs_launch<T, false>(c, P.S, nx, P.pa[l], zero_init);
+}
+
+// One V(1,1) cycle on level l of the semicoarsening hierarchy (Sec. 3.2);
+// the coarsest level gets four sweeps.  zero_init: the level iterate is
+// zero on entry.
+template <typename T, bool TR>
+void par_vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
+  const int S = P.S, nx = P.pn[l], h = P.h, nl = (int)P.pn.size();
+  if (l == nl - 1) {
+    for (int k = 0; k < 4; ++k) par_gs_run<T, TR>(c, P, l, zero_init && k == 0);
+    return;
+  }
+  const int nxc = P.pn[l + 1];
+  const double nn = (double)S * nx * h, cc = (double)S * nxc * h;
+  par_gs_run<T, TR>(c, P, l, zero_init);
+  {
+    KScope ks(c, KC_MG, nn * (l ? 12 : 3) * sizeof(T));
+    if (l == 0) k_par_resid<T, true><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+    else k_par_resid<T, false><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+  }
+  {
+    KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
+    k_par_restrict<T><<<dim3((nxc + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+  }
+  par_vcycle_run<T, TR>(c, P, l + 1, true);
+  {
+    KScope ks(c, KC_MG, (4.0 * nn + cc) * sizeof(T));
+    k_par_prolong<T><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+  }
+  par_gs_run<T, TR>(c, P, l, 0);
+}
+
+template <typename T, bool TR>
+void par_norm_run(const Ctx &c, const PrecPlan<T, TR> &P, int mode) {
+  const size_t n = (size_t)P.h * P.h;
+  const int nblk = std::min(kMgNormBlocks, (int)blocks1d(n));
+  KScope ks(c, KC_MG, (double)P.S * n * 2 * sizeof(T));
+  if (mode == 1) k_par_norm<T, 1><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.pa[0]);
+  else k_par_norm<T, 0><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.pa[0]);
+}
+
 template <typename T, bool TR>
 void mg_norm_run(const Ctx &c, const PrecPlan<T, TR> &P, int mode) {
   const int nblk = std::min(kMgNormBlocks, (int)blocks1d(P.lslot[0]));
@@ -539,6 +649,21 @@ void corner_begin(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const b
     KScope ks(c, KC_LAYOUT, 0.0);
     k_corner_rhs<T, TR><<<dim3((h + 255) / 256, h, P.S), 256, 0, c.stream>>>(P.cr, jp);
   }
+  if (P.par) {
+    if (o.mg_fixed > 0) {
+      for (int k = 0; k < o.mg_fixed; ++k) {
+        par_vcycle_run<T, TR>(c, P, 0, k == 0);
+        k_par_count<T><<<P.S, 64, 0, c.stream>>>(P.pa[0]);
+      }
+      return;
+    }
+    par_norm_run<T, TR>(c, P, 0);
+    for (int k = 0; k < std::min(first, o.mg_maxcyc); ++k) {
+      par_vcycle_run<T, TR>(c, P, 0, k == 0);
+      par_norm_run<T, TR>(c, P, 1);
+    }
+    return;
+  }
   if (o.mg_fixed > 0) {
     for (int k = 0; k < o.mg_fixed; ++k) {
       vcycle_run<T, TR>(c, P, 0, k == 0);
@@ -549,6 +674,19 @@ void corner_begin(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const b
   mg_norm_run<T, TR>(c, P, 0);
   for (int k = 0; k < std::min(first, o.mg_maxcyc); ++k) {
     vcycle_run<T, TR>(c, P, 0, k == 0);
+    mg_norm_run<T, TR>(c, P, 1);
+  }
+}
+
+// One more adaptive cycle and its residual norm (after the first cycles),
+// on the corner hierarchy of the plan's kind.
+template <typename T, bool TR>
+void corner_cycle(const Ctx &c, const PrecPlan<T, TR> &P) {
+  if (P.par) {
+    par_vcycle_run<T, TR>(c, P, 0, false);
+    par_norm_run<T, TR>(c, P, 1);
+  } else {
+    vcycle_run<T, TR>(c, P, 0, false);
     mg_norm_run<T, TR>(c, P, 1);
   }
 }
@@ -565,8 +703,7 @@ int corner_finish(const Ctx &c, const PrecPlan<T, TR> &P, const blp_prec_opts &o
     bool open = false;
     for (int s = 0; s < S; ++s) open = open || !ctrl_h[s].gate;
     if (!open) break;
-    vcycle_run<T, TR>(c, P, 0, false);
-    mg_norm_run<T, TR>(c, P, 1);
+    corner_cycle<T, TR>(c, P);
   }
   return BLP_OK;
 }
@@ -1126,8 +1263,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
             if (!open) break;
             for (int k = 0; k < NC; ++k) {
               if (!live(k, incyc)) continue;
-              vcycle_run<TV, TR>(cx[k], P[k]->prec, 0, false);
-              mg_norm_run<TV, TR>(cx[k], P[k]->prec, 1);
+              corner_cycle<TV, TR>(cx[k], P[k]->prec);
             }
           }
         }

@@ -1937,7 +1937,8 @@ __global__ void k_mg_count(const MgArgs<T> *A) {
 // Corner block: right-hand side and copy-back (blockIdx.z = system).
 // Forward: b_C = b_C - A_CX z_X - A_CY z_Y, the couplings sitting on the
 // transition column (E_h to (h+1, j) in Y) and row (N_h to (i, h+1) in X).
-// b_0 is written in the skewed layout of level 0.  The right-hand-side kernel
+// b_0 is written in the skewed layout of level 0 (natural layout for the
+// parabolic-case hierarchy).  The right-hand-side kernel
 // also resets the corner control block; for a gated system it closes the
 // corner gate, which switches the whole cycle off.
 // ---------------------------------------------------------------------------
@@ -1956,6 +1957,7 @@ struct CornerIO {
   int maxcyc;
   double rtol;
   const int *gate;
+  int natural;  // level-0 vectors in the natural layout (parabolic case)
 };
 template <typename T, bool TR>
 __global__ void k_corner_rhs(const CornerIO<T> *A, const int *jp) {
@@ -1983,7 +1985,7 @@ __global__ void k_corner_rhs(const CornerIO<T> *A, const int *jp) {
     if (i == h) val -= a.g.E[h] * z[vidx(h + 1, j, n1)];
     if (j == h) val -= a.g.N[h] * z[vidx(i, h + 1, n1)];
   }
-  a.b0[level_skew<T, TR>(h).at(i, j)] = val;
+  a.b0[a.natural ? vidx(i, j, h) : level_skew<T, TR>(h).at(i, j)] = val;
 }
 
 template <typename T, bool TR>
@@ -1994,7 +1996,8 @@ __global__ void k_corner_copy(const CornerIO<T> *A, const int *jp) {
   const int j = blockIdx.y + 1;
   const int h = a.h;
   if (i > h) return;
-  (a.z + step_of(jp) * a.ldz)[vidx(i, j, a.n1)] = a.z0[level_skew<T, TR>(h).at(i, j)];
+  (a.z + step_of(jp) * a.ldz)[vidx(i, j, a.n1)] =
+      a.z0[a.natural ? vidx(i, j, h) : level_skew<T, TR>(h).at(i, j)];
 }
 
 // Sample a nodal field at every f-th node: rc(k, m) = rf(f k, f m), natural

@@ -52,6 +52,24 @@ def test_general_mesh_matches_oracle(kind, N, eps, nl):
     np.testing.assert_allclose(y, y_o, rtol=4e-16, atol=0)
 
 
+@pytest.mark.parametrize("kind", ["shishkin", "bakhvalov-shishkin"])
+@pytest.mark.parametrize("N,eps", [(128, 1e-5), (2048, 1e-8), (256, 1e-2)])
+def test_parabolic_mesh_matches_oracle(kind, N, eps):
+    """y_layer 'parabolic' (eq. tau parabolic): the y axis takes the scale
+    sqrt(eps), the x axis is unchanged."""
+    (tx, ty), x, y = blp.mesh(N, eps, 2.5, (0.99, 0.3), kind, None, "parabolic")
+    tx_o, x_o, _ = O.mesh_axis(N, eps, 2.5, 0.99, kind, None)
+    ty_o, y_o, _ = O.mesh_axis(N, eps, 2.5, 0.3, kind, None, layer="parabolic")
+    assert (tx, ty) == (tx_o, ty_o)
+    np.testing.assert_allclose(x, x_o, rtol=4e-16, atol=0)
+    np.testing.assert_allclose(y, y_o, rtol=4e-16, atol=0)
+    o = blp._mesh_opts(2.5, (1.0, 1.0), kind, None, "parabolic")
+    o.y_layer = 2  # neither layer type
+    with pytest.raises(blp.BlpError):
+        blp._check(blp.lib().blp_mesh(N, eps, C.byref(o), np.zeros(N + 1).ctypes.data_as(blp._dp),
+                                      np.zeros(N + 1).ctypes.data_as(blp._dp), None), "blp_mesh")
+
+
 @pytest.mark.parametrize("kind,nl", [("shishkin", 64), ("shishkin", 1), ("shishkin", 63),
                                      ("bakhvalov-shishkin", 0 - 2), ("nonsense", None)])
 def test_mesh_rejects_bad_layer_options(kind, nl):

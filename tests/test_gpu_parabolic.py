@@ -1,0 +1,240 @@
+"""GPU parity of the case with one parabolic and one exponential layer
+(c2 = 0; Sec. 3, eq. tau parabolic; Sec. 3.2, corner multigrid with
+x-semicoarsening and Galerkin coarse operators; Sec. 3.3, Tables 3 and 4),
+through the C ABI against the CPU oracle.
+
+Tolerances, as for two exponential layers:
+  * preconditioner applies with a fixed cycle count (a fixed linear map):
+    <= 1e-11 relative in FP64; the FP32 apply within 2e-3 of the FP64 map;
+  * adaptive corner rule: the same cycle counts, <= 1e-11 relative;
+  * FP64 solves: equal iteration counts, residual histories within 1e-6
+    relative, error against a tight oracle solve <= 1e-8 relative;
+  * mixed solves: <= 1e-6 relative;
+  * the paper's tables: every count of Table 4, every error of Table 3 to
+    its printed digits, the corner cycles per solve, at N = 128 to 2048."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_13468_amd import inputs
+from tests.mms import parabolic_mms
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(v):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.as_tensor(np.ascontiguousarray(v, dtype=np.float64), device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def read_golden(name):
+    out = {}
+    for line in open(os.path.join(GOLD, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            e, n, v = line.split()
+            out[(float(e), int(n))] = float(v)
+    return out
+
+
+def instance(N, eps, seed, layer_cells=None):
+    """c1 = 1 + a x (a ~ U(0,1)), c2 = 0, r ~ U(0.5, 2), 3x3 sine series."""
+    rng = np.random.default_rng(seed)
+    akl = rng.uniform(-1.0, 1.0, size=(3, 3))
+    r = rng.uniform(0.5, 2.0)
+    a = rng.uniform(0.0, 1.0)
+    return inputs.Instance(N=N, eps=eps, c1=(1.0, a, 0.0), c2=(0.0, 0.0, 0.0), r_const=r,
+                           a=akl, sigma=2.5, layer_cells=layer_cells, y_layer="parabolic")
+
+
+def pair(inst, mg_fixed=0, r_nodal=None):
+    from paper_2108_13468_amd import blp
+    gp = blp.from_instance(inst, nodal_r=r_nodal)
+    gp.precondition(mg_fixed=mg_fixed)
+    op = O.Problem(inst.N, inst.eps, c1=inst.c1_at, c2=inst.c2_at,
+                   r=inst.r_const if r_nodal is None else r_nodal, sigma=inst.sigma,
+                   clow_x=inst.clow[0], clow_y=inst.clow[1], layer_cells=inst.layer_cells,
+                   y_layer="parabolic")
+    x, y = gp.nodes()
+    np.testing.assert_allclose(x, op.x, rtol=4e-16, atol=0)
+    np.testing.assert_allclose(y, op.y, rtol=4e-16, atol=0)
+    return gp, op
+
+
+# h = N/2 columns per corner level 0: one to sixteen per lane of the sweep
+# wave (64 to 2048), odd h (a single level: the four-sweep coarsest solve on
+# the corner block itself), and h = 96 (levels 96, 48, 24, 12, 6, 3).
+PREC_CASES = [(64, 1e-4, None), (130, 1e-6, None), (200, 1e-5, 96), (256, 1e-8, None),
+              (600, 1e-6, None), (1024, 1e-7, None), (2048, 1e-6, None)]
+
+
+@pytest.mark.parametrize("N,eps,nl", PREC_CASES)
+def test_preconditioner_parity_fixed_cycles(N, eps, nl):
+    say("parabolic M^-1, 2 cycles: N=%d eps=%g layer cells %s" % (N, eps, nl))
+    inst = instance(N, eps, seed=N, layer_cells=nl)
+    gp, op = pair(inst, mg_fixed=2)
+    b = np.random.default_rng(N).standard_normal(op.n)
+    ref = op.M_inv(b, mg_fixed=2)
+    z = host(gp.apply("MINV", dev(b)))
+    err = np.abs(z - ref).max() / np.abs(ref).max()
+    say("  FP64 rel err %.3e" % err)
+    assert err <= 1e-11
+    z32 = host(gp.apply("MINV32", dev(b)))
+    err32 = np.abs(z32 - ref).max() / np.abs(ref).max()
+    say("  FP32 rel err %.3e" % err32)
+    assert err32 <= 2e-3
+
+
+@pytest.mark.parametrize("N,eps", [(64, 1e-2), (256, 1e-5), (512, 1e-8)])
+def test_preconditioner_adaptive_cycles_match(N, eps):
+    say("parabolic M^-1, adaptive rule: N=%d eps=%g" % (N, eps))
+    inst = instance(N, eps, seed=N + 1)
+    gp, op = pair(inst)
+    b = np.random.default_rng(N + 1).standard_normal(op.n)
+    ref = op.M_inv(b, mg_rtol=1e-2)
+    z = host(gp.apply("MINV", dev(b)))
+    say("  cycles GPU %d oracle %d" % (gp.last_cycles, op.last_prec_stats.mg_cycles_max))
+    assert gp.last_cycles == op.last_prec_stats.mg_cycles_max
+    assert np.abs(z - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_nodal_reaction_and_many_cycles_reach_the_exact_corner():
+    """A nodal r(x, y) enters the level-0 couplings and every Galerkin
+    level; 40 cycles give the idealised M-hat (exact corner solve)."""
+    say("parabolic nodal r, 40 cycles")
+    N, eps = 96, 1e-5
+    inst = instance(N, eps, seed=11)
+    r = np.random.default_rng(11).uniform(0.5, 2.0, size=(N - 1) ** 2)
+    gp, op = pair(inst, mg_fixed=40, r_nodal=r)
+    b = np.random.default_rng(12).standard_normal(op.n)
+    z = host(gp.apply("MINV", dev(b)))
+    ref = op.M_inv(b, corner="exact")
+    assert np.abs(z - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_transposed_forms_are_rejected():
+    from paper_2108_13468_amd import blp
+    inst = instance(64, 1e-4, seed=3)
+    gp, op = pair(inst)
+    b = dev(np.ones(op.n))
+    with pytest.raises(blp.BlpError) as e:
+        gp.apply("MINVT", b)
+    assert e.value.code == -1
+    with pytest.raises(blp.BlpError) as e:
+        gp.solve_adjoint(b)
+    assert e.value.code == -1
+    # the forward path still works afterwards
+    U, info = gp.solve(b, tol=1e-8)
+    assert info[0]["converged"]
+
+
+@pytest.mark.parametrize("N,eps,nl", [(130, 1e-4, None), (256, 1e-6, None), (200, 1e-8, 96)])
+def test_solve_parity(N, eps, nl):
+    say("parabolic solve parity N=%d eps=%g" % (N, eps))
+    inst = instance(N, eps, seed=N + 5, layer_cells=nl)
+    gp, op = pair(inst)
+    F = O.sine_series(N, op.x, op.y, inst.a)
+    u_o, st, info_o, hist_o = op.fgmres(F, tol=1e-8, scaled=True, mg_rtol=1e-2)
+    U, info, hist = gp.solve(dev(F), tol=1e-8, scaled=True, hist=True)
+    info = info[0]
+    say("  iterations GPU %d oracle %d, cycles %d-%d" % (
+        info["iterations"], info_o.iterations, info["mg_cycles_min"], info["mg_cycles_max"]))
+    assert info["converged"] and info["iterations"] == info_o.iterations
+    assert info["mg_cycles_max"] == info_o.mg_cycles_max
+    k = info["iterations"]
+    np.testing.assert_allclose(hist[0, :k + 1], hist_o[:k + 1], rtol=1e-6)
+    u_t, _, _, _ = op.fgmres(F, tol=1e-11, scaled=True, mg_rtol=1e-2)
+    err = np.abs(host(U) - u_t).max() / np.abs(u_t).max()
+    Um, infom = gp.solve(dev(F), tol=1e-8, scaled=True, precision="mixed")
+    errm = np.abs(host(Um) - u_t).max() / np.abs(u_t).max()
+    say("  FP64 error %.2e, mixed error %.2e (%d iterations)" % (
+        err, errm, infom[0]["iterations"]))
+    assert err <= 1e-8
+    assert infom[0]["converged"] and errm <= 1e-6
+
+
+@pytest.mark.parametrize("eps", [1e-5, 1e-6, 1e-7, 1e-8])
+def test_tables_3_and_4_on_the_device(eps):
+    """Sec. 3.3 in FP64 on the GPU (sigma = 5/2, Clow = 0.99, ||R||_2 <=
+    10 ln N / N with the estimate test, corner reduction 1e2): every
+    iteration count of Table 4, every error of Table 3 to the printed
+    digits, three corner cycles (two or three at N = 2048)."""
+    from paper_2108_13468_amd import blp
+    errs = read_golden("table3_parabolic_errors.txt")
+    its = read_golden("table4_parabolic_iterations.txt")
+    for N in (128, 256, 512, 1024, 2048):
+        inst = inputs.mms_parabolic(N, eps)
+        gp = blp.from_instance(inst).precondition()
+        x, y = gp.nodes()
+        u, f = parabolic_mms(eps, x, y)
+        U, info = gp.solve(dev(f), tol=10 * np.log(N) / N, absolute=True, scaled=False,
+                           stop_on_estimate=True)
+        info = info[0]
+        err = np.abs(host(U) - u).max()
+        say("  eps %g N %d: %d iterations (Table 4: %d), error %.4e (Table 3: %.3e), "
+            "cycles %d-%d" % (eps, N, info["iterations"], its[(eps, N)], err, errs[(eps, N)],
+                              info["mg_cycles_min"], info["mg_cycles_max"]))
+        assert info["converged"] and info["iterations"] == int(its[(eps, N)])
+        assert err == pytest.approx(errs[(eps, N)], rel=6e-4)
+        lo = 2 if N == 2048 else 3
+        assert lo <= info["mg_cycles_min"] <= info["mg_cycles_max"] <= 3
+        gp.close()
+
+
+def test_full_size_mixed_solve():
+    """N = 2048, eps = 1e-6, relative residual 1e-8 (Jacobi-scaled system)
+    in the mixed mode: the residual of the result, measured with the
+    oracle's operator, meets the target, and the result agrees with the FP64
+    solve to the mixed bound."""
+    from paper_2108_13468_amd import blp
+    N, eps = 2048, 1e-6
+    inst = instance(N, eps, seed=21)
+    gp = blp.from_instance(inst).precondition()
+    op = O.Problem(N, eps, c1=inst.c1_at, c2=inst.c2_at, r=inst.r_const, sigma=inst.sigma,
+                   y_layer="parabolic")
+    F = O.sine_series(N, op.x, op.y, inst.a)
+    Fd = dev(F)
+    Um, im = gp.solve(Fd, tol=1e-8, scaled=True, precision="mixed")
+    U6, i6 = gp.solve(Fd, tol=1e-8, scaled=True)
+    um, u6 = host(Um), host(U6)
+    R = F - op.A(um)
+    # the solver's norm: the Jacobi-scaled residual D^{-1/2} (F - A u)
+    D = np.abs(np.asarray(op.csr().diagonal()))
+    rel = np.linalg.norm(R / np.sqrt(D)) / np.linalg.norm(F / np.sqrt(D))
+    diff = np.abs(um - u6).max() / np.abs(u6).max()
+    say("  mixed: %d iterations, scaled rel res %.2e, vs FP64 %.2e (FP64: %d iterations)" % (
+        im[0]["iterations"], rel, diff, i6[0]["iterations"]))
+    assert im[0]["converged"] and i6[0]["converged"]
+    assert rel <= 1e-8
+    assert diff <= 1e-6
+
+
+def test_batch_mixes_corner_kinds():
+    """A batch holding parabolic and exponential problems of one mesh size
+    solves each with its own corner cycle; results equal the single solves."""
+    from paper_2108_13468_amd import blp
+    N = 256
+    insts = [instance(N, 1e-6, seed=31), inputs.plain(N, 1e-6, seed=32),
+             instance(N, 1e-4, seed=33)]
+    ps = [blp.from_instance(i).precondition() for i in insts]
+    Fs = [p.sine_rhs(i.a) for p, i in zip(ps, insts)]
+    B = blp.Batch(ps)
+    U, info = B.solve(Fs, tol=1e-8)
+    for k, (p, F) in enumerate(zip(ps, Fs)):
+        u1, i1 = p.solve(F, tol=1e-8)
+        assert info[k]["converged"] and info[k]["iterations"] == i1[0]["iterations"]
+        assert np.abs(host(U[k]) - host(u1)).max() <= 1e-12 * np.abs(host(u1)).max()
