@@ -567,18 +567,22 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
 constexpr int kMgNormBlocks = 256;
 
 // Parabolic case: one downstream Gauss-Seidel sweep of level l for every
-// system (one wave each; C columns per lane, the smallest chunk that covers
-// the level).
+// system (one workgroup each): one wave up to 64 columns (the scan spanning
+// only as many lanes as there are columns), then up to four waves (one per
+// SIMD) with one column per thread, then four waves with 2 or 4 columns per
+// thread.
 template <typename T, bool L0>
 void par_gs_launch(const Ctx &c, int S, int nx, const ParArgs<T> *A, int zero_init) {
-  const int C = nx <= 64 ? 1 : nx <= 128 ? 2 : nx <= 256 ? 4 : nx <= 512 ? 8 : 16;
-  switch (C) {
-    case 1: k_par_gs<T, 1, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
-    case 2: k_par_gs<T, 2, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
-    case 4: k_par_gs<T, 4, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
-    case 8: k_par_gs<T, 8, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
-    default: k_par_gs<T, 16, L0><<<S, 64, 0, c.stream>>>(A, zero_init); break;
-  }
+  if (nx <= 2) k_par_gs<T, 1, 1, L0, 2><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 4) k_par_gs<T, 1, 1, L0, 4><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 8) k_par_gs<T, 1, 1, L0, 8><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 16) k_par_gs<T, 1, 1, L0, 16><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 64) k_par_gs<T, 1, 1, L0, 64><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 128) k_par_gs<T, 2, 1, L0, 64><<<S, 128, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 256) k_par_gs<T, 4, 1, L0, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 512) k_par_gs<T, 4, 2, L0, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
+  else if constexpr (L0)  // only level 0 is wider than 512 columns
+    k_par_gs<T, 4, 4, true, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
 }
 
 template <typename T, bool TR>

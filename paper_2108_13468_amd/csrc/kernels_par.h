@@ -26,11 +26,10 @@
 // recurrence z_i = alpha_i - beta_i z_{i+1}: alpha holds the right-hand
 // side less the row above (already new), the row below and the West
 // neighbour (both still old), over the diagonal; beta = a_E / a_C.  One
-// wave sweeps one system: each lane owns C consecutive columns, composes
-// its columns' affine maps, a shuffle scan over the lanes composes the
-// chunks, and each lane re-runs its chunk from the value entering it.
-// Rows are strictly sequential (a row needs the whole row above), so the
-// sweep is latency bound: depth ny x (scan of nx / C lanes).
+// workgroup sweeps one system with a thread per column; the recurrence is
+// an affine scan over the row.  Rows are strictly sequential (a row needs
+// the whole row above), so the sweep is latency bound: depth ny x (one
+// row's scan).
 #pragma once
 #include "common.h"
 
@@ -240,118 +239,264 @@ __global__ void k_par_prolong(const ParArgs<T> *A) {
   gptr(a.z)[q] += s;
 }
 
-// Wave-wide suffix composition of affine maps x -> A x + B (lane L ends
-// with map_L o map_{L+1} o ... o map_63).
-template <typename T>
-BLP_DEV void suffix_compose(T &A, T &B) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const T A2 = __shfl_down(A, d, 64), B2 = __shfl_down(B, d, 64);
-    if (lane + d < 64) {
-      B = A * B2 + B;
-      A = A * A2;
-    }
+// One downstream Gauss-Seidel sweep of a level, one workgroup of W waves
+// (at most one per SIMD) per system; thread t owns the C consecutive
+// columns t C + 1 .. t C + C (nx <= 64 W C).  Per row each thread forms its
+// columns' maps z_i = alpha_i - beta_i z_{i+1} and composes them (right to
+// left), a DPP scan composes the threads' maps within each wave, the
+// waves' aggregates (through LDS) give the value entering each wave from
+// the right, and each thread re-runs its columns from the value entering
+// its chunk.  Neighbour values across chunk edges (the row above, new; this
+// row and the row below, old) come by DPP within one wave, through LDS with
+// several (old rows double-buffered by row parity).  The operands of a row
+// (right-hand side, 1/centre, couplings, the old values below it) are
+// loaded kParAhead rows ahead.  zero_init: the iterate is zero on entry
+// (its old values are not read).  SW: the lanes the scan spans (a one-wave
+// sweep of at most 16 columns needs only the in-row DPP steps).
+constexpr int kParAhead = 4;
+constexpr int kParMaxRows = 1024;  // h: at most 1024 layer cells
+
+template <typename T, bool L0, int C>
+struct ParRowOps {
+  T b[C], ic[C], zs[C];   // right-hand side, 1 / centre, old value one row down
+  T p[L0 ? 1 : 9][L0 ? 1 : C];  // coarse levels: the couplings (plane 4, the
+                                // centre, unused)
+};
+
+// Neighbour value across the wave by one DPP move per 32 bits (CTRL
+// wave_shr:1 0x138 or wave_shl:1 0x130); the lane without a source reads 0.
+template <int CTRL>
+BLP_DEV float par_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+BLP_DEV double par_shift(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Suffix composition of the lanes' affine maps x -> A + M x over the first
+// SW lanes (the lanes at and beyond the level's width hold the constant map
+// 0): at most 16 lanes need only the in-row DPP steps.
+template <typename T, int SW>
+BLP_DEV void par_scan_down(T &A, T &M, int lane) {
+  if constexpr (SW > 16) {
+    scan_affine_down(A, M, lane);
+  } else {
+#define BLP_PCOMBINE(CTRL)                                                   \
+  {                                                                         \
+    const T a_ = dpp_mov<CTRL, 0xF>(T(0), A), m_ = dpp_mov<CTRL, 0xF>(T(1), M); \
+    A = A + M * a_;                                                         \
+    M = M * m_;                                                             \
+  }
+    if constexpr (SW > 1) BLP_PCOMBINE(0x101)
+    if constexpr (SW > 2) BLP_PCOMBINE(0x102)
+    if constexpr (SW > 4) BLP_PCOMBINE(0x104)
+    if constexpr (SW > 8) BLP_PCOMBINE(0x108)
+#undef BLP_PCOMBINE
   }
 }
 
-// One downstream Gauss-Seidel sweep of a level, one wave per system; lane
-// L owns columns L C + 1 .. L C + C.  zero_init: the iterate is zero on
-// entry (its old values are not read).
-template <typename T, int C, bool L0>
-__global__ __launch_bounds__(64) void k_par_gs(const ParArgs<T> *A, int zero_init) {
+template <typename T, int W, int C, bool L0, int SW>
+__global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero_init) {
+  constexpr int NT = 64 * W, NC = NT * C;
+  // W > 1: the north row (new values) and the old values of row j (at
+  // [j & 1]) in LDS, index = column; with the waves' aggregate maps
+  __shared__ T s_new[W > 1 ? NC + 2 : 1];
+  __shared__ T s_old[2][W > 1 ? NC + 2 : 1];
+  __shared__ T s_agA[W], s_agM[W];
+  // level 0: the y tables S_j, N_j of every row, zero at j = 1 (S) and
+  // j = ny (N), where the coupling leaves the corner block
+  __shared__ T s_S[L0 ? kParMaxRows + 1 : 1], s_N[L0 ? kParMaxRows + 1 : 1];
   const ParArgs<T> a = A[blockIdx.x];
-  if (gptr(a.ctrl)->gate) return;
-  const int lane = threadIdx.x, nx = a.nx, ny = a.ny;
-  const int i0 = lane * C + 1;
+  if (gptr(a.ctrl)->gate) return;  // the same for every thread of the block
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nx = a.nx, ny = a.ny, i0 = t * C + 1;
+  bool in[C];
+  unsigned lob[C];  // byte offsets of the thread's columns (clamped into the level)
+#pragma unroll
+  for (int k = 0; k < C; ++k) {
+    in[k] = i0 + k <= nx;
+    lob[k] = (unsigned)((in[k] ? i0 + k : nx) - 1) * (unsigned)sizeof(T);
+  }
   const GridG<T> g = gview(a.g);
-  const BLP_GLOBAL T *b = gptr(a.b);
-  const BLP_GLOBAL T *ic = gptr(a.ic);
+  const BLP_GLOBAL T *B = gptr(a.b);
+  const BLP_GLOBAL T *IC = gptr(a.ic);
   const BLP_GLOBAL T *P = gptr(a.a);
-  BLP_GLOBAL T *z = gptr(a.z);
-  const size_t pl = (size_t)nx * ny;
-  // per-lane x data of level 0 (constant down the columns)
+  BLP_GLOBAL T *Z = gptr(a.z);
+  BLP_GLOBAL T *Tw = gptr(a.t);  // free during a sweep: padding lanes store here
+  const int pl = nx * ny;  // at most 1024 x 1024: 32-bit offsets
+  if (L0) {
+    for (int j = t + 1; j <= ny; j += NT) {
+      s_S[j] = j > 1 ? g.S[j] : T(0);
+      s_N[j] = j < ny ? g.N[j] : T(0);
+    }
+  }
   T xW[C], xE[C];
 #pragma unroll
   for (int k = 0; k < C; ++k) {
-    const int i = i0 + k;
-    xW[k] = T(0);
-    xE[k] = T(0);
-    if (L0 && i <= nx) {
-      xW[k] = pc0(g, nx, i, 1, -1, 0);
-      xE[k] = pc0(g, nx, i, 1, 1, 0);
+    xW[k] = xE[k] = T(0);
+    if (L0 && in[k]) {
+      xW[k] = pc0(g, nx, i0 + k, 1, -1, 0);
+      xE[k] = pc0(g, nx, i0 + k, 1, 1, 0);
     }
   }
-  // rows: north (new), current (old), south (old)
-  T zn[C], zc[C], zs[C];
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    zn[k] = T(0);
-    zc[k] = T(0);
-    const int i = i0 + k;
-    if (!zero_init && i <= nx) zc[k] = z[vidx(i, ny, nx)];
+  if (W > 1) {
+    for (int k = t; k < NC + 2; k += NT) {
+      s_new[k] = T(0);
+      s_old[0][k] = T(0);
+      s_old[1][k] = T(0);
+    }
   }
-  for (int j = ny; j >= 1; --j) {
+  // Row bases are uniform (scalar registers), the column offsets the
+  // thread's own constants.  Operands are loaded unconditionally (row
+  // indices clamped to the level; what a clamped load brings is replaced at
+  // its use), so that no branch or copy waits for loads in flight.
+  auto at = [&](const BLP_GLOBAL T *row, int k) {
+    return *(const BLP_GLOBAL T *)((const BLP_GLOBAL char *)row + lob[k]);
+  };
+  auto load = [&](int j, ParRowOps<T, L0, C> &o) {
+    const int jj = j >= 1 ? j : 1, js = jj > 1 ? jj - 1 : 1;
+    const int rb = (jj - 1) * nx;
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      const int i = i0 + k;
-      zs[k] = T(0);
-      if (!zero_init && j > 1 && i <= nx) zs[k] = z[vidx(i, j - 1, nx)];
+      o.b[k] = at(B + rb, k);
+      o.ic[k] = at(IC + rb, k);
+      o.zs[k] = at(Z + (js - 1) * nx, k);
     }
-    // neighbours' edge values: left (column i0 - 1) and right (i0 + C)
-    const T znl = __shfl_up(zn[C - 1], 1, 64), znr = __shfl_down(zn[0], 1, 64);
-    const T zcl = __shfl_up(zc[C - 1], 1, 64);
-    const T zsl = __shfl_up(zs[C - 1], 1, 64), zsr = __shfl_down(zs[0], 1, 64);
+    if (!L0) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+          if (q != 4) o.p[q][k] = at(P + q * pl + rb, k);
+    }
+  };
+  T zn[C], zc[C];  // the row above (new) and this row (old), own columns
+#pragma unroll
+  for (int k = 0; k < C; ++k) zn[k] = T(0);
+  // One row: operands in cur (loaded kParAhead rows earlier); those of row
+  // j - kParAhead are loaded into nxt, the buffer row j + 1 has released.
+  auto row = [&](int j, const ParRowOps<T, L0, C> &cur, ParRowOps<T, L0, C> &nxt) {
+    T zs[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) zs[k] = (zero_init || j == 1 || !in[k]) ? T(0) : cur.zs[k];
+    T nl, nr, sl, sr, cl;  // edge neighbours: columns i0 - 1 (l) and i0 + C (r)
+    if (W > 1) {
+#pragma unroll
+      for (int k = 0; k < C; ++k) s_old[(j - 1) & 1][i0 + k] = zs[k];  // 0 past the level
+      load(j - kParAhead, nxt);
+      // the rows written above and the north row are visible; the loads of
+      // later rows and the stores of earlier rows stay in flight
+      lds_barrier();
+      nl = s_new[i0 - 1];
+      nr = s_new[i0 + C];
+      sl = s_old[(j - 1) & 1][i0 - 1];
+      sr = s_old[(j - 1) & 1][i0 + C];
+      cl = s_old[j & 1][i0 - 1];
+    } else {
+      load(j - kParAhead, nxt);
+      nl = par_shift<0x138>(zn[C - 1]);  // lane l-1 (lane 0: the boundary, 0)
+      nr = par_shift<0x130>(zn[0]);      // lane l+1 (lane 63: beyond the level)
+      sl = par_shift<0x138>(zs[C - 1]);
+      sr = par_shift<0x130>(zs[0]);
+      cl = par_shift<0x138>(zc[C - 1]);
+    }
     T al[C], be[C];
+    T aS = T(0), aN = T(0);
+    if (L0) {
+      aS = s_S[j];
+      aN = s_N[j];
+    }
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      const int i = i0 + k;
-      const bool in = i <= nx;
-      const int ii = in ? i : 1;
-      const size_t q = vidx(ii, j, nx);
-      const T nW = k ? zn[k - 1] : (lane ? znl : T(0));
-      const T nE = k + 1 < C ? zn[k + 1] : (lane < 63 ? znr : T(0));
-      const T sW = k ? zs[k - 1] : (lane ? zsl : T(0));
-      const T sE = k + 1 < C ? zs[k + 1] : (lane < 63 ? zsr : T(0));
-      const T cW = k ? zc[k - 1] : (lane ? zcl : T(0));
-      T acc = b[q], aE;
+      const T nW = k ? zn[k - 1] : nl, nE = k + 1 < C ? zn[k + 1] : nr;
+      const T sW = k ? zs[k - 1] : sl, sE = k + 1 < C ? zs[k + 1] : sr;
+      const T cW = k ? zc[k - 1] : cl;
+      T acc = cur.b[k], aE;
       if (L0) {
-        const T aS = j > 1 ? g.S[j] : T(0), aN = j < ny ? g.N[j] : T(0);
         acc -= aS * zs[k] + aN * zn[k] + xW[k] * cW;
         aE = xE[k];
       } else {
-        acc -= P[0 * pl + q] * sW + P[1 * pl + q] * zs[k] + P[2 * pl + q] * sE;
-        acc -= P[3 * pl + q] * cW;
-        acc -= P[6 * pl + q] * nW + P[7 * pl + q] * zn[k] + P[8 * pl + q] * nE;
-        aE = P[5 * pl + q];
+        acc -= cur.p[0][k] * sW + cur.p[1][k] * zs[k] + cur.p[2][k] * sE;
+        acc -= cur.p[3][k] * cW;
+        acc -= cur.p[6][k] * nW + cur.p[7][k] * zn[k] + cur.p[8][k] * nE;
+        aE = cur.p[5][k];
       }
-      const T d = ic[q];
-      al[k] = in ? acc * d : T(0);
-      be[k] = in ? aE * d : T(0);
+      al[k] = in[k] ? acc * cur.ic[k] : T(0);
+      be[k] = in[k] ? aE * cur.ic[k] : T(0);
     }
-    // compose the chunk right to left: z_{i0} = Ac z_in + Bc
-    T Ac = T(1), Bc = T(0);
+    // the chunk's map x -> Am + Mm x from the value x entering at i0 + C
+    T Am = T(0), Mm = T(1);
 #pragma unroll
     for (int k = C - 1; k >= 0; --k) {
-      Bc = al[k] - be[k] * Bc;
-      Ac = -be[k] * Ac;
+      Am = al[k] - be[k] * Am;
+      Mm = -be[k] * Mm;
     }
-    suffix_compose(Ac, Bc);
-    // value entering the chunk from the right: z at column i0 + C
-    T zr = __shfl_down(Bc, 1, 64);
-    if (lane == 63) zr = T(0);
+    par_scan_down<T, SW>(Am, Mm, lane);
+    if (W > 1) {
+      if (lane == 0) {
+        s_agA[w] = Am;
+        s_agM[w] = Mm;
+      }
+      lds_barrier();
+    }
+    // value entering this wave: the waves to its right applied to zero
+    T zin = T(0);
+#pragma unroll
+    for (int v = W - 1; v > 0; --v)
+      if (v > w) zin = s_agA[v] + s_agM[v] * zin;
+    // value entering this thread's chunk: the next lane's composed map
+    // applied to zin (the wave's last lane: zin itself)
+    T ar = par_shift<0x130>(Am), mr = par_shift<0x130>(Mm);
+    if (lane == 63) {
+      ar = T(0);
+      mr = T(1);
+    }
+    T zr = ar + mr * zin;
+    T z[C];
 #pragma unroll
     for (int k = C - 1; k >= 0; --k) {
       zr = al[k] - be[k] * zr;
-      zn[k] = zr;
+      z[k] = zr;
     }
+    // stores are unconditional (a padding lane writes to the free vector t),
+    // so that every row issues the same memory operations
+    BLP_GLOBAL char *zrow = (BLP_GLOBAL char *)(Z + (j - 1) * nx);
+    BLP_GLOBAL char *trow = (BLP_GLOBAL char *)(Tw + (j - 1) * nx);
 #pragma unroll
     for (int k = 0; k < C; ++k) {
-      const int i = i0 + k;
-      if (i <= nx) z[vidx(i, j, nx)] = zn[k];
+      *(BLP_GLOBAL T *)((in[k] ? zrow : trow) + lob[k]) = z[k];
+      // every read of s_new for this row came before the barrier above
+      if (W > 1) s_new[i0 + k] = in[k] ? z[k] : T(0);
+      zn[k] = in[k] ? z[k] : T(0);
       zc[k] = zs[k];
     }
+  };
+  // operand buffers of rows ny .. ny - kParAhead + 1
+  ParRowOps<T, L0, C> r[kParAhead + 1];
+#pragma unroll
+  for (int u = 0; u < kParAhead; ++u) load(ny - u, r[u]);
+#pragma unroll
+  for (int k = 0; k < C; ++k)
+    zc[k] = (zero_init || !in[k]) ? T(0) : at(Z + (ny - 1) * nx, k);
+  __syncthreads();  // LDS rows zeroed, y tables in place
+  if (W > 1) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) s_old[ny & 1][i0 + k] = zc[k];
   }
+  // the buffers in turn (indices fixed at compile time: no register copies
+  // between rows); whole groups of kParAhead + 1 rows, then the rest
+  int j = ny;
+  for (; j - kParAhead >= 1; j -= kParAhead + 1) {
+#pragma unroll
+    for (int u = 0; u <= kParAhead; ++u)
+      row(j - u, r[u], r[(u + kParAhead) % (kParAhead + 1)]);
+  }
+#pragma unroll
+  for (int u = 0; u < kParAhead; ++u)
+    if (j - u >= 1) row(j - u, r[u], r[(u + kParAhead) % (kParAhead + 1)]);
 }
 
 // Stopping rule of the corner iteration: mode 0 ||S b||^2 before the first
