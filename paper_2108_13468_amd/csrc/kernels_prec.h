@@ -876,11 +876,13 @@ __global__ __launch_bounds__(64 * W) void k_lines(const LineArgs<T> *A) {
   // this thread's nodes; threads past the line read node 0 and are masked
   const bool act = tid * EP < hp;
   const size_t toff = act ? (size_t)tid * EP : 0;
-  const BLP_GLOBAL T *__restrict__ bp = gptr(a.b[r] + toff);
-  const BLP_GLOBAL T *__restrict__ dp = gptr(a.fd[r] + toff);
-  const BLP_GLOBAL T *__restrict__ mp = gptr(a.fm[r] + toff);
-  const BLP_GLOBAL T *__restrict__ wp = gptr(a.fw[r] + toff);
-  BLP_GLOBAL T *__restrict__ zp = gptr(a.z[r] + toff);
+  // region pointers picked by selects (an index into the record's arrays by
+  // the runtime region would place the record in private memory)
+  const BLP_GLOBAL T *__restrict__ bp = gptr((r ? a.b[1] : a.b[0]) + toff);
+  const BLP_GLOBAL T *__restrict__ dp = gptr((r ? a.fd[1] : a.fd[0]) + toff);
+  const BLP_GLOBAL T *__restrict__ mp = gptr((r ? a.fm[1] : a.fm[0]) + toff);
+  const BLP_GLOBAL T *__restrict__ wp = gptr((r ? a.fw[1] : a.fw[0]) + toff);
+  BLP_GLOBAL T *__restrict__ zp = gptr((r ? a.z[1] : a.z[0]) + toff);
   const BLP_GLOBAL T *cc = gptr(r == 0 ? g.E : g.N);  // previous-line coupling table
 
   auto load = [&](int q, LineOps<T, EP> &B) {
