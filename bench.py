@@ -43,7 +43,7 @@ KERNEL_NAMES = {"sweep": "k_sweep<float, false, 16, *, *> (all sweeps: interior 
 # FETCH_SIZE then WRITE_SIZE, scaled by a plain copy of known size), valid
 # while the sweep source is the one it was measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_traffic.txt")
-SWEEP_SOURCE = os.path.join(ROOT, "paper_2108_13468_amd", "csrc", "kernels_prec.h")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_2108_13468_amd", "csrc", "kernels_sweep.h")
 # worker pool of the CPU baselines: the host's cores available to this
 # process, at most 16 (one GPU's share of a shared host)
 POOL_MAX = 16

@@ -421,7 +421,7 @@ void level_diag(blp_problem *p, const LevelDev<double> &l64, LevelDev<T> &d) {
   k_diag_skew<T, true><<<blocks1d(d.nslot), 256, 0, p->stream>>>(l64.grid(), st, d.ic[1], d.nslot);
 }
 
-int build_exp_levels(blp_problem *p);
+int build_exp_levels(blp_problem *p, bool level0_only);
 int build_par_levels(blp_problem *p);
 
 int build_preconditioner(blp_problem *p) {
@@ -445,11 +445,10 @@ int build_preconditioner(blp_problem *p) {
                                                                     p->f32.fac[v][k], fl);
   }
   // ---- corner multigrid hierarchy (Sec. 3.2) ------------------------------
-  if (p->ylayer == BLP_LAYER_PARABOLIC) {
-    BLP_TRY(build_par_levels(p));
-  } else {
-    BLP_TRY(build_exp_levels(p));
-  }
+  // (the parabolic hierarchy's level 0 is the same corner block, kept in the
+  // two-exponential-layer layout so that its sweeps are those kernels)
+  BLP_TRY(build_exp_levels(p, p->ylayer == BLP_LAYER_PARABOLIC));
+  if (p->ylayer == BLP_LAYER_PARABOLIC) BLP_TRY(build_par_levels(p));
   BLP_TRY(p->alloc(&p->tmp32a, p->n));
   BLP_TRY(p->alloc(&p->tmp32b, p->n));
   HIP_TRY(hipGetLastError());
@@ -457,8 +456,9 @@ int build_preconditioner(blp_problem *p) {
   return BLP_OK;
 }
 
-// Two exponential layers: full coarsening, rediscretised levels.
-int build_exp_levels(blp_problem *p) {
+// Two exponential layers: full coarsening, rediscretised levels (level 0
+// alone: the corner block of either hierarchy).
+int build_exp_levels(blp_problem *p, bool level0_only) {
   const int h = p->h, n1 = p->n1;
   std::vector<LevelHost> LH;
   {
@@ -480,7 +480,7 @@ int build_exp_levels(blp_problem *p) {
     // coarsen by two while the level has an even node count above 2; the
     // coarse node k is fine node 2k, so the transition node stays a node and
     // the width beyond it (to the first interior-mesh node) is unchanged.
-    while (LH.back().n % 2 == 0 && LH.back().n > 2) {
+    while (!level0_only && LH.back().n % 2 == 0 && LH.back().n > 2) {
       const LevelHost &f = LH.back();
       LevelHost c;
       c.n = f.n / 2;
@@ -544,9 +544,11 @@ int build_par_levels(blp_problem *p) {
     const int nx = D[l].nx;
     const size_t n = (size_t)nx * h;
     const ParSetupLevel f{p->grid64(), D[0].sx, D[0].sy, l ? D[l].a : nullptr, nx, h};
-    BLP_TRY(p->alloc(&D[l].ic, n));
-    k_par_invc<<<grid2d(nx, h), 256, 0, p->stream>>>(f, D[l].ic);
-    BLP_TRY(to32(D[l].ic, &F[l].ic, n));
+    if (l > 0) {  // level 0 is smoothed with the two-exponential-layer level-0 tables
+      BLP_TRY(p->alloc(&D[l].ic, n));
+      k_par_invc<<<grid2d(nx, h), 256, 0, p->stream>>>(f, D[l].ic);
+      BLP_TRY(to32(D[l].ic, &F[l].ic, n));
+    }
     if (l + 1 < L) {
       BLP_TRY(zalloc(p, &D[l].wl, n));
       BLP_TRY(zalloc(p, &D[l].wr, n));

@@ -58,7 +58,7 @@ struct SysWork {
   T *bI = nullptr, *zI = nullptr;                    // interior region, skewed
   T *bL[2] = {nullptr, nullptr}, *zL[2] = {nullptr, nullptr};  // edge lines [Y, X]
   std::vector<T *> z, b, t;                          // corner levels, skewed
-  std::vector<T *> pz, pb, pt;                       // parabolic-case corner levels, natural
+  std::vector<T *> pz, pb, pt;  // parabolic-case corner levels 1.. (natural; level 0 is z, b, t [0])
 };
 
 struct System {
@@ -115,7 +115,7 @@ int alloc_work(System &s, hipStream_t st, SysWork<T> &w, const FineDev<T> &f,
   w.pz.assign(PL.size(), nullptr);
   w.pb.assign(PL.size(), nullptr);
   w.pt.assign(PL.size(), nullptr);
-  for (size_t l = 0; l < PL.size(); ++l) {
+  for (size_t l = 1; l < PL.size(); ++l) {
     const size_t n = (size_t)PL[l].nx * h;
     BLP_TRY(s.mem.get(&w.pz[l], n, st, true));
     BLP_TRY(s.mem.get(&w.pb[l], n, st, true));
@@ -297,9 +297,11 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
     }
     la.gate = y.gate;
     lnA[s] = la;
+    // the corner right-hand side and result are level 0's skewed vectors in
+    // both hierarchies
+    cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.b[0], w.z[0], y.ctrl,
+                        p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate};
     if (P.par) {
-      cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.pb[0], w.pz[0], y.ctrl,
-                          p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate, 1};
       const std::vector<ParLevelDev<T>> &PL = par_levels<T>(p);
       for (int l = 0; l < npl; ++l) {
         const bool last = l + 1 == npl;
@@ -307,16 +309,14 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
                               g,         PL[0].sx,
                               PL[0].sy,  PL[l].a,
                               PL[l].ic,  PL[l].wl,
-                              PL[l].wr,  w.pz[l],
-                              w.pb[l],   w.pt[l],
+                              PL[l].wr,  l ? w.pz[l] : w.z[0],
+                              l ? w.pb[l] : w.b[0],
+                              l ? w.pt[l] : w.t[0],
                               last ? 0 : PL[l + 1].nx,
                               last ? nullptr : w.pz[l + 1],
                               last ? nullptr : w.pb[l + 1],
-                              y.ctrl,    y.mg_partials};
+                              y.ctrl};
       }
-    } else {
-      cr[s] = CornerIO<T>{g, h, n1, v, io[s].ldv, dh, z, io[s].ldz, w.b[0], w.z[0], y.ctrl,
-                          p->popts.mg_maxcyc, p->popts.mg_rtol, y.gate, 0};
     }
     for (int l = 0; l < nl; ++l) {
       const MgLevel<T> lv = L[l].view(TR, w.z[l], w.b[l], w.t[l]);
@@ -328,9 +328,10 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
       swt[l][s] = split(SweepArgs<T>{lv.g, 1, L[l].n, 1, L[l].n, w.t[l], ic, w.z[l], &y.ctrl->gate}, l, s);
     }
   }
-  // the coarse levels run as one fused cycle per system
+  // the coarse levels run as one fused cycle per system (two exponential
+  // layers; the parabolic plan uses level 0 alone)
   P.lc = -1;
-  for (int l = 0; l < nl; ++l)
+  for (int l = 0; l < (P.par ? 0 : nl); ++l)
     if (P.ln[l] <= kLdsN<T>) {
       if (nl - l <= kCoarseMax) P.lc = l;
       break;
@@ -566,33 +567,44 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
 // blocks of the corner residual-norm reduction (one partial each)
 constexpr int kMgNormBlocks = 256;
 
-// Parabolic case: one downstream Gauss-Seidel sweep of level l for every
-// system (one workgroup each): one wave up to 64 columns (the scan spanning
-// only as many lanes as there are columns), then up to four waves (one per
-// SIMD) with one column per thread, then four waves with 2 or 4 columns per
-// thread.
-template <typename T, bool L0>
+// Parabolic case: one downstream Gauss-Seidel sweep of coarse level l for
+// every system (one workgroup each): one wave up to 64 columns (the scan
+// spanning only as many lanes as there are columns), then up to four waves
+// (one per SIMD) with one column per thread, then four waves with two.
+template <typename T>
 void par_gs_launch(const Ctx &c, int S, int nx, const ParArgs<T> *A, int zero_init) {
-  if (nx <= 2) k_par_gs<T, 1, 1, L0, 2><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 4) k_par_gs<T, 1, 1, L0, 4><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 8) k_par_gs<T, 1, 1, L0, 8><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 16) k_par_gs<T, 1, 1, L0, 16><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 64) k_par_gs<T, 1, 1, L0, 64><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 128) k_par_gs<T, 2, 1, L0, 64><<<S, 128, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 256) k_par_gs<T, 4, 1, L0, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 512) k_par_gs<T, 4, 2, L0, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
-  else if constexpr (L0)  // only level 0 is wider than 512 columns
-    k_par_gs<T, 4, 4, true, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
+  if (nx <= 2) k_par_gs<T, 1, 1, 2><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 4) k_par_gs<T, 1, 1, 4><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 8) k_par_gs<T, 1, 1, 8><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 16) k_par_gs<T, 1, 1, 16><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 64) k_par_gs<T, 1, 1, 64><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 128) k_par_gs<T, 2, 1, 64><<<S, 128, 0, c.stream>>>(A, zero_init);
+  else if (nx <= 256) k_par_gs<T, 4, 1, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
+  else k_par_gs<T, 4, 2, 64><<<S, 256, 0, c.stream>>>(A, zero_init);  // coarse levels: <= 512
 }
 
 template <typename T, bool TR>
 void par_gs_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, int zero_init) {
   const int nx = P.pn[l];
-  // words per node: level 0 b, z in and out (+ nodal r); coarse levels also
-  // the nine couplings and 1/centre
-  KScope ks(c, KC_SWEEP, (double)P.S * nx * P.h * (l ? 12 : 3) * sizeof(T));
-  if (l == 0) par_gs_launch<T, true>(c, P.S, nx, P.pa[l], zero_init);
-  else par_gs_launch<T, false>(c, P.S, nx, P.pa[l], zero_init);
+  // words per node: b, z in and out, the nine couplings and 1/centre
+  KScope ks(c, KC_SWEEP, (double)P.S * nx * P.h * 12 * sizeof(T));
+  par_gs_launch<T>(c, P.S, nx, P.pa[l], zero_init);
+}
+
+// One Gauss-Seidel sweep of level 0: the level-0 sweep of the
+// two-exponential-layer cycle (same block, same order of results), from b
+// when the iterate is zero, else from the right-hand side with the old
+// West and South values folded in.
+template <typename T, bool TR>
+void par_level0_smooth(const Ctx &c, const PrecPlan<T, TR> &P, bool zero_init) {
+  const int S = P.S, n = P.ln[0];
+  const double nn = (double)S * n * n;
+  if (!zero_init) {
+    KScope ks(c, KC_GSRHS, nn * 3 * sizeof(T));
+    k_gs_rhs<T, TR><<<dim3(blocks1d(P.lslot[0]), S), 256, 0, c.stream>>>(P.mg[0]);
+  }
+  KScope ks(c, KC_SWEEP, nn * 2 * sizeof(T));
+  sweep_launch<T, TR>(c, S, n, zero_init ? P.swb[0] : P.swt[0], P.varL[0]);
 }
 
 // One V(1,1) cycle on level l of the semicoarsening hierarchy (Sec. 3.2);
@@ -602,16 +614,32 @@ template <typename T, bool TR>
 void par_vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
   const int S = P.S, nx = P.pn[l], h = P.h, nl = (int)P.pn.size();
   if (l == nl - 1) {
-    for (int k = 0; k < 4; ++k) par_gs_run<T, TR>(c, P, l, zero_init && k == 0);
+    for (int k = 0; k < 4; ++k) {
+      if (l == 0) par_level0_smooth<T, TR>(c, P, zero_init && k == 0);
+      else par_gs_run<T, TR>(c, P, l, zero_init && k == 0);
+    }
     return;
   }
   const int nxc = P.pn[l + 1];
   const double nn = (double)S * nx * h, cc = (double)S * nxc * h;
+  if (l == 0) {
+    par_level0_smooth<T, TR>(c, P, zero_init);
+    {
+      KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
+      k_par_rr0<T><<<dim3((nxc + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[0]);
+    }
+    par_vcycle_run<T, TR>(c, P, 1, true);
+    {
+      KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
+      k_par_prolong0<T><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[0]);
+    }
+    par_level0_smooth<T, TR>(c, P, false);
+    return;
+  }
   par_gs_run<T, TR>(c, P, l, zero_init);
   {
-    KScope ks(c, KC_MG, nn * (l ? 12 : 3) * sizeof(T));
-    if (l == 0) k_par_resid<T, true><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
-    else k_par_resid<T, false><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+    KScope ks(c, KC_MG, nn * 12 * sizeof(T));
+    k_par_resid<T><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
   }
   {
     KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
@@ -619,19 +647,10 @@ void par_vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_ini
   }
   par_vcycle_run<T, TR>(c, P, l + 1, true);
   {
-    KScope ks(c, KC_MG, (4.0 * nn + cc) * sizeof(T));
+    KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
     k_par_prolong<T><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
   }
   par_gs_run<T, TR>(c, P, l, 0);
-}
-
-template <typename T, bool TR>
-void par_norm_run(const Ctx &c, const PrecPlan<T, TR> &P, int mode) {
-  const size_t n = (size_t)P.h * P.h;
-  const int nblk = std::min(kMgNormBlocks, (int)blocks1d(n));
-  KScope ks(c, KC_MG, (double)P.S * n * 2 * sizeof(T));
-  if (mode == 1) k_par_norm<T, 1><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.pa[0]);
-  else k_par_norm<T, 0><<<dim3(nblk, P.S), 256, 0, c.stream>>>(P.pa[0]);
 }
 
 template <typename T, bool TR>
@@ -654,17 +673,19 @@ void corner_begin(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const b
     k_corner_rhs<T, TR><<<dim3((h + 255) / 256, h, P.S), 256, 0, c.stream>>>(P.cr, jp);
   }
   if (P.par) {
+    // the stopping rule is that of level 0, the same rescaled norm as for two
+    // exponential layers
     if (o.mg_fixed > 0) {
       for (int k = 0; k < o.mg_fixed; ++k) {
         par_vcycle_run<T, TR>(c, P, 0, k == 0);
-        k_par_count<T><<<P.S, 64, 0, c.stream>>>(P.pa[0]);
+        k_mg_count<T><<<P.S, 64, 0, c.stream>>>(P.mg[0]);
       }
       return;
     }
-    par_norm_run<T, TR>(c, P, 0);
+    mg_norm_run<T, TR>(c, P, 0);
     for (int k = 0; k < std::min(first, o.mg_maxcyc); ++k) {
       par_vcycle_run<T, TR>(c, P, 0, k == 0);
-      par_norm_run<T, TR>(c, P, 1);
+      mg_norm_run<T, TR>(c, P, 1);
     }
     return;
   }
@@ -688,7 +709,7 @@ template <typename T, bool TR>
 void corner_cycle(const Ctx &c, const PrecPlan<T, TR> &P) {
   if (P.par) {
     par_vcycle_run<T, TR>(c, P, 0, false);
-    par_norm_run<T, TR>(c, P, 1);
+    mg_norm_run<T, TR>(c, P, 1);
   } else {
     vcycle_run<T, TR>(c, P, 0, false);
     mg_norm_run<T, TR>(c, P, 1);

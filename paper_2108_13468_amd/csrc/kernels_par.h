@@ -2,16 +2,17 @@
 // with c2 = 0 the corner block couples West-East about 1/eps times more
 // strongly than North-South, so the cycle coarsens by two in x only.
 //
-// Levels.  Level l has nx_l = h >> l columns and all h rows; node (i, j) is
-// word (j - 1) nx_l + (i - 1) of every level vector (natural layout).
-// Level 0 is the corner block A_CC, each row multiplied by hbar_i kbar_j;
-// its five couplings come from the fine grid's axis tables (nothing is
-// stored), and the rescaling is applied where it matters: the level-0
-// right-hand side b is kept unscaled (Gauss-Seidel is the same for a row
-// and its multiple), the residual handed to the coarser level and the norm
-// of the stopping rule are those of the rescaled system.  Coarse levels are
-// the Galerkin products A_{l+1} = P_l^T A_l P_l, 9-point stencils stored as
-// nine planes (plane 3 (dj+1) + (di+1) holds the coupling to (i+di, j+dj)).
+// Levels.  Level l has nx_l = h >> l columns and all h rows.  Level 0 is the
+// corner block A_CC, each row multiplied by hbar_i kbar_j; it is the same
+// 5-point block as level 0 of the two-exponential-layer hierarchy, and it is
+// held and smoothed as that one is (skewed vectors, the wavefront sweep
+// kernels, their residual norm, which is that of the rescaled system).  The
+// level-0 right-hand side b is kept unscaled (Gauss-Seidel is the same for
+// a row and its multiple); the residual handed to level 1 is that of the
+// rescaled system.  Coarse levels (l >= 1) are the Galerkin products
+// A_{l+1} = P_l^T A_l P_l, 9-point stencils stored as nine planes (plane
+// 3 (dj+1) + (di+1) holds the coupling to (i+di, j+dj)); node (i, j) is word
+// (j - 1) nx_l + (i - 1) of their vectors (natural layout).
 //
 // Transfers.  P_l injects the even columns (fine node 2I is coarse node I)
 // and interpolates an odd column from its two even neighbours with the
@@ -22,7 +23,8 @@
 // Restriction is P^T.
 //
 // Smoothing.  One downstream Gauss-Seidel sweep visits the rows from top
-// to bottom and each row from right to left.  A row is one first-order
+// to bottom and each row from right to left (on the 5-point level 0 this is
+// the wavefront order's result).  On a coarse level a row is one first-order
 // recurrence z_i = alpha_i - beta_i z_{i+1}: alpha holds the right-hand
 // side less the row above (already new), the row below and the West
 // neighbour (both still old), over the diagonal; beta = a_E / a_C.  One
@@ -122,13 +124,12 @@ __global__ void k_par_rap(ParSetupLevel f, const double *wl, const double *wr, i
     }
 }
 
-// 1 / (centre coupling) of a level (level 0: of the unscaled stencil, which
-// is what its sweep divides by).
+// 1 / (centre coupling) of a coarse level.
 __global__ void k_par_invc(ParSetupLevel f, double *ic) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
   const int j = blockIdx.y + 1;
   if (i > f.nx) return;
-  ic[vidx(i, j, f.nx)] = f.a ? 1.0 / f.coef(i, j, 0, 0) : 1.0 / f.g.C(i, j);
+  ic[vidx(i, j, f.nx)] = 1.0 / f.coef(i, j, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -136,7 +137,8 @@ __global__ void k_par_invc(ParSetupLevel f, double *ic) {
 // ---------------------------------------------------------------------------
 
 // One system's view of a level (blockIdx selects the record) and of the
-// next coarser level for the transfers.
+// next coarser level for the transfers.  Level 0's z and b are the skewed
+// vectors of the two-exponential-layer level 0 (level_skew(h)).
 template <typename T>
 struct ParArgs {
   int nx, ny;
@@ -149,58 +151,65 @@ struct ParArgs {
   int nxc;              // next coarser level: columns and vectors
   T *zc, *bc;
   MgCtrl *ctrl;
-  double *partials;
 };
 
-// Level-0 coupling (unscaled 5-point, zero outside the corner block) and a
-// stored plane entry, at storage precision.
+// (A z)_(i,j) of a coarse level in FP64, z read through the global space; a
+// neighbour outside the level counts as zero.
 template <typename T>
-BLP_DEV T pc0(const GridG<T> &g, int h, int i, int j, int di, int dj) {
-  if (dj == 0) return di < 0 ? (i > 1 ? g.W[i] : T(0)) : (i < h ? g.E[i] : T(0));
-  return dj < 0 ? (j > 1 ? g.S[j] : T(0)) : (j < h ? g.N[j] : T(0));
-}
-
-// (A z)_(i,j) of a level in FP64 (level 0: unscaled), z read through the
-// global space; a neighbour outside the level counts as zero.
-template <typename T, bool L0>
-BLP_DEV double par_apply(const ParArgs<T> &a, const GridG<T> &g, const BLP_GLOBAL T *z, int i,
-                         int j) {
+BLP_DEV double par_apply(const ParArgs<T> &a, const BLP_GLOBAL T *z, int i, int j) {
   const int nx = a.nx, ny = a.ny;
+  const BLP_GLOBAL T *A = gptr(a.a);
+  const size_t pl = (size_t)nx * ny, q = vidx(i, j, nx);
   double s = 0.0;
-  if (L0) {
-    s = (double)g.C(i, j) * (double)z[vidx(i, j, nx)];
-    if (i > 1) s += (double)g.W[i] * (double)z[vidx(i - 1, j, nx)];
-    if (i < nx) s += (double)g.E[i] * (double)z[vidx(i + 1, j, nx)];
-    if (j > 1) s += (double)g.S[j] * (double)z[vidx(i, j - 1, nx)];
-    if (j < ny) s += (double)g.N[j] * (double)z[vidx(i, j + 1, nx)];
-  } else {
-    const BLP_GLOBAL T *A = gptr(a.a);
-    const size_t pl = (size_t)nx * ny, q = vidx(i, j, nx);
 #pragma unroll
-    for (int dj = -1; dj <= 1; ++dj)
+  for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-      for (int di = -1; di <= 1; ++di) {
-        const int qi = i + di, qj = j + dj;
-        if (qi < 1 || qi > nx || qj < 1 || qj > ny) continue;
-        s += (double)A[(3 * (dj + 1) + (di + 1)) * pl + q] * (double)z[vidx(qi, qj, nx)];
-      }
-  }
+    for (int di = -1; di <= 1; ++di) {
+      const int qi = i + di, qj = j + dj;
+      if (qi < 1 || qi > nx || qj < 1 || qj > ny) continue;
+      s += (double)A[(3 * (dj + 1) + (di + 1)) * pl + q] * (double)z[vidx(qi, qj, nx)];
+    }
   return s;
 }
 
-// Residual handed to the next level: level 0 t = S (b - A z) (the rescaled
-// system's residual), coarse levels t = b - A z.  One thread per node.
-template <typename T, bool L0>
+// Residual of a coarse level, t = b - A z.  One thread per node.
+template <typename T>
 __global__ void k_par_resid(const ParArgs<T> *A) {
   const ParArgs<T> a = A[blockIdx.z];
   if (gptr(a.ctrl)->gate) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
   if (i > a.nx) return;
-  const GridG<T> g = gview(a.g);
   const size_t q = vidx(i, j, a.nx);
-  double r = (double)gptr(a.b)[q] - par_apply<T, L0>(a, g, gptr(a.z), i, j);
-  if (L0) r *= (double)a.sx[i] * (double)a.sy[j];
+  const double r = (double)gptr(a.b)[q] - par_apply<T>(a, gptr(a.z), i, j);
   gptr(a.t)[q] = T(r);
+}
+
+// Level 0 to level 1 in one pass: the rescaled residual S (b - A_CC z) at
+// the fine columns 2I-1, 2I, 2I+1 of row J (b and z skewed, FP64
+// arithmetic, couplings out of the corner block left out), restricted by
+// P^T in that order.  One thread per level-1 node.
+template <typename T>
+__global__ void k_par_rr0(const ParArgs<T> *A) {
+  const ParArgs<T> a = A[blockIdx.z];
+  if (gptr(a.ctrl)->gate) return;
+  const int I = blockIdx.x * blockDim.x + threadIdx.x + 1, J = blockIdx.y + 1;
+  if (I > a.nxc) return;
+  const int h = a.nx;
+  const GridG<T> g = gview(a.g);
+  const SkewT<T, false> sk = level_skew<T, false>(h);
+  const BLP_GLOBAL T *z = gptr(a.z), *b = gptr(a.b);
+  auto res = [&](int i) {
+    double s = (double)g.C(i, J) * (double)z[sk.at(i, J)];
+    if (i > 1) s += (double)g.W[i] * (double)z[sk.at(i - 1, J)];
+    if (i < h) s += (double)g.E[i] * (double)z[sk.at(i + 1, J)];
+    if (J > 1) s += (double)g.S[J] * (double)z[sk.at(i, J - 1)];
+    if (J < h) s += (double)g.N[J] * (double)z[sk.at(i, J + 1)];
+    return ((double)b[sk.at(i, J)] - s) * ((double)a.sx[i] * (double)a.sy[J]);
+  };
+  double s = (double)gptr(a.wr)[vidx(2 * I - 1, J, h)] * res(2 * I - 1);
+  s += res(2 * I);
+  if (2 * I + 1 <= h) s += (double)gptr(a.wl)[vidx(2 * I + 1, J, h)] * res(2 * I + 1);
+  gptr(a.bc)[vidx(I, J, a.nxc)] = T(s);
 }
 
 // Coarse right-hand side bc = P^T t, one thread per coarse node, the fine
@@ -239,7 +248,28 @@ __global__ void k_par_prolong(const ParArgs<T> *A) {
   gptr(a.z)[q] += s;
 }
 
-// One downstream Gauss-Seidel sweep of a level, one workgroup of W waves
+// Coarse-grid correction of level 0 (skewed z) from level 1, z += P zc.
+template <typename T>
+__global__ void k_par_prolong0(const ParArgs<T> *A) {
+  const ParArgs<T> a = A[blockIdx.z];
+  if (gptr(a.ctrl)->gate) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
+  const int h = a.nx;
+  if (i > h) return;
+  const BLP_GLOBAL T *zc = gptr(a.zc);
+  const size_t q = vidx(i, j, h);
+  T s;
+  if (i % 2 == 0) {
+    s = zc[vidx(i / 2, j, a.nxc)];
+  } else {
+    s = T(0);
+    if (i > 1) s += gptr(a.wl)[q] * zc[vidx((i - 1) / 2, j, a.nxc)];
+    s += gptr(a.wr)[q] * zc[vidx((i + 1) / 2, j, a.nxc)];
+  }
+  gptr(a.z)[level_skew<T, false>(h).at(i, j)] += s;
+}
+
+// One downstream Gauss-Seidel sweep of a coarse level, one workgroup of W waves
 // (at most one per SIMD) per system; thread t owns the C consecutive
 // columns t C + 1 .. t C + C (nx <= 64 W C).  Per row each thread forms its
 // columns' maps z_i = alpha_i - beta_i z_{i+1} and composes them (right to
@@ -254,13 +284,11 @@ __global__ void k_par_prolong(const ParArgs<T> *A) {
 // (its old values are not read).  SW: the lanes the scan spans (a one-wave
 // sweep of at most 16 columns needs only the in-row DPP steps).
 constexpr int kParAhead = 4;
-constexpr int kParMaxRows = 1024;  // h: at most 1024 layer cells
 
-template <typename T, bool L0, int C>
+template <typename T, int C>
 struct ParRowOps {
   T b[C], ic[C], zs[C];   // right-hand side, 1 / centre, old value one row down
-  T p[L0 ? 1 : 9][L0 ? 1 : C];  // coarse levels: the couplings (plane 4, the
-                                // centre, unused)
+  T p[9][C];              // the couplings (plane 4, the centre, unused)
 };
 
 // Neighbour value across the wave by one DPP move per 32 bits (CTRL
@@ -298,7 +326,7 @@ BLP_DEV void par_scan_down(T &A, T &M, int lane) {
   }
 }
 
-template <typename T, int W, int C, bool L0, int SW>
+template <typename T, int W, int C, int SW>
 __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero_init) {
   constexpr int NT = 64 * W, NC = NT * C;
   // W > 1: the north row (new values) and the old values of row j (at
@@ -306,9 +334,6 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
   __shared__ T s_new[W > 1 ? NC + 2 : 1];
   __shared__ T s_old[2][W > 1 ? NC + 2 : 1];
   __shared__ T s_agA[W], s_agM[W];
-  // level 0: the y tables S_j, N_j of every row, zero at j = 1 (S) and
-  // j = ny (N), where the coupling leaves the corner block
-  __shared__ T s_S[L0 ? kParMaxRows + 1 : 1], s_N[L0 ? kParMaxRows + 1 : 1];
   const ParArgs<T> a = A[blockIdx.x];
   if (gptr(a.ctrl)->gate) return;  // the same for every thread of the block
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -320,28 +345,12 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
     in[k] = i0 + k <= nx;
     lob[k] = (unsigned)((in[k] ? i0 + k : nx) - 1) * (unsigned)sizeof(T);
   }
-  const GridG<T> g = gview(a.g);
   const BLP_GLOBAL T *B = gptr(a.b);
   const BLP_GLOBAL T *IC = gptr(a.ic);
   const BLP_GLOBAL T *P = gptr(a.a);
   BLP_GLOBAL T *Z = gptr(a.z);
   BLP_GLOBAL T *Tw = gptr(a.t);  // free during a sweep: padding lanes store here
-  const int pl = nx * ny;  // at most 1024 x 1024: 32-bit offsets
-  if (L0) {
-    for (int j = t + 1; j <= ny; j += NT) {
-      s_S[j] = j > 1 ? g.S[j] : T(0);
-      s_N[j] = j < ny ? g.N[j] : T(0);
-    }
-  }
-  T xW[C], xE[C];
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    xW[k] = xE[k] = T(0);
-    if (L0 && in[k]) {
-      xW[k] = pc0(g, nx, i0 + k, 1, -1, 0);
-      xE[k] = pc0(g, nx, i0 + k, 1, 1, 0);
-    }
-  }
+  const int pl = nx * ny;  // at most 512 x 1024: 32-bit offsets
   if (W > 1) {
     for (int k = t; k < NC + 2; k += NT) {
       s_new[k] = T(0);
@@ -356,7 +365,7 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
   auto at = [&](const BLP_GLOBAL T *row, int k) {
     return *(const BLP_GLOBAL T *)((const BLP_GLOBAL char *)row + lob[k]);
   };
-  auto load = [&](int j, ParRowOps<T, L0, C> &o) {
+  auto load = [&](int j, ParRowOps<T, C> &o) {
     const int jj = j >= 1 ? j : 1, js = jj > 1 ? jj - 1 : 1;
     const int rb = (jj - 1) * nx;
 #pragma unroll
@@ -365,20 +374,18 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
       o.ic[k] = at(IC + rb, k);
       o.zs[k] = at(Z + (js - 1) * nx, k);
     }
-    if (!L0) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q)
+    for (int q = 0; q < 9; ++q)
 #pragma unroll
-        for (int k = 0; k < C; ++k)
-          if (q != 4) o.p[q][k] = at(P + q * pl + rb, k);
-    }
+      for (int k = 0; k < C; ++k)
+        if (q != 4) o.p[q][k] = at(P + q * pl + rb, k);
   };
   T zn[C], zc[C];  // the row above (new) and this row (old), own columns
 #pragma unroll
   for (int k = 0; k < C; ++k) zn[k] = T(0);
   // One row: operands in cur (loaded kParAhead rows earlier); those of row
   // j - kParAhead are loaded into nxt, the buffer row j + 1 has released.
-  auto row = [&](int j, const ParRowOps<T, L0, C> &cur, ParRowOps<T, L0, C> &nxt) {
+  auto row = [&](int j, const ParRowOps<T, C> &cur, ParRowOps<T, C> &nxt) {
     T zs[C];
 #pragma unroll
     for (int k = 0; k < C; ++k) zs[k] = (zero_init || j == 1 || !in[k]) ? T(0) : cur.zs[k];
@@ -404,26 +411,16 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
       cl = par_shift<0x138>(zc[C - 1]);
     }
     T al[C], be[C];
-    T aS = T(0), aN = T(0);
-    if (L0) {
-      aS = s_S[j];
-      aN = s_N[j];
-    }
 #pragma unroll
     for (int k = 0; k < C; ++k) {
       const T nW = k ? zn[k - 1] : nl, nE = k + 1 < C ? zn[k + 1] : nr;
       const T sW = k ? zs[k - 1] : sl, sE = k + 1 < C ? zs[k + 1] : sr;
       const T cW = k ? zc[k - 1] : cl;
-      T acc = cur.b[k], aE;
-      if (L0) {
-        acc -= aS * zs[k] + aN * zn[k] + xW[k] * cW;
-        aE = xE[k];
-      } else {
-        acc -= cur.p[0][k] * sW + cur.p[1][k] * zs[k] + cur.p[2][k] * sE;
-        acc -= cur.p[3][k] * cW;
-        acc -= cur.p[6][k] * nW + cur.p[7][k] * zn[k] + cur.p[8][k] * nE;
-        aE = cur.p[5][k];
-      }
+      T acc = cur.b[k];
+      acc -= cur.p[0][k] * sW + cur.p[1][k] * zs[k] + cur.p[2][k] * sE;
+      acc -= cur.p[3][k] * cW;
+      acc -= cur.p[6][k] * nW + cur.p[7][k] * zn[k] + cur.p[8][k] * nE;
+      const T aE = cur.p[5][k];
       al[k] = in[k] ? acc * cur.ic[k] : T(0);
       be[k] = in[k] ? aE * cur.ic[k] : T(0);
     }
@@ -475,7 +472,7 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
     }
   };
   // operand buffers of rows ny .. ny - kParAhead + 1
-  ParRowOps<T, L0, C> r[kParAhead + 1];
+  ParRowOps<T, C> r[kParAhead + 1];
 #pragma unroll
   for (int u = 0; u < kParAhead; ++u) load(ny - u, r[u]);
 #pragma unroll
@@ -497,52 +494,4 @@ __global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero
 #pragma unroll
   for (int u = 0; u < kParAhead; ++u)
     if (j - u >= 1) row(j - u, r[u], r[(u + kParAhead) % (kParAhead + 1)]);
-}
-
-// Stopping rule of the corner iteration: mode 0 ||S b||^2 before the first
-// cycle, mode 1 ||S (b - A z)||^2 after each; the last block of a system
-// compares and sets its gate (as the two-exponential-layer rule does).
-template <typename T, int mode>
-__global__ __launch_bounds__(256) void k_par_norm(const ParArgs<T> *A) {
-  __shared__ double sh[16];
-  __shared__ bool last;
-  const ParArgs<T> a = A[blockIdx.y];
-  MgCtrl *ctrl = a.ctrl;
-  if (gptr(ctrl)->gate) return;  // uniform across the system's blocks
-  const GridG<T> g = gview(a.g);
-  const int nx = a.nx;
-  const size_t n = (size_t)nx * a.ny;
-  double acc = 0.0;
-  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-       q += (size_t)gridDim.x * blockDim.x) {
-    const int i = (int)(q % nx) + 1, j = (int)(q / nx) + 1;
-    double v = (double)gptr(a.b)[q];
-    if (mode == 1) v -= par_apply<T, true>(a, g, gptr(a.z), i, j);
-    v *= (double)a.sx[i] * (double)a.sy[j];
-    acc += v * v;
-  }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
-  if (!arrive_last(&ctrl->counter, &last, gridDim.x)) return;
-  double s = 0.0;
-  for (int b2 = threadIdx.x; b2 < (int)gridDim.x; b2 += blockDim.x) s += collect(&a.partials[b2]);
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) {
-    reset_counter(&ctrl->counter);
-    if (mode == 0) {
-      ctrl->bnorm2 = s;
-      if (s == 0.0) ctrl->gate = 1;
-    } else {
-      ctrl->cycles += 1;
-      ctrl->res2 = s;
-      if (s <= ctrl->rtol2 * ctrl->bnorm2 || ctrl->cycles >= ctrl->maxcyc) ctrl->gate = 1;
-    }
-  }
-}
-
-// Count a fixed-mode cycle (no norm evaluation).  One thread per system.
-template <typename T>
-__global__ void k_par_count(const ParArgs<T> *A) {
-  MgCtrl *c = A[blockIdx.x].ctrl;
-  if (threadIdx.x == 0 && !c->gate) c->cycles += 1;
 }
