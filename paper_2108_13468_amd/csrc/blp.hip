@@ -84,12 +84,17 @@ struct LevelDev {
 };
 
 // A level of the parabolic-case corner hierarchy: nx columns, h rows.
+// Natural-order arrays are the FP64 set-up's (a, ic; wl and wr also level
+// 0's in the cycle); the coarse levels' cycle arrays are skewed (sk).
 template <typename T>
 struct ParLevelDev {
   int nx = 0;
-  T *a = nullptr;            // nine coupling planes (coarse levels only)
-  T *ic = nullptr;           // 1 / centre coupling
-  T *wl = nullptr, *wr = nullptr;  // weights toward the next level (not on the coarsest)
+  ParSkew sk;                      // coarse levels: layout of the cycle arrays
+  T *a = nullptr;                  // nine coupling planes, natural (FP64, coarse levels)
+  T *ic = nullptr;                 // 1 / centre coupling, natural (FP64, coarse levels)
+  T *wl = nullptr, *wr = nullptr;  // weights toward the next level, natural (FP64; FP32 on level 0)
+  T *sa = nullptr, *sic = nullptr; // skewed planes and 1 / centre (coarse levels)
+  T *swl = nullptr, *swr = nullptr;  // skewed weights (coarse levels with a coarser one)
   T *sx = nullptr, *sy = nullptr;  // level 0: rescaling factors hbar_i, kbar_j (0..h+1)
 };
 
@@ -544,21 +549,38 @@ int build_par_levels(blp_problem *p) {
     const int nx = D[l].nx;
     const size_t n = (size_t)nx * h;
     const ParSetupLevel f{p->grid64(), D[0].sx, D[0].sy, l ? D[l].a : nullptr, nx, h};
-    if (l > 0) {  // level 0 is smoothed with the two-exponential-layer level-0 tables
+    // level 0 is smoothed with the two-exponential-layer level-0 tables
+    const ParSkew sk = l ? par_skew(nx, h) : ParSkew{};
+    const size_t ns = sk.nslot();
+    auto skew = [&](const double *src, double **d64, float **d32, int np) {
+      BLP_TRY(zalloc(p, d64, np * ns));
+      BLP_TRY(zalloc(p, d32, np * ns));
+      k_par_skew<double><<<grid2d(nx, h), 256, 0, p->stream>>>(src, *d64, sk, np);
+      k_par_skew<float><<<grid2d(nx, h), 256, 0, p->stream>>>(src, *d32, sk, np);
+      return BLP_OK;
+    };
+    if (l > 0) {
+      if (nx > kParMaxCols) return BLP_E_INVAL;
+      D[l].sk = F[l].sk = sk;
       BLP_TRY(p->alloc(&D[l].ic, n));
       k_par_invc<<<grid2d(nx, h), 256, 0, p->stream>>>(f, D[l].ic);
-      BLP_TRY(to32(D[l].ic, &F[l].ic, n));
+      BLP_TRY(skew(D[l].ic, &D[l].sic, &F[l].sic, 1));
+      BLP_TRY(skew(D[l].a, &D[l].sa, &F[l].sa, 9));
     }
     if (l + 1 < L) {
       BLP_TRY(zalloc(p, &D[l].wl, n));
       BLP_TRY(zalloc(p, &D[l].wr, n));
       k_par_weights<<<grid2d((nx + 1) / 2, h), 256, 0, p->stream>>>(f, D[l].wl, D[l].wr);
+      if (l == 0) {
+        BLP_TRY(to32(D[0].wl, &F[0].wl, n));
+        BLP_TRY(to32(D[0].wr, &F[0].wr, n));
+      } else {
+        BLP_TRY(skew(D[l].wl, &D[l].swl, &F[l].swl, 1));
+        BLP_TRY(skew(D[l].wr, &D[l].swr, &F[l].swr, 1));
+      }
       const int nxc = nx / 2;
       BLP_TRY(p->alloc(&D[l + 1].a, (size_t)9 * nxc * h));
       k_par_rap<<<grid2d(nxc, h), 256, 0, p->stream>>>(f, D[l].wl, D[l].wr, nxc, D[l + 1].a);
-      BLP_TRY(to32(D[l].wl, &F[l].wl, n));
-      BLP_TRY(to32(D[l].wr, &F[l].wr, n));
-      BLP_TRY(to32(D[l + 1].a, &F[l + 1].a, (size_t)9 * nxc * h));
     }
     HIP_TRY(hipGetLastError());
   }

@@ -58,7 +58,7 @@ struct SysWork {
   T *bI = nullptr, *zI = nullptr;                    // interior region, skewed
   T *bL[2] = {nullptr, nullptr}, *zL[2] = {nullptr, nullptr};  // edge lines [Y, X]
   std::vector<T *> z, b, t;                          // corner levels, skewed
-  std::vector<T *> pz, pb, pt;  // parabolic-case corner levels 1.. (natural; level 0 is z, b, t [0])
+  std::vector<T *> pz, pb, pt;  // parabolic-case corner levels 1.. (skewed; level 0 is z, b, t [0])
 };
 
 struct System {
@@ -116,7 +116,8 @@ int alloc_work(System &s, hipStream_t st, SysWork<T> &w, const FineDev<T> &f,
   w.pb.assign(PL.size(), nullptr);
   w.pt.assign(PL.size(), nullptr);
   for (size_t l = 1; l < PL.size(); ++l) {
-    const size_t n = (size_t)PL[l].nx * h;
+    // zero-filled: padding words of right-hand sides must hold zero
+    const size_t n = PL[l].sk.nslot();
     BLP_TRY(s.mem.get(&w.pz[l], n, st, true));
     BLP_TRY(s.mem.get(&w.pb[l], n, st, true));
     BLP_TRY(s.mem.get(&w.pt[l], n, st, true));
@@ -186,6 +187,7 @@ struct PrecPlan {
   // parabolic-case corner (x-semicoarsening): level columns and records
   bool par = false;
   std::vector<int> pn;
+  std::vector<ParSkew> psk;
   std::vector<ParArgs<T> *> pa;
   std::vector<MgArgs<T> *> mg;
   std::vector<SweepArgs<T> *> swb, swt;  // per level: sweep from b, from t
@@ -235,7 +237,11 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
   const std::vector<ParLevelDev<T>> &PL0 = par_levels<T>(p0);
   const int npl = (int)PL0.size();
   P.pn.resize(npl);
-  for (int l = 0; l < npl; ++l) P.pn[l] = PL0[l].nx;
+  P.psk.resize(npl);
+  for (int l = 0; l < npl; ++l) {
+    P.pn[l] = PL0[l].nx;
+    P.psk[l] = PL0[l].sk;
+  }
   std::vector<std::vector<ParArgs<T>>> pa(npl, std::vector<ParArgs<T>>(S));
   P.ln.resize(nl);
   P.lslot.resize(nl);
@@ -305,17 +311,26 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
       const std::vector<ParLevelDev<T>> &PL = par_levels<T>(p);
       for (int l = 0; l < npl; ++l) {
         const bool last = l + 1 == npl;
-        pa[l][s] = ParArgs<T>{PL[l].nx,  h,
-                              g,         PL[0].sx,
-                              PL[0].sy,  PL[l].a,
-                              PL[l].ic,  PL[l].wl,
-                              PL[l].wr,  l ? w.pz[l] : w.z[0],
-                              l ? w.pb[l] : w.b[0],
-                              l ? w.pt[l] : w.t[0],
-                              last ? 0 : PL[l + 1].nx,
-                              last ? nullptr : w.pz[l + 1],
-                              last ? nullptr : w.pb[l + 1],
-                              y.ctrl};
+        ParArgs<T> r{};
+        r.nx = PL[l].nx;
+        r.ny = h;
+        r.sk = PL[l].sk;
+        r.skc = last ? ParSkew{} : PL[l + 1].sk;
+        r.g = g;
+        r.sx = PL[0].sx;
+        r.sy = PL[0].sy;
+        r.a = PL[l].sa;
+        r.ic = PL[l].sic;
+        r.wl = l ? PL[l].swl : PL[0].wl;
+        r.wr = l ? PL[l].swr : PL[0].wr;
+        r.z = l ? w.pz[l] : w.z[0];
+        r.b = l ? w.pb[l] : w.b[0];
+        r.t = l ? w.pt[l] : w.t[0];
+        r.nxc = last ? 0 : PL[l + 1].nx;
+        r.zc = last ? nullptr : w.pz[l + 1];
+        r.bc = last ? nullptr : w.pb[l + 1];
+        r.ctrl = y.ctrl;
+        pa[l][s] = r;
       }
     }
     for (int l = 0; l < nl; ++l) {
@@ -568,27 +583,30 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
 constexpr int kMgNormBlocks = 256;
 
 // Parabolic case: one downstream Gauss-Seidel sweep of coarse level l for
-// every system (one workgroup each): one wave up to 64 columns (the scan
-// spanning only as many lanes as there are columns), then up to four waves
-// (one per SIMD) with one column per thread, then four waves with two.
+// every system (one workgroup each, one wave per 64 lanes of column pairs),
+// after the pass that folds the old values into the right-hand side (none
+// on a zero iterate).
 template <typename T>
-void par_gs_launch(const Ctx &c, int S, int nx, const ParArgs<T> *A, int zero_init) {
-  if (nx <= 2) k_par_gs<T, 1, 1, 2><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 4) k_par_gs<T, 1, 1, 4><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 8) k_par_gs<T, 1, 1, 8><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 16) k_par_gs<T, 1, 1, 16><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 64) k_par_gs<T, 1, 1, 64><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 128) k_par_gs<T, 2, 1, 64><<<S, 128, 0, c.stream>>>(A, zero_init);
-  else if (nx <= 256) k_par_gs<T, 4, 1, 64><<<S, 256, 0, c.stream>>>(A, zero_init);
-  else k_par_gs<T, 4, 2, 64><<<S, 256, 0, c.stream>>>(A, zero_init);  // coarse levels: <= 512
+void par_wave_launch(const Ctx &c, int S, const ParSkew &sk, const ParArgs<T> *A, int zero_init) {
+  const int W = (sk.L + 63) / 64;
+  if (W <= 1) k_par_wave<T, 1, 2, kParAhead><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (W == 2) k_par_wave<T, 2, 2, kParAhead><<<S, 128, 0, c.stream>>>(A, zero_init);
+  else if (W == 3) k_par_wave<T, 3, 2, kParAhead><<<S, 192, 0, c.stream>>>(A, zero_init);
+  else k_par_wave<T, 4, 2, kParAhead><<<S, 256, 0, c.stream>>>(A, zero_init);  // nx <= 512
 }
 
 template <typename T, bool TR>
 void par_gs_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, int zero_init) {
-  const int nx = P.pn[l];
-  // words per node: b, z in and out, the nine couplings and 1/centre
-  KScope ks(c, KC_SWEEP, (double)P.S * nx * P.h * 12 * sizeof(T));
-  par_gs_launch<T>(c, P.S, nx, P.pa[l], zero_init);
+  const ParSkew &sk = P.psk[l];
+  const double nn = (double)P.S * sk.nx * sk.ny;
+  if (!zero_init) {
+    // b, four couplings and the old iterate in, the right-hand side out
+    KScope ks(c, KC_GSRHS, nn * 7 * sizeof(T));
+    k_par_pre<T><<<dim3(blocks1d(sk.nslot()), P.S), 256, 0, c.stream>>>(P.pa[l]);
+  }
+  // the right-hand side, four couplings and 1 / centre in, the iterate out
+  KScope ks(c, KC_SWEEP, nn * 7 * sizeof(T));
+  par_wave_launch<T>(c, P.S, sk, P.pa[l], zero_init);
 }
 
 // One Gauss-Seidel sweep of level 0: the level-0 sweep of the
@@ -622,11 +640,12 @@ void par_vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_ini
   }
   const int nxc = P.pn[l + 1];
   const double nn = (double)S * nx * h, cc = (double)S * nxc * h;
+  const dim3 gc(blocks1d(P.psk[l + 1].nslot()), S);  // over the next level's words
   if (l == 0) {
     par_level0_smooth<T, TR>(c, P, zero_init);
     {
       KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
-      k_par_rr0<T><<<dim3((nxc + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[0]);
+      k_par_rr0<T><<<gc, 256, 0, c.stream>>>(P.pa[0]);
     }
     par_vcycle_run<T, TR>(c, P, 1, true);
     {
@@ -636,19 +655,20 @@ void par_vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_ini
     par_level0_smooth<T, TR>(c, P, false);
     return;
   }
+  const dim3 gf(blocks1d(P.psk[l].nslot()), S);  // over this level's words
   par_gs_run<T, TR>(c, P, l, zero_init);
   {
     KScope ks(c, KC_MG, nn * 12 * sizeof(T));
-    k_par_resid<T><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+    k_par_resid<T><<<gf, 256, 0, c.stream>>>(P.pa[l]);
   }
   {
     KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
-    k_par_restrict<T><<<dim3((nxc + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+    k_par_restrict<T><<<gc, 256, 0, c.stream>>>(P.pa[l]);
   }
   par_vcycle_run<T, TR>(c, P, l + 1, true);
   {
     KScope ks(c, KC_MG, (2.0 * nn + cc) * sizeof(T));
-    k_par_prolong<T><<<dim3((nx + 255) / 256, h, S), 256, 0, c.stream>>>(P.pa[l]);
+    k_par_prolong<T><<<gf, 256, 0, c.stream>>>(P.pa[l]);
   }
   par_gs_run<T, TR>(c, P, l, 0);
 }

@@ -11,8 +11,10 @@
 // a row and its multiple); the residual handed to level 1 is that of the
 // rescaled system.  Coarse levels (l >= 1) are the Galerkin products
 // A_{l+1} = P_l^T A_l P_l, 9-point stencils stored as nine planes (plane
-// 3 (dj+1) + (di+1) holds the coupling to (i+di, j+dj)); node (i, j) is word
-// (j - 1) nx_l + (i - 1) of their vectors (natural layout).
+// 3 (dj+1) + (di+1) holds the coupling to (i+di, j+dj)).  The set-up builds
+// them in FP64 in natural order (node (i, j) at word (j - 1) nx_l + (i - 1));
+// the cycle keeps them, 1 / centre, the weights and the level vectors in the
+// skewed order of the coarse sweep (ParSkew).
 //
 // Transfers.  P_l injects the even columns (fine node 2I is coarse node I)
 // and interpolates an odd column from its two even neighbours with the
@@ -24,14 +26,11 @@
 //
 // Smoothing.  One downstream Gauss-Seidel sweep visits the rows from top
 // to bottom and each row from right to left (on the 5-point level 0 this is
-// the wavefront order's result).  On a coarse level a row is one first-order
-// recurrence z_i = alpha_i - beta_i z_{i+1}: alpha holds the right-hand
-// side less the row above (already new), the row below and the West
-// neighbour (both still old), over the diagonal; beta = a_E / a_C.  One
-// workgroup sweeps one system with a thread per column; the recurrence is
-// an affine scan over the row.  Rows are strictly sequential (a row needs
-// the whole row above), so the sweep is latency bound: depth ny x (one
-// row's scan).
+// the wavefront order's result).  A node's new value depends on its East
+// neighbour and the three nodes of the row above, all visited before it; on
+// a coarse level the sweep runs as a wavefront over lanes that own column
+// pairs (k_par_wave), a node (column c, row t from the top) at step
+// t + c / 2, so a sweep is h + nx_l / 2 - 1 dependent steps.
 #pragma once
 #include "common.h"
 
@@ -133,19 +132,75 @@ __global__ void k_par_invc(ParSetupLevel f, double *ic) {
 }
 
 // ---------------------------------------------------------------------------
+// Skewed layout of a coarse level
+// ---------------------------------------------------------------------------
+
+// Coarse-level vectors and planes are stored in the order the wavefront
+// sweep visits them.  Columns count from the right (c = nx - i, 0 .. nx-1),
+// rows from the top (t = ny - j).  Lane l of the sweep owns the M columns
+// l M .. l M + M - 1 (L = ceil(nx / M) lanes) and updates row t = p - l at
+// step p, so skewed row p holds every lane's M words of its row p - l: node
+// (c, t) is word (t + c / M) (L + 1) M + c.  Words c >= nx of a skewed row
+// (among them lane index L, which lanes past the level read and write) and
+// words whose row p - c / M is outside 0 .. ny - 1 are padding; padding holds
+// zero in every plane and right-hand side, so the sweep computes zero there.
+struct ParSkew {
+  int nx = 0, ny = 0;  // columns and rows of the level
+  int L = 0, M = 0;    // sweep lanes and columns per lane
+  __host__ __device__ int rs() const { return (L + 1) * M; }  // words per skewed row
+  __host__ __device__ int rows() const { return ny + L - 1; }
+  __host__ __device__ size_t nslot() const { return (size_t)rows() * rs(); }
+  // word of node (c, t), c in 0 .. nx - 1, t in 0 .. ny - 1
+  BLP_DEV size_t slot(int c, int t) const { return (size_t)(t + c / M) * rs() + c; }
+  // word of natural node (i, j)
+  BLP_DEV size_t at(int i, int j) const { return slot(nx - i, ny - j); }
+  // word q: its skewed row p and column c, and whether it holds a node (row t)
+  BLP_DEV bool node(size_t q, int &c, int &t) const {
+    const int p = (int)(q / (size_t)rs());
+    c = (int)(q - (size_t)p * rs());
+    t = p - c / M;
+    return c < nx && t >= 0 && t < ny;
+  }
+};
+
+// Sweep shape of a coarse level with nx columns: two columns per lane, one
+// wave per 64 lanes (at most four waves: nx <= 512).
+inline ParSkew par_skew(int nx, int ny) {
+  ParSkew s;
+  s.nx = nx;
+  s.ny = ny;
+  s.M = 2;
+  s.L = (nx + s.M - 1) / s.M;
+  return s;
+}
+constexpr int kParMaxCols = 512;
+
+// Natural-layout level arrays (np planes of nx ny words, FP64) into the
+// skewed layout (np planes of nslot words, zero-filled beforehand) in TD.
+template <typename TD>
+__global__ void k_par_skew(const double *src, TD *dst, ParSkew sk, int np) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
+  if (i > sk.nx) return;
+  const size_t n = (size_t)sk.nx * sk.ny, ns = sk.nslot(), q = sk.at(i, j);
+  for (int k = 0; k < np; ++k) dst[k * ns + q] = TD(src[k * n + vidx(i, j, sk.nx)]);
+}
+
+// ---------------------------------------------------------------------------
 // The cycle (T = storage and sweep precision; residuals in FP64)
 // ---------------------------------------------------------------------------
 
 // One system's view of a level (blockIdx selects the record) and of the
 // next coarser level for the transfers.  Level 0's z and b are the skewed
-// vectors of the two-exponential-layer level 0 (level_skew(h)).
+// vectors of the two-exponential-layer level 0 (level_skew(h)), its weights
+// natural; coarse levels hold everything in their skewed layout.
 template <typename T>
 struct ParArgs {
   int nx, ny;
+  ParSkew sk, skc;      // this level's layout (coarse levels) and the next coarser level's
   Grid<T> g;            // fine grid tables (level-0 couplings)
   const T *sx, *sy;     // level-0 rescaling factors hbar_i, kbar_j (1..h)
-  const T *a;           // planes (coarse levels); nullptr on level 0
-  const T *ic;          // 1 / centre coupling
+  const T *a;           // planes, plane q at word q sk.nslot() (coarse levels)
+  const T *ic;          // 1 / centre coupling (coarse levels)
   const T *wl, *wr;     // interpolation weights toward the next level
   T *z, *b, *t;         // iterate, right-hand side, residual
   int nxc;              // next coarser level: columns and vectors
@@ -153,47 +208,71 @@ struct ParArgs {
   MgCtrl *ctrl;
 };
 
-// (A z)_(i,j) of a coarse level in FP64, z read through the global space; a
-// neighbour outside the level counts as zero.
+// Word q of a level's skewed vectors for a flat launch over the words (and
+// the system in blockIdx.y); false past the end.
+BLP_DEV bool par_word(size_t n, size_t &q) {
+  q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  return q < n;
+}
+
+// Right-hand side of a sweep on a nonzero iterate, t = b - (couplings to
+// the old values): West (c + 1, t), South-West (c + 1, t + 1), South (c, t + 1),
+// South-East (c - 1, t + 1).  One thread per word; padding keeps zero.
 template <typename T>
-BLP_DEV double par_apply(const ParArgs<T> &a, const BLP_GLOBAL T *z, int i, int j) {
-  const int nx = a.nx, ny = a.ny;
-  const BLP_GLOBAL T *A = gptr(a.a);
-  const size_t pl = (size_t)nx * ny, q = vidx(i, j, nx);
+__global__ void k_par_pre(const ParArgs<T> *A) {
+  const ParArgs<T> a = A[blockIdx.y];
+  if (gptr(a.ctrl)->gate) return;
+  const ParSkew sk = a.sk;
+  size_t q;
+  int c, t;
+  if (!par_word(sk.nslot(), q) || !sk.node(q, c, t)) return;
+  const BLP_GLOBAL T *z = gptr(a.z), *P = gptr(a.a);
+  const size_t ns = sk.nslot();
+  const bool w = c + 1 < sk.nx, e = c > 0, s = t + 1 < sk.ny;
+  T r = gptr(a.b)[q];
+  if (s && w) r -= P[q] * z[sk.slot(c + 1, t + 1)];
+  if (s) r -= P[ns + q] * z[sk.slot(c, t + 1)];
+  if (s && e) r -= P[2 * ns + q] * z[sk.slot(c - 1, t + 1)];
+  if (w) r -= P[3 * ns + q] * z[sk.slot(c + 1, t)];
+  gptr(a.t)[q] = r;
+}
+
+// Residual of a coarse level, t = b - A z, in FP64.  One thread per word.
+template <typename T>
+__global__ void k_par_resid(const ParArgs<T> *A) {
+  const ParArgs<T> a = A[blockIdx.y];
+  if (gptr(a.ctrl)->gate) return;
+  const ParSkew sk = a.sk;
+  size_t q;
+  int c, t;
+  if (!par_word(sk.nslot(), q) || !sk.node(q, c, t)) return;
+  const BLP_GLOBAL T *z = gptr(a.z), *P = gptr(a.a);
+  const size_t ns = sk.nslot();
   double s = 0.0;
 #pragma unroll
   for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
     for (int di = -1; di <= 1; ++di) {
-      const int qi = i + di, qj = j + dj;
-      if (qi < 1 || qi > nx || qj < 1 || qj > ny) continue;
-      s += (double)A[(3 * (dj + 1) + (di + 1)) * pl + q] * (double)z[vidx(qi, qj, nx)];
+      const int cc = c - di, tt = t - dj;  // natural (i + di, j + dj)
+      if (cc < 0 || cc >= sk.nx || tt < 0 || tt >= sk.ny) continue;
+      s += (double)P[(3 * (dj + 1) + (di + 1)) * ns + q] * (double)z[sk.slot(cc, tt)];
     }
-  return s;
-}
-
-// Residual of a coarse level, t = b - A z.  One thread per node.
-template <typename T>
-__global__ void k_par_resid(const ParArgs<T> *A) {
-  const ParArgs<T> a = A[blockIdx.z];
-  if (gptr(a.ctrl)->gate) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
-  if (i > a.nx) return;
-  const size_t q = vidx(i, j, a.nx);
-  const double r = (double)gptr(a.b)[q] - par_apply<T>(a, gptr(a.z), i, j);
-  gptr(a.t)[q] = T(r);
+  gptr(a.t)[q] = T((double)gptr(a.b)[q] - s);
 }
 
 // Level 0 to level 1 in one pass: the rescaled residual S (b - A_CC z) at
 // the fine columns 2I-1, 2I, 2I+1 of row J (b and z skewed, FP64
 // arithmetic, couplings out of the corner block left out), restricted by
-// P^T in that order.  One thread per level-1 node.
+// P^T in that order.  One thread per level-1 word.
 template <typename T>
 __global__ void k_par_rr0(const ParArgs<T> *A) {
-  const ParArgs<T> a = A[blockIdx.z];
+  const ParArgs<T> a = A[blockIdx.y];
   if (gptr(a.ctrl)->gate) return;
-  const int I = blockIdx.x * blockDim.x + threadIdx.x + 1, J = blockIdx.y + 1;
-  if (I > a.nxc) return;
+  const ParSkew cs = a.skc;
+  size_t q;
+  int cc, tc;
+  if (!par_word(cs.nslot(), q) || !cs.node(q, cc, tc)) return;
+  const int I = cs.nx - cc, J = cs.ny - tc;
   const int h = a.nx;
   const GridG<T> g = gview(a.g);
   const SkewT<T, false> sk = level_skew<T, false>(h);
@@ -209,46 +288,56 @@ __global__ void k_par_rr0(const ParArgs<T> *A) {
   double s = (double)gptr(a.wr)[vidx(2 * I - 1, J, h)] * res(2 * I - 1);
   s += res(2 * I);
   if (2 * I + 1 <= h) s += (double)gptr(a.wl)[vidx(2 * I + 1, J, h)] * res(2 * I + 1);
-  gptr(a.bc)[vidx(I, J, a.nxc)] = T(s);
+  gptr(a.bc)[q] = T(s);
 }
 
-// Coarse right-hand side bc = P^T t, one thread per coarse node, the fine
+// Coarse right-hand side bc = P^T t, one thread per coarse word, the fine
 // columns 2I-1, 2I, 2I+1 added in that order.
 template <typename T>
 __global__ void k_par_restrict(const ParArgs<T> *A) {
-  const ParArgs<T> a = A[blockIdx.z];
+  const ParArgs<T> a = A[blockIdx.y];
   if (gptr(a.ctrl)->gate) return;
-  const int I = blockIdx.x * blockDim.x + threadIdx.x + 1, J = blockIdx.y + 1;
-  if (I > a.nxc) return;
-  const BLP_GLOBAL T *t = gptr(a.t);
-  const int nx = a.nx;
-  T s = gptr(a.wr)[vidx(2 * I - 1, J, nx)] * t[vidx(2 * I - 1, J, nx)];
-  s += t[vidx(2 * I, J, nx)];
-  if (2 * I + 1 <= nx) s += gptr(a.wl)[vidx(2 * I + 1, J, nx)] * t[vidx(2 * I + 1, J, nx)];
-  gptr(a.bc)[vidx(I, J, a.nxc)] = s;
+  const ParSkew cs = a.skc, fs = a.sk;
+  size_t q;
+  int cc, tc;
+  if (!par_word(cs.nslot(), q) || !cs.node(q, cc, tc)) return;
+  const int I = cs.nx - cc, J = cs.ny - tc;
+  const BLP_GLOBAL T *t = gptr(a.t), *wl = gptr(a.wl), *wr = gptr(a.wr);
+  size_t f = fs.at(2 * I - 1, J);
+  T s = wr[f] * t[f];
+  f = fs.at(2 * I, J);
+  s += t[f];
+  if (2 * I + 1 <= fs.nx) {
+    f = fs.at(2 * I + 1, J);
+    s += wl[f] * t[f];
+  }
+  gptr(a.bc)[q] = s;
 }
 
-// Coarse-grid correction z += P zc, one thread per fine node.
+// Coarse-grid correction z += P zc, one thread per fine word.
 template <typename T>
 __global__ void k_par_prolong(const ParArgs<T> *A) {
-  const ParArgs<T> a = A[blockIdx.z];
+  const ParArgs<T> a = A[blockIdx.y];
   if (gptr(a.ctrl)->gate) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
-  if (i > a.nx) return;
+  const ParSkew fs = a.sk, cs = a.skc;
+  size_t q;
+  int c, t;
+  if (!par_word(fs.nslot(), q) || !fs.node(q, c, t)) return;
+  const int i = fs.nx - c, j = fs.ny - t;
   const BLP_GLOBAL T *zc = gptr(a.zc);
-  const size_t q = vidx(i, j, a.nx);
   T s;
   if (i % 2 == 0) {
-    s = zc[vidx(i / 2, j, a.nxc)];
+    s = zc[cs.at(i / 2, j)];
   } else {
     s = T(0);
-    if (i > 1) s += gptr(a.wl)[q] * zc[vidx((i - 1) / 2, j, a.nxc)];
-    s += gptr(a.wr)[q] * zc[vidx((i + 1) / 2, j, a.nxc)];
+    if (i > 1) s += gptr(a.wl)[q] * zc[cs.at((i - 1) / 2, j)];
+    s += gptr(a.wr)[q] * zc[cs.at((i + 1) / 2, j)];
   }
   gptr(a.z)[q] += s;
 }
 
-// Coarse-grid correction of level 0 (skewed z) from level 1, z += P zc.
+// Coarse-grid correction of level 0 (skewed z of level_skew(h)) from level
+// 1, z += P zc; one thread per level-0 node.
 template <typename T>
 __global__ void k_par_prolong0(const ParArgs<T> *A) {
   const ParArgs<T> a = A[blockIdx.z];
@@ -256,242 +345,143 @@ __global__ void k_par_prolong0(const ParArgs<T> *A) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
   const int h = a.nx;
   if (i > h) return;
+  const ParSkew cs = a.skc;
   const BLP_GLOBAL T *zc = gptr(a.zc);
   const size_t q = vidx(i, j, h);
   T s;
   if (i % 2 == 0) {
-    s = zc[vidx(i / 2, j, a.nxc)];
+    s = zc[cs.at(i / 2, j)];
   } else {
     s = T(0);
-    if (i > 1) s += gptr(a.wl)[q] * zc[vidx((i - 1) / 2, j, a.nxc)];
-    s += gptr(a.wr)[q] * zc[vidx((i + 1) / 2, j, a.nxc)];
+    if (i > 1) s += gptr(a.wl)[q] * zc[cs.at((i - 1) / 2, j)];
+    s += gptr(a.wr)[q] * zc[cs.at((i + 1) / 2, j)];
   }
   gptr(a.z)[level_skew<T, false>(h).at(i, j)] += s;
 }
 
-// One downstream Gauss-Seidel sweep of a coarse level, one workgroup of W waves
-// (at most one per SIMD) per system; thread t owns the C consecutive
-// columns t C + 1 .. t C + C (nx <= 64 W C).  Per row each thread forms its
-// columns' maps z_i = alpha_i - beta_i z_{i+1} and composes them (right to
-// left), a DPP scan composes the threads' maps within each wave, the
-// waves' aggregates (through LDS) give the value entering each wave from
-// the right, and each thread re-runs its columns from the value entering
-// its chunk.  Neighbour values across chunk edges (the row above, new; this
-// row and the row below, old) come by DPP within one wave, through LDS with
-// several (old rows double-buffered by row parity).  The operands of a row
-// (right-hand side, 1/centre, couplings, the old values below it) are
-// loaded kParAhead rows ahead.  zero_init: the iterate is zero on entry
-// (its old values are not read).  SW: the lanes the scan spans (a one-wave
-// sweep of at most 16 columns needs only the in-row DPP steps).
-constexpr int kParAhead = 4;
+// One downstream Gauss-Seidel sweep of a coarse level (rows top to bottom,
+// each right to left) as a wavefront.  Lane l of the workgroup's W waves
+// owns columns l M .. l M + M - 1 and updates row t = p - l at step p.  The
+// new values a node needs are its East neighbour (same row) and the three
+// nodes above it: for the lane's first column the East value is lane
+// l - 1's last column of the previous step; for its last column the
+// North-West value is lane l + 1's first column, computed earlier in the
+// same step.  So a step forms the first M - 1 columns right to left, then
+// the last one once the next lane's first column is in: DPP moves within a
+// wave, an LDS word and a barrier across waves (two barriers per step).
+// The old values (West, South-West, South, South-East) are folded into the
+// right-hand side beforehand (k_par_pre; on a zero iterate the right-hand
+// side is b), so per node the sweep reads the right-hand side, the
+// couplings East, North-West, North, North-East and 1 / centre, and writes
+// the node.  Every lane loads and stores at every step (padding: zeros in,
+// zeros out), D steps of operands ahead in rotated register buffers; every
+// step's memory operations are the same, so the waits stay counted.
+constexpr int kParAhead = 6;  // steps of operands in flight (six loads and a store each)
 
-template <typename T, int C>
-struct ParRowOps {
-  T b[C], ic[C], zs[C];   // right-hand side, 1 / centre, old value one row down
-  T p[9][C];              // the couplings (plane 4, the centre, unused)
+template <typename T, int M>
+struct ParStepOps {
+  typedef T V __attribute__((ext_vector_type(M)));
+  V r, e, nw, n, ne, ic;  // right-hand side, planes 5, 6, 7, 8, 1 / centre
 };
 
-// Neighbour value across the wave by one DPP move per 32 bits (CTRL
-// wave_shr:1 0x138 or wave_shl:1 0x130); the lane without a source reads 0.
-template <int CTRL>
-BLP_DEV float par_shift(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-template <int CTRL>
-BLP_DEV double par_shift(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-
-// Suffix composition of the lanes' affine maps x -> A + M x over the first
-// SW lanes (the lanes at and beyond the level's width hold the constant map
-// 0): at most 16 lanes need only the in-row DPP steps.
-template <typename T, int SW>
-BLP_DEV void par_scan_down(T &A, T &M, int lane) {
-  if constexpr (SW > 16) {
-    scan_affine_down(A, M, lane);
-  } else {
-#define BLP_PCOMBINE(CTRL)                                                   \
-  {                                                                         \
-    const T a_ = dpp_mov<CTRL, 0xF>(T(0), A), m_ = dpp_mov<CTRL, 0xF>(T(1), M); \
-    A = A + M * a_;                                                         \
-    M = M * m_;                                                             \
-  }
-    if constexpr (SW > 1) BLP_PCOMBINE(0x101)
-    if constexpr (SW > 2) BLP_PCOMBINE(0x102)
-    if constexpr (SW > 4) BLP_PCOMBINE(0x104)
-    if constexpr (SW > 8) BLP_PCOMBINE(0x108)
-#undef BLP_PCOMBINE
-  }
-}
-
-template <typename T, int W, int C, int SW>
-__global__ __launch_bounds__(64 * W) void k_par_gs(const ParArgs<T> *A, int zero_init) {
-  constexpr int NT = 64 * W, NC = NT * C;
-  // W > 1: the north row (new values) and the old values of row j (at
-  // [j & 1]) in LDS, index = column; with the waves' aggregate maps
-  __shared__ T s_new[W > 1 ? NC + 2 : 1];
-  __shared__ T s_old[2][W > 1 ? NC + 2 : 1];
-  __shared__ T s_agA[W], s_agM[W];
+template <typename T, int W, int M, int D>
+__global__ __launch_bounds__(64 * W) void k_par_wave(const ParArgs<T> *A, int zero_init) {
+  static_assert(M >= 2, "the step order needs two or more columns per lane");
+  typedef typename ParStepOps<T, M>::V V;
+  __shared__ T s_e[W], s_nw[W];  // a wave's last lane's last column, first lane's first
   const ParArgs<T> a = A[blockIdx.x];
   if (gptr(a.ctrl)->gate) return;  // the same for every thread of the block
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int nx = a.nx, ny = a.ny, i0 = t * C + 1;
-  bool in[C];
-  unsigned lob[C];  // byte offsets of the thread's columns (clamped into the level)
-#pragma unroll
-  for (int k = 0; k < C; ++k) {
-    in[k] = i0 + k <= nx;
-    lob[k] = (unsigned)((in[k] ? i0 + k : nx) - 1) * (unsigned)sizeof(T);
-  }
-  const BLP_GLOBAL T *B = gptr(a.b);
-  const BLP_GLOBAL T *IC = gptr(a.ic);
-  const BLP_GLOBAL T *P = gptr(a.a);
-  BLP_GLOBAL T *Z = gptr(a.z);
-  BLP_GLOBAL T *Tw = gptr(a.t);  // free during a sweep: padding lanes store here
-  const int pl = nx * ny;  // at most 512 x 1024: 32-bit offsets
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const ParSkew sk = a.sk;
+  const int L = sk.L, rv = L + 1, nrow = sk.rows();  // rv: chunks per skewed row
+  // lanes past the level use the padding chunk; the lane's byte offset in
+  // a skewed row is its own constant, the row bases are uniform (scalar)
+  const unsigned lob = (unsigned)(tid < L ? tid : L) * (unsigned)sizeof(V);
+  const size_t pv = sk.nslot() / M;  // chunks per plane
+  const BLP_GLOBAL V *R = reinterpret_cast<const BLP_GLOBAL V *>(gptr(zero_init ? a.b : a.t));
+  const BLP_GLOBAL V *P = reinterpret_cast<const BLP_GLOBAL V *>(gptr(a.a));
+  const BLP_GLOBAL V *P5 = P + 5 * pv, *P6 = P + 6 * pv, *P7 = P + 7 * pv, *P8 = P + 8 * pv;
+  const BLP_GLOBAL V *IC = reinterpret_cast<const BLP_GLOBAL V *>(gptr(a.ic));
+  BLP_GLOBAL V *Z = reinterpret_cast<BLP_GLOBAL V *>(gptr(a.z));
+  auto at = [&](const BLP_GLOBAL V *row) {
+    return *reinterpret_cast<const BLP_GLOBAL V *>(reinterpret_cast<const BLP_GLOBAL char *>(row) + lob);
+  };
+  auto load = [&](int u, ParStepOps<T, M> &o) {  // step u's operands (past the end: the last row)
+    const int off = (u < nrow ? u : nrow - 1) * rv;
+    o.r = at(R + off);
+    o.e = at(P5 + off);
+    o.nw = at(P6 + off);
+    o.n = at(P7 + off);
+    o.ne = at(P8 + off);
+    o.ic = at(IC + off);
+  };
   if (W > 1) {
-    for (int k = t; k < NC + 2; k += NT) {
-      s_new[k] = T(0);
-      s_old[0][k] = T(0);
-      s_old[1][k] = T(0);
+    if (tid < W) {
+      s_e[tid] = T(0);
+      s_nw[tid] = T(0);
     }
+    __syncthreads();
   }
-  // Row bases are uniform (scalar registers), the column offsets the
-  // thread's own constants.  Operands are loaded unconditionally (row
-  // indices clamped to the level; what a clamped load brings is replaced at
-  // its use), so that no branch or copy waits for loads in flight.
-  auto at = [&](const BLP_GLOBAL T *row, int k) {
-    return *(const BLP_GLOBAL T *)((const BLP_GLOBAL char *)row + lob[k]);
-  };
-  auto load = [&](int j, ParRowOps<T, C> &o) {
-    const int jj = j >= 1 ? j : 1, js = jj > 1 ? jj - 1 : 1;
-    const int rb = (jj - 1) * nx;
+  T zp[M];       // this lane's columns at the previous step (the row above)
+  T e0p = T(0);  // the previous step's East value of column 0 (its North-East now)
 #pragma unroll
-    for (int k = 0; k < C; ++k) {
-      o.b[k] = at(B + rb, k);
-      o.ic[k] = at(IC + rb, k);
-      o.zs[k] = at(Z + (js - 1) * nx, k);
+  for (int k = 0; k < M; ++k) zp[k] = T(0);
+  auto step = [&](int p, const ParStepOps<T, M> &cur, ParStepOps<T, M> &nxt) {
+    load(p + D, nxt);
+    // terms in the previous step's values
+    T pre[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      T x = cur.r[k] - cur.n[k] * zp[k];
+      x -= cur.ne[k] * (k ? zp[k - 1] : e0p);
+      if (k + 1 < M) x -= cur.nw[k] * zp[k + 1];
+      pre[k] = x;
     }
+    // East value of column 0: lane l - 1's last column (previous step); the
+    // first lane of a wave takes it from the wave before (zero for wave 0)
+    T ein = T(0);
+    if (W > 1) ein = w > 0 ? s_e[w > 0 ? w - 1 : 0] : T(0);
+    const T e0 = dpp_mov<0x138>(ein, zp[M - 1]);
+    T z[M];
+    z[0] = (pre[0] - cur.e[0] * e0) * cur.ic[0];
 #pragma unroll
-    for (int q = 0; q < 9; ++q)
-#pragma unroll
-      for (int k = 0; k < C; ++k)
-        if (q != 4) o.p[q][k] = at(P + q * pl + rb, k);
-  };
-  T zn[C], zc[C];  // the row above (new) and this row (old), own columns
-#pragma unroll
-  for (int k = 0; k < C; ++k) zn[k] = T(0);
-  // One row: operands in cur (loaded kParAhead rows earlier); those of row
-  // j - kParAhead are loaded into nxt, the buffer row j + 1 has released.
-  auto row = [&](int j, const ParRowOps<T, C> &cur, ParRowOps<T, C> &nxt) {
-    T zs[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) zs[k] = (zero_init || j == 1 || !in[k]) ? T(0) : cur.zs[k];
-    T nl, nr, sl, sr, cl;  // edge neighbours: columns i0 - 1 (l) and i0 + C (r)
+    for (int k = 1; k + 1 < M; ++k) z[k] = (pre[k] - cur.e[k] * z[k - 1]) * cur.ic[k];
+    const T x = pre[M - 1] - cur.e[M - 1] * z[M - 2];
+    // North-West value of the last column: lane l + 1's first column (this
+    // step); the last lane of a wave takes it from the wave after
+    T nwin = T(0);
     if (W > 1) {
-#pragma unroll
-      for (int k = 0; k < C; ++k) s_old[(j - 1) & 1][i0 + k] = zs[k];  // 0 past the level
-      load(j - kParAhead, nxt);
-      // the rows written above and the north row are visible; the loads of
-      // later rows and the stores of earlier rows stay in flight
+      if (lane == 0) s_nw[w] = z[0];
       lds_barrier();
-      nl = s_new[i0 - 1];
-      nr = s_new[i0 + C];
-      sl = s_old[(j - 1) & 1][i0 - 1];
-      sr = s_old[(j - 1) & 1][i0 + C];
-      cl = s_old[j & 1][i0 - 1];
-    } else {
-      load(j - kParAhead, nxt);
-      nl = par_shift<0x138>(zn[C - 1]);  // lane l-1 (lane 0: the boundary, 0)
-      nr = par_shift<0x130>(zn[0]);      // lane l+1 (lane 63: beyond the level)
-      sl = par_shift<0x138>(zs[C - 1]);
-      sr = par_shift<0x130>(zs[0]);
-      cl = par_shift<0x138>(zc[C - 1]);
+      nwin = w + 1 < W ? s_nw[w + 1 < W ? w + 1 : w] : T(0);
     }
-    T al[C], be[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      const T nW = k ? zn[k - 1] : nl, nE = k + 1 < C ? zn[k + 1] : nr;
-      const T sW = k ? zs[k - 1] : sl, sE = k + 1 < C ? zs[k + 1] : sr;
-      const T cW = k ? zc[k - 1] : cl;
-      T acc = cur.b[k];
-      acc -= cur.p[0][k] * sW + cur.p[1][k] * zs[k] + cur.p[2][k] * sE;
-      acc -= cur.p[3][k] * cW;
-      acc -= cur.p[6][k] * nW + cur.p[7][k] * zn[k] + cur.p[8][k] * nE;
-      const T aE = cur.p[5][k];
-      al[k] = in[k] ? acc * cur.ic[k] : T(0);
-      be[k] = in[k] ? aE * cur.ic[k] : T(0);
-    }
-    // the chunk's map x -> Am + Mm x from the value x entering at i0 + C
-    T Am = T(0), Mm = T(1);
-#pragma unroll
-    for (int k = C - 1; k >= 0; --k) {
-      Am = al[k] - be[k] * Am;
-      Mm = -be[k] * Mm;
-    }
-    par_scan_down<T, SW>(Am, Mm, lane);
+    const T nwv = dpp_mov<0x130>(nwin, z[0]);
+    z[M - 1] = (x - cur.nw[M - 1] * nwv) * cur.ic[M - 1];
     if (W > 1) {
-      if (lane == 0) {
-        s_agA[w] = Am;
-        s_agM[w] = Mm;
-      }
+      if (lane == 63) s_e[w] = z[M - 1];
       lds_barrier();
     }
-    // value entering this wave: the waves to its right applied to zero
-    T zin = T(0);
+    V zv;
 #pragma unroll
-    for (int v = W - 1; v > 0; --v)
-      if (v > w) zin = s_agA[v] + s_agM[v] * zin;
-    // value entering this thread's chunk: the next lane's composed map
-    // applied to zin (the wave's last lane: zin itself)
-    T ar = par_shift<0x130>(Am), mr = par_shift<0x130>(Mm);
-    if (lane == 63) {
-      ar = T(0);
-      mr = T(1);
+    for (int k = 0; k < M; ++k) {
+      zv[k] = z[k];
+      zp[k] = z[k];
     }
-    T zr = ar + mr * zin;
-    T z[C];
-#pragma unroll
-    for (int k = C - 1; k >= 0; --k) {
-      zr = al[k] - be[k] * zr;
-      z[k] = zr;
-    }
-    // stores are unconditional (a padding lane writes to the free vector t),
-    // so that every row issues the same memory operations
-    BLP_GLOBAL char *zrow = (BLP_GLOBAL char *)(Z + (j - 1) * nx);
-    BLP_GLOBAL char *trow = (BLP_GLOBAL char *)(Tw + (j - 1) * nx);
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-      *(BLP_GLOBAL T *)((in[k] ? zrow : trow) + lob[k]) = z[k];
-      // every read of s_new for this row came before the barrier above
-      if (W > 1) s_new[i0 + k] = in[k] ? z[k] : T(0);
-      zn[k] = in[k] ? z[k] : T(0);
-      zc[k] = zs[k];
-    }
+    *reinterpret_cast<BLP_GLOBAL V *>(reinterpret_cast<BLP_GLOBAL char *>(Z + p * rv) + lob) = zv;
+    e0p = e0;
   };
-  // operand buffers of rows ny .. ny - kParAhead + 1
-  ParRowOps<T, C> r[kParAhead + 1];
-#pragma unroll
-  for (int u = 0; u < kParAhead; ++u) load(ny - u, r[u]);
-#pragma unroll
-  for (int k = 0; k < C; ++k)
-    zc[k] = (zero_init || !in[k]) ? T(0) : at(Z + (ny - 1) * nx, k);
-  __syncthreads();  // LDS rows zeroed, y tables in place
-  if (W > 1) {
-#pragma unroll
-    for (int k = 0; k < C; ++k) s_old[ny & 1][i0 + k] = zc[k];
-  }
   // the buffers in turn (indices fixed at compile time: no register copies
-  // between rows); whole groups of kParAhead + 1 rows, then the rest
-  int j = ny;
-  for (; j - kParAhead >= 1; j -= kParAhead + 1) {
+  // between steps); whole groups of D + 1 steps, then the rest
+  ParStepOps<T, M> buf[D + 1];
 #pragma unroll
-    for (int u = 0; u <= kParAhead; ++u)
-      row(j - u, r[u], r[(u + kParAhead) % (kParAhead + 1)]);
+  for (int u = 0; u < D; ++u) load(u, buf[u]);
+  int p = 0;
+  for (; p + D < nrow; p += D + 1) {
+#pragma unroll
+    for (int u = 0; u <= D; ++u) step(p + u, buf[u], buf[(u + D) % (D + 1)]);
   }
 #pragma unroll
-  for (int u = 0; u < kParAhead; ++u)
-    if (j - u >= 1) row(j - u, r[u], r[(u + kParAhead) % (kParAhead + 1)]);
+  for (int u = 0; u < D; ++u)
+    if (p + u < nrow) step(p + u, buf[u], buf[(u + D) % (D + 1)]);
 }
