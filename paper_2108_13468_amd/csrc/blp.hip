@@ -95,6 +95,7 @@ struct ParLevelDev {
   T *wl = nullptr, *wr = nullptr;  // weights toward the next level, natural (FP64; FP32 on level 0)
   T *sa = nullptr, *sic = nullptr; // skewed planes and 1 / centre (coarse levels)
   T *swl = nullptr, *swr = nullptr;  // skewed weights (coarse levels with a coarser one)
+  T *ssw = nullptr;                // skewed sweep planes (couplings over the centre)
   T *sx = nullptr, *sy = nullptr;  // level 0: rescaling factors hbar_i, kbar_j (0..h+1)
 };
 
@@ -566,6 +567,10 @@ int build_par_levels(blp_problem *p) {
       k_par_invc<<<grid2d(nx, h), 256, 0, p->stream>>>(f, D[l].ic);
       BLP_TRY(skew(D[l].ic, &D[l].sic, &F[l].sic, 1));
       BLP_TRY(skew(D[l].a, &D[l].sa, &F[l].sa, 9));
+      BLP_TRY(zalloc(p, &D[l].ssw, 4 * ns));
+      BLP_TRY(zalloc(p, &F[l].ssw, 4 * ns));
+      k_par_skew_sweep<double><<<grid2d(nx, h), 256, 0, p->stream>>>(D[l].a, D[l].ssw, sk);
+      k_par_skew_sweep<float><<<grid2d(nx, h), 256, 0, p->stream>>>(D[l].a, F[l].ssw, sk);
     }
     if (l + 1 < L) {
       BLP_TRY(zalloc(p, &D[l].wl, n));

@@ -321,6 +321,7 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
         r.sy = PL[0].sy;
         r.a = PL[l].sa;
         r.ic = PL[l].sic;
+        r.sw = PL[l].ssw;
         r.wl = l ? PL[l].swl : PL[0].wl;
         r.wr = l ? PL[l].swr : PL[0].wr;
         r.z = l ? w.pz[l] : w.z[0];
@@ -583,16 +584,22 @@ void vcycle_run(const Ctx &c, const PrecPlan<T, TR> &P, int l, bool zero_init) {
 constexpr int kMgNormBlocks = 256;
 
 // Parabolic case: one downstream Gauss-Seidel sweep of coarse level l for
-// every system (one workgroup each, one wave per 64 lanes of column pairs),
+// every system (one workgroup each, one wave per 64 lanes of M columns),
 // after the pass that folds the old values into the right-hand side (none
 // on a zero iterate).
+template <typename T, int M>
+void par_wave_launch_m(const Ctx &c, int S, int W, const ParArgs<T> *A, int zero_init) {
+  constexpr int D = par_ahead<T, M>();
+  if (W <= 1) k_par_wave<T, 1, M, D><<<S, 64, 0, c.stream>>>(A, zero_init);
+  else if (W == 2) k_par_wave<T, 2, M, D><<<S, 128, 0, c.stream>>>(A, zero_init);
+  else if (W == 3) k_par_wave<T, 3, M, D><<<S, 192, 0, c.stream>>>(A, zero_init);
+  else k_par_wave<T, 4, M, D><<<S, 256, 0, c.stream>>>(A, zero_init);
+}
 template <typename T>
 void par_wave_launch(const Ctx &c, int S, const ParSkew &sk, const ParArgs<T> *A, int zero_init) {
-  const int W = (sk.L + 63) / 64;
-  if (W <= 1) k_par_wave<T, 1, 2, kParAhead><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (W == 2) k_par_wave<T, 2, 2, kParAhead><<<S, 128, 0, c.stream>>>(A, zero_init);
-  else if (W == 3) k_par_wave<T, 3, 2, kParAhead><<<S, 192, 0, c.stream>>>(A, zero_init);
-  else k_par_wave<T, 4, 2, kParAhead><<<S, 256, 0, c.stream>>>(A, zero_init);  // nx <= 512
+  const int W = (sk.L + 63) / 64;  // at most four: nx <= 512 (par_skew)
+  if (sk.M == 2) par_wave_launch_m<T, 2>(c, S, W, A, zero_init);
+  else par_wave_launch_m<T, 4>(c, S, W, A, zero_init);
 }
 
 template <typename T, bool TR>

@@ -28,9 +28,9 @@
 // to bottom and each row from right to left (on the 5-point level 0 this is
 // the wavefront order's result).  A node's new value depends on its East
 // neighbour and the three nodes of the row above, all visited before it; on
-// a coarse level the sweep runs as a wavefront over lanes that own column
-// pairs (k_par_wave), a node (column c, row t from the top) at step
-// t + c / 2, so a sweep is h + nx_l / 2 - 1 dependent steps.
+// a coarse level the sweep runs as a wavefront over lanes that own M
+// columns each (k_par_wave, M = 2 or 4), a node (column c, row t from the
+// top) at step t + c / M, so a sweep is h + nx_l / M - 1 dependent steps.
 #pragma once
 #include "common.h"
 
@@ -163,13 +163,14 @@ struct ParSkew {
   }
 };
 
-// Sweep shape of a coarse level with nx columns: two columns per lane, one
-// wave per 64 lanes (at most four waves: nx <= 512).
+// Sweep shape of a coarse level with nx columns: two columns per lane up
+// to 128 columns (one wave), four above (one wave up to 256, two up to 512:
+// fewer waves, fewer barriers per step, at the same number of steps).
 inline ParSkew par_skew(int nx, int ny) {
   ParSkew s;
   s.nx = nx;
   s.ny = ny;
-  s.M = 2;
+  s.M = nx <= 128 ? 2 : 4;
   s.L = (nx + s.M - 1) / s.M;
   return s;
 }
@@ -183,6 +184,18 @@ __global__ void k_par_skew(const double *src, TD *dst, ParSkew sk, int np) {
   if (i > sk.nx) return;
   const size_t n = (size_t)sk.nx * sk.ny, ns = sk.nslot(), q = sk.at(i, j);
   for (int k = 0; k < np; ++k) dst[k * ns + q] = TD(src[k * n + vidx(i, j, sk.nx)]);
+}
+
+// The sweep's couplings to new values over the centre, skewed: plane k
+// (0..3) holds a_q / a_C of plane q = 5 + k (East, North-West, North,
+// North-East), formed in FP64 from the natural planes.
+template <typename TD>
+__global__ void k_par_skew_sweep(const double *a, TD *dst, ParSkew sk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1, j = blockIdx.y + 1;
+  if (i > sk.nx) return;
+  const size_t n = (size_t)sk.nx * sk.ny, ns = sk.nslot(), q = sk.at(i, j), v = vidx(i, j, sk.nx);
+  const double c = a[4 * n + v];
+  for (int k = 0; k < 4; ++k) dst[k * ns + q] = TD(a[(5 + k) * n + v] / c);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,6 +214,7 @@ struct ParArgs {
   const T *sx, *sy;     // level-0 rescaling factors hbar_i, kbar_j (1..h)
   const T *a;           // planes, plane q at word q sk.nslot() (coarse levels)
   const T *ic;          // 1 / centre coupling (coarse levels)
+  const T *sw;          // the sweep's planes over the centre (k_par_skew_sweep)
   const T *wl, *wr;     // interpolation weights toward the next level
   T *z, *b, *t;         // iterate, right-hand side, residual
   int nxc;              // next coarser level: columns and vectors
@@ -371,18 +385,80 @@ __global__ void k_par_prolong0(const ParArgs<T> *A) {
 // wave, an LDS word and a barrier across waves (two barriers per step).
 // The old values (West, South-West, South, South-East) are folded into the
 // right-hand side beforehand (k_par_pre; on a zero iterate the right-hand
-// side is b), so per node the sweep reads the right-hand side, the
-// couplings East, North-West, North, North-East and 1 / centre, and writes
-// the node.  Every lane loads and stores at every step (padding: zeros in,
+// side is b), so per node the sweep reads the right-hand side, 1 / centre
+// and the couplings East, North-West, North, North-East over the centre,
+// and writes the node: z = r / a_C - sum (a_q / a_C) z_q, the terms in
+// values that arrive last subtracted last, so that a step's dependent
+// chain is two DPP moves and two fused multiply-adds.  Every lane loads and stores at every step (padding: zeros in,
 // zeros out), D steps of operands ahead in rotated register buffers; every
 // step's memory operations are the same, so the waits stay counted.
-constexpr int kParAhead = 6;  // steps of operands in flight (six loads and a store each)
+// Steps of operands in flight: a step issues six loads and a store of
+// M sizeof(T) bytes per lane (16-byte pieces), and the wait counter tracks
+// at most 63 memory operations.
+template <typename T, int M>
+constexpr int par_ahead() {
+  return (M * sizeof(T) <= 16) ? 8 : 4;
+}
 
 template <typename T, int M>
 struct ParStepOps {
   typedef T V __attribute__((ext_vector_type(M)));
-  V r, e, nw, n, ne, ic;  // right-hand side, planes 5, 6, 7, 8, 1 / centre
+  V r, e, nw, n, ne, ic;  // right-hand side, the four sweep planes, 1 / centre
 };
+
+// Raw buffer access to one array: a lane's constant byte offset (vo) plus a
+// uniform byte offset (so, a scalar register), so that stepping through
+// the skewed rows costs no vector instruction.  Accesses past the array's
+// bytes read zero and write nothing.
+typedef unsigned int ParU2 __attribute__((ext_vector_type(2)));
+typedef unsigned int ParU4 __attribute__((ext_vector_type(4)));
+BLP_DEV __amdgpu_buffer_rsrc_t par_rsrc(const void *p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+template <typename V>
+BLP_DEV V par_ld(__amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+  static_assert(sizeof(V) == 8 || sizeof(V) % 16 == 0, "chunk of 8 or 16k bytes");
+  V out;
+  if constexpr (sizeof(V) == 8) {
+    const ParU2 x = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    __builtin_memcpy(&out, &x, 8);
+  } else {
+#pragma unroll
+    for (int k = 0; k < (int)sizeof(V) / 16; ++k) {
+      const ParU4 x = __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16 * k, so, 0);
+      __builtin_memcpy(reinterpret_cast<char *>(&out) + 16 * k, &x, 16);
+    }
+  }
+  return out;
+}
+template <typename V>
+BLP_DEV void par_st(const V &v, __amdgpu_buffer_rsrc_t r, unsigned vo, int so) {
+  if constexpr (sizeof(V) == 8) {
+    ParU2 x;
+    __builtin_memcpy(&x, &v, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(x, r, vo, so, 0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < (int)sizeof(V) / 16; ++k) {
+      ParU4 x;
+      __builtin_memcpy(&x, reinterpret_cast<const char *>(&v) + 16 * k, 16);
+      __builtin_amdgcn_raw_buffer_store_b128(x, r, vo + 16 * k, so, 0);
+    }
+  }
+}
+
+// Neighbour value across the wave by one DPP move per 32 bits (CTRL
+// wave_shr:1 0x138 or wave_shl:1 0x130); the lane without a source reads 0.
+template <int CTRL>
+BLP_DEV float par_shift(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+BLP_DEV double par_shift(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
 
 template <typename T, int W, int M, int D>
 __global__ __launch_bounds__(64 * W) void k_par_wave(const ParArgs<T> *A, int zero_init) {
@@ -396,25 +472,25 @@ __global__ __launch_bounds__(64 * W) void k_par_wave(const ParArgs<T> *A, int ze
   const ParSkew sk = a.sk;
   const int L = sk.L, rv = L + 1, nrow = sk.rows();  // rv: chunks per skewed row
   // lanes past the level use the padding chunk; the lane's byte offset in
-  // a skewed row is its own constant, the row bases are uniform (scalar)
+  // a skewed row is its own constant, the row offset is uniform
   const unsigned lob = (unsigned)(tid < L ? tid : L) * (unsigned)sizeof(V);
-  const size_t pv = sk.nslot() / M;  // chunks per plane
-  const BLP_GLOBAL V *R = reinterpret_cast<const BLP_GLOBAL V *>(gptr(zero_init ? a.b : a.t));
-  const BLP_GLOBAL V *P = reinterpret_cast<const BLP_GLOBAL V *>(gptr(a.a));
-  const BLP_GLOBAL V *P5 = P + 5 * pv, *P6 = P + 6 * pv, *P7 = P + 7 * pv, *P8 = P + 8 * pv;
-  const BLP_GLOBAL V *IC = reinterpret_cast<const BLP_GLOBAL V *>(gptr(a.ic));
-  BLP_GLOBAL V *Z = reinterpret_cast<BLP_GLOBAL V *>(gptr(a.z));
-  auto at = [&](const BLP_GLOBAL V *row) {
-    return *reinterpret_cast<const BLP_GLOBAL V *>(reinterpret_cast<const BLP_GLOBAL char *>(row) + lob);
-  };
+  const size_t pb = sk.nslot() * sizeof(T);  // bytes per plane or vector
+  const __amdgpu_buffer_rsrc_t rR = par_rsrc(zero_init ? a.b : a.t, pb);
+  const __amdgpu_buffer_rsrc_t rE = par_rsrc(a.sw, pb);
+  const __amdgpu_buffer_rsrc_t rNW = par_rsrc(a.sw + sk.nslot(), pb);
+  const __amdgpu_buffer_rsrc_t rN = par_rsrc(a.sw + 2 * sk.nslot(), pb);
+  const __amdgpu_buffer_rsrc_t rNE = par_rsrc(a.sw + 3 * sk.nslot(), pb);
+  const __amdgpu_buffer_rsrc_t rIC = par_rsrc(a.ic, pb);
+  const __amdgpu_buffer_rsrc_t rZ = par_rsrc(a.z, pb);
+  const int rb = rv * (int)sizeof(V);  // bytes per skewed row
   auto load = [&](int u, ParStepOps<T, M> &o) {  // step u's operands (past the end: the last row)
-    const int off = (u < nrow ? u : nrow - 1) * rv;
-    o.r = at(R + off);
-    o.e = at(P5 + off);
-    o.nw = at(P6 + off);
-    o.n = at(P7 + off);
-    o.ne = at(P8 + off);
-    o.ic = at(IC + off);
+    const int so = (u < nrow ? u : nrow - 1) * rb;
+    o.r = par_ld<V>(rR, lob, so);
+    o.e = par_ld<V>(rE, lob, so);
+    o.nw = par_ld<V>(rNW, lob, so);
+    o.n = par_ld<V>(rN, lob, so);
+    o.ne = par_ld<V>(rNE, lob, so);
+    o.ic = par_ld<V>(rIC, lob, so);
   };
   if (W > 1) {
     if (tid < W) {
@@ -429,36 +505,39 @@ __global__ __launch_bounds__(64 * W) void k_par_wave(const ParArgs<T> *A, int ze
   for (int k = 0; k < M; ++k) zp[k] = T(0);
   auto step = [&](int p, const ParStepOps<T, M> &cur, ParStepOps<T, M> &nxt) {
     load(p + D, nxt);
-    // terms in the previous step's values
-    T pre[M];
+    // issued here, D steps ahead of their use: the instruction scheduler
+    // may not sink them toward later steps
+    __builtin_amdgcn_sched_barrier(0);
+    // terms in values of earlier steps (couplings already over the centre)
+    T rest[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-      T x = cur.r[k] - cur.n[k] * zp[k];
-      x -= cur.ne[k] * (k ? zp[k - 1] : e0p);
-      if (k + 1 < M) x -= cur.nw[k] * zp[k + 1];
-      pre[k] = x;
-    }
+    for (int k = 0; k < M; ++k)
+      rest[k] = cur.r[k] * cur.ic[k] - cur.n[k] * zp[k] - cur.ne[k] * (k ? zp[k - 1] : e0p);
     // East value of column 0: lane l - 1's last column (previous step); the
     // first lane of a wave takes it from the wave before (zero for wave 0)
-    T ein = T(0);
-    if (W > 1) ein = w > 0 ? s_e[w > 0 ? w - 1 : 0] : T(0);
-    const T e0 = dpp_mov<0x138>(ein, zp[M - 1]);
+    T e0;
+    if constexpr (W > 1) e0 = dpp_mov<0x138>(w > 0 ? s_e[w > 0 ? w - 1 : 0] : T(0), zp[M - 1]);
+    else e0 = par_shift<0x138>(zp[M - 1]);
     T z[M];
-    z[0] = (pre[0] - cur.e[0] * e0) * cur.ic[0];
+    z[0] = (rest[0] - cur.nw[0] * zp[1]) - cur.e[0] * e0;
 #pragma unroll
-    for (int k = 1; k + 1 < M; ++k) z[k] = (pre[k] - cur.e[k] * z[k - 1]) * cur.ic[k];
-    const T x = pre[M - 1] - cur.e[M - 1] * z[M - 2];
+    for (int k = 1; k + 1 < M; ++k) z[k] = (rest[k] - cur.nw[k] * zp[k + 1]) - cur.e[k] * z[k - 1];
     // North-West value of the last column: lane l + 1's first column (this
     // step); the last lane of a wave takes it from the wave after
-    T nwin = T(0);
-    if (W > 1) {
+    T nwv;
+    if constexpr (W > 1) {
       if (lane == 0) s_nw[w] = z[0];
       lds_barrier();
-      nwin = w + 1 < W ? s_nw[w + 1 < W ? w + 1 : w] : T(0);
+      nwv = dpp_mov<0x130>(w + 1 < W ? s_nw[w + 1 < W ? w + 1 : w] : T(0), z[0]);
+    } else {
+      nwv = par_shift<0x130>(z[0]);
     }
-    const T nwv = dpp_mov<0x130>(nwin, z[0]);
-    z[M - 1] = (x - cur.nw[M - 1] * nwv) * cur.ic[M - 1];
-    if (W > 1) {
+    if constexpr (M == 2) {  // the North-West value arrives last
+      z[1] = (rest[1] - cur.e[1] * z[0]) - cur.nw[1] * nwv;
+    } else {  // column M - 2 arrives last
+      z[M - 1] = (rest[M - 1] - cur.nw[M - 1] * nwv) - cur.e[M - 1] * z[M - 2];
+    }
+    if constexpr (W > 1) {
       if (lane == 63) s_e[w] = z[M - 1];
       lds_barrier();
     }
@@ -468,7 +547,7 @@ __global__ __launch_bounds__(64 * W) void k_par_wave(const ParArgs<T> *A, int ze
       zv[k] = z[k];
       zp[k] = z[k];
     }
-    *reinterpret_cast<BLP_GLOBAL V *>(reinterpret_cast<BLP_GLOBAL char *>(Z + p * rv) + lob) = zv;
+    par_st<V>(zv, rZ, lob, p * rb);
     e0p = e0;
   };
   // the buffers in turn (indices fixed at compile time: no register copies
