@@ -457,11 +457,14 @@ void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A, int var
 }
 
 template <typename T, bool TR, int EP, int W>
-void lines_launch_k(const Ctx &c, int S, const LineArgs<T> *A) {
-  // D lines of operands in flight: 4 EP words per line and wave, within the
-  // 63 outstanding memory operations a wave can track and its registers
-  constexpr int D = EP >= 16 ? (sizeof(T) == 8 ? 1 : 2) : (EP >= 4 ? 4 : 6);
-  k_lines<T, TR, EP, W, D><<<2 * S, 64 * W, 0, c.stream>>>(A);
+void lines_launch_k(const Ctx &c, int S, int hp, const LineArgs<T> *A) {
+  // D lines of operands in flight: 4 EP words per line and thread (two
+  // buffers of them fill the registers at 16 FP32 or 8 FP64 words), within
+  // the 63 outstanding memory operations a wave can track
+  constexpr int B = EP * (int)sizeof(T);  // bytes per operand and thread
+  constexpr int D = B >= 128 ? 1 : (B >= 64 ? 2 : (B >= 16 ? 4 : 6));
+  if (hp == 64 * W * EP) k_lines<T, TR, EP, W, D, true><<<2 * S, 64 * W, 0, c.stream>>>(A);
+  else k_lines<T, TR, EP, W, D, false><<<2 * S, 64 * W, 0, c.stream>>>(A);
 }
 
 // Line solves: threads hold EP contiguous nodes, W waves per region (EP x
@@ -476,24 +479,24 @@ inline int lines_variants(int hp) {
 template <typename T, bool TR>
 void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A, int var = 0) {
   if (hp <= 64) {
-    lines_launch_k<T, TR, 1, 1>(c, S, A);
+    lines_launch_k<T, TR, 1, 1>(c, S, hp, A);
   } else if (hp <= 128) {
-    if (var == 1) lines_launch_k<T, TR, 1, 2>(c, S, A);
-    else lines_launch_k<T, TR, 2, 1>(c, S, A);
+    if (var == 1) lines_launch_k<T, TR, 1, 2>(c, S, hp, A);
+    else lines_launch_k<T, TR, 2, 1>(c, S, hp, A);
   } else if (hp <= 256) {
-    if (var == 1) lines_launch_k<T, TR, 2, 2>(c, S, A);
-    else if (var == 2) lines_launch_k<T, TR, 1, 4>(c, S, A);
-    else lines_launch_k<T, TR, 4, 1>(c, S, A);
+    if (var == 1) lines_launch_k<T, TR, 2, 2>(c, S, hp, A);
+    else if (var == 2) lines_launch_k<T, TR, 1, 4>(c, S, hp, A);
+    else lines_launch_k<T, TR, 4, 1>(c, S, hp, A);
   } else if (hp <= 512) {
-    if (var == 1) lines_launch_k<T, TR, 4, 2>(c, S, A);
-    else if (var == 2) lines_launch_k<T, TR, 2, 4>(c, S, A);
-    else if (var == 3) lines_launch_k<T, TR, 1, 8>(c, S, A);
-    else lines_launch_k<T, TR, 8, 1>(c, S, A);
+    if (var == 1) lines_launch_k<T, TR, 4, 2>(c, S, hp, A);
+    else if (var == 2) lines_launch_k<T, TR, 2, 4>(c, S, hp, A);
+    else if (var == 3) lines_launch_k<T, TR, 1, 8>(c, S, hp, A);
+    else lines_launch_k<T, TR, 8, 1>(c, S, hp, A);
   } else {
-    if (var == 1) lines_launch_k<T, TR, 8, 2>(c, S, A);
-    else if (var == 2) lines_launch_k<T, TR, 4, 4>(c, S, A);
-    else if (var == 3) lines_launch_k<T, TR, 2, 8>(c, S, A);
-    else lines_launch_k<T, TR, 16, 1>(c, S, A);
+    if (var == 1) lines_launch_k<T, TR, 8, 2>(c, S, hp, A);
+    else if (var == 2) lines_launch_k<T, TR, 4, 4>(c, S, hp, A);
+    else if (var == 3) lines_launch_k<T, TR, 2, 8>(c, S, hp, A);
+    else lines_launch_k<T, TR, 16, 1>(c, S, hp, A);
   }
 }
 

@@ -338,7 +338,8 @@ __global__ void k_diag_skew(Grid<double> g, SkewT<T, TR> sk, T *ic, size_t nslot
 // w = -super/pivot); zero in padding, so padding nodes give y = z = 0.
 //
 // One workgroup of W waves per region; thread g holds the EP contiguous
-// nodes p = g EP + e (one or two 16-byte accesses per operand).  Each
+// nodes p = g EP + e (one or two 16-byte accesses per operand); FULL
+// variants serve lines whose stride hp is exactly 64 W EP.  Each
 // recurrence is an affine scan: a sequential pass over the thread's nodes, a
 // DPP scan across the wave, the wave totals combined through LDS (one
 // barrier per scan), and a fix-up pass.  The operands of D lines ahead are in flight
@@ -393,7 +394,7 @@ struct LineOps {
   T c;  // coupling to the previous line
 };
 
-template <typename T, bool TR, int EP, int W, int D>
+template <typename T, bool TR, int EP, int W, int D, bool FULL>
 __global__ __launch_bounds__(64 * W) void k_lines(const LineArgs<T> *A) {
   const LineArgs<T> a = A[blockIdx.x >> 1];  // two workgroups (regions) per system
   if (gated(a.gate)) return;
@@ -407,7 +408,8 @@ __global__ __launch_bounds__(64 * W) void k_lines(const LineArgs<T> *A) {
   const int h = a.h, hp = a.hp, L = a.n1 - h;
   const Grid<T> &g = a.g;
   // this thread's nodes; threads past the line read node 0 and are masked
-  const bool act = tid * EP < hp;
+  // (FULL: the threads' nodes are exactly the line's hp, none is past it)
+  const bool act = FULL || tid * EP < hp;
   const size_t toff = act ? (size_t)tid * EP : 0;
   // region pointers picked by selects (an index into the record's arrays by
   // the runtime region would place the record in private memory)
