@@ -470,8 +470,9 @@ void lines_launch_k(const Ctx &c, int S, int hp, const LineArgs<T> *A) {
 // Line solves: threads hold EP contiguous nodes, W waves per region (EP x
 // 64 W >= hp).  A line is a chain of dependent scans, so its latency sets the
 // pace: one wave (no workgroup barriers between the scan phases) is the
-// default; variants with more waves and fewer nodes per thread remain for
-// the autotuner.
+// default, except FP64 lines longer than 512 nodes, whose 16 nodes per
+// thread would not fit the registers (four waves of four nodes measured
+// 30% faster there); the other variants remain for the autotuner.
 inline int lines_variants(int hp) {
   return hp <= 64 ? 1 : (hp <= 128 ? 2 : (hp <= 256 ? 3 : 4));
 }
@@ -493,8 +494,9 @@ void lines_launch(const Ctx &c, int S, int hp, const LineArgs<T> *A, int var = 0
     else if (var == 3) lines_launch_k<T, TR, 1, 8>(c, S, hp, A);
     else lines_launch_k<T, TR, 8, 1>(c, S, hp, A);
   } else {
+    // FP64 lines of 16 nodes per thread exceed the registers: four waves
     if (var == 1) lines_launch_k<T, TR, 8, 2>(c, S, hp, A);
-    else if (var == 2) lines_launch_k<T, TR, 4, 4>(c, S, hp, A);
+    else if (var == 2 || (var == 0 && sizeof(T) == 8)) lines_launch_k<T, TR, 4, 4>(c, S, hp, A);
     else if (var == 3) lines_launch_k<T, TR, 2, 8>(c, S, hp, A);
     else lines_launch_k<T, TR, 16, 1>(c, S, hp, A);
   }
