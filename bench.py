@@ -624,10 +624,12 @@ def parabolic(args):
                      "iterations": ir[0]["iterations"],
                      "corner_cycles": [ir[0]["mg_cycles_min"], ir[0]["mg_cycles_max"]],
                      "rel_res_unscaled": unscaled_rel_res(gp, F, Ur)}
-    roof = roofline_of(kt, names={"sweep": "k_par_gs<double, *, *, *, *> (the semicoarsening "
-                                           "levels' Gauss-Seidel sweeps)"}, prefer="sweep")
-    roof["note"] = ("row-sequential Gauss-Seidel on levels of 1024 rows, one workgroup per "
-                    "system: instruction latency per row, not bandwidth, sets the pace")
+    roof = roofline_of(kt, names={"sweep": "k_par_wave<double, *, *, *> and k_sweep<double, ...> "
+                                           "(the corner levels' Gauss-Seidel sweeps)"},
+                       prefer="sweep")
+    roof["note"] = ("wavefront Gauss-Seidel on levels of 1024 rows, one workgroup per system "
+                    "and level: h + nx/M - 1 dependent steps per sweep, each step's instruction "
+                    "issue in one wave, not bandwidth, sets the pace")
     out = {"metric": "parabolic case: solve time, N=2048, eps=1e-7, the paper's stopping rule",
            "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
