@@ -550,27 +550,28 @@ int build_par_levels(blp_problem *p) {
     const int nx = D[l].nx;
     const size_t n = (size_t)nx * h;
     const ParSetupLevel f{p->grid64(), D[0].sx, D[0].sy, l ? D[l].a : nullptr, nx, h};
-    // level 0 is smoothed with the two-exponential-layer level-0 tables
-    const ParSkew sk = l ? par_skew(nx, h) : ParSkew{};
-    const size_t ns = sk.nslot();
+    // level 0 is smoothed with the two-exponential-layer level-0 tables;
+    // each precision has its own coarse sweep shape
+    const ParSkew sk64 = l ? par_skew(nx, h, 8) : ParSkew{}, sk32 = l ? par_skew(nx, h, 4) : ParSkew{};
     auto skew = [&](const double *src, double **d64, float **d32, int np) {
-      BLP_TRY(zalloc(p, d64, np * ns));
-      BLP_TRY(zalloc(p, d32, np * ns));
-      k_par_skew<double><<<grid2d(nx, h), 256, 0, p->stream>>>(src, *d64, sk, np);
-      k_par_skew<float><<<grid2d(nx, h), 256, 0, p->stream>>>(src, *d32, sk, np);
+      BLP_TRY(zalloc(p, d64, np * sk64.nslot()));
+      BLP_TRY(zalloc(p, d32, np * sk32.nslot()));
+      k_par_skew<double><<<grid2d(nx, h), 256, 0, p->stream>>>(src, *d64, sk64, np);
+      k_par_skew<float><<<grid2d(nx, h), 256, 0, p->stream>>>(src, *d32, sk32, np);
       return BLP_OK;
     };
     if (l > 0) {
       if (nx > kParMaxCols) return BLP_E_INVAL;
-      D[l].sk = F[l].sk = sk;
+      D[l].sk = sk64;
+      F[l].sk = sk32;
       BLP_TRY(p->alloc(&D[l].ic, n));
       k_par_invc<<<grid2d(nx, h), 256, 0, p->stream>>>(f, D[l].ic);
       BLP_TRY(skew(D[l].ic, &D[l].sic, &F[l].sic, 1));
       BLP_TRY(skew(D[l].a, &D[l].sa, &F[l].sa, 9));
-      BLP_TRY(zalloc(p, &D[l].ssw, 4 * ns));
-      BLP_TRY(zalloc(p, &F[l].ssw, 4 * ns));
-      k_par_skew_sweep<double><<<grid2d(nx, h), 256, 0, p->stream>>>(D[l].a, D[l].ssw, sk);
-      k_par_skew_sweep<float><<<grid2d(nx, h), 256, 0, p->stream>>>(D[l].a, F[l].ssw, sk);
+      BLP_TRY(zalloc(p, &D[l].ssw, 4 * sk64.nslot()));
+      BLP_TRY(zalloc(p, &F[l].ssw, 4 * sk32.nslot()));
+      k_par_skew_sweep<double><<<grid2d(nx, h), 256, 0, p->stream>>>(D[l].a, D[l].ssw, sk64);
+      k_par_skew_sweep<float><<<grid2d(nx, h), 256, 0, p->stream>>>(D[l].a, F[l].ssw, sk32);
     }
     if (l + 1 < L) {
       BLP_TRY(zalloc(p, &D[l].wl, n));

@@ -592,19 +592,19 @@ constexpr int kMgNormBlocks = 256;
 // every system (one workgroup each, one wave per 64 lanes of M columns),
 // after the pass that folds the old values into the right-hand side (none
 // on a zero iterate).
-template <typename T, int M>
-void par_wave_launch_m(const Ctx &c, int S, int W, const ParArgs<T> *A, int zero_init) {
-  constexpr int D = par_ahead<T, M>();
-  if (W <= 1) k_par_wave<T, 1, M, D><<<S, 64, 0, c.stream>>>(A, zero_init);
-  else if (W == 2) k_par_wave<T, 2, M, D><<<S, 128, 0, c.stream>>>(A, zero_init);
-  else if (W == 3) k_par_wave<T, 3, M, D><<<S, 192, 0, c.stream>>>(A, zero_init);
-  else k_par_wave<T, 4, M, D><<<S, 256, 0, c.stream>>>(A, zero_init);
-}
 template <typename T>
 void par_wave_launch(const Ctx &c, int S, const ParSkew &sk, const ParArgs<T> *A, int zero_init) {
-  const int W = (sk.L + 63) / 64;  // at most four: nx <= 512 (par_skew)
-  if (sk.M == 2) par_wave_launch_m<T, 2>(c, S, W, A, zero_init);
-  else par_wave_launch_m<T, 4>(c, S, W, A, zero_init);
+  // the shapes of par_skew: M = 2 and 8 in one wave, M = 4 in one or two
+  constexpr int D2 = par_ahead<T, 2>(), D4 = par_ahead<T, 4>(), D8 = par_ahead<T, 8>();
+  if (sk.M == 2) {
+    k_par_wave<T, 1, 2, D2><<<S, 64, 0, c.stream>>>(A, zero_init);
+  } else if (sk.M == 8) {
+    if constexpr (sizeof(T) == 4) k_par_wave<T, 1, 8, D8><<<S, 64, 0, c.stream>>>(A, zero_init);
+  } else if (sk.L <= 64) {
+    k_par_wave<T, 1, 4, D4><<<S, 64, 0, c.stream>>>(A, zero_init);
+  } else {
+    k_par_wave<T, 2, 4, D4><<<S, 128, 0, c.stream>>>(A, zero_init);
+  }
 }
 
 template <typename T, bool TR>

@@ -29,7 +29,7 @@
 // the wavefront order's result).  A node's new value depends on its East
 // neighbour and the three nodes of the row above, all visited before it; on
 // a coarse level the sweep runs as a wavefront over lanes that own M
-// columns each (k_par_wave, M = 2 or 4), a node (column c, row t from the
+// columns each (k_par_wave, M = 2, 4 or 8), a node (column c, row t from the
 // top) at step t + c / M, so a sweep is h + nx_l / M - 1 dependent steps.
 #pragma once
 #include "common.h"
@@ -163,14 +163,16 @@ struct ParSkew {
   }
 };
 
-// Sweep shape of a coarse level with nx columns: two columns per lane up
-// to 128 columns (one wave), four above (one wave up to 256, two up to 512:
-// fewer waves, fewer barriers per step, at the same number of steps).
-inline ParSkew par_skew(int nx, int ny) {
+// Sweep shape of a coarse level with nx columns, for words of wb bytes: two
+// columns per lane up to 128 columns (one wave), four up to 256 (one wave);
+// above, up to 512 columns, FP64 takes four (two waves) and FP32 eight (one
+// wave: 32-byte chunks, fewer barriers, loads still few enough to run four
+// steps ahead).  The launch (par_wave_launch) assumes these shapes.
+inline ParSkew par_skew(int nx, int ny, int wb) {
   ParSkew s;
   s.nx = nx;
   s.ny = ny;
-  s.M = nx <= 128 ? 2 : 4;
+  s.M = nx <= 128 ? 2 : (nx <= 256 || wb == 8 ? 4 : 8);
   s.L = (nx + s.M - 1) / s.M;
   return s;
 }
