@@ -340,9 +340,11 @@ int blp_sine_project_noalloc(blp_problem *p, int K, int L, const double *w, doub
  *              tridiagonal solve on the device, as the paper suggests), g
  *              (<= 0: g(N) = ln(N)/N)
  *   info       host, S entries (may be NULL)
- * Device work memory is allocated and freed by the call.  Errors:
- * BLP_E_INVAL, BLP_E_NOMEM, BLP_E_HIP, BLP_E_NUMERIC; BLP_W_NOCONV if any
- * problem reached maxit. */
+ * Device work memory and a pinned host staging buffer are kept per device
+ * between calls, grown when a call needs more, and held until the process
+ * ends; calls on one device run one at a time (each returns after its
+ * stream has finished the batch).  Errors: BLP_E_INVAL, BLP_E_NOMEM,
+ * BLP_E_HIP, BLP_E_NUMERIC; BLP_W_NOCONV if any problem reached maxit. */
 typedef struct {
   int N;
   double eps;

@@ -65,8 +65,9 @@ class BatchOpts(C.Structure):
 
 
 class Problem1D(C.Structure):
+    # c and r: addresses of host double arrays (const double * in the C ABI)
     _fields_ = [("N", C.c_int), ("eps", C.c_double), ("sigma", C.c_double), ("clow", C.c_double),
-                ("kind", C.c_int), ("layer_cells", C.c_int), ("c", _dp), ("r", _dp)]
+                ("kind", C.c_int), ("layer_cells", C.c_int), ("c", C.c_void_p), ("r", C.c_void_p)]
 
 
 class Opts1D(C.Structure):
@@ -453,12 +454,14 @@ def solve_1d(problems, F, maxit=100, left=True, K=0.0, g=0.0, U=None):
         keep += [cv, rv]
         arr[k] = Problem1D(q["N"], q["eps"], q.get("sigma", 2.0), q.get("clow", 1.0),
                            MESH_KINDS[q.get("kind", "shishkin")], int(q.get("layer_cells") or 0),
-                           cv.ctypes.data_as(_dp), rv.ctypes.data_as(_dp))
+                           cv.ctypes.data, rv.ctypes.data)
     for f, q in zip(F, problems):
         if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64
                 and f.is_contiguous() and f.numel() == q["N"] - 1):
             raise TypeError("F must hold contiguous float64 device vectors of N-1 values")
-    U = [torch.empty_like(f) for f in F] if U is None else U
+    if U is None:  # views of one allocation
+        sizes = [f.numel() for f in F]
+        U = list(torch.split(torch.empty(sum(sizes), dtype=torch.float64, device=F[0].device), sizes))
     fa = (C.c_void_p * S)(*[f.data_ptr() for f in F])
     ua = (C.c_void_p * S)(*[u.data_ptr() for u in U])
     infos = (Info1D * S)()

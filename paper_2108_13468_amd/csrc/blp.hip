@@ -1117,16 +1117,50 @@ int blp_bilinear_project(blp_problem *p, int m, const double *w, double *G) {
   return project(p, m, m, 1, 1, 1.0, w, nullptr, G);
 }
 
+namespace {
+// Memory of blp1d_solve, kept per device between calls and grown on demand:
+// device words (nodal c and r, work space, result records) and pinned host
+// words (c and r staged for one copy in, the records for one copy out, the
+// argument records).  Calls on one device take its mutex for their whole
+// duration (each ends with a stream synchronisation), so they run one at a
+// time and the memory is never shared by two of them.
+struct OneDCache {
+  std::mutex mu;
+  double *dev = nullptr;
+  size_t dev_words = 0;
+  unsigned char *host = nullptr;  // pinned
+  size_t host_bytes = 0;
+};
+OneDCache g_oned[kMaxDevices];
+
+int oned_reserve(OneDCache &c, size_t dev_words, size_t host_bytes) {
+  if (c.dev_words < dev_words) {
+    (void)hipFree(c.dev);
+    c.dev = nullptr;
+    c.dev_words = 0;
+    if (hipMalloc((void **)&c.dev, dev_words * sizeof(double)) != hipSuccess) return BLP_E_NOMEM;
+    c.dev_words = dev_words;
+  }
+  if (c.host_bytes < host_bytes) {
+    (void)hipHostFree(c.host);
+    c.host = nullptr;
+    c.host_bytes = 0;
+    if (hipHostMalloc((void **)&c.host, host_bytes, hipHostMallocDefault) != hipSuccess) return BLP_E_NOMEM;
+    c.host_bytes = host_bytes;
+  }
+  return BLP_OK;
+}
+}  // namespace
+
 int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, double *const *U,
                 const blp1d_opts *o, void *stream, blp1d_info *info) {
   if (S < 1 || !probs || !F || !U || !o) return BLP_E_INVAL;
   if (o->maxit < 1 || o->maxit > k1dMaxIt) return BLP_E_INVAL;
   const hipStream_t st = (hipStream_t)stream;
   const int m = o->maxit;
-  // per problem: nodal c and r (copied in), and device work space (stencil
-  // rows, factorisations, vectors, basis, Hessenberg, record), built by the
-  // kernel itself
-  std::vector<OneDArgs> args(S);
+  // per problem: nodal c and r (copied in), device work space (stencil
+  // rows, factorisations, vectors, basis, Hessenberg, built by the kernel
+  // itself) and a result record of 4 words
   std::vector<size_t> off(S + 1, 0), woff(S + 1, 0);
   std::vector<blp_mesh_opts> mo(S);
   for (int s = 0; s < S; ++s) {
@@ -1136,27 +1170,37 @@ int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, doubl
       return BLP_E_INVAL;
     const blp_mesh_opts in{q.sigma, q.clow, q.clow, q.kind, q.layer_cells, BLP_LAYER_EXPONENTIAL};
     BLP_TRY(mesh_options(q.N, &in, &mo[s]));
-    for (int k = 0; k <= q.N; ++k)
-      if (!(q.c[k] > 0) || !(q.r[k] >= 0)) return BLP_E_INVAL;
     const size_t n = (size_t)q.N - 1;
     off[s + 1] = off[s] + 2 * ((size_t)q.N + 1);
-    woff[s + 1] = woff[s] + 9 * n + (size_t)(m + 1) * n + (size_t)(m + 1) * m + 4;
+    woff[s + 1] = woff[s] + 9 * n + (size_t)(m + 1) * n + (size_t)(m + 1) * m;
   }
-  std::vector<double> host(off[S]);
+  int dev_id = -1;
+  HIP_TRY(hipGetDevice(&dev_id));
+  if (dev_id < 0 || dev_id >= kMaxDevices) return BLP_E_STATE;
+  OneDCache &cache = g_oned[dev_id];
+  std::lock_guard<std::mutex> lock(cache.mu);
+  // device: c and r, records, work space, argument records (16-byte aligned)
+  const size_t rec0 = off[S], work0 = rec0 + 4 * (size_t)S;
+  const size_t args0 = (work0 + woff[S] + 1) / 2 * 2;
+  const size_t argw = ((size_t)S * sizeof(OneDArgs) + sizeof(double) - 1) / sizeof(double);
+  // pinned host: c and r, records, argument records (the same offsets)
+  BLP_TRY(oned_reserve(cache, args0 + argw, (rec0 + 4 * (size_t)S) * sizeof(double) + argw * sizeof(double)));
+  double *hc = reinterpret_cast<double *>(cache.host);
+  double *hrec = hc + rec0;
+  OneDArgs *hargs = reinterpret_cast<OneDArgs *>(hc + rec0 + 4 * (size_t)S);
+  double *dev = cache.dev, *recs = dev + rec0, *work = dev + work0;
+  OneDArgs *dargs = reinterpret_cast<OneDArgs *>(dev + args0);
+  // c > 0 and r >= 0 (NaN fails both), checked without branches on the
+  // copies
   for (int s = 0; s < S; ++s) {
-    const int N = probs[s].N;
-    std::memcpy(host.data() + off[s], probs[s].c, (N + 1) * sizeof(double));
-    std::memcpy(host.data() + off[s] + N + 1, probs[s].r, (N + 1) * sizeof(double));
-  }
-  double *dev = nullptr, *work = nullptr;
-  OneDArgs *dargs = nullptr;
-  int rc = BLP_OK;
-  if (hipMalloc((void **)&dev, off[S] * sizeof(double)) != hipSuccess ||
-      hipMalloc((void **)&work, woff[S] * sizeof(double)) != hipSuccess ||
-      hipMalloc((void **)&dargs, S * sizeof(OneDArgs)) != hipSuccess) {
-    (void)hipFree(dev);
-    (void)hipFree(work);
-    return BLP_E_NOMEM;
+    const blp1d_problem &q = probs[s];
+    const int N = q.N;
+    double *cs = hc + off[s], *rs = cs + N + 1;
+    std::memcpy(cs, q.c, (N + 1) * sizeof(double));
+    std::memcpy(rs, q.r, (N + 1) * sizeof(double));
+    int bad = 0;
+    for (int k = 0; k <= N; ++k) bad |= !(cs[k] > 0.0) | !(rs[k] >= 0.0);
+    if (bad) return BLP_E_INVAL;
   }
   for (int s = 0; s < S; ++s) {
     const blp1d_problem &q = probs[s];
@@ -1166,7 +1210,7 @@ int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, doubl
     // blp_mesh's, evaluated per cell in the kernel)
     const double qf = (double)nl / N, layer = mm.sigma * q.eps * std::log((double)N) / mm.clow_x;
     const double tau = std::min(qf, layer);
-    OneDArgs &a = args[s];
+    OneDArgs a{};
     double *wk = work + woff[s];
     a.n = n;
     a.nl = nl;
@@ -1189,39 +1233,39 @@ int blp1d_solve(int S, const blp1d_problem *probs, const double *const *F, doubl
     a.w = wk + 8 * n;
     a.V = wk + 9 * n;
     a.H = a.V + (size_t)(m + 1) * n;
-    a.info = a.H + (size_t)(m + 1) * m;
+    a.info = recs + 4 * (size_t)s;
     a.F = F[s];
     a.U = U[s];
     a.K = o->K;
     a.g = o->g > 0 ? o->g : std::log((double)N) / N;
     a.maxit = m;
     a.left = o->left != 0;
+    hargs[s] = a;
   }
-  std::vector<double> out(4 * (size_t)S);
-  if (hipMemcpyAsync(dev, host.data(), off[S] * sizeof(double), hipMemcpyHostToDevice, st) ||
-      hipMemcpyAsync(dargs, args.data(), S * sizeof(OneDArgs), hipMemcpyHostToDevice, st)) {
+  int rc = BLP_OK;
+  if (hipMemcpyAsync(dev, hc, rec0 * sizeof(double), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(dargs, hargs, S * sizeof(OneDArgs), hipMemcpyHostToDevice, st)) {
     rc = BLP_E_HIP;
   } else {
     k_gmres1d<<<S, k1dThreads, 0, st>>>(dargs);
     if (hipGetLastError() != hipSuccess) rc = BLP_E_HIP;
-    for (int s = 0; s < S && rc == BLP_OK; ++s)
-      if (hipMemcpyAsync(&out[4 * s], args[s].info, 4 * sizeof(double), hipMemcpyDeviceToHost, st))
-        rc = BLP_E_HIP;
-    if (rc == BLP_OK && hipStreamSynchronize(st) != hipSuccess) rc = BLP_E_HIP;
+    if (rc == BLP_OK &&
+        hipMemcpyAsync(hrec, recs, 4 * (size_t)S * sizeof(double), hipMemcpyDeviceToHost, st))
+      rc = BLP_E_HIP;
   }
-  (void)hipFree(dargs);
-  (void)hipFree(work);
-  (void)hipFree(dev);
+  // the pinned buffers are reused by the next call: wait here in any case
+  if (hipStreamSynchronize(st) != hipSuccess && rc == BLP_OK) rc = BLP_E_HIP;
   if (rc != BLP_OK) return rc;
   for (int s = 0; s < S; ++s) {
+    const double *r = hrec + 4 * (size_t)s;
     if (info) {
-      info[s].iterations = (int)out[4 * s];
-      info[s].converged = out[4 * s + 1] != 0.0;
-      info[s].res_inf = out[4 * s + 2];
-      info[s].K = out[4 * s + 3];
+      info[s].iterations = (int)r[0];
+      info[s].converged = r[1] != 0.0;
+      info[s].res_inf = r[2];
+      info[s].K = r[3];
     }
-    if (!std::isfinite(out[4 * s + 2])) rc = BLP_E_NUMERIC;
-    else if (out[4 * s + 1] == 0.0 && rc == BLP_OK) rc = BLP_W_NOCONV;
+    if (!std::isfinite(r[2])) rc = BLP_E_NUMERIC;
+    else if (r[1] == 0.0 && rc == BLP_OK) rc = BLP_W_NOCONV;
   }
   return rc;
 }
