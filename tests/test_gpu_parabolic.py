@@ -77,9 +77,14 @@ def pair(inst, mg_fixed=0, r_nodal=None):
 
 # h = N/2 columns per corner level 0: one to sixteen per lane of the sweep
 # wave (64 to 2048), odd h (a single level: the four-sweep coarsest solve on
-# the corner block itself), and h = 96 (levels 96, 48, 24, 12, 6, 3).
+# the corner block itself), and h = 96 (levels 96, 48, 24, 12, 6, 3).  The
+# coarse sweeps' shapes: levels of 150 and 256 columns (four per lane, one
+# wave), 512 (FP64 four per lane on two waves, FP32 eight on one), 320 (a
+# partly filled second FP64 wave) and 300 (75 FP64 lanes; FP32 chunks of
+# eight with a ragged last one).
 PREC_CASES = [(64, 1e-4, None), (130, 1e-6, None), (200, 1e-5, 96), (256, 1e-8, None),
-              (600, 1e-6, None), (1024, 1e-7, None), (2048, 1e-6, None)]
+              (600, 1e-6, None), (1024, 1e-7, None), (1280, 1e-6, None), (1280, 1e-5, 600),
+              (2048, 1e-6, None)]
 
 
 @pytest.mark.parametrize("N,eps,nl", PREC_CASES)
