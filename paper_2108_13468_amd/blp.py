@@ -447,28 +447,36 @@ def solve_1d(problems, F, maxit=100, left=True, K=0.0, g=0.0, U=None):
     S = len(problems)
     if len(F) != S:
         raise ValueError("one right-hand side per problem")
-    keep = []
-    arr = (Problem1D * S)()
-    for k, q in enumerate(problems):
-        cv, rv = _f64(q["c"]), _f64(q["r"])
-        keep += [cv, rv]
-        arr[k] = Problem1D(q["N"], q["eps"], q.get("sigma", 2.0), q.get("clow", 1.0),
-                           MESH_KINDS[q.get("kind", "shishkin")], int(q.get("layer_cells") or 0),
-                           cv.ctypes.data, rv.ctypes.data)
-    for f, q in zip(F, problems):
+    # the problem records as one numpy array laid out as blp1d_problem
+    # (filled column by column); the c and r arrays stay referenced by keep
+    keep = [(_f64(q["c"]), _f64(q["r"])) for q in problems]
+    rec = np.zeros(S, dtype=np.dtype(Problem1D))
+    rec["N"] = [q["N"] for q in problems]
+    rec["eps"] = [q["eps"] for q in problems]
+    rec["sigma"] = [q.get("sigma", 2.0) for q in problems]
+    rec["clow"] = [q.get("clow", 1.0) for q in problems]
+    rec["kind"] = [MESH_KINDS[q.get("kind", "shishkin")] for q in problems]
+    rec["layer_cells"] = [int(q.get("layer_cells") or 0) for q in problems]
+    rec["c"] = [c.ctypes.data for c, _ in keep]
+    rec["r"] = [r.ctypes.data for _, r in keep]
+    for f, n in zip(F, rec["N"].tolist()):
         if not (isinstance(f, torch.Tensor) and f.is_cuda and f.dtype == torch.float64
-                and f.is_contiguous() and f.numel() == q["N"] - 1):
+                and f.is_contiguous() and f.numel() == n - 1):
             raise TypeError("F must hold contiguous float64 device vectors of N-1 values")
     if U is None:  # views of one allocation
         sizes = [f.numel() for f in F]
         U = list(torch.split(torch.empty(sum(sizes), dtype=torch.float64, device=F[0].device), sizes))
-    fa = (C.c_void_p * S)(*[f.data_ptr() for f in F])
-    ua = (C.c_void_p * S)(*[u.data_ptr() for u in U])
-    infos = (Info1D * S)()
+    fa = np.array([f.data_ptr() for f in F], dtype=np.uint64)
+    ua = np.array([u.data_ptr() for u in U], dtype=np.uint64)
+    infos = np.zeros(S, dtype=np.dtype(Info1D))
     stream = torch.cuda.current_stream().cuda_stream
-    rc = _check(lib().blp1d_solve(S, arr, fa, ua, C.byref(Opts1D(maxit, int(left), K, g)),
-                                  C.c_void_p(stream), infos), "blp1d_solve")
-    out = [{k: getattr(i, k) for k, _ in Info1D._fields_} for i in infos]
-    for d in out:
-        d["status"] = rc
+    rc = _check(lib().blp1d_solve(S, rec.ctypes.data_as(C.POINTER(Problem1D)),
+                                  fa.ctypes.data_as(C.POINTER(C.c_void_p)),
+                                  ua.ctypes.data_as(C.POINTER(C.c_void_p)),
+                                  C.byref(Opts1D(maxit, int(left), K, g)), C.c_void_p(stream),
+                                  infos.ctypes.data_as(C.POINTER(Info1D))), "blp1d_solve")
+    del keep
+    cols = [infos[k].tolist() for k, _ in Info1D._fields_]
+    names = [k for k, _ in Info1D._fields_]
+    out = [dict(zip(names, v), status=rc) for v in zip(*cols)]
     return U, out
