@@ -803,6 +803,7 @@ void prec_part2(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
 template <typename TV, bool TR, bool SCALE>
 struct SolvePlan {
   int S = 0;
+  std::vector<int> idx;             // the batch's systems the plan covers, in record order
   PrecPlan<TV, TR> prec;
   SpmvArgs<TV> *spmv = nullptr;     // x = Z_j -> w
   SpmvArgs<double> *resid = nullptr;  // w = F - A u (scaled if SCALE), ||w||
@@ -862,8 +863,13 @@ struct Batch {
   Alloc mem;
   // cached plans per class and kind (key: class, TV, TR, SCALE, m)
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<PlanBase>> plans;
+  // plans over the systems of a class still iterating (same key, then the
+  // systems), taken when some of the class have left the iteration
+  std::map<std::tuple<int, int, int, int, int>, std::map<std::vector<int>, std::unique_ptr<PlanBase>>>
+      subplans;
   ~Batch() {
     if (stream) (void)hipStreamSynchronize(stream);
+    subplans.clear();
     plans.clear();
     sys.clear();
     mem.release();
@@ -940,6 +946,7 @@ int build_solve_plan(Batch &B, const std::vector<int> &cls, int m, const double 
   P.F.clear();
   P.U.clear();
   P.V.clear();
+  P.idx = cls;
   P.po = B.sys[cls[0]]->p->popts;
   for (int k = 0; k < S; ++k) {
     System &y = *B.sys[cls[k]];
@@ -1095,6 +1102,50 @@ int get_solve_plan(Batch &B, int c, int m, const double *const *F, double *const
   return BLP_OK;
 }
 
+// A plan over the systems sub of class c (those still iterating), with the
+// full class plan's kernel variants.  Kernels launch one block row per
+// system of their plan; a system that has left the iteration only reads its
+// gate and exits, but with most of a class done those blocks dominate the
+// small kernels' time, so each restart cycle takes the plan of its systems.
+constexpr size_t kMaxSubPlans = 16;  // per class and kind
+template <typename TV, bool TR, bool SCALE>
+int get_subset_plan(Batch &B, int c, const std::vector<int> &sub, int m, const double *const *F,
+                    double *const *U, const SolvePlan<TV, TR, SCALE> &full,
+                    SolvePlan<TV, TR, SCALE> **out) {
+  auto &mp = B.subplans[std::make_tuple(c, (int)sizeof(TV), (int)TR, (int)SCALE, m)];
+  auto it = mp.find(sub);
+  if (it != mp.end()) {
+    auto *h = static_cast<PlanHolder<TV, TR, SCALE> *>(it->second.get());
+    bool basis = true, same = true;
+    for (size_t k = 0; k < sub.size(); ++k) {
+      const int s = sub[k];
+      basis = basis && h->plan.V[k] == B.sys[s]->V;
+      same = same && h->plan.F[k] == F[s] && h->plan.U[k] == U[s];
+    }
+    const blp_prec_opts &q = full.po, &r = h->plan.po;
+    const bool opts = q.mg_fixed == r.mg_fixed && q.mg_rtol == r.mg_rtol && q.mg_maxcyc == r.mg_maxcyc;
+    if (basis && opts) {
+      if (!same) BLP_TRY((rebind_solve_plan<TV, TR, SCALE>(B, sub, F, U, h->plan)));
+      *out = &h->plan;
+      return BLP_OK;
+    }
+    mp.erase(it);
+  }
+  if (mp.size() >= kMaxSubPlans) mp.clear();
+  std::unique_ptr<PlanHolder<TV, TR, SCALE>> h(new (std::nothrow) PlanHolder<TV, TR, SCALE>());
+  if (!h) return BLP_E_NOMEM;
+  BLP_TRY((build_solve_plan<TV, TR, SCALE>(B, sub, m, F, U, h->plan)));
+  PrecPlan<TV, TR> &Q = h->plan.prec;
+  Q.varI = full.prec.varI;
+  Q.varL = full.prec.varL;
+  Q.varLines = full.prec.varLines;
+  h->plan.rows = full.rows;
+  h->plan.tuned = full.tuned;
+  *out = &h->plan;
+  mp[sub] = std::move(h);
+  return BLP_OK;
+}
+
 // Class streams: created on first use when the batch has several classes.
 int ensure_class_streams(Batch &B) {
   const int NC = (int)B.classes.size();
@@ -1216,8 +1267,9 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
   auto t0 = std::chrono::steady_clock::now();
   for (auto &y : B.sys) BLP_TRY(ensure_krylov(*y, B.stream, m, o->precision));
   BLP_TRY(ensure_class_streams(B));
-  std::vector<SolvePlan<TV, TR, SCALE> *> P(NC);
+  std::vector<SolvePlan<TV, TR, SCALE> *> P(NC), Pfull(NC);
   for (int k = 0; k < NC; ++k) BLP_TRY((get_solve_plan<TV, TR, SCALE>(B, k, m, F, U, &P[k])));
+  Pfull = P;
   const blp_prec_opts &po = B.sys[0]->p->popts;
   // kernel timing records events between launches: no graphs then
   const bool use_graphs = B.graphs && !(B.timer && B.timer->on);
@@ -1282,6 +1334,14 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       ncol[s] = 0;
       est_ok[s] = 0;
     }
+    // each class runs this cycle on the plan of its systems in the cycle
+    for (int k = 0; k < NC; ++k) {
+      std::vector<int> sub;
+      for (int s : B.classes[k])
+        if (incyc[s]) sub.push_back(s);
+      if (sub.empty() || (int)sub.size() == Pfull[k]->S) P[k] = Pfull[k];
+      else BLP_TRY((get_subset_plan<TV, TR, SCALE>(B, k, sub, m, F, U, *Pfull[k], &P[k])));
+    }
     BLP_TRY(set_gates(incyc));
     BLP_TRY(fork(B));
     for (int k = 0; k < NC; ++k) {
@@ -1314,8 +1374,9 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
             HIP_TRY(hipMemcpyAsync(B.ctrl_h, B.ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost,
                                    B.stream));
             HIP_TRY(hipStreamSynchronize(B.stream));
+            // (systems outside the cycle keep their gate closed)
             bool open = false;
-            for (int s = 0; s < S; ++s) open = open || !B.ctrl_h[s].gate;
+            for (int s = 0; s < S; ++s) open = open || (incyc[s] && !B.ctrl_h[s].gate);
             BLP_TRY(fork(B));
             if (!open) break;
             for (int k = 0; k < NC; ++k) {
@@ -1328,9 +1389,9 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
         for (int k = 0; k < NC; ++k) {
           const size_t n = B.sys[B.classes[k][0]]->p->n;
           for (int q = 0; q < P[k]->S; ++q) {
-            System &y = *B.sys[B.classes[k][q]];
+            System &y = *B.sys[P[k]->idx[q]];
             TV *vj = (TV *)y.V + (size_t)j * n, *zj = (TV *)y.Z + (size_t)j * n;
-            if (!incyc[B.classes[k][q]]) continue;
+            if (!incyc[P[k]->idx[q]]) continue;
             if (SCALE)
               k_div<TV><<<blocks1d(n), 256, 0, cx[k].stream>>>(vj, fine<TV>(y.p).dh, zj, n);
             else
@@ -1387,7 +1448,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
     {
       int off = 0;
       for (int k = 0; k < NC; ++k)
-        for (int q = 0; q < P[k]->S; ++q) B.ncol_h[off++] = ncol[B.classes[k][q]];
+        for (int q = 0; q < P[k]->S; ++q) B.ncol_h[off++] = ncol[P[k]->idx[q]];
       HIP_TRY(hipMemcpyAsync(B.ncol, B.ncol_h, S * sizeof(int), hipMemcpyHostToDevice, B.stream));
       BLP_TRY(fork(B));
       off = 0;
