@@ -1267,9 +1267,14 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
   auto t0 = std::chrono::steady_clock::now();
   for (auto &y : B.sys) BLP_TRY(ensure_krylov(*y, B.stream, m, o->precision));
   BLP_TRY(ensure_class_streams(B));
-  std::vector<SolvePlan<TV, TR, SCALE> *> P(NC), Pfull(NC);
+  // per class: the full plan, the plan of the systems that started the
+  // current restart cycle, and the plan the steps launch
+  std::vector<SolvePlan<TV, TR, SCALE> *> P(NC), Pfull(NC), Pcyc(NC);
   for (int k = 0; k < NC; ++k) BLP_TRY((get_solve_plan<TV, TR, SCALE>(B, k, m, F, U, &P[k])));
   Pfull = P;
+  // the plan over a class's systems still in the cycle, once they are at
+  // most half of the plan's (fewer idle blocks, few plan switches)
+
   const blp_prec_opts &po = B.sys[0]->p->popts;
   // kernel timing records events between launches: no graphs then
   const bool use_graphs = B.graphs && !(B.timer && B.timer->on);
@@ -1280,6 +1285,15 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
   std::vector<int> it(S, 0), restarts(S, 0), ncol(S, 0);
   std::vector<char> active(S, 1), conv(S, 0), incyc(S, 0), est_ok(S, 0);
   std::vector<CycleStats> cs(S);
+  // the plan over a class's systems still in the cycle, once they are at
+  // most half of the plan's (fewer idle blocks, few plan switches)
+  auto shrink = [&](int k) {
+    std::vector<int> sub;
+    for (int s : B.classes[k])
+      if (incyc[s]) sub.push_back(s);
+    if (sub.empty() || 2 * (int)sub.size() > P[k]->S) return (int)BLP_OK;
+    return get_subset_plan<TV, TR, SCALE>(B, k, sub, m, F, U, *Pfull[k], &P[k]);
+  };
   // classes with at least one system flagged (launches of other classes are skipped)
   auto live = [&](int k, const std::vector<char> &on) {
     for (int s : B.classes[k])
@@ -1341,6 +1355,7 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
         if (incyc[s]) sub.push_back(s);
       if (sub.empty() || (int)sub.size() == Pfull[k]->S) P[k] = Pfull[k];
       else BLP_TRY((get_subset_plan<TV, TR, SCALE>(B, k, sub, m, F, U, *Pfull[k], &P[k])));
+      Pcyc[k] = P[k];
     }
     BLP_TRY(set_gates(incyc));
     BLP_TRY(fork(B));
@@ -1433,7 +1448,10 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       }
       if (!any) break;
       // the device gates still equal incyc unless a system left the cycle
-      if (left) BLP_TRY(set_gates(incyc));
+      if (left) {
+        BLP_TRY(set_gates(incyc));
+        for (int k = 0; k < NC; ++k) BLP_TRY(shrink(k));
+      }
       BLP_TRY(fork(B));
       for (int k = 0; k < NC; ++k) {
         if (!live(k, incyc)) continue;
@@ -1442,8 +1460,10 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
       }
       BLP_TRY(join(B));
     }
-    // u += Z y and the true residual of every system of the cycle; column
-    // counts in class order (the kernel indexes its class-local slot)
+    // u += Z y and the true residual of every system of the cycle (on the
+    // plan of the systems that started it); column counts in the plan's
+    // record order (the kernel indexes its record's slot)
+    P = Pcyc;
     BLP_TRY(set_gates(active));
     {
       int off = 0;
