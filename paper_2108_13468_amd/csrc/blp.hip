@@ -652,7 +652,7 @@ int apply_prec(blp_problem *p, const T *x, T *y, int *cycles) {
   const Ctx c{p->stream, &p->timer};
   HIP_TRY(hipMemsetAsync(B->gate, 0, sizeof(int), p->stream));
   prec_part1<T, TR>(c, P, nullptr, p->popts);
-  BLP_TRY((corner_finish<T, TR>(c, P, p->popts, kFirstCycles, B->ctrl, B->ctrl_h, 1)));
+  BLP_TRY((corner_finish<T, TR>(c, P, p->popts, first_cycles(P), B->ctrl, B->ctrl_h, 1)));
   prec_part2<T, TR>(c, P, nullptr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(B->ctrl_h, B->ctrl, sizeof(MgCtrl), hipMemcpyDeviceToHost, p->stream));

@@ -771,8 +771,15 @@ void corner_end(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp) {
   k_corner_copy<T, TR><<<dim3((P.h + 255) / 256, P.h, P.S), 256, 0, c.stream>>>(P.cr, jp);
 }
 
-// Cycles the adaptive rule enqueues before it looks at the corner residuals.
-constexpr int kFirstCycles = 5;
+// Cycles the adaptive rule enqueues before it looks at the corner residuals:
+// the count the rule usually takes (Sec. 3.2: five for two exponential
+// layers, about three with a parabolic one).  Enqueued cycles past a
+// system's stop are gated launches; a system that needs more gets them
+// through the host check.
+template <typename T, bool TR>
+int first_cycles(const PrecPlan<T, TR> &P) {
+  return P.par ? 3 : 5;
+}
 
 // Preconditioner part before the corner-cycle check: forward I, edges,
 // corner right-hand side and the first cycles; transposed (M^T, block lower
@@ -783,7 +790,7 @@ void prec_part1(const Ctx &c, const PrecPlan<T, TR> &P, const int *jp, const blp
     interior_run<T, TR>(c, P, jp);
     lines_run<T, TR>(c, P, jp);
   }
-  corner_begin<T, TR>(c, P, jp, o, kFirstCycles);
+  corner_begin<T, TR>(c, P, jp, o, first_cycles(P));
 }
 // ... and after it: corner copy-back, then (transposed) edges and interior.
 template <typename T, bool TR>
@@ -1384,7 +1391,9 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
           }
         }
         if (po.mg_fixed == 0) {
-          for (int extra = kFirstCycles; extra < po.mg_maxcyc; ++extra) {
+          int first = po.mg_maxcyc;
+          for (int k = 0; k < NC; ++k) first = std::min(first, first_cycles(P[k]->prec));
+          for (int extra = first; extra < po.mg_maxcyc; ++extra) {
             BLP_TRY(join(B));
             HIP_TRY(hipMemcpyAsync(B.ctrl_h, B.ctrl, S * sizeof(MgCtrl), hipMemcpyDeviceToHost,
                                    B.stream));
@@ -1394,8 +1403,10 @@ int fgmres_batch(Batch &B, const double *const *F, double *const *U, const blp_s
             for (int s = 0; s < S; ++s) open = open || (incyc[s] && !B.ctrl_h[s].gate);
             BLP_TRY(fork(B));
             if (!open) break;
+            // (a class whose first enqueued cycles already reach this count
+            // waits for the others)
             for (int k = 0; k < NC; ++k) {
-              if (!live(k, incyc)) continue;
+              if (!live(k, incyc) || extra < first_cycles(P[k]->prec)) continue;
               corner_cycle<TV, TR>(cx[k], P[k]->prec);
             }
           }
