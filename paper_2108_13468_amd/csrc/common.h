@@ -120,6 +120,22 @@ BLP_DEV void reset_counter(unsigned int *counter) {
   __hip_atomic_store(gptr(counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// XCD-aware block order.  The chip deals workgroups to its eight XCDs in
+// turn (consecutive workgroup ids on consecutive XCDs), and each XCD has an
+// L2 of its own.  In the skewed level layout the neighbours of a block's
+// slots lie in the slot ranges of the adjacent blocks, so with the plain
+// order every line is fetched once by each of three XCDs.  xcd_block maps
+// the hardware block b of nb to a logical block such that the blocks on one
+// XCD (equal b mod 8) take one contiguous range: XCD x gets nb / 8 blocks,
+// one more when x < nb mod 8.  It is a permutation of 0 .. nb - 1 for any
+// nb, so results do not depend on it; where blockIdx.y varies too, the
+// grouping by b mod 8 still holds, only on rotated XCDs.
+BLP_DEV int xcd_block(int b, int nb) {
+  constexpr int X = 8;
+  const int x = b % X, k = b / X, q = nb / X, r = nb % X;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Batched launches: blockIdx.z (or the block's system slot) selects one
 // system's argument record in a device array.  Vectors that change with the
 // Krylov step are addressed as base + j * ld, with j read from device memory

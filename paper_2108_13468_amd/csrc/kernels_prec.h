@@ -115,12 +115,30 @@ struct Skew {
   BLP_DEV int row(int j) const { return TR ? j - j0 : j1 - j; }
   BLP_DEV int icol(int c) const { return TR ? i0 + c : i1 - c; }
   BLP_DEV int jrow(int t) const { return TR ? j0 + t : j1 - t; }
-  // s >= 0
+  // s >= 0.  32-bit arithmetic: a rectangle of at most kSweepMaxRows rows
+  // and kSweepMaxBands bands holds far fewer than 2^32 slots.
   BLP_DEV size_t slot(int band, int s, int lane) const {
-    return (((size_t)band * nck() + s / P) * 64 + lane) * P + s % P;
+    const unsigned us = (unsigned)s;
+    return (size_t)((((unsigned)band * (unsigned)nck() + us / P) * 64u + (unsigned)lane) * P + us % P);
   }
   BLP_DEV size_t at_ct(int c, int t) const { return slot(c >> 6, t + (c & 63), c & 63); }
   BLP_DEV size_t at(int i, int j) const { return at_ct(col(i), row(j)); }
+  // decode for a slot whose wave holds 64 consecutive slots starting at a
+  // multiple of 64, so that every lane lies in the same band and chunk row:
+  // that pair comes from one scalar division per wave instead of an integer
+  // division in every lane.  Same result as decode.
+  BLP_DEV bool decode_wave(size_t q, int &i, int &j) const {
+    const int e = (int)(q % P);
+    const unsigned r = (unsigned)(q / P);
+    const int lane = (int)(r & 63u);
+    const unsigned r2 = __builtin_amdgcn_readfirstlane(r >> 6), n = (unsigned)nck();
+    const unsigned band = r2 / n, sc = r2 - band * n;
+    const int c = (int)band * 64 + lane, t = (int)sc * P + e - lane;
+    if (c >= mc() || t < 0 || t >= mr()) return false;
+    i = icol(c);
+    j = jrow(t);
+    return true;
+  }
   // slot index -> node; false on padding
   BLP_DEV bool decode(size_t q, int &i, int &j) const {
     const int e = (int)(q % P);
@@ -770,12 +788,12 @@ template <typename T, bool TR>
 __global__ void k_gs_rhs(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
   const int gate = gptr(a.ctrl)->gate;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (q >= a.L.nslot) return;
   const MgLevelG<T> L = lview(a.L);
   const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
   int i = 1, j = 1;
-  const bool node = sk.decode(q, i, j);
+  const bool node = sk.decode_wave(q, i, j);
   if (!node) i = j = 1;
   const double v = gs_rhs_value<T, TR>(L, sk, i, j, q);
   BLP_ISSUED();
@@ -788,12 +806,12 @@ template <typename T, bool TR>
 __global__ void k_mg_resid(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
   const int gate = gptr(a.ctrl)->gate;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (q >= a.L.nslot) return;
   const MgLevelG<T> L = lview(a.L);
   const SkewT<T, TR> sk = level_skew<T, TR>(L.g.nx);
   int i = 1, j = 1;
-  const bool node = sk.decode(q, i, j);
+  const bool node = sk.decode_wave(q, i, j);
   if (!node) i = j = 1;
   const double r = (double)L.b[q] - level_apply<T, TR>(L.g, sk, L.z, i, j);
   BLP_ISSUED();
@@ -834,12 +852,12 @@ template <typename T, bool TR>
 __global__ void k_mg_restrict(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
   const int gate = gptr(a.ctrl)->gate;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (q >= a.Cc.nslot) return;
   const MgLevelG<T> F = lview(a.L), Cc = lview(a.Cc);
   const SkewT<T, TR> skc = level_skew<T, TR>(Cc.g.nx), skf = level_skew<T, TR>(F.g.nx);
   int k = 1, m = 1;
-  const bool node = skc.decode(q, k, m);
+  const bool node = skc.decode_wave(q, k, m);
   if (!node) k = m = 1;
   const T v = restrict_value<T, TR>(F, Cc, skf, k, m);
   BLP_ISSUED();
@@ -908,12 +926,12 @@ template <typename T, bool TR>
 __global__ void k_mg_prolong_gs(const MgArgs<T> *A) {
   const MgArgs<T> a = A[blockIdx.y];
   const int gate = gptr(a.ctrl)->gate;
-  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t q = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (q >= a.L.nslot) return;
   const MgLevelG<T> F = lview(a.L), Cc = lview(a.Cc);
   const SkewT<T, TR> skf = level_skew<T, TR>(F.g.nx), skc = level_skew<T, TR>(Cc.g.nx);
   int i = 1, j = 1;
-  const bool node = skf.decode(q, i, j);
+  const bool node = skf.decode_wave(q, i, j);
   if (!node) i = j = 1;
   const T v = prolong_gs_value<T, TR>(F, Cc, skf, skc, i, j, q);
   BLP_ISSUED();
@@ -1423,14 +1441,15 @@ __global__ __launch_bounds__(256) void k_mg_norm(const MgArgs<T> *A) {
   constexpr int NU = 4;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   double acc = 0.0;
-  for (size_t q0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < nslot; q0 += NU * stride) {
+  const int lb = xcd_block(blockIdx.x, gridDim.x);  // logical block (partials in its order)
+  for (size_t q0 = (size_t)lb * blockDim.x + threadIdx.x; q0 < nslot; q0 += NU * stride) {
     double vs[NU];
     bool on[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
       const size_t q = q0 + u * stride, qc = q < nslot ? q : nslot - 1;
       int i = 1, j = 1;
-      const bool node = sk.decode(qc, i, j);
+      const bool node = sk.decode_wave(qc, i, j);
       if (!node) i = j = 1;
       on[u] = node & (q < nslot);
       double v = (double)L.b[qc];
@@ -1444,7 +1463,7 @@ __global__ __launch_bounds__(256) void k_mg_norm(const MgArgs<T> *A) {
   BLP_ISSUED();
   if (gate) return;
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) publish(&a.partials[blockIdx.x], acc);
+  if (threadIdx.x == 0) publish(&a.partials[lb], acc);
   if (!arrive_last(&ctrl->counter, &last, gridDim.x)) return;
   // last block: fixed-order sum of the partials (deterministic)
   double s = 0.0;

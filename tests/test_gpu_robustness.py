@@ -148,6 +148,7 @@ def test_sweep_variants_bitwise(N):
     for prec in ("fp64", "mixed"):
         ref = None
         for v in range(0, 8):
+            say("N=%d %s: sweep variant %d" % (N, prec, v))
             b = blp.Batch([p], sweep_variant=v)
             U, info = b.solve([F], tol=1e-8, precision=prec)
             L, ia = b.solve_adjoint([F], tol=1e-8, precision=prec)
