@@ -403,7 +403,7 @@ int build_prec_plan(hipStream_t st, const std::vector<System *> &sys, const std:
 // variant 1.
 inline int sweep_variants(int ncols) {
   const int nb = (ncols + 63) / 64;
-  return nb == 1 ? 4 : (nb <= 4 ? 6 : (nb <= 8 ? 7 : 4));
+  return nb == 1 ? 4 : (nb <= 4 ? 6 : (nb <= 8 ? 7 : 6));
 }
 
 template <typename T, bool TR, int K, int D, int G>
@@ -451,6 +451,9 @@ void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A, int var
       case 1: sweep_launch_k<T, TR, 4 * P, 1, 1>(c, S, nb, A); break;
       case 2: sweep_launch_k<T, TR, 2 * P, 1, 1>(c, S, nb, A); break;
       case 3: sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A); break;
+      // four compute units: at most four bands, one wave per SIMD, each
+      case 4: sweep_launch_k<T, TR, 4 * P, 4, 4>(c, S, nb, A); break;
+      case 5: sweep_launch_k<T, TR, 4 * P, 2, 4>(c, S, nb, A); break;
       default: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
     }
   }

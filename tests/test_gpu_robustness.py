@@ -136,10 +136,11 @@ def test_cycle_cap_and_reprecondition():
     assert e.value.code == BLP_E_INVAL
 
 
-@pytest.mark.parametrize("N", [128, 520, 1024])
+@pytest.mark.parametrize("N", [128, 520, 1024, 2048])
 def test_sweep_variants_bitwise(N):
     """N = 128: one-band interior; N = 520: five-band interior and corner
-    levels of 260 and 130 nodes; N = 1024: eight bands, levels 512/256/128."""
+    levels of 260 and 130 nodes; N = 1024: eight bands, levels 512/256/128;
+    N = 2048: sixteen bands (splits over two and four compute units)."""
     import torch
     from paper_2108_13468_amd import blp
     p, inst = _problem(N=N, eps=1e-6, seed=42)
