@@ -451,10 +451,12 @@ void sweep_launch(const Ctx &c, int S, int ncols, const SweepArgs<T> *A, int var
       case 1: sweep_launch_k<T, TR, 4 * P, 1, 1>(c, S, nb, A); break;
       case 2: sweep_launch_k<T, TR, 2 * P, 1, 1>(c, S, nb, A); break;
       case 3: sweep_launch_k<T, TR, 4 * P, 2, 2>(c, S, nb, A); break;
-      // four compute units: at most four bands, one wave per SIMD, each
       case 4: sweep_launch_k<T, TR, 4 * P, 4, 4>(c, S, nb, A); break;
-      case 5: sweep_launch_k<T, TR, 4 * P, 2, 4>(c, S, nb, A); break;
-      default: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
+      case 5: sweep_launch_k<T, TR, 4 * P, 4, 2>(c, S, nb, A); break;
+      default:
+        // four compute units: at most four bands, one wave per SIMD, each
+        sweep_launch_k<T, TR, 4 * P, 2, 4>(c, S, nb, A);
+        break;
     }
   }
 }
